@@ -1,0 +1,411 @@
+"""Pins of the FP64 oracle to facts outside itself (CPU only).
+
+Each test fixes part of the oracle with something the paper or the
+mathematics determines: closed-form lattice sums with textbook FCC shell
+counts, the dimer closed form, finite differences of the energy, Newton's
+third law, invariances, the open-boundary virial identity, Hermite tail
+conditions, NVE conservation and time reversibility of velocity Verlet, the
+Langevin equipartition, and the published Philox known-answer vectors.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+AU = oracle.Pot()
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fcc_shell_energy(pot, a, shells):
+    """Energy of one atom in a perfect FCC crystal from (count, r/a) shells,
+    written with math.exp independently of the oracle."""
+    rho = 0.0
+    rep = 0.0
+    for cnt, ra in shells:
+        r = ra * a
+        rho += cnt * pot.xi ** 2 * math.exp(-2 * pot.q * (r / pot.r0 - 1))
+        rep += cnt * pot.A * math.exp(-pot.p * (r / pot.r0 - 1))
+    return -math.sqrt(rho) + rep
+
+
+# FCC coordination shells: 12 at a/sqrt2, 6 at a, 24 at a sqrt(3/2),
+# 12 at a sqrt2, 24 at a sqrt(5/2); the next (8 at a sqrt3 = 7.07 A) lies
+# beyond the 7.0 A cutoff.
+FCC5 = [(12, math.sqrt(0.5)), (6, 1.0), (24, math.sqrt(1.5)), (12, math.sqrt(2.0)),
+        (24, math.sqrt(2.5))]
+
+
+def center_energy(pot, a):
+    x, y, z, _ = oracle.build_wire(a, 3.2 * pot.r_cut, 3.2 * pot.r_cut, 0)
+    L = 3.2 * pot.r_cut
+    k = int(round(0.5 * L / (0.5 * a)))
+    zc = k * 0.5 * a
+    i = int(np.argmin(x ** 2 + y ** 2 + (z - zc) ** 2))
+    assert x[i] == 0 and y[i] == 0
+    # the central atom must be farther than r_cut from every surface
+    r_surf = min(1.6 * pot.r_cut, zc, z.max() - zc)
+    assert r_surf > pot.r_cut + 0.5
+    r = oracle.forces(pot, x, y, z, 1)
+    return r["e_atom"][i]
+
+
+def test_cohesive_energy_closed_form():
+    """Table 1 with r0 = 2.884 A: central atom of a large FCC cluster at
+    a = 4.08 A equals the 5-shell closed form and the Au cohesive energy the
+    parameters were fitted to (about -3.78 eV/atom)."""
+    e = center_energy(AU, 4.08)
+    ref = fcc_shell_energy(AU, 4.08, FCC5)
+    assert abs(e - ref) < 1e-12
+    assert abs(e - (-3.7792)) < 1e-3
+
+
+def test_equilibrium_lattice_constant():
+    """The fit reproduces the lattice parameter: dE/da = 0 near a = 4.079 A,
+    which is the value Table 1 prints in its r0 column."""
+    h = 1e-4
+    a_grid = np.linspace(4.070, 4.090, 11)
+    dE = [(center_energy(AU, a + h) - center_energy(AU, a - h)) / (2 * h) for a in a_grid]
+    dE = np.array(dE)
+    assert dE[0] < 0 < dE[-1]
+    j = int(np.argmax(dE > 0))
+    a_eq = a_grid[j - 1] - dE[j - 1] * (a_grid[j] - a_grid[j - 1]) / (dE[j] - dE[j - 1])
+    assert abs(a_eq - 4.079) < 1e-3
+
+
+def test_r0_as_printed_gives_unbound_crystal():
+    """Reading check: with r0 = 4.079 A (the printed column) the crystal has a
+    large positive energy, so the printed value cannot be the pair distance."""
+    pot = oracle.Pot(r0=4.079)
+    assert fcc_shell_energy(pot, 4.08, FCC5) > 10.0
+
+
+def test_hard_cut_mode():
+    """r_tail == r_cut reproduces the paper's hard cut at 5.8 A (4 shells)."""
+    pot = oracle.Pot(r_tail=5.8, r_cut=5.8)
+    e = center_energy(pot, 4.08)
+    assert abs(e - fcc_shell_energy(pot, 4.08, FCC5[:4])) < 1e-12
+
+
+def test_dimer_closed_form():
+    """Two atoms: E = 2 [V(r) - xi exp(-q (r/r0 - 1))] and the force on each
+    is dE/dr along the bond (attractive beyond the dimer minimum)."""
+    for r in (2.3, 2.884, 3.5, 5.0, 6.0):
+        x = np.array([0.0, r])
+        y = np.zeros(2)
+        z = np.zeros(2)
+        out = oracle.forces(AU, x, y, z, 0)
+        s = r / AU.r0 - 1
+        E = 2 * (AU.A * math.exp(-AU.p * s) - AU.xi * math.exp(-AU.q * s))
+        dE = 2 * (-AU.p / AU.r0 * AU.A * math.exp(-AU.p * s)
+                  + AU.q / AU.r0 * AU.xi * math.exp(-AU.q * s))
+        assert abs(out["E"] - E) < 1e-13
+        assert abs(out["fx"][0] - dE) < 1e-12
+        assert abs(out["fx"][1] + dE) < 1e-12
+    out = oracle.forces(AU, np.array([0.0, AU.r0]), np.zeros(2), np.zeros(2), 0)
+    assert abs(out["E"] - 2 * (AU.A - AU.xi)) < 1e-13
+
+
+def test_linear_trimer_closed_form():
+    """Three collinear atoms at 0, a, a+b: closed-form energy."""
+    a, b = 2.8, 3.3
+    x = np.array([0.0, a, a + b])
+    out = oracle.forces(AU, x, np.zeros(3), np.zeros(3), 0)
+    phi = lambda r: AU.xi ** 2 * math.exp(-2 * AU.q * (r / AU.r0 - 1))
+    V = lambda r: AU.A * math.exp(-AU.p * (r / AU.r0 - 1))
+    c = a + b
+    E = (-math.sqrt(phi(a) + phi(c)) - math.sqrt(phi(a) + phi(b)) - math.sqrt(phi(b) + phi(c))
+         + 2 * (V(a) + V(b) + V(c)))
+    assert abs(out["E"] - E) < 1e-12
+
+
+def random_cluster(n, seed, box=9.0, dmin=2.3):
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(0, box, 3)
+        if all(np.linalg.norm(p - q) > dmin for q in pts):
+            pts.append(p)
+    P = np.array(pts)
+    return P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_forces_are_minus_energy_gradient(seed):
+    """Central finite differences of the oracle energy, h = 1e-5 A."""
+    x, y, z = random_cluster(30, seed)
+    out = oracle.forces(AU, x, y, z, 0)
+    # the cluster must exercise the cubic tail
+    d = np.sqrt((x[:, None] - x) ** 2 + (y[:, None] - y) ** 2 + (z[:, None] - z) ** 2)
+    assert np.any((d > AU.r_tail) & (d < AU.r_cut))
+    h = 1e-5
+    F = np.stack([out["fx"], out["fy"], out["fz"]], 1)
+    fmax = np.abs(F).max()
+    for i in range(0, 30, 3):
+        for c, arr in enumerate((x, y, z)):
+            arr[i] += h
+            ep = oracle.forces(AU, x, y, z, 0)["E"]
+            arr[i] -= 2 * h
+            em = oracle.forces(AU, x, y, z, 0)["E"]
+            arr[i] += h
+            fd = -(ep - em) / (2 * h)
+            assert abs(fd - F[i, c]) < 1e-7 * max(1.0, fmax), (i, c, fd, F[i, c])
+
+
+def test_newton_third_law_and_invariance():
+    x, y, z = random_cluster(36, 7)
+    out = oracle.forces(AU, x, y, z, 0)
+    F = np.stack([out["fx"], out["fy"], out["fz"]], 1)
+    assert np.abs(F.sum(0)).max() < 1e-12 * np.abs(F).sum()
+    # translation
+    t = oracle.forces(AU, x + 123.4, y - 7.7, z + 0.3, 0)
+    assert abs(t["E"] - out["E"]) < 1e-11
+    # rotation: energy invariant, forces rotate
+    th = 0.7
+    Rm = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    Rm = Rm @ np.array([[1, 0, 0], [0, math.cos(1.1), -math.sin(1.1)], [0, math.sin(1.1), math.cos(1.1)]])
+    P = np.stack([x, y, z], 1) @ Rm.T
+    r = oracle.forces(AU, P[:, 0], P[:, 1], P[:, 2], 0)
+    assert abs(r["E"] - out["E"]) < 1e-11
+    Fr = np.stack([r["fx"], r["fy"], r["fz"]], 1)
+    assert np.abs(Fr - F @ Rm.T).max() < 1e-11
+
+
+def test_virial_open_boundary_identity():
+    """For a finite cluster with central pair forces, the pair virial
+    -sum_{i<j} E' d d / r equals sum_i r_i (x) F_i (W symmetric)."""
+    x, y, z = random_cluster(36, 11)
+    out = oracle.forces(AU, x, y, z, 0)
+    P = np.stack([x, y, z], 1)
+    F = np.stack([out["fx"], out["fy"], out["fz"]], 1)
+    M = P.T @ F
+    W = out["w6"]
+    full = np.array([[W[0], W[3], W[4]], [W[3], W[1], W[5]], [W[4], W[5], W[2]]])
+    assert np.abs(M - M.T).max() < 1e-10
+    assert np.abs(full - M).max() < 1e-10
+
+
+def test_cubic_tail_conditions():
+    """The tail matches value and slope at r_tail and vanishes with zero
+    slope at r_cut; beyond r_cut both functions are zero."""
+    eps = 1e-9
+    for kind in (0, 1):
+        f_in, d_in = oracle.radial(AU, kind, AU.r_tail)
+        f_out, d_out = oracle.radial(AU, kind, AU.r_tail + eps)
+        assert abs(f_in - f_out) < 1e-8 * abs(f_in)
+        assert abs(d_in - d_out) < 1e-6 * abs(d_in)
+        f_c, d_c = oracle.radial(AU, kind, AU.r_cut)
+        assert abs(f_c) < 1e-15 and abs(d_c) < 1e-15
+        assert oracle.radial(AU, kind, AU.r_cut + 1e-6) == (0.0, 0.0)
+        # inside: the plain exponential of eq 1 / eq 2
+        r = 3.1
+        f, d = oracle.radial(AU, kind, r)
+        pre, k = (AU.xi ** 2, 2 * AU.q) if kind == 0 else (AU.A, AU.p)
+        assert abs(f - pre * math.exp(-k * (r / AU.r0 - 1))) < 1e-14
+        # derivative by finite differences inside the tail
+        r = 6.8
+        h = 1e-6
+        fd = (oracle.radial(AU, kind, r + h)[0] - oracle.radial(AU, kind, r - h)[0]) / (2 * h)
+        assert abs(fd - oracle.radial(AU, kind, r)[1]) < 1e-8
+
+
+def test_cell_list_mode_equals_brute_force():
+    x, y, z, _ = oracle.build_wire(4.08, 20.0, 40.0, 2)
+    rng = np.random.default_rng(5)
+    x = x + rng.uniform(-0.1, 0.1, x.size)
+    a = oracle.forces(AU, x, y, z, 0)
+    b = oracle.forces(AU, x, y, z, 1)
+    for k in ("e_atom", "fx", "fy", "fz", "rho"):
+        assert np.abs(a[k] - b[k]).max() < 1e-12
+    s = oracle.forces_sampled(AU, x, y, z, np.array([0, 17, 100, x.size - 1]))
+    for k in ("fx", "fy", "fz", "e_atom", "rho"):
+        assert np.abs(s[k] - a[k][[0, 17, 100, x.size - 1]]).max() < 1e-12
+
+
+def test_wire_geometry():
+    """[100] FCC cylinder: even-parity sites of the a/2 cubic grid inside the
+    radius, nearest-neighbour distance a/sqrt2, (002) spacing a/2, 4-fold
+    symmetry, two grip planes per end, and the atom count within 1 % of the
+    bulk density 4/a^3 times the cylinder volume for a 10 nm wire."""
+    a = 4.08
+    x, y, z, f = oracle.build_wire(a, 30.0, 200.0, 2)
+    ijk = np.round(np.stack([x, y, z], 1) / (a / 2)).astype(int)
+    assert np.all(ijk.sum(1) % 2 == 0)
+    assert np.all(x ** 2 + y ** 2 <= 15.0 ** 2 + 1e-9)
+    assert z.min() == 0 and z.max() < 200.0
+    layers = np.unique(z)
+    assert np.allclose(np.diff(layers), a / 2)
+    assert set(np.unique(f)) == {0, 1, 2}
+    assert np.all(f[z <= layers[1]] == 1) and np.all(f[z >= layers[-2]] == 2)
+    assert np.all(f[(z > layers[1]) & (z < layers[-2])] == 0)
+    # 4-fold rotation maps the lattice onto itself
+    s1 = {(int(i), int(j), int(k)) for i, j, k in ijk}
+    s2 = {(-j, i, k) for i, j, k in s1}
+    assert s1 == s2
+    xb, _, _, _ = oracle.build_wire(a, 100.0, 40.8, 2)
+    vol = math.pi * 50.0 ** 2 * 40.8
+    assert abs(xb.size / (4 / a ** 3 * vol) - 1) < 0.01
+    # nearest-neighbour distance
+    P = np.stack([x, y, z], 1)[:300]
+    d = np.sqrt(((P[:, None] - P) ** 2).sum(-1)) + np.eye(300) * 100
+    assert abs(d.min() - a / math.sqrt(2)) < 1e-12
+
+
+def read_kat():
+    rows = []
+    with open(os.path.join(GOLD, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(t, 16) for t in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    for ctr, key, exp in read_kat():
+        assert list(oracle.philox4x32_10(ctr, key)) == exp
+
+
+def _py_philox(ctr, key):
+    """Independent pure-Python Philox4x32-10 (integer arithmetic)."""
+    c = list(ctr)
+    k0, k1 = key
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + 0x9E3779B9) & 0xFFFFFFFF
+            k1 = (k1 + 0xBB67AE85) & 0xFFFFFFFF
+        p0 = 0xD2511F53 * c[0]
+        p1 = 0xCD9E8D57 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+    return c
+
+
+def test_philox_random_counters_match_python():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        ctr = [int(v) for v in rng.integers(0, 2 ** 32, 4)]
+        key = [int(v) for v in rng.integers(0, 2 ** 32, 2)]
+        assert list(oracle.philox4x32_10(ctr, key)) == _py_philox(ctr, key)
+
+
+def test_uniform_and_gauss_definition_and_moments():
+    seed = 13113890000 + 5
+    u = oracle.uniform4(seed, 3, 77, 123456, 0)
+    o = _py_philox([77, 123456, 3, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    assert np.allclose(u, [(v + 0.5) / 2 ** 32 for v in o], rtol=0, atol=0)
+    g = np.array([oracle.gauss3(seed, 3, t, 9, 0) for t in range(20000)])
+    assert abs(g.mean()) < 0.02
+    assert abs(g.var() - 1) < 0.03
+    # Box-Muller of the first pair
+    u = oracle.uniform4(seed, 3, 0, 9, 0)
+    r = math.sqrt(-2 * math.log(u[0]))
+    assert abs(g[0, 0] - r * math.cos(2 * math.pi * u[1])) < 1e-14
+    assert abs(g[0, 1] - r * math.sin(2 * math.pi * u[1])) < 1e-14
+
+
+def small_wire_state(T, jitter=0.0, v_pull=0.5, gamma=1.0, D=15.0, L=30.6, seed=99):
+    x, y, z, f = oracle.build_wire(4.08, D, L, 2)
+    st = oracle.State(x, y, z, f)
+    zlo = z[f == 1].max()
+    zhi = z[f == 2].min()
+    md = oracle.MD(T=T, v_pull=v_pull, gamma=gamma, z_lo=zlo, z_hi=zhi, seed=seed, rep_id=1)
+    oracle.init_state(md, st, jitter)
+    oracle.compute_forces(AU, st, 0)
+    return st, md
+
+
+def test_init_state_exact_temperature_and_zero_momentum():
+    kb, acc, _ = oracle.constants()
+    st, md = small_wire_state(298.0, jitter=0.02, v_pull=0.0)
+    dyn = st.flag == 0
+    m = oracle.MASS_AU
+    assert abs(st.vx[dyn].sum()) < 1e-10 and abs(st.vz[dyn].sum()) < 1e-10
+    ke = 0.5 * m * (st.vx[dyn] ** 2 + st.vy[dyn] ** 2 + st.vz[dyn] ** 2).sum() / acc
+    T = 2 * ke / ((3 * dyn.sum() - 3) * kb)
+    assert abs(T - 298.0) < 1e-9
+    x0, _, _, _ = oracle.build_wire(4.08, 15.0, 30.6, 2)
+    dx = st.x - x0
+    assert 0.015 < np.abs(dx).max() <= 0.02
+    assert np.all(st.vz[st.flag == 1] == 0)
+    obs = oracle.observe(AU, md, st, 1.0, 30.6)
+    assert abs(obs[2] - 298.0) < 1e-9
+
+
+def test_nve_energy_conservation():
+    """gamma = 0 and static grips: velocity Verlet conserves the total energy
+    (bounded fluctuation, no secular drift) with the C1 cubic tail."""
+    kb, acc, _ = oracle.constants()
+    st, md = small_wire_state(50.0, v_pull=0.0, gamma=0.0)
+    m = oracle.MASS_AU
+
+    def etot():
+        ke = 0.5 * m * (st.vx ** 2 + st.vy ** 2 + st.vz ** 2).sum() / acc
+        return st.e_atom.sum() + ke
+
+    e0 = etot()
+    es = []
+    for _ in range(20):
+        oracle.run(AU, md, st, 50, 0)
+        es.append(etot())
+    es = np.array(es)
+    n = st.x.size
+    assert np.abs(es - e0).max() / n < 2e-5     # eV/atom
+    slope = np.polyfit(np.arange(es.size) * 50 * md.dt, es, 1)[0] / n
+    assert abs(slope) < 1e-5                   # eV/atom/ps
+
+
+def test_velocity_verlet_time_reversible():
+    st, md = small_wire_state(30.0, v_pull=0.0, gamma=0.0)
+    x0, y0, z0 = st.x.copy(), st.y.copy(), st.z.copy()
+    oracle.run(AU, md, st, 100, 0)
+    assert np.abs(st.x - x0).max() > 1e-3
+    st.vx, st.vy, st.vz = -st.vx, -st.vy, -st.vz
+    st.step = 0
+    oracle.run(AU, md, st, 100, 0)
+    assert max(np.abs(st.x - x0).max(), np.abs(st.y - y0).max(), np.abs(st.z - z0).max()) < 1e-9
+
+
+def test_free_atom_ballistic_and_grip_motion():
+    """An isolated dynamic atom moves ballistically under velocity Verlet;
+    grips sit at z0 and z0 + v_pull n dt."""
+    x = np.array([0.0, 50.0, 100.0])
+    st = oracle.State(x, np.zeros(3), np.zeros(3), np.array([0, 1, 2], np.uint8))
+    st.vx[0], st.vy[0], st.vz[0] = 1.5, -0.5, 2.0
+    md = oracle.MD(gamma=0.0, v_pull=0.7, z_lo=0, z_hi=0)
+    oracle.compute_forces(AU, st, 0)
+    oracle.run(AU, md, st, 37, 0)
+    t = 37 * md.dt
+    assert abs(st.x[0] - 1.5 * t) < 1e-13 and abs(st.z[0] - 2.0 * t) < 1e-13
+    assert st.z[1] == 0.0 and abs(st.z[2] - 0.7 * 37 * md.dt) < 1e-15
+    assert st.vz[2] == 0.7 and st.vz[1] == 0.0
+
+
+def test_langevin_equipartition():
+    """BAOAB samples the Maxwell-Boltzmann velocities: <T> -> T."""
+    st, md = small_wire_state(300.0, v_pull=0.0, gamma=5.0)
+    Ts = []
+    for _ in range(40):
+        oracle.run(AU, md, st, 50, 1)
+        Ts.append(oracle.observe(AU, md, st, 1.0, 30.6)[2])
+    Ts = np.array(Ts[10:])
+    assert abs(Ts.mean() - 300.0) < 12.0
+
+
+def test_observe_gap_and_stress_sign():
+    """A wire cut in two by a gap reports that gap; a wire stretched
+    affinely along z is in tension (positive sigma_zz)."""
+    x, y, z, f = oracle.build_wire(4.08, 15.0, 40.8, 2)
+    z2 = np.where(z > 20.0, z + 9.0, z)
+    st = oracle.State(x, y, z2, f)
+    md = oracle.MD(v_pull=0.0)
+    obs = oracle.observe(AU, md, st, 1000.0, 40.8)
+    assert abs(obs[6] - (9.0 + 2.04)) < 1e-12
+    st2 = oracle.State(x * 0.99, y * 0.99, z * 1.02, f)
+    obs2 = oracle.observe(AU, md, st2, 1000.0, 40.8)
+    assert obs2[4] > 0
+    st3 = oracle.State(x, y, z * 0.98, f)
+    assert oracle.observe(AU, md, st3, 1000.0, 40.8)[4] < obs2[4]
