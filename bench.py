@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the TB-SMA nanowire-elongation step on one MI355X.
+
+Workload (default): 512 independent Au [100] nanowires, diameter 3 nm,
+lengths uniform in 5-40 nm (whole (002) layers), 298 K Langevin, dt = 2 fs,
+top grips pulled at 0.5 A/ps; FP32 pair arithmetic, FP64 integration; all
+replicas advanced together by a HIP graph of steps.  One step = integrator,
+per-replica neighbour-list rebuilds where needed, density pass, force pass,
+second half-kick and per-replica reductions.
+
+Printed (one JSON line on stdout): batched atom-timesteps/s over the timed
+steps, the same replicas run one per launch (plain path), the force kernel
+against the HBM roofline (algorithmic bytes / average launch time measured
+with HIP events on the launch stream), and the FP64 CPU oracle timed on a
+bounded sample on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--steps-per-graph", type=int, default=50)
+    ap.add_argument("--per-replica", type=int, default=32,
+                    help="replicas timed one per launch for the plain-path rate")
+    ap.add_argument("--per-replica-steps", type=int, default=20)
+    ap.add_argument("--pass-launches", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-replica", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(replica ensembles would shard by replica with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1311_3890_amd import _abi as A
+    from paper_1311_3890_amd.engine import WireBatch
+
+    torch.cuda.set_device(0)
+    wl = W.CONFIGS[args.workload]()
+    strain_max = 0.1 if args.workload == "cfg5" else 0.5
+    log(f"[bench] workload {wl.name}: building {len(wl.replicas)} replicas")
+    b = WireBatch(wl.replicas, wl.precision, n_log=100, strain_max=strain_max,
+                  skin=wl.skin, gamma=wl.gamma)
+    b.prepare()
+    n_real = int(b.n_atoms.sum())
+    S = args.steps_per_graph
+    log(f"[bench] {b.R} replicas, {n_real} atoms ({b.N} slots), qbits {b.qbits}; "
+        f"warmup {args.warmup}")
+    b.run_batch(args.warmup, S)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps of the batched graph path -----------------------------
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    b.run_batch(args.steps, S)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = n_real * args.steps / (ms * 1e-3)
+    log(f"[bench] batched: {args.steps} steps in {ms:.1f} ms -> {value:.4e} atom-steps/s")
+    st = b.status()
+    bad = int(np.count_nonzero(st & (A.ST_NONFINITE | A.ST_OVERFLOW)))
+
+    # ---- per-kernel timing of the two force passes (HIP events, same stream) ----------
+    kbar = b.mean_neighbors()
+    lib = A.lib()
+
+    def time_pass(p):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        A.check(lib.tbsma_forces_pass(C.byref(b.params), C.byref(b.sys), C.byref(b.nlist),
+                                      C.byref(b.out), b.work, p, b.stream()))
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for _ in range(args.pass_launches):
+            A.check(lib.tbsma_forces_pass(C.byref(b.params), C.byref(b.sys), C.byref(b.nlist),
+                                          C.byref(b.out), b.work, p, b.stream()))
+        evs[1].record(stream)
+        torch.cuda.synchronize()
+        return evs[0].elapsed_time(evs[1]) / args.pass_launches
+
+    t_dens = time_pass(1)
+    t_force = time_pass(2)
+    bytes_force = n_real * (4.0 * kbar + 36.0)
+    bytes_dens = n_real * (4.0 * kbar + 24.0)
+    gbs_force = bytes_force / (t_force * 1e-3) / 1e9
+    gbs_dens = bytes_dens / (t_dens * 1e-3) / 1e9
+    log(f"[bench] mean listed neighbours {kbar:.2f}; density {t_dens * 1e3:.1f} us "
+        f"({gbs_dens:.0f} GB/s), force {t_force * 1e3:.1f} us ({gbs_force:.0f} GB/s)")
+
+    # ---- plain path: the same kind of replicas, one replica per launch ----------------
+    pr = None
+    if not args.no_per_replica:
+        idx = np.linspace(0, b.R - 1, min(args.per_replica, b.R)).round().astype(int)
+        atoms_steps = 0.0
+        t_tot = 0.0
+        t_graph = 0.0
+        for r in idx:
+            s1 = WireBatch([wl.replicas[r]], wl.precision, n_log=100, strain_max=strain_max,
+                           qbits=b.qbits, skin=wl.skin, gamma=wl.gamma)
+            s1.prepare()
+            s1.step(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.step(args.per_replica_steps)
+            torch.cuda.synchronize()
+            t_tot += time.perf_counter() - t0
+            s1.run_batch(args.per_replica_steps, args.per_replica_steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.run_batch(args.per_replica_steps, args.per_replica_steps)
+            torch.cuda.synchronize()
+            t_graph += time.perf_counter() - t0
+            atoms_steps += int(s1.n_atoms[0]) * args.per_replica_steps
+            del s1
+        pr = atoms_steps / t_tot
+        prg = atoms_steps / t_graph
+        log(f"[bench] one replica per launch ({len(idx)} replicas): {pr:.4e} atom-steps/s; "
+            f"with a graph per replica {prg:.4e}; batched/plain = {value / pr:.1f}x")
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample, this host's cores ---------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rp = wl.replicas[0]
+        x, y, z, f = oracle.build_wire(W.A_LAT, rp.D, rp.L, rp.n_grip)
+        stt = oracle.State(x, y, z, f)
+        zlo = z[f == 1].max()
+        zhi = z[f == 2].min()
+        md = oracle.MD(dt=W.DT, gamma=wl.gamma, T=rp.T, v_pull=rp.v_pull, z_lo=zlo, z_hi=zhi,
+                       seed=rp.seed, rep_id=rp.rep_id)
+        pot = oracle.Pot()
+        oracle.init_state(md, stt, rp.jitter)
+        oracle.compute_forces(pot, stt, 1)
+        t0 = time.perf_counter()
+        oracle.run(pot, md, stt, 1, 1)
+        t1 = time.perf_counter() - t0
+        k = max(1, int(args.cpu_seconds / max(t1, 1e-6)))
+        t0 = time.perf_counter()
+        oracle.run(pot, md, stt, k, 1)
+        tc = time.perf_counter() - t0
+        cpu = {"value": x.size * k / tc, "unit": "atom-timesteps/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"replica 0 of the workload ({x.size} atoms, D {rp.D / 10:.1f} nm x "
+                         f"L {rp.L / 10:.2f} nm), {k} FP64 steps, cell-list mode, OpenMP"}
+        log(f"[bench] oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": "atom-timesteps/s, batched vs per-replica TB-SMA NVT; force-kernel % HBM peak",
+        "value": value,
+        "unit": "atom-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "replicas": b.R, "atoms": n_real,
+                   "precision": "f32 pair math, f64 integration and sums",
+                   "steps_per_graph": S, "skin_A": b.skin, "r_cut_A": b.pot.r_cut,
+                   "parallelism": "replica batch, 1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_force_mixed",
+                     "algorithmic_bytes_per_launch": bytes_force,
+                     "avg_launch_us": t_force * 1e3,
+                     "mean_listed_neighbours": kbar},
+        "kernels": {"density": {"avg_launch_us": t_dens * 1e3, "GB/s": gbs_dens,
+                                "frac": gbs_dens / HBM_PEAK_GBS}},
+        "per_replica_value": pr,
+        "batched_over_per_replica": (value / pr) if pr else None,
+        "bad_replicas": bad,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

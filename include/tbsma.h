@@ -1,0 +1,363 @@
+/*
+ * tbsma.h - C ABI of libtbsma: TB-SMA (second-moment tight-binding,
+ * Cleri-Rosato) molecular dynamics of gold nanowires under elongation on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the method of French, Pervaje, Santos, Iacovella and
+ * Cummings, "Probing the Statistical Validity of the Ductile-to-Brittle
+ * Transition in Metallic Nanowires using GPU Computing":
+ *   - energy: eqs 1-3 (band term, repulsive term, total) with the Au
+ *     parameters of Table 1 (r0 read as the nearest-neighbour distance
+ *     2.884 A, the value that reproduces the fitted cohesive energy);
+ *   - forces: the two-stage evaluation of Methods ("TB-SMA potential"): a
+ *     first loop over neighbours for the density rho_i, a global
+ *     synchronisation, a second loop for the forces, which depend on rho of
+ *     both atoms of a pair;
+ *   - dynamics: velocity Verlet with dt = 2 fs and two rigid grip layers at
+ *     each end of a [100] wire (Simulation details, Figure 1), here with a
+ *     Langevin thermostat and a continuously pulled top grip;
+ *   - observables: engineering strain (eq 4) and virial stress (eq 5).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Units: Angstrom, eV, amu, ps, K.  The wire axis [100] is z.
+ * Memory: every buffer is owned by the caller.  Pointers documented "device"
+ *   are HIP device memory of the current device; "host" pointers are ordinary
+ *   host memory read during the call.  The library allocates no device memory
+ *   in any call; its scratch lives in the caller's workspace (see
+ *   tbsma_workspace_query).
+ * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
+ *   stream.  Calls enqueue work and return without waiting, except where a
+ *   call says it synchronises.
+ * Layout: R replicas (independent wires) share one index space of N atom
+ *   slots.  Replica r owns slots [rep_off[r], rep_off[r+1]); every offset is a
+ *   multiple of TBSMA_TILE, and the slots after a replica's real atoms are
+ *   padding (flag TBSMA_PAD).  Per-atom arrays are structure-of-arrays.
+ *   Atoms keep their slot for the whole run: the slot minus rep_off[r] is the
+ *   atom's tag (the counter word of its random numbers).
+ * Errors: calls return TBSMA_OK (0) or a negative code; the message of the
+ *   last failure on the calling thread is returned by tbsma_last_error().
+ *   Conditions found on the device while running (neighbour-list overflow,
+ *   non-finite values, atoms outside their grid, rupture) are per-replica
+ *   status bits, not return codes; tbsma_step and tbsma_run_batch also turn
+ *   an overflow into TBSMA_ECAPACITY when they return.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef TBSMA_H
+#define TBSMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TBSMA_TILE 64 /* atom-slot granularity of a replica (one wavefront) */
+#define TBSMA_NOBS 10 /* doubles per observable record */
+
+/* return codes */
+#define TBSMA_OK 0
+#define TBSMA_EINVAL (-1)    /* invalid argument or inconsistent sizes */
+#define TBSMA_ECAPACITY (-2) /* neighbour-list rows too short */
+#define TBSMA_EHIP (-3)      /* a HIP runtime call failed */
+#define TBSMA_EDEVICE (-4)   /* current device is not gfx950 */
+
+/* precision of the pair arithmetic */
+#define TBSMA_FP64 0  /* everything in FP64 */
+#define TBSMA_MIXED 1 /* FP32 pair math and forces; FP64 x, v, sums, grips */
+
+/* per-atom flags */
+#define TBSMA_DYN 0        /* integrated */
+#define TBSMA_GRIP_FIXED 1 /* rigid bottom grip, held at its reference */
+#define TBSMA_GRIP_PULL 2  /* rigid top grip, moved along +z at v_pull */
+#define TBSMA_PAD 3        /* padding slot, no atom */
+
+/* per-replica status bits (tbsma_md.status) */
+#define TBSMA_ST_OVERFLOW 1u   /* a neighbour-list row exceeded k_cap */
+#define TBSMA_ST_NONFINITE 2u  /* NaN/Inf in energy or kinetic energy */
+#define TBSMA_ST_OUTSIDE 4u    /* an atom left its cell grid (still exact) */
+#define TBSMA_ST_RUPTURED 8u   /* axial gap >= r_cut found at a logged step */
+#define TBSMA_ST_REBUILT 16u   /* neighbour list rebuilt at some step */
+
+/* observable record (tbsma_md.obs), TBSMA_NOBS doubles */
+#define TBSMA_OBS_STEP 0    /* step index of the state */
+#define TBSMA_OBS_EPOT 1    /* potential energy, eq 3 (eV) */
+#define TBSMA_OBS_KE 2      /* kinetic energy of dynamic atoms, peculiar (eV) */
+#define TBSMA_OBS_T 3       /* temperature, 3 N_dyn - 3 degrees of freedom */
+#define TBSMA_OBS_WZZ 4     /* 1/2 sum_i sum_j E'_ij dz^2 / r (eV) */
+#define TBSMA_OBS_SZZ 5     /* virial stress sigma_zz of eq 5 (GPa) */
+#define TBSMA_OBS_STRAIN 6  /* engineering strain of eq 4 */
+#define TBSMA_OBS_GAP 7     /* largest empty axial gap, exact when >= cell/2 */
+#define TBSMA_OBS_D 8       /* displacement of the pulled grip (A) */
+#define TBSMA_OBS_STATUS 9  /* status bits of the replica at that step */
+
+/*
+ * Potential and list parameters (Methods, Table 1).
+ *  A, xi, p, q, r0  Table 1 (Au: 0.2061 eV, 1.790 eV, 10.229, 4.036, 2.884 A).
+ *  r_tail, r_cut    each radial function is the exponential of eq 1 / eq 2 up
+ *                   to r_tail and a cubic Hermite tail reaching value and slope
+ *                   zero at r_cut; r_tail == r_cut is the paper's hard cut.
+ *  skin             Verlet skin; lists hold pairs with r < r_cut + skin.
+ *  cell             cell edge (>= r_cut + skin, and cell/2 <= r_cut).
+ *  mass             atomic mass (amu).
+ *  precision        TBSMA_FP64 or TBSMA_MIXED.
+ *  qbits            MIXED only: positions are quantised to 2^-qbits A about
+ *                   the centre of each replica's grid (16 <= qbits <= 24);
+ *                   the grid half-extent must stay below 2^(31-qbits) A.
+ */
+typedef struct {
+  double A, xi, p, q, r0;
+  double r_tail, r_cut;
+  double skin;
+  double cell;
+  double mass;
+  int32_t precision;
+  int32_t qbits;
+} tbsma_params;
+
+/*
+ * Atoms and the replica layout.
+ *  R, N          replicas, atom slots (N = rep_off_h[R], multiple of TILE).
+ *  C             cells of all replica grids (C = cell_off_h[R]).
+ *  max_zbins     axial bins per replica for the rupture gap (>= 2 gz of every
+ *                replica).
+ *  rep_off_h     host [R+1] slot offsets (non-decreasing multiples of TILE).
+ *  cell_off_h    host [R+1] cell offsets, cell_off_h[r+1]-cell_off_h[r] =
+ *                gx*gy*gz of replica r.
+ *  rep_off, cell_off   device copies of the two arrays above.
+ *  tile_rep      device [N/TILE]: replica of each tile of TILE slots.
+ *  grid_dim      device [3R] int: cells along x, y, z of each replica.
+ *  grid_lo       device [3R] double: lower corner of each replica's grid.
+ *  rep_id        device [R]: persistent replica id (random-counter word).
+ *  x, y, z       device [N] FP64 positions.
+ *  vx, vy, vz    device [N] FP64 velocities (A/ps).
+ *  z0            device [N] FP64 reference z of grip atoms (set by
+ *                tbsma_init_state).
+ *  flag          device [N] TBSMA_DYN / GRIP_FIXED / GRIP_PULL / PAD.
+ *  qpos          device [4N] int32 (MIXED; NULL for FP64): quantised x, y, z
+ *                and, after the density pass, the bits of FP32 g_i.
+ */
+typedef struct {
+  int32_t R;
+  int32_t max_zbins;
+  int64_t N;
+  int64_t C;
+  const int64_t *rep_off_h;
+  const int64_t *cell_off_h;
+  const int64_t *rep_off;
+  const int64_t *cell_off;
+  const int32_t *tile_rep;
+  const int32_t *grid_dim;
+  const double *grid_lo;
+  const int32_t *rep_id;
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  double *z0;
+  uint8_t *flag;
+  int32_t *qpos;
+} tbsma_system;
+
+/*
+ * Cell lists.  cell_start: device [C + R] int32.  For replica r and local
+ * cell c (c = (cz*gy + cy)*gx + cx), the slots of its atoms are
+ * cell_atoms[cell_start[cell_off[r]+r+c] .. cell_start[cell_off[r]+r+c+1]),
+ * in ascending slot order.  cell_atoms: device [N] int32.
+ */
+typedef struct {
+  int32_t *cell_start;
+  int32_t *cell_atoms;
+} tbsma_cells;
+
+/*
+ * Verlet lists (full: both i->j and j->i).  Column-major: entry k of atom i
+ * is nl[k*N + i], k < nn[i] <= k_cap, ascending by (cell scan order, slot).
+ * x_ref, y_ref, z_ref: device [N] positions at the last build.
+ */
+typedef struct {
+  int32_t *nl;
+  int32_t *nn;
+  int32_t k_cap;
+  int32_t reserved;
+  double *x_ref, *y_ref, *z_ref;
+} tbsma_nlist;
+
+/*
+ * Force-pass outputs.  fx, fy, fz, e_atom: device [N], float for MIXED and
+ * double for FP64.  g: device [N] double, FP64 only (1/sqrt(rho_i), 0 when
+ * rho_i = 0); NULL for MIXED.  rep_energy, rep_wzz: device [R] double, written
+ * by tbsma_forces: sum of E_i (eq 3) and 1/2 sum_i sum_j E'_ij dz^2/r.
+ */
+typedef struct {
+  void *fx, *fy, *fz;
+  void *e_atom;
+  double *g;
+  double *rep_energy;
+  double *rep_wzz;
+} tbsma_forces_out;
+
+/*
+ * Dynamics settings and observables.
+ *  dt, gamma     time step (ps) and Langevin friction (1/ps; 0 = NVE).
+ *  lab_frame     0: the thermostat acts on the velocity relative to the
+ *                affine stretching profile u(z) = v_pull (z - z_lo) /
+ *                (z_hi - z_lo + D); 1: on the lab-frame velocity.
+ *  n_log         observables are recorded when the new step index is a
+ *                multiple of n_log (>= 1);  n_slots: ring slots per replica.
+ *  T, v_pull, z_lo, z_hi, vol, L0: device [R] double: target temperature,
+ *                grip speed, inner faces of the fixed and pulled grips at
+ *                t = 0, constant hard-sphere volume (eq 5), initial length
+ *                (eq 4).
+ *  seed          device [R] uint64: Philox key of each replica.
+ *  dof           device [R] int32: kinetic degrees of freedom (3 N_dyn - 3).
+ *  step          device [1] int64: index of the current state; advanced by
+ *                one per step on the device.
+ *  obs           device [n_slots * R * TBSMA_NOBS]: record of replica r at
+ *                logged step s is at ((s / n_log) % n_slots) * R + r.
+ *  status        device [R] uint32 status bits (OR-accumulated).
+ */
+typedef struct {
+  double dt, gamma;
+  int32_t lab_frame;
+  int32_t n_log;
+  int32_t n_slots;
+  int32_t reserved;
+  const double *T, *v_pull, *z_lo, *z_hi, *vol, *L0;
+  const uint64_t *seed;
+  const int32_t *dof;
+  int64_t *step;
+  double *obs;
+  uint32_t *status;
+} tbsma_md;
+
+/*
+ * Bytes of device workspace that every call below takes as `work` for this
+ * system (per-replica displacement maxima, cell counters, per-tile partial
+ * sums, axial bins).  Host-only; returns TBSMA_EINVAL on bad sizes.
+ */
+int tbsma_workspace_query(const tbsma_params *prm, const tbsma_system *sys,
+                          size_t *bytes);
+
+/*
+ * Puts a freshly allocated workspace into its initial state (enqueued on
+ * stream).  Call once after allocating it, before any other call uses it.
+ */
+int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
+                         void *work, void *stream);
+
+/*
+ * Host-side wire builder (Simulation details, Figure 1): the [100] FCC
+ * cylinder of lattice constant a, diameter D and length L with the axis
+ * through an atom column; sites (i, j, k) a/2 with i+j+k even,
+ * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, in (k, j, i) order; the n_grip
+ * lowest planes get TBSMA_GRIP_FIXED and the n_grip highest TBSMA_GRIP_PULL.
+ * x, y, z, flag are host arrays of capacity cap (may be NULL when cap = 0).
+ * *n_out receives the atom count; TBSMA_ECAPACITY if it exceeds cap.
+ */
+int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
+                     double *y, double *z, uint8_t *flag, int64_t cap,
+                     int64_t *n_out);
+
+/*
+ * Initial state (Simulation details: random Gaussian velocities): every
+ * real atom's position gets a uniform jitter of +-jitter per component
+ * (Philox stream 2); dynamic atoms get Maxwell-Boltzmann velocities at T[r]
+ * (stream 1), minus their centre-of-mass velocity, rescaled to exactly T[r]
+ * over dof[r], plus the stretching profile at t = 0; fixed grips are at rest
+ * and pulled grips move at v_pull.  Sets z0 = z and *step = 0.  Synchronises
+ * the stream.
+ */
+int tbsma_init_state(const tbsma_params *prm, tbsma_system *sys,
+                     const tbsma_md *md, void *work, double jitter,
+                     void *stream);
+
+/*
+ * Cell binning (the cell list behind the Verlet list): bins every real atom
+ * of every replica into its grid (atoms outside are clamped to the border
+ * cells, which keeps the list exact, and raise TBSMA_ST_OUTSIDE in the
+ * workspace only) and writes cell_start / cell_atoms.
+ */
+int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
+                      tbsma_cells *cells, void *work, void *stream);
+
+/*
+ * Verlet lists of every replica from its cells: all j != i of the same
+ * replica with |r_j - r_i| < r_cut + skin; stores the positions as x_ref.
+ * When need_cap is non-NULL the call synchronises and, if a row exceeded
+ * k_cap, writes the longest row length to *need_cap and returns
+ * TBSMA_ECAPACITY (rows are then truncated and must be rebuilt).
+ */
+int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
+                    const tbsma_cells *cells, tbsma_nlist *nl, void *work,
+                    int32_t *need_cap, void *stream);
+
+/*
+ * Energies and forces of eqs 1-3 in two passes over the Verlet list:
+ * pass 1 rho_i -> g_i = 1/sqrt(rho_i); pass 2
+ * F_i = sum_j E'_ij (r_j - r_i)/r_ij with E'_ij = 2V'(r) - (g_i+g_j)phi'(r)/2,
+ * E_i = -sqrt(rho_i) + sum_j V(r_ij), and per-replica sums of E_i and of the
+ * zz virial into out->rep_energy / out->rep_wzz.
+ */
+int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
+                 const tbsma_nlist *nl, tbsma_forces_out *out, void *work,
+                 void *stream);
+
+/*
+ * One of the two passes of tbsma_forces on its own, for timing and for
+ * callers that keep g: pass 1 is the density pass (writes g_i), pass 2 the
+ * force pass (reads the g_i of pass 1, writes forces, energies and the
+ * per-tile sums; no per-replica reduction).  In MIXED precision both read the
+ * quantised positions in qpos as last written by the library (every call that
+ * moves atoms or builds lists keeps them current).  TBSMA_EINVAL for any other
+ * pass number.
+ */
+int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
+                      const tbsma_nlist *nl, tbsma_forces_out *out, void *work,
+                      int32_t pass, void *stream);
+
+/*
+ * n_steps MD steps of every replica, one launch per kernel per step (the
+ * plain path; with R = 1 it is one replica per launch).  Each step: half
+ * kick, half drift, Langevin O step (noise counter (tag, step, rep_id, 0)),
+ * half drift, grips placed at z0 (fixed) or z0 + v_pull (step+1) dt (pulled);
+ * per-replica rebuild of cells and lists where some atom moved more than
+ * skin/2 since the last build; both force passes; half kick; per-replica
+ * reductions and observables.  Forces in `out` must hold F at the current
+ * state on entry (tbsma_forces).  Synchronises at the end and returns
+ * TBSMA_ECAPACITY if any list overflowed during the call.
+ */
+int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
+               tbsma_nlist *nl, tbsma_forces_out *out, const tbsma_md *md,
+               void *work, int64_t n_steps, void *stream);
+
+/*
+ * The same n_steps as tbsma_step for all replicas, captured once as a HIP
+ * graph of steps_per_graph steps and replayed (the last partial chunk is
+ * launched directly).  Every decision (rebuilds, logging, step index) is
+ * taken on the device, so replays need no host work.  The instantiated graph
+ * is cached for identical arguments.  Synchronises at the end and returns
+ * TBSMA_ECAPACITY if any list overflowed.
+ */
+int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
+                    tbsma_cells *cells, tbsma_nlist *nl,
+                    tbsma_forces_out *out, const tbsma_md *md, void *work,
+                    int64_t n_steps, int32_t steps_per_graph, void *stream);
+
+/*
+ * Diagnostics of the random numbers: for tag = 0 .. n-1 writes the four
+ * Philox4x32-10 words of counter (tag, lo32(step), rep_id, stream_id) under
+ * key (lo32(seed), hi32(seed)) to out_u32[4 tag ..] and the three Box-Muller
+ * normals to out_gauss[3 tag ..] (device buffers; either may be NULL).
+ */
+int tbsma_rng_fill(uint64_t seed, uint32_t rep_id, uint64_t step,
+                   uint32_t stream_id, int64_t n, uint32_t *out_u32,
+                   double *out_gauss, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tbsma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBSMA_H */

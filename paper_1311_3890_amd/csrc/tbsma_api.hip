@@ -1,0 +1,658 @@
+// C ABI of libtbsma (declared in include/tbsma.h): argument checks,
+// workspace layout, constant folding for the kernels, the plain step loop
+// and the graph-captured batched loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tbsma.h"
+#include "tbsma_device.hpp"
+#include "tbsma_kernels.hpp"
+
+using namespace tbsma;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(TBSMA_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+// The kernels are built for gfx950 only.
+int check_device() {
+  static std::mutex mu;
+  static int known[64] = {0};  // 0 unknown, 1 ok, 2 bad
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(TBSMA_EDEVICE, "device %d", dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if (known[dev] == 0) {
+    hipDeviceProp_t p;
+    HIPCHK(hipGetDeviceProperties(&p, dev));
+    known[dev] = strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+  }
+  if (known[dev] != 1)
+    return fail(TBSMA_EDEVICE, "libtbsma is built for gfx950 only");
+  return TBSMA_OK;
+}
+
+int check_params(const tbsma_params *p) {
+  if (!p) return fail(TBSMA_EINVAL, "params is NULL");
+  if (!(p->r0 > 0 && p->A > 0 && p->xi > 0 && p->p > 0 && p->q > 0))
+    return fail(TBSMA_EINVAL, "potential parameters must be positive");
+  if (!(p->r_tail > 0 && p->r_tail <= p->r_cut))
+    return fail(TBSMA_EINVAL, "need 0 < r_tail <= r_cut");
+  if (!(p->skin >= 0)) return fail(TBSMA_EINVAL, "skin must be >= 0");
+  if (!(p->cell >= p->r_cut + p->skin))
+    return fail(TBSMA_EINVAL, "cell edge %g < r_cut + skin", p->cell);
+  if (!(0.5 * p->cell <= p->r_cut))
+    return fail(TBSMA_EINVAL, "cell/2 must not exceed r_cut");
+  if (!(p->mass > 0)) return fail(TBSMA_EINVAL, "mass must be positive");
+  if (p->precision != TBSMA_FP64 && p->precision != TBSMA_MIXED)
+    return fail(TBSMA_EINVAL, "unknown precision %d", p->precision);
+  if (p->precision == TBSMA_MIXED && (p->qbits < 16 || p->qbits > 24))
+    return fail(TBSMA_EINVAL, "qbits %d outside 16..24", p->qbits);
+  return TBSMA_OK;
+}
+
+int check_system(const tbsma_params *p, const tbsma_system *s) {
+  if (!s) return fail(TBSMA_EINVAL, "system is NULL");
+  if (s->R < 0 || s->N < 0 || s->C < 0)
+    return fail(TBSMA_EINVAL, "negative sizes");
+  if (s->R == 0) return TBSMA_OK;
+  if (s->N % TBSMA_TILE) return fail(TBSMA_EINVAL, "N not a multiple of 64");
+  if (s->N >= (int64_t)1 << 31) return fail(TBSMA_EINVAL, "N >= 2^31");
+  if (!s->rep_off_h || !s->cell_off_h)
+    return fail(TBSMA_EINVAL, "host offsets missing");
+  if (s->rep_off_h[0] != 0 || s->rep_off_h[s->R] != s->N)
+    return fail(TBSMA_EINVAL, "rep_off must run from 0 to N");
+  if (s->cell_off_h[0] != 0 || s->cell_off_h[s->R] != s->C)
+    return fail(TBSMA_EINVAL, "cell_off must run from 0 to C");
+  for (int r = 0; r < s->R; ++r) {
+    if (s->rep_off_h[r + 1] < s->rep_off_h[r] ||
+        s->rep_off_h[r] % TBSMA_TILE)
+      return fail(TBSMA_EINVAL, "rep_off[%d] not a non-decreasing "
+                  "multiple of 64", r);
+    if (s->cell_off_h[r + 1] <= s->cell_off_h[r])
+      return fail(TBSMA_EINVAL, "replica %d has no cells", r);
+  }
+  if (s->C + s->R >= (int64_t)1 << 31)
+    return fail(TBSMA_EINVAL, "too many cells");
+  if (s->max_zbins < 2) return fail(TBSMA_EINVAL, "max_zbins < 2");
+  if (!s->rep_off || !s->cell_off || !s->tile_rep || !s->grid_dim ||
+      !s->grid_lo || !s->rep_id || !s->x || !s->y || !s->z || !s->vx ||
+      !s->vy || !s->vz || !s->z0 || !s->flag)
+    return fail(TBSMA_EINVAL, "a device array of the system is NULL");
+  if (p && p->precision == TBSMA_MIXED && !s->qpos)
+    return fail(TBSMA_EINVAL, "mixed precision needs qpos");
+  return TBSMA_OK;
+}
+
+struct Layout {
+  size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum,
+      total;
+};
+
+size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout layout(const tbsma_system *s) {
+  Layout L;
+  size_t o = 0;
+  int64_t R = s->R, nt = s->N / TBSMA_TILE;
+  L.maxdisp = o;
+  o += up(8 * (size_t)R);
+  L.cnt = o;
+  o += up(4 * (size_t)s->C);
+  L.part = o;
+  o += up(8 * (size_t)kNPart * nt);
+  L.zbmin = o;
+  o += up(8 * (size_t)R * s->max_zbins);
+  L.zbmax = o;
+  o += up(8 * (size_t)R * s->max_zbins);
+  L.wstatus = o;
+  o += up(4 * (size_t)R);
+  L.ticket = o;
+  o += 256;
+  L.nnmax = o;
+  o += 256;
+  L.rsum = o;
+  o += up(8 * 8 * (size_t)R);
+  L.total = o;
+  return L;
+}
+
+Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
+  Dev d;
+  memset(&d, 0, sizeof(d));
+  d.R = s->R;
+  d.max_zbins = s->max_zbins;
+  d.N = s->N;
+  d.C = s->C;
+  d.rep_off = s->rep_off;
+  d.cell_off = s->cell_off;
+  d.tile_rep = s->tile_rep;
+  d.grid_dim = s->grid_dim;
+  d.rep_id = s->rep_id;
+  d.grid_lo = s->grid_lo;
+  d.x = s->x;
+  d.y = s->y;
+  d.z = s->z;
+  d.vx = s->vx;
+  d.vy = s->vy;
+  d.vz = s->vz;
+  d.z0 = s->z0;
+  d.flag = s->flag;
+  d.qpos = reinterpret_cast<int4 *>(s->qpos);
+  Layout L = layout(s);
+  char *w = static_cast<char *>(work);
+  d.maxdisp = reinterpret_cast<unsigned long long *>(w + L.maxdisp);
+  d.cnt = reinterpret_cast<int32_t *>(w + L.cnt);
+  d.part = reinterpret_cast<double *>(w + L.part);
+  d.zbmin = reinterpret_cast<unsigned long long *>(w + L.zbmin);
+  d.zbmax = reinterpret_cast<unsigned long long *>(w + L.zbmax);
+  d.wstatus = reinterpret_cast<uint32_t *>(w + L.wstatus);
+  d.ticket = reinterpret_cast<uint32_t *>(w + L.ticket);
+  d.nnmax = reinterpret_cast<int32_t *>(w + L.nnmax);
+  d.rsum = reinterpret_cast<double *>(w + L.rsum);
+  d.cell = p->cell;
+  d.inv_cell = 1.0 / p->cell;
+  d.skin_half2 = 0.25 * p->skin * p->skin;
+  d.qscale = ldexp(1.0, p->precision == TBSMA_MIXED ? p->qbits : 0);
+  d.inv_qscale = 1.0 / d.qscale;
+  d.mass = p->mass;
+  d.all = 0;
+  return d;
+}
+
+void attach_lists(Dev &d, const tbsma_cells *c, const tbsma_nlist *n) {
+  if (c) {
+    d.cell_start = c->cell_start;
+    d.cell_atoms = c->cell_atoms;
+  }
+  if (n) {
+    d.nl = n->nl;
+    d.nn = n->nn;
+    d.k_cap = n->k_cap;
+    d.xr = n->x_ref;
+    d.yr = n->y_ref;
+    d.zr = n->z_ref;
+  }
+}
+
+// Cubic Hermite tail of f = pre exp(-k (r/r0 - 1)) on (r_tail, r_cut], as
+// coefficients of t = (r - r_tail)/(r_cut - r_tail).
+void hermite(double pre, double k, const tbsma_params *p, double c[4]) {
+  double w = p->r_cut - p->r_tail;
+  double fs = pre * exp(-k * (p->r_tail / p->r0 - 1.0));
+  double ms = -(k / p->r0) * fs * w;
+  c[0] = fs;
+  c[1] = ms;
+  c[2] = -3.0 * fs - 2.0 * ms;
+  c[3] = 2.0 * fs + ms;
+}
+
+PotD make_potd(const tbsma_params *p) {
+  PotD P;
+  P.rc = p->r_cut;
+  P.rc2 = p->r_cut * p->r_cut;
+  P.rt = p->r_tail;
+  P.r0 = p->r0;
+  P.xi2 = p->xi * p->xi;
+  P.A = p->A;
+  P.k2q = 2.0 * p->q;
+  P.kp = p->p;
+  double w = p->r_cut - p->r_tail;
+  P.w = w > 0 ? w : 1.0;
+  double cf[4], cv[4];
+  hermite(P.xi2, P.k2q, p, cf);
+  hermite(P.A, P.kp, p, cv);
+  P.f0 = cf[0];
+  P.f1 = cf[1];
+  P.f2 = cf[2];
+  P.f3 = cf[3];
+  P.v0 = cv[0];
+  P.v1 = cv[1];
+  P.v2 = cv[2];
+  P.v3 = cv[3];
+  return P;
+}
+
+PotF make_potf(const tbsma_params *p) {
+  PotF P;
+  const double log2e = 1.4426950408889634074;
+  double s = ldexp(1.0, -p->qbits);  // Angstrom per quantum
+  double xi2 = p->xi * p->xi;
+  P.rc2 = (float)((p->r_cut / s) * (p->r_cut / s));
+  P.rt = (float)(p->r_tail / s);
+  P.aF = (float)(-2.0 * p->q * log2e * s / p->r0);
+  P.bF = (float)(log2(xi2) + 2.0 * p->q * log2e);
+  P.aP = P.aF;
+  P.bP = (float)(log2(xi2 * 2.0 * p->q / p->r0) + 2.0 * p->q * log2e);
+  P.aV = (float)(-p->p * log2e * s / p->r0);
+  P.bV = (float)(log2(p->A) + p->p * log2e);
+  P.c2p = (float)(2.0 * p->p / p->r0);
+  double w = p->r_cut - p->r_tail;
+  double wi = w > 0 ? 1.0 / w : 0.0;
+  P.tS = (float)(s * wi);
+  P.tB = (float)(-p->r_tail * wi);
+  double cf[4], cv[4];
+  hermite(xi2, 2.0 * p->q, p, cf);
+  hermite(p->A, p->p, p, cv);
+  P.f0 = (float)cf[0];
+  P.f1 = (float)cf[1];
+  P.f2 = (float)cf[2];
+  P.f3 = (float)cf[3];
+  P.v0 = (float)cv[0];
+  P.v1 = (float)cv[1];
+  P.v2 = (float)cv[2];
+  P.v3 = (float)cv[3];
+  P.dv0 = (float)(2.0 * cv[1] * wi);
+  P.dv1 = (float)(4.0 * cv[2] * wi);
+  P.dv2 = (float)(6.0 * cv[3] * wi);
+  P.dp0 = (float)(-cf[1] * wi);
+  P.dp1 = (float)(-2.0 * cf[2] * wi);
+  P.dp2 = (float)(-3.0 * cf[3] * wi);
+  P.wscale = (float)(0.5 * s);
+  return P;
+}
+
+int check_md(const tbsma_md *m, int R) {
+  if (!m) return fail(TBSMA_EINVAL, "md is NULL");
+  if (!(m->dt > 0) || !(m->gamma >= 0))
+    return fail(TBSMA_EINVAL, "need dt > 0 and gamma >= 0");
+  if (m->n_log < 1 || m->n_slots < 1)
+    return fail(TBSMA_EINVAL, "n_log and n_slots must be >= 1");
+  if (R > 0 && (!m->T || !m->v_pull || !m->z_lo || !m->z_hi || !m->vol ||
+                !m->L0 || !m->seed || !m->dof || !m->step || !m->obs ||
+                !m->status))
+    return fail(TBSMA_EINVAL, "a device array of md is NULL");
+  return TBSMA_OK;
+}
+
+DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
+  DevMD M;
+  memset(&M, 0, sizeof(M));
+  M.dt = m->dt;
+  M.gamma = m->gamma;
+  M.c1 = exp(-m->gamma * m->dt);
+  M.r_cut = p->r_cut;
+  M.lab_frame = m->lab_frame;
+  M.n_log = m->n_log;
+  M.n_slots = m->n_slots;
+  M.T = m->T;
+  M.v_pull = m->v_pull;
+  M.z_lo = m->z_lo;
+  M.z_hi = m->z_hi;
+  M.vol = m->vol;
+  M.L0 = m->L0;
+  M.seed = m->seed;
+  M.dof = m->dof;
+  M.step = m->step;
+  M.obs = m->obs;
+  M.status = m->status;
+  return M;
+}
+
+int check_out(const tbsma_params *p, const tbsma_forces_out *o) {
+  if (!o || !o->fx || !o->fy || !o->fz || !o->e_atom)
+    return fail(TBSMA_EINVAL, "force outputs missing");
+  if (p->precision == TBSMA_FP64 && !o->g)
+    return fail(TBSMA_EINVAL, "FP64 precision needs the g array");
+  return TBSMA_OK;
+}
+
+int check_lists(const tbsma_cells *c, const tbsma_nlist *n) {
+  if (c && (!c->cell_start || !c->cell_atoms))
+    return fail(TBSMA_EINVAL, "cell arrays missing");
+  if (n && (!n->nl || !n->nn || !n->x_ref || !n->y_ref || !n->z_ref ||
+            n->k_cap < 1))
+    return fail(TBSMA_EINVAL, "neighbour-list arrays missing");
+  return TBSMA_OK;
+}
+
+#define TRY(expr)             \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ != TBSMA_OK)      \
+      return rc_;             \
+  } while (0)
+
+// One MD step (see tbsma_step) enqueued on s.
+void enqueue_step(const tbsma_params *p, const Dev &d, const DevMD &M,
+                  const tbsma_forces_out *o, const PotF &PF, const PotD &PD,
+                  hipStream_t s) {
+  bool mixed = p->precision == TBSMA_MIXED;
+  double rl = p->r_cut + p->skin;
+  launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
+  launch_cells(d, s);
+  launch_nlist(d, rl * rl, s);
+  launch_forces(d, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
+  launch_integrate_b(d, M, mixed, o->fx, o->fy, o->fz, s);
+  launch_reduce_step(d, M, s);
+}
+
+int finish_run(const Dev &d, const tbsma_md *m, hipStream_t s) {
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  int32_t nnmax = 0;
+  HIPCHK(hipMemcpy(&nnmax, d.nnmax, 4, hipMemcpyDeviceToHost));
+  std::vector<uint32_t> st(d.R);
+  if (d.R > 0)
+    HIPCHK(hipMemcpy(st.data(), m->status, 4 * (size_t)d.R,
+                     hipMemcpyDeviceToHost));
+  for (int r = 0; r < d.R; ++r)
+    if (st[r] & TBSMA_ST_OVERFLOW)
+      return fail(TBSMA_ECAPACITY,
+                  "neighbour list overflow in replica %d (longest row %d, "
+                  "k_cap %d)", r, nnmax, d.k_cap);
+  return TBSMA_OK;
+}
+
+struct GraphCache {
+  std::mutex mu;
+  std::vector<char> key;
+  hipGraphExec_t exec = nullptr;
+};
+GraphCache g_graph;
+
+void append(std::vector<char> &k, const void *p, size_t n) {
+  const char *c = static_cast<const char *>(p);
+  k.insert(k.end(), c, c + n);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tbsma_last_error(void) { return g_err.c_str(); }
+
+int tbsma_workspace_query(const tbsma_params *prm, const tbsma_system *sys,
+                          size_t *bytes) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!bytes) return fail(TBSMA_EINVAL, "bytes is NULL");
+  *bytes = sys->R > 0 ? layout(sys).total : 256;
+  return TBSMA_OK;
+}
+
+int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
+                         void *work, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (sys->R == 0) return TBSMA_OK;
+  if (!work) return fail(TBSMA_EINVAL, "work is NULL");
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Layout L = layout(sys);
+  char *w = static_cast<char *>(work);
+  // zero everything (as 32-bit words), then the min-bins to the empty key
+  launch_fill_u32(reinterpret_cast<uint32_t *>(w), (int64_t)(L.total / 4), 0u,
+                  s);
+  launch_fill_u64(reinterpret_cast<unsigned long long *>(w + L.zbmin),
+                  (int64_t)sys->R * sys->max_zbins, ~0ull, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
+                     double *y, double *z, uint8_t *flag, int64_t cap,
+                     int64_t *n_out) {
+  if (!(a > 0) || !(D >= 0) || !(L >= 0) || n_grip < 0 || !n_out)
+    return fail(TBSMA_EINVAL, "bad wire arguments");
+  double h = 0.5 * a;
+  double rad2 = (D / a) * (D / a);
+  int64_t layers = 0;
+  while ((double)layers * h < L) ++layers;
+  int64_t m = (int64_t)floor(D / a) + 1;
+  int64_t n = 0;
+  for (int64_t k = 0; k < layers; ++k) {
+    uint8_t fl = k < n_grip ? TBSMA_GRIP_FIXED
+                 : k >= layers - n_grip ? TBSMA_GRIP_PULL
+                                        : TBSMA_DYN;
+    for (int64_t j = -m; j <= m; ++j)
+      for (int64_t i = -m; i <= m; ++i) {
+        if ((i + j + k) & 1) continue;
+        if ((double)(i * i + j * j) > rad2) continue;
+        if (n < cap) {
+          x[n] = (double)i * h;
+          y[n] = (double)j * h;
+          z[n] = (double)k * h;
+          flag[n] = fl;
+        }
+        ++n;
+      }
+  }
+  *n_out = n;
+  if (n > cap) return fail(TBSMA_ECAPACITY, "wire has %lld atoms", (long long)n);
+  return TBSMA_OK;
+}
+
+int tbsma_init_state(const tbsma_params *prm, tbsma_system *sys,
+                     const tbsma_md *md, void *work, double jitter,
+                     void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  TRY(check_md(md, sys->R));
+  if (sys->R == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  DevMD M = make_devmd(prm, md);
+  launch_init(d, M, prm->precision == TBSMA_MIXED, jitter, s);
+  launch_set_step(md->step, 0, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return TBSMA_OK;
+}
+
+int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
+                      tbsma_cells *cells, void *work, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  TRY(check_lists(cells, nullptr));
+  if (!cells) return fail(TBSMA_EINVAL, "cells is NULL");
+  if (sys->R == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nullptr);
+  d.all = 1;
+  launch_fill_u32(reinterpret_cast<uint32_t *>(d.cnt), sys->C, 0u, s);
+  launch_cells(d, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
+                    const tbsma_cells *cells, tbsma_nlist *nl, void *work,
+                    int32_t *need_cap, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
+  TRY(check_lists(cells, nl));
+  if (sys->R == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nl);
+  d.all = 1;
+  double rl = prm->r_cut + prm->skin;
+  launch_fill_u32(reinterpret_cast<uint32_t *>(d.nnmax), 1, 0u, s);
+  launch_nlist(d, rl * rl, s);
+  if (prm->precision == TBSMA_MIXED) launch_quantise(d, s);
+  HIPCHK(hipGetLastError());
+  if (need_cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t mx = 0;
+    HIPCHK(hipMemcpy(&mx, d.nnmax, 4, hipMemcpyDeviceToHost));
+    *need_cap = mx > nl->k_cap ? mx : nl->k_cap;
+    if (mx > nl->k_cap)
+      return fail(TBSMA_ECAPACITY, "longest row %d exceeds k_cap %d", mx,
+                  nl->k_cap);
+  }
+  return TBSMA_OK;
+}
+
+int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
+                 const tbsma_nlist *nl, tbsma_forces_out *out, void *work,
+                 void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!nl) return fail(TBSMA_EINVAL, "nlist is NULL");
+  TRY(check_lists(nullptr, nl));
+  TRY(check_out(prm, out));
+  if (sys->R == 0) return TBSMA_OK;
+  if (!out->rep_energy || !out->rep_wzz)
+    return fail(TBSMA_EINVAL, "rep_energy / rep_wzz missing");
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, nullptr, nl);
+  bool mixed = prm->precision == TBSMA_MIXED;
+  if (mixed) launch_quantise(d, s);
+  launch_forces(d, mixed, make_potf(prm), make_potd(prm), out->fx, out->fy,
+                out->fz, out->e_atom, out->g, s);
+  launch_reduce_forces(d, out->rep_energy, out->rep_wzz, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
+                      const tbsma_nlist *nl, tbsma_forces_out *out, void *work,
+                      int32_t pass, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!nl) return fail(TBSMA_EINVAL, "nlist is NULL");
+  TRY(check_lists(nullptr, nl));
+  TRY(check_out(prm, out));
+  if (pass != 1 && pass != 2) return fail(TBSMA_EINVAL, "pass must be 1 or 2");
+  if (sys->R == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, nullptr, nl);
+  launch_force_pass(d, prm->precision == TBSMA_MIXED, pass, make_potf(prm),
+                    make_potd(prm), out->fx, out->fy, out->fz, out->e_atom,
+                    out->g, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
+               tbsma_nlist *nl, tbsma_forces_out *out, const tbsma_md *md,
+               void *work, int64_t n_steps, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
+  TRY(check_lists(cells, nl));
+  TRY(check_out(prm, out));
+  TRY(check_md(md, sys->R));
+  if (n_steps < 0) return fail(TBSMA_EINVAL, "n_steps < 0");
+  if (sys->R == 0 || n_steps == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nl);
+  DevMD M = make_devmd(prm, md);
+  PotF PF = make_potf(prm);
+  PotD PD = make_potd(prm);
+  for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
+  return finish_run(d, md, s);
+}
+
+int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
+                    tbsma_cells *cells, tbsma_nlist *nl,
+                    tbsma_forces_out *out, const tbsma_md *md, void *work,
+                    int64_t n_steps, int32_t steps_per_graph, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
+  TRY(check_lists(cells, nl));
+  TRY(check_out(prm, out));
+  TRY(check_md(md, sys->R));
+  if (n_steps < 0 || steps_per_graph < 1)
+    return fail(TBSMA_EINVAL, "need n_steps >= 0 and steps_per_graph >= 1");
+  if (sys->R == 0 || n_steps == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nl);
+  DevMD M = make_devmd(prm, md);
+  PotF PF = make_potf(prm);
+  PotD PD = make_potd(prm);
+  int64_t chunks = n_steps / steps_per_graph;
+  int64_t rest = n_steps % steps_per_graph;
+  if (chunks > 0) {
+    std::lock_guard<std::mutex> lk(g_graph.mu);
+    std::vector<char> key;
+    append(key, prm, sizeof(*prm));
+    append(key, &d, sizeof(d));
+    append(key, &M, sizeof(M));
+    append(key, out, sizeof(*out));
+    append(key, &steps_per_graph, sizeof(steps_per_graph));
+    append(key, &s, sizeof(s));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    append(key, &dev, sizeof(dev));
+    if (!g_graph.exec || key != g_graph.key) {
+      if (g_graph.exec) {
+        (void)hipGraphExecDestroy(g_graph.exec);
+        g_graph.exec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int32_t k = 0; k < steps_per_graph; ++k)
+        enqueue_step(prm, d, M, out, PF, PD, s);
+      hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (ce != hipSuccess)
+        return fail(TBSMA_EHIP, "graph capture: %s", hipGetErrorString(ce));
+      hipError_t ie = hipGraphInstantiate(&g_graph.exec, graph, nullptr,
+                                          nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        g_graph.exec = nullptr;
+        return fail(TBSMA_EHIP, "graph instantiate: %s",
+                    hipGetErrorString(ie));
+      }
+      g_graph.key = key;
+    }
+    for (int64_t c = 0; c < chunks; ++c)
+      HIPCHK(hipGraphLaunch(g_graph.exec, s));
+  }
+  for (int64_t k = 0; k < rest; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
+  return finish_run(d, md, s);
+}
+
+int tbsma_rng_fill(uint64_t seed, uint32_t rep_id, uint64_t step,
+                   uint32_t stream_id, int64_t n, uint32_t *out_u32,
+                   double *out_gauss, void *stream) {
+  if (n < 0) return fail(TBSMA_EINVAL, "n < 0");
+  if (n == 0) return TBSMA_OK;
+  TRY(check_device());
+  launch_rng_fill(seed, rep_id, step, stream_id, n, out_u32, out_gauss,
+                  static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+}  // extern "C"

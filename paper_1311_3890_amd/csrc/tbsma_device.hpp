@@ -1,0 +1,191 @@
+// Device-side helpers of libtbsma: constants, Philox4x32-10, wave
+// reductions, XCD-aware block numbering and the kernel argument bundles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tbsma {
+
+constexpr int kTile = 64;   // slots per tile = one wavefront
+constexpr int kBlock = 256; // threads of every per-atom kernel
+constexpr int kNPart = 8;   // FP64 partial sums per tile
+
+// per-tile partial sums
+constexpr int kPartE = 0;   // sum of E_i
+constexpr int kPartW = 1;   // sum of w_i = 1/2 sum_j E'_ij dz^2 / r
+constexpr int kPartK = 2;   // sum over dynamic atoms of m |v - u|^2
+constexpr int kPartKz = 3;  // sum over dynamic atoms of m (v_z - u_z)^2
+constexpr int kPartA = 4;   // init: sum v_x, v_y, v_z, count (4..7)
+
+// Physical constants: k_B (eV/K) and 1 eV/(A amu) in A/ps^2, from the SI
+// values of the electronvolt and the atomic mass unit.
+constexpr double kBoltz = 8.617333262e-5;
+constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-4;
+constexpr double kEvA3ToGPa = 160.21766208;
+
+// Float constants of the mixed-precision pair kernels.  Distances are in
+// position quanta (2^-qbits A); every scale is folded into the constants.
+struct PotF {
+  float rc2;        // r_cut^2 in quanta^2
+  float rt;         // r_tail in quanta
+  float aP, bP;     // (2q/r0) phi(r) = exp2(aP r + bP)
+  float aF, bF;     // phi(r) = exp2(aF r + bF)
+  float aV, bV;     // V(r)   = exp2(aV r + bV)
+  float c2p;        // 2 p / r0
+  float tS, tB;     // t = tS r + tB on the tail
+  float f0, f1, f2, f3;   // phi on the tail: cubic in t
+  float v0, v1, v2, v3;   // V on the tail: cubic in t
+  float dv0, dv1, dv2;    // 2 V'(r) on the tail: quadratic in t
+  float dp0, dp1, dp2;    // -phi'(r) on the tail: quadratic in t
+  float wscale;     // 2^-qbits / 2: converts the virial accumulator to eV
+};
+
+// Double constants of the FP64 pair kernels (Angstrom units).
+struct PotD {
+  double rc, rc2, rt, r0, xi2, A, k2q, kp, w;
+  double f0, f1, f2, f3;  // phi tail cubic in t = (r - rt)/w
+  double v0, v1, v2, v3;  // V tail cubic in t
+};
+
+// Device view of the system (plain pointers, passed by value).
+struct Dev {
+  int32_t R, max_zbins;
+  int64_t N, C;
+  const int64_t *rep_off, *cell_off;
+  const int32_t *tile_rep, *grid_dim, *rep_id;
+  const double *grid_lo;
+  double *x, *y, *z, *vx, *vy, *vz, *z0;
+  uint8_t *flag;
+  int4 *qpos;
+  // cells and lists
+  int32_t *cell_start, *cell_atoms;
+  int32_t *nl, *nn;
+  int32_t k_cap;
+  double *xr, *yr, *zr;
+  // workspace
+  unsigned long long *maxdisp;  // [R] bits of max |x - x_ref|^2 (>= 0)
+  int32_t *cnt;                 // [C]
+  double *part;                 // [N/64 * kNPart]
+  unsigned long long *zbmin, *zbmax;  // [R * max_zbins] ordered keys of z
+  uint32_t *wstatus;            // [R]
+  uint32_t *ticket;             // [1]
+  int32_t *nnmax;               // [1]
+  double *rsum;                 // [R * 8] per-replica scratch sums
+  // parameters used on the device
+  double cell, inv_cell, skin_half2, qscale, inv_qscale, mass;
+  int32_t all;                  // 1: rebuild every replica
+};
+
+struct DevMD {
+  double dt, gamma, c1, r_cut;
+  int32_t lab_frame, n_log, n_slots, pad;
+  const double *T, *v_pull, *z_lo, *z_hi, *vol, *L0;
+  const uint64_t *seed;
+  const int32_t *dof;
+  int64_t *step;
+  double *obs;
+  uint32_t *status;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
+// that each XCD works on one contiguous range of tiles, which keeps the
+// neighbours' positions in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  int64_t nb = gridDim.x, b = blockIdx.x;
+  int64_t q = nb / 8, rem = nb % 8, xc = b % 8, k = b / 8;
+  int64_t start = xc < rem ? xc * (q + 1) : rem * (q + 1) + (xc - rem) * q;
+  return start + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint4 rng_words(uint64_t seed, uint32_t rep,
+                                           uint32_t tag, uint64_t step,
+                                           uint32_t stream) {
+  return philox4x32_10(make_uint4(tag, (uint32_t)step, rep, stream),
+                       make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+}
+
+__device__ __forceinline__ double u01(uint32_t w) {
+  return ((double)w + 0.5) * 0x1p-32;
+}
+
+// Three standard normals of one counter (Box-Muller, FP64).
+__device__ __forceinline__ void gauss3(uint64_t seed, uint32_t rep,
+                                       uint32_t tag, uint64_t step,
+                                       uint32_t stream, double &n0,
+                                       double &n1, double &n2) {
+  uint4 o = rng_words(seed, rep, tag, step, stream);
+  const double twopi = 6.283185307179586476925286766559;
+  double a = sqrt(-2.0 * log(u01(o.x)));
+  double b = sqrt(-2.0 * log(u01(o.z)));
+  double s, c;
+  sincos(twopi * u01(o.y), &s, &c);
+  n0 = a * c;
+  n1 = a * s;
+  n2 = b * cos(twopi * u01(o.w));
+}
+
+// Order-preserving map of a double to an unsigned key (for atomic min/max).
+__device__ __forceinline__ unsigned long long dkey(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dkey_inv(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ bool rebuilds(const Dev &S, int r) {
+  return S.all || __longlong_as_double((long long)S.maxdisp[r]) > S.skin_half2;
+}
+
+// Cell coordinate along one axis, clamped to the grid (clamping keeps the
+// 27-cell search exact); *out set when clamped.
+__device__ __forceinline__ int cell_coord(double v, double lo, double inv_h,
+                                          int dim, bool &out) {
+  double t = floor((v - lo) * inv_h);
+  if (!(t >= 0.0)) {
+    out = true;
+    return 0;
+  }
+  if (t > (double)(dim - 1)) {
+    out = true;
+    return dim - 1;
+  }
+  return (int)t;
+}
+
+}  // namespace tbsma

@@ -1,0 +1,930 @@
+// HIP kernels of libtbsma for gfx950 (MI355X): cell binning, Verlet lists,
+// the two TB-SMA force passes (FP64 and mixed precision), the BAOAB
+// integrator with rigid grips, per-replica reductions and initial state.
+//
+// One thread per atom slot; a wavefront (64 lanes) is one tile of slots and
+// never straddles two replicas, so per-replica sums are exact per wave and
+// need no atomics.  Kernels over slots use 256-thread blocks.
+#include "tbsma_device.hpp"
+#include "tbsma_kernels.hpp"
+
+namespace tbsma {
+
+// ---------------------------------------------------------------------------
+// workspace / small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long *p, int64_t n,
+                           unsigned long long v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_set_step(int64_t *step, int64_t v) { *step = v; }
+
+// Quantised copy of the positions (mixed precision): q = rint((x - o) 2^qbits)
+// about the centre o of the replica's grid; w keeps its value.
+__device__ __forceinline__ int quant1(double v, double o, double qs,
+                                      bool &out) {
+  double t = rint((v - o) * qs);
+  if (!(t > -2147483000.0 && t < 2147483000.0)) {
+    out = true;
+    t = t > 0.0 ? 2147483000.0 : -2147483000.0;
+  }
+  return (int)t;
+}
+
+__device__ __forceinline__ void quantise(const Dev &S, int r, int64_t i,
+                                         double x, double y, double z,
+                                         bool &out) {
+  const int32_t *gd = S.grid_dim + 3 * r;
+  const double *lo = S.grid_lo + 3 * r;
+  double hc = 0.5 * S.cell;
+  int4 q = S.qpos[i];
+  q.x = quant1(x, lo[0] + hc * gd[0], S.qscale, out);
+  q.y = quant1(y, lo[1] + hc * gd[1], S.qscale, out);
+  q.z = quant1(z, lo[2] + hc * gd[2], S.qscale, out);
+  S.qpos[i] = q;
+}
+
+__global__ void __launch_bounds__(kBlock) k_quantise(Dev S) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;
+  int r = S.tile_rep[i / kTile];
+  bool out = false;
+  if (S.flag[i] == 3) {
+    S.qpos[i] = make_int4(0, 0, 0, 0);
+    return;
+  }
+  quantise(S, r, i, S.x[i], S.y[i], S.z[i], out);
+  if (out) atomicOr(&S.wstatus[r], 4u);
+}
+
+// ---------------------------------------------------------------------------
+// cell binning: count -> per-replica scan -> fill -> per-cell sort
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int atom_cell(const Dev &S, int r, int64_t i,
+                                         bool &out) {
+  const int32_t *gd = S.grid_dim + 3 * r;
+  const double *lo = S.grid_lo + 3 * r;
+  int cx = cell_coord(S.x[i], lo[0], S.inv_cell, gd[0], out);
+  int cy = cell_coord(S.y[i], lo[1], S.inv_cell, gd[1], out);
+  int cz = cell_coord(S.z[i], lo[2], S.inv_cell, gd[2], out);
+  return (cz * gd[1] + cy) * gd[0] + cx;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_count(Dev S) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;
+  int r = S.tile_rep[i / kTile];
+  if (!rebuilds(S, r) || S.flag[i] == 3) return;
+  bool out = false;
+  int c = atom_cell(S, r, i, out);
+  atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
+  if (out) atomicOr(&S.wstatus[r], 4u);
+}
+
+// One workgroup per replica: exclusive scan of its cell counts into
+// cell_start; the counters become fill cursors.
+__global__ void __launch_bounds__(1024) k_cell_scan(Dev S) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  int r = blockIdx.x;
+  if (!rebuilds(S, r)) return;
+  int64_t c0 = S.cell_off[r], nc = S.cell_off[r + 1] - c0;
+  int32_t *start = S.cell_start + c0 + r;
+  int32_t base = (int32_t)S.rep_off[r];
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t b = 0; b < nc; b += 1024) {
+    int64_t c = b + threadIdx.x;
+    int32_t v = c < nc ? S.cnt[c0 + c] : 0;
+    // inclusive wave scan
+    int32_t s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int32_t t = __shfl_up(s, o, 64);
+      if (lane >= o) s += t;
+    }
+    if (lane == 63) wsum[wid] = s;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wid) woff += wsum[w];
+      tot += wsum[w];
+    }
+    int32_t ex = carry_s + woff + s - v;
+    if (c < nc) {
+      start[c] = base + ex;
+      S.cnt[c0 + c] = base + ex;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) start[nc] = base + carry_s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_fill(Dev S) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;
+  int r = S.tile_rep[i / kTile];
+  if (!rebuilds(S, r) || S.flag[i] == 3) return;
+  bool out = false;
+  int c = atom_cell(S, r, i, out);
+  int32_t pos = atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
+  S.cell_atoms[pos] = (int32_t)i;
+}
+
+// One thread per cell: order the cell's slots ascending (the fill order is
+// not deterministic) and clear its counter for the next build.
+__global__ void __launch_bounds__(kBlock) k_cell_sort(Dev S) {
+  int64_t cg = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (cg >= S.C) return;
+  int lo = 0, hi = S.R - 1;  // replica with cell_off[r] <= cg < cell_off[r+1]
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (S.cell_off[mid] <= cg) lo = mid;
+    else hi = mid - 1;
+  }
+  int r = lo;
+  if (!rebuilds(S, r)) return;
+  int64_t c = cg - S.cell_off[r];
+  int32_t *start = S.cell_start + S.cell_off[r] + r;
+  int32_t a = start[c], e = start[c + 1];
+  int32_t *v = S.cell_atoms;
+  for (int32_t k = a + 1; k < e; ++k) {
+    int32_t key = v[k];
+    int32_t m = k - 1;
+    while (m >= a && v[m] > key) {
+      v[m + 1] = v[m];
+      --m;
+    }
+    v[m + 1] = key;
+  }
+  S.cnt[cg] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Verlet lists: scan the 27 cells around the atom's cell (FP64 distances)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;
+  int r = S.tile_rep[i / kTile];
+  if (!rebuilds(S, r)) return;
+  if (S.flag[i] == 3) {
+    S.nn[i] = 0;
+    return;
+  }
+  const int32_t *gd = S.grid_dim + 3 * r;
+  const double *lo = S.grid_lo + 3 * r;
+  double xi = S.x[i], yi = S.y[i], zi = S.z[i];
+  bool out = false;
+  int cx = cell_coord(xi, lo[0], S.inv_cell, gd[0], out);
+  int cy = cell_coord(yi, lo[1], S.inv_cell, gd[1], out);
+  int cz = cell_coord(zi, lo[2], S.inv_cell, gd[2], out);
+  const int32_t *start = S.cell_start + S.cell_off[r] + r;
+  int cnt = 0;
+  const int64_t N = S.N;
+  for (int kz = cz - 1; kz <= cz + 1; ++kz) {
+    if (kz < 0 || kz >= gd[2]) continue;
+    for (int ky = cy - 1; ky <= cy + 1; ++ky) {
+      if (ky < 0 || ky >= gd[1]) continue;
+      for (int kx = cx - 1; kx <= cx + 1; ++kx) {
+        if (kx < 0 || kx >= gd[0]) continue;
+        int c = (kz * gd[1] + ky) * gd[0] + kx;
+        int32_t a = start[c], e = start[c + 1];
+        for (int32_t s = a; s < e; ++s) {
+          int32_t j = S.cell_atoms[s];
+          if (j == (int32_t)i) continue;
+          double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+          if (dx * dx + dy * dy + dz * dz < rl2) {
+            if (cnt < S.k_cap) S.nl[(int64_t)cnt * N + i] = j;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > S.k_cap) {
+    atomicMax(S.nnmax, cnt);
+    atomicOr(&S.wstatus[r], 1u);
+    cnt = S.k_cap;
+  }
+  S.nn[i] = cnt;
+  S.xr[i] = xi;
+  S.yr[i] = yi;
+  S.zr[i] = zi;
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: density rho_i -> g_i = 1/sqrt(rho_i)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
+  int64_t b0 = xcd_block() * kBlock;
+  int64_t i = b0 + threadIdx.x;
+  bool valid = i < S.N;
+  int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+  int n = valid ? S.nn[i] : 0;
+  int nmax = wave_max_i(n);
+  const int4 *__restrict__ qp = S.qpos;
+  const int32_t *__restrict__ col = S.nl + b0;
+  const int64_t N = S.N;
+  float rho = 0.0f;
+  for (int k = 0; k < nmax; ++k) {
+    if (k < n) {
+      int j = col[(int64_t)k * N + threadIdx.x];
+      int4 qj = qp[j];
+      float dx = (float)(qj.x - qi.x);
+      float dy = (float)(qj.y - qi.y);
+      float dz = (float)(qj.z - qi.z);
+      float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      float rr = __builtin_amdgcn_sqrtf(r2);
+      float f = __builtin_amdgcn_exp2f(fmaf(P.aF, rr, P.bF));
+      float t = fmaf(rr, P.tS, P.tB);
+      float ft = fmaf(fmaf(fmaf(P.f3, t, P.f2), t, P.f1), t, P.f0);
+      f = rr > P.rt ? ft : f;
+      rho += (r2 < P.rc2 && r2 > 0.0f) ? f : 0.0f;
+    }
+  }
+  if (valid) {
+    float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
+    S.qpos[i].w = __float_as_int(g);
+  }
+}
+
+__device__ __forceinline__ double radial_d(const PotD &P, bool dens,
+                                           double r) {
+  if (r > P.rc) return 0.0;
+  if (r <= P.rt) {
+    return dens ? P.xi2 * exp(-P.k2q * (r / P.r0 - 1.0))
+                : P.A * exp(-P.kp * (r / P.r0 - 1.0));
+  }
+  double t = (r - P.rt) / P.w;
+  return dens ? fma(fma(fma(P.f3, t, P.f2), t, P.f1), t, P.f0)
+              : fma(fma(fma(P.v3, t, P.v2), t, P.v1), t, P.v0);
+}
+
+__device__ __forceinline__ double dradial_d(const PotD &P, bool dens,
+                                            double r) {
+  if (r > P.rc) return 0.0;
+  if (r <= P.rt) {
+    return dens ? -(P.k2q / P.r0) * P.xi2 * exp(-P.k2q * (r / P.r0 - 1.0))
+                : -(P.kp / P.r0) * P.A * exp(-P.kp * (r / P.r0 - 1.0));
+  }
+  double t = (r - P.rt) / P.w;
+  return dens ? fma(fma(3.0 * P.f3, t, 2.0 * P.f2), t, P.f1) / P.w
+              : fma(fma(3.0 * P.v3, t, 2.0 * P.v2), t, P.v1) / P.w;
+}
+
+__global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
+                                                         double *g) {
+  int64_t b0 = xcd_block() * kBlock;
+  int64_t i = b0 + threadIdx.x;
+  bool valid = i < S.N;
+  int n = valid ? S.nn[i] : 0;
+  double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
+         zi = valid ? S.z[i] : 0.0;
+  const int64_t N = S.N;
+  double rho = 0.0;
+  for (int k = 0; k < n; ++k) {
+    int j = S.nl[(int64_t)k * N + i];
+    double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r > 0.0) rho += radial_d(P, true, r);
+  }
+  if (valid) g[i] = rho > 0.0 ? 1.0 / sqrt(rho) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: forces, per-atom energies, per-tile sums of E and of the zz virial
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
+                                                        float *fx, float *fy,
+                                                        float *fz,
+                                                        float *eat) {
+  int64_t b0 = xcd_block() * kBlock;
+  int64_t i = b0 + threadIdx.x;
+  bool valid = i < S.N;
+  int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+  int n = valid ? S.nn[i] : 0;
+  int nmax = wave_max_i(n);
+  float gi = __int_as_float(qi.w);
+  float hgi = 0.5f * gi;
+  const int4 *__restrict__ qp = S.qpos;
+  const int32_t *__restrict__ col = S.nl + b0;
+  const int64_t N = S.N;
+  float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
+  for (int k = 0; k < nmax; ++k) {
+    if (k < n) {
+      int j = col[(int64_t)k * N + threadIdx.x];
+      int4 qj = qp[j];
+      float dx = (float)(qj.x - qi.x);
+      float dy = (float)(qj.y - qi.y);
+      float dz = (float)(qj.z - qi.z);
+      float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      float ri = __builtin_amdgcn_rsqf(r2);
+      float rr = r2 * ri;
+      float eV = __builtin_amdgcn_exp2f(fmaf(P.aV, rr, P.bV));
+      float eP = __builtin_amdgcn_exp2f(fmaf(P.aP, rr, P.bP));
+      float G = fmaf(0.5f, __int_as_float(qj.w), hgi);
+      float ep = fmaf(G, eP, -P.c2p * eV);
+      float t = fmaf(rr, P.tS, P.tB);
+      float vt = fmaf(fmaf(fmaf(P.v3, t, P.v2), t, P.v1), t, P.v0);
+      float dvt = fmaf(fmaf(P.dv2, t, P.dv1), t, P.dv0);
+      float dpt = fmaf(fmaf(P.dp2, t, P.dp1), t, P.dp0);
+      bool tail = rr > P.rt;
+      ep = tail ? fmaf(G, dpt, dvt) : ep;
+      eV = tail ? vt : eV;
+      bool in = r2 < P.rc2 && r2 > 0.0f;
+      float s = in ? ep * ri : 0.0f;
+      ev += in ? eV : 0.0f;
+      ax = fmaf(s, dx, ax);
+      ay = fmaf(s, dy, ay);
+      float sz = s * dz;
+      az += sz;
+      wz = fmaf(sz, dz, wz);
+    }
+  }
+  double e_i = 0.0, w_i = 0.0;
+  if (valid) {
+    float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
+    fx[i] = ax;
+    fy[i] = ay;
+    fz[i] = az;
+    eat[i] = e;
+    e_i = (double)e;
+    w_i = (double)wz * (double)P.wscale;
+  }
+  e_i = wave_sum(e_i);
+  w_i = wave_sum(w_i);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    double *pt = S.part + (i / kTile) * kNPart;
+    pt[kPartE] = e_i;
+    pt[kPartW] = w_i;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
+                                                       const double *g,
+                                                       double *fx, double *fy,
+                                                       double *fz,
+                                                       double *eat) {
+  int64_t b0 = xcd_block() * kBlock;
+  int64_t i = b0 + threadIdx.x;
+  bool valid = i < S.N;
+  int n = valid ? S.nn[i] : 0;
+  double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
+         zi = valid ? S.z[i] : 0.0;
+  double gi = valid ? g[i] : 0.0;
+  const int64_t N = S.N;
+  double ax = 0, ay = 0, az = 0, ev = 0, wz = 0, rho = 0;
+  for (int k = 0; k < n; ++k) {
+    int j = S.nl[(int64_t)k * N + i];
+    double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(r > 0.0) || r > P.rc) continue;
+    double ep = 2.0 * dradial_d(P, false, r) -
+                0.5 * (gi + g[j]) * dradial_d(P, true, r);
+    double s = ep / r;
+    ax += s * dx;
+    ay += s * dy;
+    az += s * dz;
+    wz += s * dz * dz;
+    ev += radial_d(P, false, r);
+    rho += radial_d(P, true, r);
+  }
+  double e_i = 0.0, w_i = 0.0;
+  if (valid) {
+    double e = ev - sqrt(rho);
+    fx[i] = ax;
+    fy[i] = ay;
+    fz[i] = az;
+    eat[i] = e;
+    e_i = e;
+    w_i = 0.5 * wz;
+  }
+  e_i = wave_sum(e_i);
+  w_i = wave_sum(w_i);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    double *pt = S.part + (i / kTile) * kNPart;
+    pt[kPartE] = e_i;
+    pt[kPartW] = w_i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// integrator (BAOAB + grips) and per-replica reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
+                                           double D) {
+  double vp = M.v_pull[r];
+  if (M.lab_frame || vp == 0.0) return 0.0;
+  return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
+}
+
+template <typename FT, bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
+                                                        const FT *fx,
+                                                        const FT *fy,
+                                                        const FT *fz) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool valid = i < S.N;
+  int r = valid ? S.tile_rep[i / kTile] : 0;
+  int64_t step = *M.step;
+  const double dt = M.dt, hdt = 0.5 * dt;
+  uint8_t f = valid ? S.flag[i] : 3;
+  double disp2 = 0.0;
+  if (f != 3) {
+    double x = S.x[i], y = S.y[i], z = S.z[i];
+    double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
+    if (f == 0) {
+      double ac = hdt * kAccel / S.mass;
+      vx += ac * (double)fx[i];
+      vy += ac * (double)fy[i];
+      vz += ac * (double)fz[i];
+      x += hdt * vx;
+      y += hdt * vy;
+      z += hdt * vz;
+      if (M.gamma > 0.0) {
+        double n0, n1, n2;
+        uint32_t tag = (uint32_t)(i - S.rep_off[r]);
+        gauss3(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u, n0,
+               n1, n2);
+        double sg = sqrt(kBoltz * M.T[r] / S.mass * kAccel) *
+                    sqrt(1.0 - M.c1 * M.c1);
+        double uz = stream_u(M, r, z, M.v_pull[r] * ((double)step + 0.5) * dt);
+        vx = M.c1 * vx + sg * n0;
+        vy = M.c1 * vy + sg * n1;
+        vz = uz + M.c1 * (vz - uz) + sg * n2;
+      }
+      x += hdt * vx;
+      y += hdt * vy;
+      z += hdt * vz;
+      S.x[i] = x;
+      S.y[i] = y;
+      S.z[i] = z;
+      S.vx[i] = vx;
+      S.vy[i] = vy;
+      S.vz[i] = vz;
+    } else if (f == 1) {
+      z = S.z0[i];
+      S.z[i] = z;
+      S.vx[i] = 0.0;
+      S.vy[i] = 0.0;
+      S.vz[i] = 0.0;
+    } else {
+      double vp = M.v_pull[r];
+      z = S.z0[i] + vp * (double)(step + 1) * dt;
+      S.z[i] = z;
+      S.vx[i] = 0.0;
+      S.vy[i] = 0.0;
+      S.vz[i] = vp;
+    }
+    if (MIXED) {
+      bool out = false;
+      quantise(S, r, i, x, y, z, out);
+      if (out) atomicOr(&S.wstatus[r], 4u);
+    }
+    double ex = x - S.xr[i], ey = y - S.yr[i], ez = z - S.zr[i];
+    disp2 = ex * ex + ey * ey + ez * ez;
+    if (!(disp2 == disp2)) disp2 = 1.0e300;  // NaN forces a rebuild
+  }
+  disp2 = wave_max(disp2);
+  if ((threadIdx.x & 63) == 0 && valid)
+    atomicMax(&S.maxdisp[r], (unsigned long long)__double_as_longlong(disp2));
+}
+
+template <typename FT>
+__global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
+                                                        const FT *fx,
+                                                        const FT *fy,
+                                                        const FT *fz) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool valid = i < S.N;
+  int r = valid ? S.tile_rep[i / kTile] : 0;
+  int64_t step = *M.step;
+  const double hdt = 0.5 * M.dt;
+  uint8_t f = valid ? S.flag[i] : 3;
+  double k2 = 0.0, kz = 0.0;
+  bool logstep = ((step + 1) % M.n_log) == 0;
+  if (f != 3) {
+    double z = S.z[i];
+    if (f == 0) {
+      double ac = hdt * kAccel / S.mass;
+      double vx = S.vx[i] + ac * (double)fx[i];
+      double vy = S.vy[i] + ac * (double)fy[i];
+      double vz = S.vz[i] + ac * (double)fz[i];
+      S.vx[i] = vx;
+      S.vy[i] = vy;
+      S.vz[i] = vz;
+      double D = M.v_pull[r] * (double)(step + 1) * M.dt;
+      double wv = vz - stream_u(M, r, z, D);
+      k2 = S.mass * (vx * vx + vy * vy + wv * wv);
+      kz = S.mass * wv * wv;
+    }
+    if (logstep) {
+      // axial bins of width cell/2 for the rupture gap
+      int nb = 2 * S.grid_dim[3 * r + 2];
+      double t = floor((z - S.grid_lo[3 * r + 2]) * 2.0 * S.inv_cell);
+      int b = t >= 0.0 ? (t < (double)nb ? (int)t : nb - 1) : 0;
+      unsigned long long kk = dkey(z);
+      atomicMin(&S.zbmin[(int64_t)r * S.max_zbins + b], kk);
+      atomicMax(&S.zbmax[(int64_t)r * S.max_zbins + b], kk);
+    }
+  }
+  k2 = wave_sum(k2);
+  kz = wave_sum(kz);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    double *pt = S.part + (i / kTile) * kNPart;
+    pt[kPartK] = k2;
+    pt[kPartKz] = kz;
+  }
+}
+
+// Deterministic block sum of the partials of tiles [t0, t1) (entries k0..k1).
+template <int NV>
+__device__ __forceinline__ void block_sum_tiles(const double *part,
+                                                int64_t t0, int64_t t1,
+                                                int k0, double *out,
+                                                double *lds /* [NV*256] */) {
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += part[t * kNPart + k0 + v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lds[v * 256 + threadIdx.x] = acc[v];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        lds[v * 256 + threadIdx.x] += lds[v * 256 + threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = lds[v * 256];
+}
+
+__global__ void __launch_bounds__(256) k_reduce_forces(Dev S, double *rep_e,
+                                                       double *rep_w) {
+  __shared__ double lds[2 * 256];
+  int r = blockIdx.x;
+  int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
+  double s[2];
+  block_sum_tiles<2>(S.part, t0, t1, kPartE, s, lds);
+  if (threadIdx.x == 0) {
+    rep_e[r] = s[0];
+    rep_w[r] = s[1];
+  }
+}
+
+// End of a step, one workgroup per replica: sums, observables, status, and
+// (last workgroup to finish) the step index.
+__global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
+  __shared__ double lds[4 * 256];
+  int r = blockIdx.x;
+  int64_t step = *M.step;
+  int64_t n1 = step + 1;
+  int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
+  double s[4];
+  block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
+  bool logstep = (n1 % M.n_log) == 0;
+  int nb = 2 * S.grid_dim[3 * r + 2];
+  unsigned long long *bmin = S.zbmin + (int64_t)r * S.max_zbins;
+  unsigned long long *bmax = S.zbmax + (int64_t)r * S.max_zbins;
+  if (threadIdx.x == 0) {
+    double E = s[0], wzz = s[1];
+    double KE = 0.5 * s[2] / kAccel, Kz = s[3] / kAccel;
+    int dof = M.dof[r];
+    double T = dof > 0 ? 2.0 * KE / ((double)dof * kBoltz) : 0.0;
+    double D = M.v_pull[r] * (double)n1 * M.dt;
+    uint32_t st = S.wstatus[r];
+    if (!isfinite(E) || !isfinite(KE)) st |= 2u;
+    if (__longlong_as_double((long long)S.maxdisp[r]) > S.skin_half2)
+      st |= 16u;
+    if (logstep) {
+      double gap = 0.0, pmax = 0.0;
+      bool have = false;
+      for (int b = 0; b < nb; ++b) {
+        unsigned long long mn = bmin[b];
+        if (mn == ~0ull) continue;
+        if (have) gap = fmax(gap, dkey_inv(mn) - pmax);
+        pmax = dkey_inv(bmax[b]);
+        have = true;
+      }
+      if (gap >= M.r_cut) st |= 8u;
+      double *o = M.obs + ((n1 / M.n_log) % M.n_slots) * (int64_t)S.R * 10 +
+                  (int64_t)r * 10;
+      o[0] = (double)n1;
+      o[1] = E;
+      o[2] = KE;
+      o[3] = T;
+      o[4] = wzz;
+      o[5] = (wzz - Kz) / M.vol[r] * kEvA3ToGPa;
+      o[6] = D / M.L0[r];
+      o[7] = gap;
+      o[8] = D;
+      o[9] = (double)(M.status[r] | st);
+    }
+    M.status[r] |= st;
+    S.wstatus[r] = 0u;
+    S.maxdisp[r] = 0ull;
+  }
+  __syncthreads();
+  if (logstep) {
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      bmin[b] = ~0ull;
+      bmax[b] = 0ull;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    uint32_t prev = atomicAdd(S.ticket, 1u);
+    if (prev == (uint32_t)S.R - 1) {
+      *M.step = n1;
+      *S.ticket = 0u;
+      __threadfence();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initial state
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
+                                                   double jitter) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool valid = i < S.N;
+  int r = valid ? S.tile_rep[i / kTile] : 0;
+  uint8_t f = valid ? S.flag[i] : 3;
+  double sx = 0, sy = 0, sz = 0, cn = 0;
+  if (f != 3) {
+    uint32_t tag = (uint32_t)(i - S.rep_off[r]);
+    uint32_t rid = (uint32_t)S.rep_id[r];
+    if (jitter != 0.0) {
+      uint4 o = rng_words(M.seed[r], rid, tag, 0, 2u);
+      S.x[i] += jitter * (2.0 * u01(o.x) - 1.0);
+      S.y[i] += jitter * (2.0 * u01(o.y) - 1.0);
+      S.z[i] += jitter * (2.0 * u01(o.z) - 1.0);
+    }
+    double vx = 0, vy = 0, vz = 0;
+    if (f == 0) {
+      double sg = sqrt(kBoltz * M.T[r] / S.mass * kAccel);
+      double n0, n1, n2;
+      gauss3(M.seed[r], rid, tag, 0, 1u, n0, n1, n2);
+      vx = sg * n0;
+      vy = sg * n1;
+      vz = sg * n2;
+      sx = vx;
+      sy = vy;
+      sz = vz;
+      cn = 1.0;
+    } else if (f == 2) {
+      vz = M.v_pull[r];
+    }
+    S.vx[i] = vx;
+    S.vy[i] = vy;
+    S.vz[i] = vz;
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  sz = wave_sum(sz);
+  cn = wave_sum(cn);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    double *pt = S.part + (i / kTile) * kNPart;
+    pt[kPartA + 0] = sx;
+    pt[kPartA + 1] = sy;
+    pt[kPartA + 2] = sz;
+    pt[kPartA + 3] = cn;
+  }
+}
+
+// mode 0: centre-of-mass velocity -> rsum[8r..8r+2]; mode 1: rescale factor
+// -> rsum[8r+3].
+__global__ void __launch_bounds__(256) k_init_reduce(Dev S, DevMD M,
+                                                     int mode) {
+  __shared__ double lds[4 * 256];
+  int r = blockIdx.x;
+  int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
+  double s[4];
+  block_sum_tiles<4>(S.part, t0, t1, kPartA, s, lds);
+  if (threadIdx.x == 0) {
+    double *rs = S.rsum + 8 * r;
+    if (mode == 0) {
+      double c = s[3] > 0.0 ? s[3] : 1.0;
+      rs[0] = s[0] / c;
+      rs[1] = s[1] / c;
+      rs[2] = s[2] / c;
+    } else {
+      int dof = M.dof[r];
+      double s2 = s[0];
+      rs[3] = (s2 > 0.0 && dof > 0)
+                  ? sqrt((double)dof * kBoltz * M.T[r] /
+                         (S.mass * s2 / kAccel))
+                  : 0.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_init_b(Dev S) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool valid = i < S.N;
+  int r = valid ? S.tile_rep[i / kTile] : 0;
+  uint8_t f = valid ? S.flag[i] : 3;
+  double s2 = 0.0;
+  if (f == 0) {
+    const double *rs = S.rsum + 8 * r;
+    double vx = S.vx[i] - rs[0], vy = S.vy[i] - rs[1], vz = S.vz[i] - rs[2];
+    S.vx[i] = vx;
+    S.vy[i] = vy;
+    S.vz[i] = vz;
+    s2 = vx * vx + vy * vy + vz * vz;
+  }
+  s2 = wave_sum(s2);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    double *pt = S.part + (i / kTile) * kNPart;
+    pt[kPartA + 0] = s2;
+    pt[kPartA + 1] = 0.0;
+    pt[kPartA + 2] = 0.0;
+    pt[kPartA + 3] = 0.0;
+  }
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_init_c(Dev S, DevMD M) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;
+  int r = S.tile_rep[i / kTile];
+  uint8_t f = S.flag[i];
+  if (f == 3) {
+    if (MIXED) S.qpos[i] = make_int4(0, 0, 0, 0);
+    return;
+  }
+  double z = S.z[i];
+  if (f == 0) {
+    double sc = S.rsum[8 * r + 3];
+    S.vx[i] *= sc;
+    S.vy[i] *= sc;
+    S.vz[i] = S.vz[i] * sc + stream_u(M, r, z, 0.0);
+  }
+  S.z0[i] = z;
+  if (MIXED) {
+    bool out = false;
+    quantise(S, r, i, S.x[i], S.y[i], z, out);
+    if (out) atomicOr(&S.wstatus[r], 4u);
+  }
+}
+
+__global__ void k_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
+                           uint32_t stream, int64_t n, uint32_t *w,
+                           double *g) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (w) {
+    uint4 o = rng_words(seed, rep, (uint32_t)t, step, stream);
+    w[4 * t + 0] = o.x;
+    w[4 * t + 1] = o.y;
+    w[4 * t + 2] = o.z;
+    w[4 * t + 3] = o.w;
+  }
+  if (g) {
+    double a, b, c;
+    gauss3(seed, rep, (uint32_t)t, step, stream, a, b, c);
+    g[3 * t + 0] = a;
+    g[3 * t + 1] = b;
+    g[3 * t + 2] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) {
+  return (unsigned)((n + b - 1) / b);
+}
+
+void launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
+                     hipStream_t s) {
+  if (n > 0) k_fill_u64<<<nblk(n, 256), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n > 0) k_fill_u32<<<nblk(n, 256), 256, 0, s>>>(p, n, v);
+}
+void launch_set_step(int64_t *p, int64_t v, hipStream_t s) {
+  k_set_step<<<1, 1, 0, s>>>(p, v);
+}
+void launch_quantise(const Dev &S, hipStream_t s) {
+  k_quantise<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
+}
+
+void launch_cells(const Dev &S, hipStream_t s) {
+  k_cell_count<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
+  k_cell_scan<<<S.R, 1024, 0, s>>>(S);
+  k_cell_fill<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
+  k_cell_sort<<<nblk(S.C, kBlock), kBlock, 0, s>>>(S);
+}
+
+void launch_nlist(const Dev &S, double rl2, hipStream_t s) {
+  k_nlist<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl2);
+}
+
+void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
+                   void *fx, void *fy, void *fz, void *eat, double *g,
+                   hipStream_t s) {
+  unsigned nb = nblk(S.N, kBlock);
+  if (mixed) {
+    k_density_mixed<<<nb, kBlock, 0, s>>>(S, PF);
+    k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
+                                        (float *)fz, (float *)eat);
+  } else {
+    k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);
+    k_force_fp64<<<nb, kBlock, 0, s>>>(S, PD, g, (double *)fx, (double *)fy,
+                                       (double *)fz, (double *)eat);
+  }
+}
+
+void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
+                       const PotD &PD, void *fx, void *fy, void *fz, void *eat,
+                       double *g, hipStream_t s) {
+  unsigned nb = nblk(S.N, kBlock);
+  if (mixed) {
+    if (pass == 1)
+      k_density_mixed<<<nb, kBlock, 0, s>>>(S, PF);
+    else
+      k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
+                                          (float *)fz, (float *)eat);
+  } else {
+    if (pass == 1)
+      k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);
+    else
+      k_force_fp64<<<nb, kBlock, 0, s>>>(S, PD, g, (double *)fx, (double *)fy,
+                                         (double *)fz, (double *)eat);
+  }
+}
+
+void launch_reduce_forces(const Dev &S, double *re, double *rw,
+                          hipStream_t s) {
+  k_reduce_forces<<<S.R, 256, 0, s>>>(S, re, rw);
+}
+
+void launch_integrate_a(const Dev &S, const DevMD &M, bool mixed,
+                        const void *fx, const void *fy, const void *fz,
+                        hipStream_t s) {
+  unsigned nb = nblk(S.N, kBlock);
+  if (mixed)
+    k_integrate_a<float, true><<<nb, kBlock, 0, s>>>(
+        S, M, (const float *)fx, (const float *)fy, (const float *)fz);
+  else
+    k_integrate_a<double, false><<<nb, kBlock, 0, s>>>(
+        S, M, (const double *)fx, (const double *)fy, (const double *)fz);
+}
+
+void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
+                        const void *fx, const void *fy, const void *fz,
+                        hipStream_t s) {
+  unsigned nb = nblk(S.N, kBlock);
+  if (mixed)
+    k_integrate_b<float><<<nb, kBlock, 0, s>>>(
+        S, M, (const float *)fx, (const float *)fy, (const float *)fz);
+  else
+    k_integrate_b<double><<<nb, kBlock, 0, s>>>(
+        S, M, (const double *)fx, (const double *)fy, (const double *)fz);
+}
+
+void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {
+  k_reduce_step<<<S.R, 256, 0, s>>>(S, M);
+}
+
+void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
+                 hipStream_t s) {
+  unsigned nb = nblk(S.N, kBlock);
+  k_init_a<<<nb, kBlock, 0, s>>>(S, M, jitter);
+  k_init_reduce<<<S.R, 256, 0, s>>>(S, M, 0);
+  k_init_b<<<nb, kBlock, 0, s>>>(S);
+  k_init_reduce<<<S.R, 256, 0, s>>>(S, M, 1);
+  if (mixed)
+    k_init_c<true><<<nb, kBlock, 0, s>>>(S, M);
+  else
+    k_init_c<false><<<nb, kBlock, 0, s>>>(S, M);
+}
+
+void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
+                     uint32_t stream, int64_t n, uint32_t *w, double *g,
+                     hipStream_t s) {
+  if (n > 0)
+    k_rng_fill<<<nblk(n, 256), 256, 0, s>>>(seed, rep, step, stream, n, w, g);
+}
+
+}  // namespace tbsma

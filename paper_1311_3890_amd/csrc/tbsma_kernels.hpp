@@ -1,0 +1,36 @@
+// Launchers of the libtbsma kernels (host side).
+#pragma once
+
+#include "tbsma_device.hpp"
+
+namespace tbsma {
+
+void launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
+                     hipStream_t s);
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void launch_set_step(int64_t *p, int64_t v, hipStream_t s);
+void launch_quantise(const Dev &S, hipStream_t s);
+void launch_cells(const Dev &S, hipStream_t s);
+void launch_nlist(const Dev &S, double rl2, hipStream_t s);
+void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
+                   void *fx, void *fy, void *fz, void *eat, double *g,
+                   hipStream_t s);
+void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
+                       const PotD &PD, void *fx, void *fy, void *fz, void *eat,
+                       double *g, hipStream_t s);
+void launch_reduce_forces(const Dev &S, double *re, double *rw,
+                          hipStream_t s);
+void launch_integrate_a(const Dev &S, const DevMD &M, bool mixed,
+                        const void *fx, const void *fy, const void *fz,
+                        hipStream_t s);
+void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
+                        const void *fx, const void *fy, const void *fz,
+                        hipStream_t s);
+void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s);
+void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
+                 hipStream_t s);
+void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
+                     uint32_t stream, int64_t n, uint32_t *w, double *g,
+                     hipStream_t s);
+
+}  // namespace tbsma

@@ -1,0 +1,307 @@
+"""Replica batches on the GPU: layout, device buffers and calls into libtbsma.
+
+``WireBatch`` packs R nanowire replicas into one slot space (each replica's
+slots padded to a multiple of 64), sizes one cell grid per replica, allocates
+every buffer as a torch tensor on the current device, and forwards each
+operation to the C ABI of libtbsma (include/tbsma.h).  Nothing here computes
+any part of the method; PyTorch provides device memory and the stream only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+MASS_AU = 196.96657  # amu
+
+
+@dataclass
+class Potential:
+    """TB-SMA parameters for Au (Table 1), r0 read as the nearest-neighbour
+    distance 2.884 A; cubic tail from r_tail to r_cut."""
+    A: float = 0.2061
+    xi: float = 1.790
+    p: float = 10.229
+    q: float = 4.036
+    r0: float = 2.884
+    r_tail: float = 6.5
+    r_cut: float = 7.0
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def build_wire_host(a: float, D: float, L: float, n_grip: int = 2):
+    """Host-side wire geometry from libtbsma (tbsma_build_wire)."""
+    lib = A.lib()
+    n = C.c_int64()
+    rc = lib.tbsma_build_wire(a, D, L, n_grip, None, None, None, None, 0, C.byref(n))
+    if rc not in (A.OK, A.ECAPACITY):
+        A.check(rc)
+    x, y, z = (np.empty(n.value) for _ in range(3))
+    f = np.empty(n.value, dtype=np.uint8)
+    A.check(lib.tbsma_build_wire(a, D, L, n_grip, x.ctypes.data, y.ctypes.data,
+                                 z.ctypes.data, f.ctypes.data, n.value, C.byref(n)))
+    return x, y, z, f
+
+
+class WireBatch:
+    """R independent [100] Au nanowires advanced together on one GPU."""
+
+    def __init__(self, replicas: Sequence, precision: str = "mixed", *, skin: float = 1.0,
+                 cell: float = 8.0, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
+                 n_log: int = 100, n_slots: int = 64, strain_max: float = 0.5,
+                 lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
+                 device=None, wires=None, qbits: int | None = None):
+        self.replicas = list(replicas)
+        self.pot = pot or Potential()
+        self.precision = precision
+        self.skin, self.cell, self.k_cap = skin, cell, k_cap
+        self.gamma, self.dt, self.lab_frame = gamma, dt, lab_frame
+        self.n_log, self.n_slots = n_log, n_slots
+        self.a = a
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        R = len(self.replicas)
+        self.R = R
+        # --- host geometry and layout -------------------------------------------------
+        self.wires = wires if wires is not None else [
+            build_wire_host(a, rp.D, rp.L, rp.n_grip) for rp in self.replicas]
+        self.n_atoms = np.array([w[0].size for w in self.wires], dtype=np.int64)
+        pad = (self.n_atoms + A.TILE - 1) // A.TILE * A.TILE
+        self.rep_off = np.zeros(R + 1, dtype=np.int64)
+        self.rep_off[1:] = np.cumsum(pad)
+        N = int(self.rep_off[-1])
+        self.N = N
+        margin = cell
+        gdim = np.zeros((R, 3), dtype=np.int32)
+        glo = np.zeros((R, 3), dtype=np.float64)
+        for r, rp in enumerate(self.replicas):
+            gxy = int(math.ceil((rp.D + 2 * margin) / cell))
+            gz = int(math.ceil((rp.L * (1.0 + strain_max) + 2 * margin) / cell))
+            gdim[r] = (gxy, gxy, gz)
+            glo[r] = (-0.5 * gxy * cell, -0.5 * gxy * cell, -margin)
+        self.grid_dim, self.grid_lo = gdim, glo
+        ncell = gdim.prod(axis=1).astype(np.int64)
+        self.cell_off = np.zeros(R + 1, dtype=np.int64)
+        self.cell_off[1:] = np.cumsum(ncell)
+        self.C = int(self.cell_off[-1])
+        self.max_zbins = int(2 * gdim[:, 2].max())
+        half = float((gdim * cell).max()) / 2.0
+        self.qbits = int(qbits) if qbits is not None else int(
+            min(24, math.floor(31 - math.log2(1.1 * half + 16.0))))
+        # --- host arrays of the atoms -----------------------------------------------
+        xh = np.zeros(N)
+        yh = np.zeros(N)
+        zh = np.zeros(N)
+        fh = np.full(N, A.PAD, dtype=np.uint8)
+        z_lo = np.zeros(R)
+        z_hi = np.zeros(R)
+        dof = np.zeros(R, dtype=np.int32)
+        for r, (x, y, z, f) in enumerate(self.wires):
+            o = self.rep_off[r]
+            n = x.size
+            xh[o:o + n], yh[o:o + n], zh[o:o + n], fh[o:o + n] = x, y, z, f
+            z_lo[r] = z[f == A.GRIP_FIXED].max() if np.any(f == A.GRIP_FIXED) else z.min()
+            z_hi[r] = z[f == A.GRIP_PULL].min() if np.any(f == A.GRIP_PULL) else z.max()
+            dof[r] = max(0, 3 * int((f == A.DYN).sum()) - 3)
+        # pads sit at the replica's grid corner (never used)
+        self.z_lo, self.z_hi, self.dof = z_lo, z_hi, dof
+        r_hs = 0.5 * self.pot.r0
+        self.vol = self.n_atoms * (4.0 / 3.0) * math.pi * r_hs ** 3
+        self.L0 = np.array([rp.L for rp in self.replicas], dtype=np.float64)
+        tile_rep = np.repeat(np.arange(R, dtype=np.int32), pad // A.TILE)
+        # --- device buffers ------------------------------------------------------------
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        ft = torch.float32 if precision == "mixed" else torch.float64
+        self.t = {}
+        T = self.t
+        T["rep_off"] = torch.tensor(self.rep_off, device=dev)
+        T["cell_off"] = torch.tensor(self.cell_off, device=dev)
+        T["tile_rep"] = torch.tensor(tile_rep, device=dev)
+        T["grid_dim"] = torch.tensor(gdim.reshape(-1), device=dev)
+        T["grid_lo"] = torch.tensor(glo.reshape(-1), device=dev)
+        T["rep_id"] = torch.tensor([rp.rep_id for rp in self.replicas], dtype=torch.int32,
+                                   device=dev)
+        T["x"] = torch.tensor(xh, **f64)
+        T["y"] = torch.tensor(yh, **f64)
+        T["z"] = torch.tensor(zh, **f64)
+        for k in ("vx", "vy", "vz", "z0", "x_ref", "y_ref", "z_ref"):
+            T[k] = torch.zeros(N, **f64)
+        T["flag"] = torch.tensor(fh, device=dev)
+        T["qpos"] = torch.zeros(4 * N, dtype=torch.int32, device=dev)
+        T["cell_start"] = torch.zeros(self.C + R, dtype=torch.int32, device=dev)
+        T["cell_atoms"] = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
+        T["nl"] = torch.zeros(k_cap * N, dtype=torch.int32, device=dev)
+        T["nn"] = torch.zeros(N, dtype=torch.int32, device=dev)
+        for k in ("fx", "fy", "fz", "e_atom"):
+            T[k] = torch.zeros(N, dtype=ft, device=dev)
+        T["g"] = torch.zeros(N, **f64)
+        T["rep_energy"] = torch.zeros(R, **f64)
+        T["rep_wzz"] = torch.zeros(R, **f64)
+        T["T"] = torch.tensor([rp.T for rp in self.replicas], **f64)
+        T["v_pull"] = torch.tensor([rp.v_pull for rp in self.replicas], **f64)
+        T["z_lo"] = torch.tensor(z_lo, **f64)
+        T["z_hi"] = torch.tensor(z_hi, **f64)
+        T["vol"] = torch.tensor(self.vol, **f64)
+        T["L0"] = torch.tensor(self.L0, **f64)
+        seeds = np.array([rp.seed for rp in self.replicas], dtype=np.uint64).view(np.int64)
+        T["seed"] = torch.tensor(seeds, device=dev)
+        T["dof"] = torch.tensor(dof, device=dev)
+        T["step"] = torch.zeros(1, dtype=torch.int64, device=dev)
+        T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
+        T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
+        # --- ABI structs -------------------------------------------------------------------
+        self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
+                               self.pot.r_tail, self.pot.r_cut, skin, cell, MASS_AU,
+                               A.MIXED if precision == "mixed" else A.FP64, self.qbits)
+        self._rep_off_h = (C.c_int64 * (R + 1))(*self.rep_off.tolist())
+        self._cell_off_h = (C.c_int64 * (R + 1))(*self.cell_off.tolist())
+        self.sys = A.System(R, self.max_zbins, N, self.C,
+                            C.cast(self._rep_off_h, C.c_void_p),
+                            C.cast(self._cell_off_h, C.c_void_p),
+                            *[_ptr(T[k]) for k in ("rep_off", "cell_off", "tile_rep", "grid_dim",
+                                                   "grid_lo", "rep_id", "x", "y", "z", "vx",
+                                                   "vy", "vz", "z0", "flag")],
+                            _ptr(T["qpos"]) if precision == "mixed" else None)
+        self.cells = A.Cells(_ptr(T["cell_start"]), _ptr(T["cell_atoms"]))
+        self.nlist = A.NList(_ptr(T["nl"]), _ptr(T["nn"]), k_cap, 0, _ptr(T["x_ref"]),
+                             _ptr(T["y_ref"]), _ptr(T["z_ref"]))
+        self.out = A.ForcesOut(_ptr(T["fx"]), _ptr(T["fy"]), _ptr(T["fz"]), _ptr(T["e_atom"]),
+                               _ptr(T["g"]) if precision == "fp64" else None,
+                               _ptr(T["rep_energy"]), _ptr(T["rep_wzz"]))
+        self.md = A.MD(dt, gamma, lab_frame, n_log, n_slots, 0,
+                       *[_ptr(T[k]) for k in ("T", "v_pull", "z_lo", "z_hi", "vol", "L0", "seed",
+                                              "dof", "step", "obs", "status")])
+        nb = C.c_size_t()
+        A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
+                                              C.byref(nb)))
+        T["work"] = torch.zeros(int(nb.value), dtype=torch.uint8, device=dev)
+        self.work = _ptr(T["work"])
+        A.check(A.lib().tbsma_workspace_init(C.byref(self.params), C.byref(self.sys), self.work,
+                                             self.stream()))
+
+    # ------------------------------------------------------------------------------------
+    def stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def init_state(self, jitter: float | None = None):
+        """Jitter + Maxwell-Boltzmann velocities (tbsma_init_state)."""
+        if jitter is None:
+            js = {rp.jitter for rp in self.replicas}
+            if len(js) != 1:
+                raise ValueError("replicas disagree on the jitter amplitude")
+            jitter = js.pop()
+        A.check(A.lib().tbsma_init_state(C.byref(self.params), C.byref(self.sys),
+                                         C.byref(self.md), self.work, float(jitter),
+                                         self.stream()))
+
+    def build_lists(self):
+        """Cells and Verlet lists of every replica; grows k_cap on overflow."""
+        lib = A.lib()
+        A.check(lib.tbsma_build_cells(C.byref(self.params), C.byref(self.sys),
+                                      C.byref(self.cells), self.work, self.stream()))
+        need = C.c_int32()
+        rc = lib.tbsma_neighbors(C.byref(self.params), C.byref(self.sys), C.byref(self.cells),
+                                 C.byref(self.nlist), self.work, C.byref(need), self.stream())
+        if rc == A.ECAPACITY:
+            self.resize_nlist(int(need.value * 1.15) + 8)
+            return self.build_lists()
+        A.check(rc)
+
+    def resize_nlist(self, k_cap: int):
+        self.k_cap = k_cap
+        self.t["nl"] = torch.zeros(k_cap * self.N, dtype=torch.int32, device=self.device)
+        self.nlist.nl = _ptr(self.t["nl"])
+        self.nlist.k_cap = k_cap
+
+    def compute_forces(self):
+        A.check(A.lib().tbsma_forces(C.byref(self.params), C.byref(self.sys),
+                                     C.byref(self.nlist), C.byref(self.out), self.work,
+                                     self.stream()))
+
+    def prepare(self, jitter: float | None = None):
+        """Initial state, lists and forces: ready for step / run_batch."""
+        self.init_state(jitter)
+        self.build_lists()
+        self.compute_forces()
+
+    def step(self, n: int):
+        """n plain steps (one launch per kernel per step)."""
+        A.check(A.lib().tbsma_step(C.byref(self.params), C.byref(self.sys), C.byref(self.cells),
+                                   C.byref(self.nlist), C.byref(self.out), C.byref(self.md),
+                                   self.work, int(n), self.stream()))
+
+    def run_batch(self, n: int, steps_per_graph: int = 50):
+        """n steps replayed from a captured HIP graph.  The legacy default
+        stream cannot be captured, so the call then runs on a side stream
+        ordered after, and before, the caller's stream."""
+        cur = torch.cuda.current_stream(self.device)
+        side = None
+        if cur.cuda_stream == 0:
+            if not hasattr(self, "_side"):
+                self._side = torch.cuda.Stream(self.device)
+            side = self._side
+            side.wait_stream(cur)
+        s = C.c_void_p(side.cuda_stream) if side is not None else self.stream()
+        try:
+            A.check(A.lib().tbsma_run_batch(C.byref(self.params), C.byref(self.sys),
+                                            C.byref(self.cells), C.byref(self.nlist),
+                                            C.byref(self.out), C.byref(self.md), self.work,
+                                            int(n), int(steps_per_graph), s))
+        finally:
+            if side is not None:
+                cur.wait_stream(side)
+
+    # ------------------------------------------------------------------------------------
+    def _slice(self, key, r):
+        o = int(self.rep_off[r])
+        return self.t[key][o:o + int(self.n_atoms[r])].detach().cpu().numpy()
+
+    def positions(self, r: int):
+        return tuple(self._slice(k, r).astype(np.float64) for k in ("x", "y", "z"))
+
+    def velocities(self, r: int):
+        return tuple(self._slice(k, r).astype(np.float64) for k in ("vx", "vy", "vz"))
+
+    def forces(self, r: int):
+        return tuple(self._slice(k, r).astype(np.float64) for k in ("fx", "fy", "fz"))
+
+    def energies(self, r: int):
+        return self._slice("e_atom", r).astype(np.float64)
+
+    def flags(self, r: int):
+        return self._slice("flag", r)
+
+    def neighbor_rows(self, r: int):
+        """List of neighbour slot arrays (replica-local indices) of replica r."""
+        nn = self.t["nn"].cpu().numpy()
+        nl = self.t["nl"].view(self.k_cap, self.N).cpu().numpy()
+        o = int(self.rep_off[r])
+        return [np.sort(nl[:nn[o + i], o + i]) - o for i in range(int(self.n_atoms[r]))]
+
+    def status(self):
+        return self.t["status"].cpu().numpy().view(np.uint32)
+
+    def step_index(self) -> int:
+        return int(self.t["step"].item())
+
+    def obs(self):
+        """Observable ring buffer as [n_slots, R, NOBS]."""
+        return self.t["obs"].view(self.n_slots, self.R, A.NOBS).cpu().numpy()
+
+    def obs_at(self, step: int):
+        slot = (step // self.n_log) % self.n_slots
+        return self.obs()[slot]
+
+    def mean_neighbors(self) -> float:
+        nn = self.t["nn"].double()
+        return float(nn.sum().item() / max(1, int(self.n_atoms.sum())))

@@ -1,0 +1,95 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and its host-side wire builder and argument checks behave (no device
+work is started here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1311_3890_amd import _abi as A
+from paper_1311_3890_amd.engine import build_wire_host
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tbsma.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tbsma_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for n in ("tbsma_build_cells", "tbsma_neighbors", "tbsma_forces", "tbsma_step",
+              "tbsma_run_batch"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(A.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    assert set(declared_functions()) == set(A.SIGNATURES)
+
+
+@pytest.mark.parametrize("D,L", [(15.0, 30.6), (30.0, 200.0), (20.0, 12.24), (25.0, 100.0)])
+def test_host_wire_builder_equals_oracle(D, L):
+    x, y, z, f = build_wire_host(4.08, D, L, 2)
+    xo, yo, zo, fo = oracle.build_wire(4.08, D, L, 2)
+    assert x.size == xo.size
+    assert np.array_equal(x, xo) and np.array_equal(y, yo) and np.array_equal(z, zo)
+    assert np.array_equal(f, fo)
+
+
+def test_wire_builder_capacity_and_errors():
+    lib = A.lib()
+    n = C.c_int64()
+    assert lib.tbsma_build_wire(4.08, 15.0, 30.0, 2, None, None, None, None, 0,
+                                C.byref(n)) == A.ECAPACITY
+    assert n.value == 336
+    assert lib.tbsma_build_wire(-1.0, 15.0, 30.0, 2, None, None, None, None, 0,
+                                C.byref(n)) == A.EINVAL
+    assert b"bad wire" in lib.tbsma_last_error()
+    # empty wire
+    assert lib.tbsma_build_wire(4.08, 15.0, 0.0, 2, None, None, None, None, 0,
+                                C.byref(n)) == A.OK
+    assert n.value == 0
+
+
+def _params(**kw):
+    p = A.Params(0.2061, 1.790, 10.229, 4.036, 2.884, 6.5, 7.0, 1.0, 8.0, 196.96657, A.MIXED, 21)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(cell=7.5), b"cell edge"),
+    (dict(r_tail=7.5), b"r_tail"),
+    (dict(qbits=30), b"qbits"),
+    (dict(precision=7), b"precision"),
+    (dict(cell=20.0), b"cell/2"),
+])
+def test_parameter_checks(kw, msg):
+    sysm = A.System()
+    sysm.R = 0
+    nb = C.c_size_t()
+    rc = A.lib().tbsma_workspace_query(C.byref(_params(**kw)), C.byref(sysm), C.byref(nb))
+    assert rc == A.EINVAL
+    assert msg in A.lib().tbsma_last_error()
+
+
+def test_layout_checks():
+    """Offsets that are not multiples of 64 or do not end at N are refused."""
+    rep = (C.c_int64 * 2)(0, 100)
+    cel = (C.c_int64 * 2)(0, 10)
+    s = A.System(1, 4, 100, 10, C.cast(rep, C.c_void_p), C.cast(cel, C.c_void_p))
+    nb = C.c_size_t()
+    assert A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s), C.byref(nb)) == A.EINVAL
+    rep2 = (C.c_int64 * 2)(0, 128)
+    s2 = A.System(1, 4, 128, 10, C.cast(rep2, C.c_void_p), C.cast(cel, C.c_void_p))
+    assert A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s2), C.byref(nb)) == A.EINVAL
+    assert b"NULL" in A.lib().tbsma_last_error()

@@ -1,0 +1,429 @@
+"""GPU parity of libtbsma against the FP64 oracle (run on an MI355X).
+
+Every comparison feeds the oracle the same seeded inputs, or the positions the
+GPU reached, and compares element by element:
+  * random numbers: Philox words bit-exact, Box-Muller normals to 1e-14;
+  * Verlet lists: exact set equality with brute force (r < r_cut + skin);
+  * forces: FP64 mode eps_F <= 1e-12, mixed mode eps_F <= 1e-5, where
+    eps_F = max_i |F_i - F_i^ref| / max_i |F_i^ref|; energies alike;
+  * dynamics: FP64 lockstep with the oracle integrator; batched == alone and
+    graph == eager bit for bit.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_1311_3890_amd import _abi as A
+from paper_1311_3890_amd.engine import WireBatch
+
+pytestmark = pytest.mark.gpu
+AU = oracle.Pot()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def eps_F(F, Fr):
+    F, Fr = np.asarray(F), np.asarray(Fr)
+    return np.sqrt(((F - Fr) ** 2).sum(1)).max() / np.sqrt((Fr ** 2).sum(1)).max()
+
+
+def stackF(t):
+    return np.stack(t, 1)
+
+
+def orc_state(b: WireBatch, r: int):
+    x, y, z = b.positions(r)
+    st = oracle.State(x, y, z, b.flags(r))
+    st.vx, st.vy, st.vz = b.velocities(r)
+    o = int(b.rep_off[r])
+    n = int(b.n_atoms[r])
+    st.z0 = b.t["z0"][o:o + n].cpu().numpy().copy()
+    st.step = b.step_index()
+    return st
+
+
+def orc_md(b: WireBatch, r: int):
+    rp = b.replicas[r]
+    return oracle.MD(dt=b.dt, gamma=b.gamma, T=rp.T, v_pull=rp.v_pull, z_lo=b.z_lo[r],
+                     z_hi=b.z_hi[r], seed=rp.seed, rep_id=rp.rep_id, lab_frame=b.lab_frame)
+
+
+def R(D, L, T=10.0, v=0.5, r=0, jitter=0.0):
+    return W.Replica(D, W.snap_length(L), T, v, W.seed_of(r), r, jitter=jitter)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+def test_rng_words_and_normals():
+    n = 2048
+    for seed, rep, step, strm in [(0, 0, 0, 0), (W.seed_of(7), 7, 123456789, 0),
+                                  (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 40 + 5, 2)]:
+        note(f"rng seed={seed} rep={rep} step={step} stream={strm}")
+        w = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+        g = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+        A.check(A.lib().tbsma_rng_fill(seed, rep, step, strm, n, C.c_void_p(w.data_ptr()),
+                                       C.c_void_p(g.data_ptr()), None))
+        torch.cuda.synchronize()
+        wh = w.cpu().numpy().view(np.uint32).reshape(n, 4)
+        gh = g.cpu().numpy().reshape(n, 3)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        for t in range(0, n, 7):
+            ref = oracle.philox4x32_10([t, step & 0xFFFFFFFF, rep, strm], key)
+            assert np.array_equal(wh[t], ref), t
+            assert np.abs(gh[t] - oracle.gauss3(seed, rep, t, step, strm)).max() < 1e-14
+
+
+def brute_sets(x, y, z, rl):
+    P = np.stack([x, y, z], 1)
+    out = []
+    for i in range(P.shape[0]):
+        d2 = ((P - P[i]) ** 2).sum(1)
+        d2[i] = np.inf
+        out.append(np.nonzero(d2 < rl * rl)[0])
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_neighbor_lists_are_exact_sets(precision):
+    reps = [R(15.0, 30.0, r=0, jitter=0.1), R(20.0, 20.0, T=298.0, r=1, jitter=0.1),
+            R(30.0, 40.0, r=2, jitter=0.1)]
+    note(f"nlist sets {precision} R={len(reps)}")
+    b = WireBatch(reps, precision)
+    b.prepare()
+    torch.cuda.synchronize()
+    for r in range(b.R):
+        x, y, z = b.positions(r)
+        ref = brute_sets(x, y, z, b.pot.r_cut + b.skin)
+        got = b.neighbor_rows(r)
+        for i in range(len(ref)):
+            assert np.array_equal(got[i], ref[i]), (r, i)
+    # rows are stored in ascending cell-scan order: check determinism
+    b2 = WireBatch(reps, precision)
+    b2.prepare()
+    torch.cuda.synchronize()
+    assert torch.equal(b.t["nl"], b2.t["nl"]) and torch.equal(b.t["nn"], b2.t["nn"])
+
+
+def test_forces_fp64_config1():
+    wl = W.cfg1_plain_fp64()
+    rp = wl.replicas[0]
+    rp.jitter = 0.02
+    note("forces fp64 cfg1")
+    b = WireBatch([rp], "fp64")
+    b.prepare()
+    torch.cuda.synchronize()
+    x, y, z = b.positions(0)
+    ref = oracle.forces(AU, x, y, z, 0)
+    F = stackF(b.forces(0))
+    Fr = stackF((ref["fx"], ref["fy"], ref["fz"]))
+    assert eps_F(F, Fr) <= 1e-12
+    assert np.abs(b.energies(0) - ref["e_atom"]).max() <= 1e-12
+    assert abs(b.t["rep_energy"][0].item() - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert abs(b.t["rep_wzz"][0].item() + ref["w6"][2]) <= 1e-10 * max(1.0, abs(ref["w6"][2]))
+
+
+def test_forces_mixed_single_wire():
+    rp = W.cfg2_single_mixed().replicas[0]
+    note(f"forces mixed cfg2 D={rp.D} L={rp.L}")
+    b = WireBatch([rp], "mixed")
+    b.prepare()
+    torch.cuda.synchronize()
+    x, y, z = b.positions(0)
+    ref = oracle.forces(AU, x, y, z, 1)
+    F = stackF(b.forces(0))
+    Fr = stackF((ref["fx"], ref["fy"], ref["fz"]))
+    e = eps_F(F, Fr)
+    note(f"  eps_F = {e:.3e}  max|F| = {np.abs(Fr).max():.3f}")
+    assert e <= 1e-5
+    E = b.t["rep_energy"][0].item()
+    assert abs(E - ref["E"]) <= 1e-6 * abs(ref["E"])
+    assert np.abs(b.energies(0) - ref["e_atom"]).max() <= 2e-5
+    wz = b.t["rep_wzz"][0].item()
+    assert abs(wz + ref["w6"][2]) <= 1e-4 * max(1.0, abs(ref["w6"][2]))
+
+
+def test_forces_mixed_ragged_batch():
+    reps = [R(15.0, 12.0, r=0, jitter=0.02), R(30.0, 60.0, T=298.0, r=1, jitter=0.02),
+            R(20.0, 33.0, r=2, jitter=0.02), R(25.0, 8.2, r=3, jitter=0.02)]
+    note("forces mixed ragged batch")
+    b = WireBatch(reps, "mixed")
+    b.prepare()
+    torch.cuda.synchronize()
+    assert np.any(b.n_atoms % 64 != 0)
+    for r in range(b.R):
+        x, y, z = b.positions(r)
+        ref = oracle.forces(AU, x, y, z, 0)
+        F = stackF(b.forces(r))
+        assert eps_F(F, stackF((ref["fx"], ref["fy"], ref["fz"]))) <= 1e-5, r
+        assert abs(b.t["rep_energy"][r].item() - ref["E"]) <= 1e-6 * abs(ref["E"])
+    # padding slots carry no force or energy
+    for r in range(b.R):
+        o, n, e = int(b.rep_off[r]), int(b.n_atoms[r]), int(b.rep_off[r + 1])
+        assert torch.all(b.t["fx"][o + n:e] == 0) and torch.all(b.t["e_atom"][o + n:e] == 0)
+
+
+def test_init_state_matches_oracle():
+    rp = R(20.0, 30.0, T=298.0, v=0.5, r=5, jitter=0.02)
+    note("init state fp64")
+    b = WireBatch([rp], "fp64")
+    b.init_state()
+    torch.cuda.synchronize()
+    x0, y0, z0, f = oracle.build_wire(4.08, rp.D, rp.L, 2)
+    st = oracle.State(x0, y0, z0, f)
+    md = orc_md(b, 0)
+    oracle.init_state(md, st, rp.jitter)
+    x, y, z = b.positions(0)
+    assert max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max()) < 1e-14
+    v = stackF(b.velocities(0))
+    vr = stackF((st.vx, st.vy, st.vz))
+    assert np.abs(v - vr).max() < 1e-12 * np.abs(vr).max()
+    o = oracle.observe(AU, md, st, 1.0, rp.L)
+    assert abs(o[2] - 298.0) < 1e-8
+
+
+def test_step_fp64_lockstep_with_oracle():
+    wl = W.cfg1_plain_fp64()
+    rp = wl.replicas[0]
+    note("fp64 lockstep 20 steps")
+    b = WireBatch([rp], "fp64", n_log=10)
+    b.prepare()
+    torch.cuda.synchronize()
+    st = orc_state(b, 0)
+    oracle.compute_forces(AU, st, 0)
+    md = orc_md(b, 0)
+    for k in range(4):
+        b.step(5)
+        oracle.run(AU, md, st, 5, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        v = stackF(b.velocities(0))
+        dv = np.abs(v - stackF((st.vx, st.vy, st.vz))).max()
+        note(f"  after {5 * (k + 1)} steps: |dx| {dx:.2e}  |dv| {dv:.2e}")
+        assert dx < 1e-11 and dv < 1e-9
+    assert b.step_index() == 20
+    ob = b.obs_at(20)[0]
+    orf = oracle.observe(AU, md, st, b.vol[0], b.L0[0])
+    assert ob[A.OBS_STEP] == 20
+    for k_gpu, k_or in ((A.OBS_EPOT, 0), (A.OBS_KE, 1), (A.OBS_T, 2), (A.OBS_WZZ, 3),
+                        (A.OBS_SZZ, 4), (A.OBS_STRAIN, 5), (A.OBS_D, 7)):
+        assert abs(ob[k_gpu] - orf[k_or]) <= 1e-9 * max(1.0, abs(orf[k_or])), (k_gpu, ob, orf)
+
+
+def test_config1_end_to_end_forces_every_step():
+    """Config 1: 1000 FP64 steps at 10 K with the top grip pulled at 0.5 A/ps;
+    forces and energies checked against the oracle at every step."""
+    wl = W.cfg1_plain_fp64()
+    note("cfg1 end-to-end 1000 steps fp64")
+    b = WireBatch(wl.replicas, "fp64", n_log=100)
+    b.prepare()
+    worst = 0.0
+    for s in range(wl.steps):
+        b.step(1)
+        x, y, z = b.positions(0)
+        ref = oracle.forces(AU, x, y, z, 0)
+        e = eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"])))
+        worst = max(worst, e)
+        assert e <= 1e-12, s
+        if (s + 1) % 100 == 0:
+            assert np.abs(b.energies(0) - ref["e_atom"]).max() <= 1e-12
+            note(f"  step {s + 1}: worst eps_F {worst:.2e}")
+    assert b.step_index() == 1000
+    ob = b.obs_at(1000)[0]
+    assert abs(ob[A.OBS_D] - 0.5 * 1000 * 0.002) < 1e-12
+    assert abs(ob[A.OBS_STRAIN] - 1.0 / b.L0[0]) < 1e-12
+    assert b.status()[0] & (A.ST_NONFINITE | A.ST_OVERFLOW) == 0
+
+
+def _three_replicas():
+    return [R(15.0, 24.0, T=298.0, v=0.5, r=0), R(20.0, 40.0, T=10.0, v=1.0, r=1),
+            R(30.0, 16.0, T=298.0, v=0.1, r=2)]
+
+
+def test_batched_equals_one_replica_at_a_time_bitwise():
+    reps = _three_replicas()
+    note("batched vs alone, 120 steps mixed")
+    b = WireBatch(reps, "mixed", n_log=40)
+    b.prepare()
+    b.run_batch(120, steps_per_graph=40)
+    for r, rp in enumerate(reps):
+        s = WireBatch([rp], "mixed", n_log=40, qbits=b.qbits)
+        s.prepare()
+        s.step(120)
+        for a_, b_ in zip(b.positions(r) + b.velocities(r), s.positions(0) + s.velocities(0)):
+            assert np.array_equal(a_, b_), r
+        assert np.array_equal(b.obs_at(120)[r], s.obs_at(120)[0])
+
+
+def test_graph_replay_equals_eager_bitwise():
+    reps = _three_replicas()
+    note("graph vs eager, 100 steps")
+    g = WireBatch(reps, "mixed", n_log=25)
+    g.prepare()
+    g.run_batch(100, steps_per_graph=30)  # 3 replays + 10 eager steps
+    e = WireBatch(reps, "mixed", n_log=25)
+    e.prepare()
+    e.step(100)
+    assert torch.equal(g.t["x"], e.t["x"]) and torch.equal(g.t["vz"], e.t["vz"])
+    assert torch.equal(g.t["obs"], e.t["obs"])
+    assert g.step_index() == e.step_index() == 100
+
+
+def test_mixed_dynamics_track_fp64_oracle_forces():
+    """Mixed precision over 200 steps at 298 K: the forces at the GPU's
+    positions stay within eps_F <= 1e-5 of the oracle and lists get rebuilt."""
+    rp = R(30.0, 40.0, T=298.0, v=0.5, r=9, jitter=0.02)
+    note("mixed 298K 200 steps with rebuilds")
+    b = WireBatch([rp], "mixed", n_log=50)
+    b.prepare()
+    for k in range(4):
+        b.run_batch(50, 25)
+        x, y, z = b.positions(0)
+        ref = oracle.forces(AU, x, y, z, 1)
+        assert eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"]))) <= 1e-5
+    assert b.status()[0] & A.ST_REBUILT
+    T = b.obs()[:, 0, A.OBS_T]
+    assert np.all(np.isfinite(T))
+
+
+def test_neighbor_overflow_is_reported_and_regrown():
+    rp = R(30.0, 30.0, r=1, jitter=0.02)
+    note("nlist overflow k_cap=40")
+    b = WireBatch([rp], "mixed", k_cap=40)
+    b.init_state()
+    lib = A.lib()
+    A.check(lib.tbsma_build_cells(C.byref(b.params), C.byref(b.sys), C.byref(b.cells), b.work,
+                                  b.stream()))
+    need = C.c_int32()
+    rc = lib.tbsma_neighbors(C.byref(b.params), C.byref(b.sys), C.byref(b.cells),
+                             C.byref(b.nlist), b.work, C.byref(need), b.stream())
+    assert rc == A.ECAPACITY
+    x, y, z = b.positions(0)
+    cnt = oracle.count_pairs(x, y, z, b.pot.r_cut + b.skin)
+    assert need.value == cnt.max()
+    b.build_lists()
+    assert b.k_cap >= cnt.max()
+    b.compute_forces()
+    torch.cuda.synchronize()
+    ref = oracle.forces(AU, x, y, z, 0)
+    assert eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"]))) <= 1e-5
+
+
+def test_degenerate_systems():
+    note("degenerate: single atom, dimer, empty batch")
+    # a single atom: no neighbours, zero density, zero force and energy
+    one = W.Replica(1.0, 2.04, 10.0, 0.0, 1, 0, n_grip=0)
+    b = WireBatch([one], "fp64")
+    assert b.n_atoms[0] == 1
+    b.prepare()
+    torch.cuda.synchronize()
+    assert b.t["fx"][0].item() == 0.0 and b.t["e_atom"][0].item() == 0.0
+    # a dimer at r0 along z: E = 2 (A - xi)
+    dim = W.Replica(1.0, 4.08 * 0.7068, 10.0, 0.0, 1, 0, n_grip=0)
+    x = np.zeros(2)
+    y = np.zeros(2)
+    z = np.array([0.0, 2.884])
+    f = np.zeros(2, dtype=np.uint8)
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        b2 = WireBatch([dim], prec, wires=[(x, y, z, f)], gamma=0.0)
+        b2.prepare(jitter=0.0)
+        torch.cuda.synchronize()
+        assert abs(b2.t["rep_energy"][0].item() - 2 * (AU.A - AU.xi)) < tol * 4
+    # an empty system is a no-op
+    s = A.System()
+    s.R = 0
+    out = A.ForcesOut()
+    nl = A.NList()
+    assert A.lib().tbsma_forces(C.byref(b.params), C.byref(s), C.byref(b.nlist),
+                                C.byref(b.out), b.work, None) == A.OK
+
+
+def test_rupture_gap_and_nonfinite_status():
+    reps = [R(15.0, 40.0, r=0), R(15.0, 40.0, r=1)]
+    note("rupture gap + NaN status")
+    b = WireBatch(reps, "fp64", n_log=1, gamma=0.0)
+    b.prepare()
+    # cut replica 0 in two: move its upper half up by 9 A
+    o, n = int(b.rep_off[0]), int(b.n_atoms[0])
+    zz = b.t["z"][o:o + n]
+    up = zz > 20.0
+    zz[up] += 9.0
+    b.t["z0"][o:o + n][up] += 9.0
+    # poison one velocity of replica 1
+    b.t["vx"][int(b.rep_off[1]) + 100] = float("nan")
+    b.compute_forces()
+    b.step(1)
+    st = b.status()
+    ob = b.obs_at(1)
+    x, y, z = b.positions(0)
+    zs = np.sort(z)
+    gap = np.diff(zs).max()
+    assert gap >= 9.0
+    assert ob[0, A.OBS_GAP] == gap
+    assert st[0] & A.ST_RUPTURED and not st[0] & A.ST_NONFINITE
+    assert st[1] & A.ST_NONFINITE and not st[1] & A.ST_RUPTURED
+
+
+def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1):
+    worst = 0.0
+    for r in reps_to_check:
+        x, y, z = b.positions(r)
+        ref = oracle.forces(AU, x, y, z, mode)
+        e = eps_F(stackF(b.forces(r)), stackF((ref["fx"], ref["fy"], ref["fz"])))
+        worst = max(worst, e)
+        assert e <= tol, r
+    return worst
+
+
+def test_full_size_config3_sampled():
+    """Config 3 at full size (512 replicas) in the benchmark's launch shape:
+    graph-replayed steps, then sampled replicas against the oracle."""
+    wl = W.cfg3_batched()
+    note(f"cfg3 full size R={len(wl.replicas)}")
+    b = WireBatch(wl.replicas, "mixed", n_log=50)
+    b.prepare()
+    b.run_batch(100, 50)
+    torch.cuda.synchronize()
+    st = b.status()
+    assert not np.any(st & (A.ST_NONFINITE | A.ST_OVERFLOW))
+    idx = [0, 1, 77, 200, 311, 450, 510, 511]
+    worst = _sampled_parity(b, idx)
+    note(f"  worst eps_F over {len(idx)} replicas: {worst:.2e}")
+    T = b.obs_at(100)[:, A.OBS_T]
+    assert np.all(np.abs(T - 298.0) < 60.0)
+
+
+def test_full_size_config5_sampled():
+    wl = W.cfg5_large()
+    note("cfg5 full size D10 x L100 nm")
+    b = WireBatch(wl.replicas, "mixed", n_log=50, strain_max=0.1)
+    b.prepare()
+    b.run_batch(50, 25)
+    torch.cuda.synchronize()
+    assert not b.status()[0] & (A.ST_NONFINITE | A.ST_OVERFLOW)
+    worst = _sampled_parity(b, [0])
+    note(f"  eps_F {worst:.2e}")
+
+
+def test_config4_mixed_shapes_sampled():
+    wl = W.cfg4_mixed_shapes()
+    note(f"cfg4 R={len(wl.replicas)}")
+    b = WireBatch(wl.replicas, "mixed", n_log=20)
+    b.prepare()
+    b.run_batch(40, 20)
+    torch.cuda.synchronize()
+    assert not np.any(b.status() & (A.ST_NONFINITE | A.ST_OVERFLOW))
+    _sampled_parity(b, [0, 1, 2, 3, 1001, 2047], mode=1)
