@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-replica", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -109,11 +111,26 @@ def main():
 
     t_dens = time_pass(1)
     t_force = time_pass(2)
-    bytes_force = n_real * (4.0 * kbar + 36.0)
-    bytes_dens = n_real * (4.0 * kbar + 24.0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {src.numel() * 8} bytes read and written")
+        del src, dst
+    # bytes each kernel must move per launch (per real atom):
+    #  density: nn 4 + Verlet row 4 kbar + own position 16 + g 4 + active
+    #           counts 8 + active list written 4 kact
+    #  force:   active counts 8 + active list 4 kact + own position and g 16
+    #           + force 12 + energy 4
+    # (neighbour positions are gathered from cache, counted once per atom in
+    # the own-position term)
+    kact = b.mean_active_pairs()
+    bytes_force = n_real * (4.0 * kact + 40.0)
+    bytes_dens = n_real * (4.0 * kbar + 4.0 * kact + 32.0)
     gbs_force = bytes_force / (t_force * 1e-3) / 1e9
     gbs_dens = bytes_dens / (t_dens * 1e-3) / 1e9
-    log(f"[bench] mean listed neighbours {kbar:.2f}; density {t_dens * 1e3:.1f} us "
+    log(f"[bench] mean listed neighbours {kbar:.2f}, active pairs {kact:.2f}; density {t_dens * 1e3:.1f} us "
         f"({gbs_dens:.0f} GB/s), force {t_force * 1e3:.1f} us ({gbs_force:.0f} GB/s)")
 
     # ---- plain path: the same kind of replicas, one replica per launch ----------------
@@ -195,7 +212,8 @@ def main():
                      "kernel": "k_force_mixed",
                      "algorithmic_bytes_per_launch": bytes_force,
                      "avg_launch_us": t_force * 1e3,
-                     "mean_listed_neighbours": kbar},
+                     "mean_listed_neighbours": kbar,
+                     "mean_active_pairs": kact},
         "kernels": {"density": {"avg_launch_us": t_dens * 1e3, "GB/s": gbs_dens,
                                 "frac": gbs_dens / HBM_PEAK_GBS}},
         "per_replica_value": pr,

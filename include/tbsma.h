@@ -170,9 +170,17 @@ typedef struct {
 } tbsma_cells;
 
 /*
- * Verlet lists (full: both i->j and j->i).  Column-major: entry k of atom i
- * is nl[k*N + i], k < nn[i] <= k_cap, ascending by (cell scan order, slot).
+ * Verlet lists (full: both i->j and j->i), stored in chunks of 8 entries:
+ * entry k of atom i is nl[((k/8)*N + i)*8 + k%8], k < nn[i] <= k_cap, in
+ * cell-scan order (cells by z, y, x; slots ascending within a cell).
+ * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.
+ * act, nact (MIXED only; NULL for FP64): device [(k_cap+16)*N] and [2N]
+ * int32, rewritten by every density pass: the pairs of the Verlet list with
+ * 0 < r <= r_cut at the current positions, in list order, in the same chunked
+ * layout with C = k_cap/8 + 2 chunks per atom: the nact[2i] pairs with
+ * r <= r_tail are entries k of chunks 0, 1, ... (chunk k/8); the nact[2i+1]
+ * tail pairs are entries k of chunks C-1, C-2, ... (chunk C-1-k/8).
  */
 typedef struct {
   int32_t *nl;
@@ -180,6 +188,8 @@ typedef struct {
   int32_t k_cap;
   int32_t reserved;
   double *x_ref, *y_ref, *z_ref;
+  int32_t *act;
+  int32_t *nact;
 } tbsma_nlist;
 
 /*

@@ -105,6 +105,8 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
     return fail(TBSMA_EINVAL, "a device array of the system is NULL");
   if (p && p->precision == TBSMA_MIXED && !s->qpos)
     return fail(TBSMA_EINVAL, "mixed precision needs qpos");
+  if (p && p->precision == TBSMA_MIXED && s->N >= (int64_t)1 << 28)
+    return fail(TBSMA_EINVAL, "mixed precision needs N < 2^28");
   return TBSMA_OK;
 }
 
@@ -196,6 +198,8 @@ void attach_lists(Dev &d, const tbsma_cells *c, const tbsma_nlist *n) {
     d.xr = n->x_ref;
     d.yr = n->y_ref;
     d.zr = n->z_ref;
+    d.act = n->act;
+    d.nact = n->nact;
   }
 }
 
@@ -321,12 +325,16 @@ int check_out(const tbsma_params *p, const tbsma_forces_out *o) {
   return TBSMA_OK;
 }
 
-int check_lists(const tbsma_cells *c, const tbsma_nlist *n) {
+int check_lists(const tbsma_params *p, const tbsma_cells *c,
+                const tbsma_nlist *n) {
   if (c && (!c->cell_start || !c->cell_atoms))
     return fail(TBSMA_EINVAL, "cell arrays missing");
   if (n && (!n->nl || !n->nn || !n->x_ref || !n->y_ref || !n->z_ref ||
-            n->k_cap < 1))
-    return fail(TBSMA_EINVAL, "neighbour-list arrays missing");
+            n->k_cap < 8 || n->k_cap % 8))
+    return fail(TBSMA_EINVAL,
+                "neighbour-list arrays missing or k_cap not a multiple of 8");
+  if (n && p->precision == TBSMA_MIXED && (!n->act || !n->nact))
+    return fail(TBSMA_EINVAL, "mixed precision needs the active-pair list");
   return TBSMA_OK;
 }
 
@@ -469,7 +477,7 @@ int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
                       tbsma_cells *cells, void *work, void *stream) {
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
-  TRY(check_lists(cells, nullptr));
+  TRY(check_lists(prm, cells, nullptr));
   if (!cells) return fail(TBSMA_EINVAL, "cells is NULL");
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
@@ -489,7 +497,7 @@ int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
-  TRY(check_lists(cells, nl));
+  TRY(check_lists(prm, cells, nl));
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -519,7 +527,7 @@ int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!nl) return fail(TBSMA_EINVAL, "nlist is NULL");
-  TRY(check_lists(nullptr, nl));
+  TRY(check_lists(prm, nullptr, nl));
   TRY(check_out(prm, out));
   if (sys->R == 0) return TBSMA_OK;
   if (!out->rep_energy || !out->rep_wzz)
@@ -543,7 +551,7 @@ int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!nl) return fail(TBSMA_EINVAL, "nlist is NULL");
-  TRY(check_lists(nullptr, nl));
+  TRY(check_lists(prm, nullptr, nl));
   TRY(check_out(prm, out));
   if (pass != 1 && pass != 2) return fail(TBSMA_EINVAL, "pass must be 1 or 2");
   if (sys->R == 0) return TBSMA_OK;
@@ -564,7 +572,7 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
-  TRY(check_lists(cells, nl));
+  TRY(check_lists(prm, cells, nl));
   TRY(check_out(prm, out));
   TRY(check_md(md, sys->R));
   if (n_steps < 0) return fail(TBSMA_EINVAL, "n_steps < 0");
@@ -587,7 +595,7 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
-  TRY(check_lists(cells, nl));
+  TRY(check_lists(prm, cells, nl));
   TRY(check_out(prm, out));
   TRY(check_md(md, sys->R));
   if (n_steps < 0 || steps_per_graph < 1)

@@ -61,6 +61,7 @@ struct Dev {
   // cells and lists
   int32_t *cell_start, *cell_atoms;
   int32_t *nl, *nn;
+  int32_t *act, *nact;          // active-pair list [k_cap*N], counts [2N]
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace
@@ -156,6 +157,28 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint32_t rep,
   n0 = a * c;
   n1 = a * s;
   n2 = b * cos(twopi * u01(o.w));
+}
+
+// The same three normals in FP32 (mixed precision): u = (w/2^8 + 1/2) 2^-24
+// from the top 24 bits of each word; sqrt(-2 ln u) from the hardware log2,
+// cos/sin(2 pi u) from the hardware sine and cosine, whose argument is in
+// revolutions.
+__device__ __forceinline__ void gauss3f(uint64_t seed, uint32_t rep,
+                                        uint32_t tag, uint64_t step,
+                                        uint32_t stream, float &n0, float &n1,
+                                        float &n2) {
+  uint4 o = rng_words(seed, rep, tag, step, stream);
+  const float s24 = 0x1p-24f;
+  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  float u0 = ((float)(o.x >> 8) + 0.5f) * s24;
+  float u1 = ((float)(o.y >> 8) + 0.5f) * s24;
+  float u2 = ((float)(o.z >> 8) + 0.5f) * s24;
+  float u3 = ((float)(o.w >> 8) + 0.5f) * s24;
+  float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+  float b = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+  n0 = a * __builtin_amdgcn_cosf(u1);
+  n1 = a * __builtin_amdgcn_sinf(u1);
+  n2 = b * __builtin_amdgcn_cosf(u3);
 }
 
 // Order-preserving map of a double to an unsigned key (for atomic min/max).

@@ -171,91 +171,238 @@ __global__ void __launch_bounds__(kBlock) k_cell_sort(Dev S) {
 }
 
 // ---------------------------------------------------------------------------
+// list layout and per-lane LDS rings
+// ---------------------------------------------------------------------------
+// Verlet and active lists are stored in chunks of 8 entries: entry k of slot
+// i is at ((k >> 3) * N + i) * 8 + (k & 7).  A lane reads its next 8 entries
+// as 32 contiguous bytes and a wavefront reads 2 KB contiguous at a time.
+__device__ __forceinline__ int64_t cl8(int64_t N, int64_t i, int64_t chunk) {
+  return (chunk * N + i) << 3;
+}
+
+// Per-lane ring of 16 list entries in LDS, interleaved over the lanes of the
+// block (entry e of lane l at e * kBlock + l, so a wavefront's appends hit
+// distinct banks).  Lanes append at their own pace; at every 8th step of a
+// wave-uniform loop, each lane holding a full chunk writes it to the list as
+// one 32-byte store, so at most 7 + 8 entries are ever pending.
+struct Ring {
+  int32_t *lds;  // this lane's first entry
+  int cnt;       // entries appended
+  int head;      // entries written to the list (a multiple of 8)
+  __device__ __forceinline__ void push(int j) {
+    lds[(cnt & 15) * kBlock] = j;
+    ++cnt;
+  }
+  __device__ __forceinline__ void store_chunk(int32_t *list, int64_t N,
+                                              int64_t i, int64_t chunk) {
+    const int32_t *e = lds + (head & 15) * kBlock;
+    int4 *dst = reinterpret_cast<int4 *>(list + cl8(N, i, chunk));
+    dst[0] = make_int4(e[0], e[kBlock], e[2 * kBlock], e[3 * kBlock]);
+    dst[1] = make_int4(e[4 * kBlock], e[5 * kBlock], e[6 * kBlock],
+                       e[7 * kBlock]);
+    head += 8;
+  }
+  // chunk index of entry `head` in a list growing upwards from chunk c0
+  // (dir = +1) or downwards (dir = -1)
+  __device__ __forceinline__ void flush(int32_t *list, int64_t N, int64_t i,
+                                        int64_t c0, int dir) {
+    if (cnt - head >= 8) store_chunk(list, N, i, c0 + dir * (head >> 3));
+  }
+  // the last, partial chunks; entries past cnt in them are never read
+  __device__ __forceinline__ void finish(int32_t *list, int64_t N, int64_t i,
+                                         int64_t c0, int dir) {
+    while (cnt > head) store_chunk(list, N, i, c0 + dir * (head >> 3));
+  }
+};
+
+__device__ __forceinline__ bool wave_any(bool p) {
+  return __ballot(p) != 0ull;
+}
+
+// Loop over the entries k < n of one lane's chunked list starting at chunk
+// c0 and moving by dir per chunk.  The indices of chunk c+1 are loaded while
+// chunk c is processed; body(j[8], k0) gets the 8 indices of chunk c (the
+// atom itself for k >= n, which every pair term excludes).
+template <class F>
+__device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
+                                           int64_t i, int self, int n,
+                                           int64_t c0, int dir, F &&body) {
+  const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
+  const int nch = (nmax + 7) >> 3;
+  int4 a = make_int4(self, self, self, self), b = a;
+  if (n > 0) {
+    const int4 *p = reinterpret_cast<const int4 *>(list + cl8(N, i, c0));
+    a = p[0];
+    b = p[1];
+  }
+  for (int c = 0; c < nch; ++c) {
+    int4 na = a, nb = b;
+    if ((c + 1) * 8 < n) {
+      const int4 *p = reinterpret_cast<const int4 *>(
+          list + cl8(N, i, c0 + (int64_t)dir * (c + 1)));
+      na = p[0];
+      nb = p[1];
+    }
+    const int k0 = c * 8;
+    int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) j[e] = k0 + e < n ? j[e] : self;
+    body(j, k0);
+    a = na;
+    b = nb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Verlet lists: scan the 27 cells around the atom's cell (FP64 distances)
 // ---------------------------------------------------------------------------
+// One lane per atom, advancing through its candidates in a wave-uniform loop
+// (one candidate per lane per step, cells in z, y, x order, slots ascending
+// within a cell), so that the list is written in whole chunks through a
+// ring.  Rows longer than k_cap are truncated and reported.
 __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= S.N) return;
-  int r = S.tile_rep[i / kTile];
-  if (!rebuilds(S, r)) return;
-  if (S.flag[i] == 3) {
-    S.nn[i] = 0;
-    return;
-  }
+  __shared__ int32_t ring_lds[16 * kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N) return;  // whole wavefronts (N is a multiple of 64)
+  const int r = S.tile_rep[i / kTile];
+  if (!rebuilds(S, r)) return;  // uniform over the wavefront
+  const int64_t N = S.N;
+  const bool real = S.flag[i] != 3;
   const int32_t *gd = S.grid_dim + 3 * r;
   const double *lo = S.grid_lo + 3 * r;
-  double xi = S.x[i], yi = S.y[i], zi = S.z[i];
+  const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
   bool out = false;
-  int cx = cell_coord(xi, lo[0], S.inv_cell, gd[0], out);
-  int cy = cell_coord(yi, lo[1], S.inv_cell, gd[1], out);
-  int cz = cell_coord(zi, lo[2], S.inv_cell, gd[2], out);
+  const int cx = cell_coord(xi, lo[0], S.inv_cell, gd[0], out);
+  const int cy = cell_coord(yi, lo[1], S.inv_cell, gd[1], out);
+  const int cz = cell_coord(zi, lo[2], S.inv_cell, gd[2], out);
   const int32_t *start = S.cell_start + S.cell_off[r] + r;
-  int cnt = 0;
-  const int64_t N = S.N;
-  for (int kz = cz - 1; kz <= cz + 1; ++kz) {
-    if (kz < 0 || kz >= gd[2]) continue;
-    for (int ky = cy - 1; ky <= cy + 1; ++ky) {
-      if (ky < 0 || ky >= gd[1]) continue;
-      for (int kx = cx - 1; kx <= cx + 1; ++kx) {
-        if (kx < 0 || kx >= gd[0]) continue;
-        int c = (kz * gd[1] + ky) * gd[0] + kx;
-        int32_t a = start[c], e = start[c + 1];
-        for (int32_t s = a; s < e; ++s) {
-          int32_t j = S.cell_atoms[s];
-          if (j == (int32_t)i) continue;
-          double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
-          if (dx * dx + dy * dy + dz * dz < rl2) {
-            if (cnt < S.k_cap) S.nl[(int64_t)cnt * N + i] = j;
-            ++cnt;
-          }
+  Ring ring{ring_lds + threadIdx.x, 0, 0};
+  int total = 0, cc = -1;
+  int32_t s = 0, e = 0;
+  bool live = real;
+  for (int it = 0;; ++it) {
+    if (live) {
+      while (s >= e) {
+        if (++cc >= 27) {
+          live = false;
+          break;
+        }
+        const int kz = cz + cc / 9 - 1, ky = cy + (cc / 3) % 3 - 1,
+                  kx = cx + cc % 3 - 1;
+        if (kx >= 0 && kx < gd[0] && ky >= 0 && ky < gd[1] && kz >= 0 &&
+            kz < gd[2]) {
+          const int c = (kz * gd[1] + ky) * gd[0] + kx;
+          s = start[c];
+          e = start[c + 1];
         }
       }
     }
+    if (!wave_any(live)) break;
+    if (live) {
+      const int32_t j = S.cell_atoms[s++];
+      if (j != (int32_t)i) {
+        const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+        if (dx * dx + dy * dy + dz * dz < rl2) {
+          if (total < S.k_cap) ring.push(j);
+          ++total;
+        }
+      }
+    }
+    if ((it & 7) == 7) ring.flush(S.nl, N, i, 0, 1);
   }
-  if (cnt > S.k_cap) {
-    atomicMax(S.nnmax, cnt);
+  ring.finish(S.nl, N, i, 0, 1);
+  if (total > S.k_cap) {
+    atomicMax(S.nnmax, total);
     atomicOr(&S.wstatus[r], 1u);
-    cnt = S.k_cap;
   }
-  S.nn[i] = cnt;
+  S.nn[i] = real ? min(total, S.k_cap) : 0;
   S.xr[i] = xi;
   S.yr[i] = yi;
   S.zr[i] = zi;
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: density rho_i -> g_i = 1/sqrt(rho_i)
+// pass 1: density rho_i -> g_i = 1/sqrt(rho_i), plus the active-pair lists
 // ---------------------------------------------------------------------------
+// Keeps a loop-invariant value in a VGPR (a VOP3 instruction reads at most
+// one scalar operand, so two uniform constants would otherwise be copied
+// into VGPRs on every iteration).
+template <class T>
+__device__ __forceinline__ T in_vgpr(T v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Gather of one quantised position by a 32-bit byte offset from a uniform
+// base (slot counts are below 2^28 in mixed precision).
+__device__ __forceinline__ int4 gather_q(const int4 *qp, int j) {
+  return *reinterpret_cast<const int4 *>(reinterpret_cast<const char *>(qp) +
+                                         ((uint32_t)j << 4));
+}
+
+// Chunks of the active list: core entries from chunk 0 upwards, tail
+// entries from chunk act_chunks-1 downwards; act_chunks = k_cap/8 + 2 holds
+// both, since nc + nt <= k_cap.
+__device__ __forceinline__ int act_chunks(const Dev &S) {
+  return (S.k_cap >> 3) + 2;
+}
+
+// One lane per atom.  Besides rho_i, the pass writes the pairs of the
+// Verlet list with 0 < r <= r_cut at the current positions into the active
+// lists, in list order: r <= r_tail ("core") and r_tail < r ("tail"), with
+// their counts in nact[2i], nact[2i+1].
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
-  int64_t b0 = xcd_block() * kBlock;
-  int64_t i = b0 + threadIdx.x;
-  bool valid = i < S.N;
-  int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  int n = valid ? S.nn[i] : 0;
-  int nmax = wave_max_i(n);
-  const int4 *__restrict__ qp = S.qpos;
-  const int32_t *__restrict__ col = S.nl + b0;
+  __shared__ int32_t ring_c[16 * kBlock];
+  __shared__ int32_t ring_t[16 * kBlock];
+  const int64_t b0 = xcd_block() * kBlock;
+  const int tid = threadIdx.x;
+  const int64_t i = b0 + tid;
+  const bool valid = i < S.N;
+  const int self = valid ? (int)i : 0;
+  const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+  const int n = valid ? S.nn[i] : 0;
   const int64_t N = S.N;
+  const int4 *__restrict__ qp = S.qpos;
+  const float aF = in_vgpr(P.aF), bF = in_vgpr(P.bF);
+  const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
+  const float f0 = in_vgpr(P.f0), f1 = in_vgpr(P.f1), f2 = in_vgpr(P.f2),
+              f3 = in_vgpr(P.f3);
+  const float rc2 = P.rc2, rt = P.rt;
+  const int64_t tc0 = act_chunks(S) - 1;
+  Ring rc{ring_c + tid, 0, 0}, rtl{ring_t + tid, 0, 0};
   float rho = 0.0f;
-  for (int k = 0; k < nmax; ++k) {
-    if (k < n) {
-      int j = col[(int64_t)k * N + threadIdx.x];
-      int4 qj = qp[j];
-      float dx = (float)(qj.x - qi.x);
-      float dy = (float)(qj.y - qi.y);
-      float dz = (float)(qj.z - qi.z);
-      float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      float rr = __builtin_amdgcn_sqrtf(r2);
-      float f = __builtin_amdgcn_exp2f(fmaf(P.aF, rr, P.bF));
-      float t = fmaf(rr, P.tS, P.tB);
-      float ft = fmaf(fmaf(fmaf(P.f3, t, P.f2), t, P.f1), t, P.f0);
-      f = rr > P.rt ? ft : f;
-      rho += (r2 < P.rc2 && r2 > 0.0f) ? f : 0.0f;
+  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+    int4 q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float dx = (float)(q[e].x - qi.x);
+      const float dy = (float)(q[e].y - qi.y);
+      const float dz = (float)(q[e].z - qi.z);
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float rr = __builtin_amdgcn_sqrtf(r2);
+      float f = __builtin_amdgcn_exp2f(fmaf(aF, rr, bF));
+      const float t = fmaf(rr, tS, tB);
+      const float ft = fmaf(fmaf(fmaf(f3, t, f2), t, f1), t, f0);
+      const bool tail = rr > rt;
+      f = tail ? ft : f;
+      const bool in = r2 < rc2 && r2 > 0.0f;
+      rho += in ? f : 0.0f;
+      if (in) {
+        if (tail) rtl.push(j[e]);
+        else rc.push(j[e]);
+      }
     }
-  }
+    rc.flush(S.act, N, i, 0, 1);
+    rtl.flush(S.act, N, i, tc0, -1);
+  });
+  rc.finish(S.act, N, i, 0, 1);
+  rtl.finish(S.act, N, i, tc0, -1);
   if (valid) {
-    float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
+    const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
     S.qpos[i].w = __float_as_int(g);
+    reinterpret_cast<int2 *>(S.nact)[i] = make_int2(rc.cnt, rtl.cnt);
   }
 }
 
@@ -283,6 +430,10 @@ __device__ __forceinline__ double dradial_d(const PotD &P, bool dens,
               : fma(fma(3.0 * P.v3, t, 2.0 * P.v2), t, P.v1) / P.w;
 }
 
+__device__ __forceinline__ int32_t nl_entry(const Dev &S, int64_t i, int k) {
+  return S.nl[cl8(S.N, i, k >> 3) + (k & 7)];
+}
+
 __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
                                                          double *g) {
   int64_t b0 = xcd_block() * kBlock;
@@ -291,10 +442,9 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
   int n = valid ? S.nn[i] : 0;
   double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
          zi = valid ? S.z[i] : 0.0;
-  const int64_t N = S.N;
   double rho = 0.0;
   for (int k = 0; k < n; ++k) {
-    int j = S.nl[(int64_t)k * N + i];
+    int j = nl_entry(S, i, k);
     double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (r > 0.0) rho += radial_d(P, true, r);
@@ -305,56 +455,99 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // ---------------------------------------------------------------------------
 // pass 2: forces, per-atom energies, per-tile sums of E and of the zz virial
 // ---------------------------------------------------------------------------
+// Over the active lists of pass 1: core pairs with the exponential forms of
+// eqs 1-2 only, tail pairs with the cubic tail only.  Per pair:
+// E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, E_i += V(r),
+// w_i += E'_ij dz^2 / (2r).
 __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         float *fx, float *fy,
                                                         float *fz,
                                                         float *eat) {
-  int64_t b0 = xcd_block() * kBlock;
-  int64_t i = b0 + threadIdx.x;
-  bool valid = i < S.N;
-  int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  int n = valid ? S.nn[i] : 0;
-  int nmax = wave_max_i(n);
-  float gi = __int_as_float(qi.w);
-  float hgi = 0.5f * gi;
-  const int4 *__restrict__ qp = S.qpos;
-  const int32_t *__restrict__ col = S.nl + b0;
+  const int64_t b0 = xcd_block() * kBlock;
+  const int tid = threadIdx.x;
+  const int64_t i = b0 + tid;
+  const bool valid = i < S.N;
+  const int self = valid ? (int)i : 0;
+  const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+  const int2 na = valid ? reinterpret_cast<const int2 *>(S.nact)[i]
+                        : make_int2(0, 0);
+  const float gi = __int_as_float(qi.w);
+  const float hgi = 0.5f * gi;
   const int64_t N = S.N;
+  const int4 *__restrict__ qp = S.qpos;
   float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
-  for (int k = 0; k < nmax; ++k) {
-    if (k < n) {
-      int j = col[(int64_t)k * N + threadIdx.x];
-      int4 qj = qp[j];
-      float dx = (float)(qj.x - qi.x);
-      float dy = (float)(qj.y - qi.y);
-      float dz = (float)(qj.z - qi.z);
-      float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      float ri = __builtin_amdgcn_rsqf(r2);
-      float rr = r2 * ri;
-      float eV = __builtin_amdgcn_exp2f(fmaf(P.aV, rr, P.bV));
-      float eP = __builtin_amdgcn_exp2f(fmaf(P.aP, rr, P.bP));
-      float G = fmaf(0.5f, __int_as_float(qj.w), hgi);
-      float ep = fmaf(G, eP, -P.c2p * eV);
-      float t = fmaf(rr, P.tS, P.tB);
-      float vt = fmaf(fmaf(fmaf(P.v3, t, P.v2), t, P.v1), t, P.v0);
-      float dvt = fmaf(fmaf(P.dv2, t, P.dv1), t, P.dv0);
-      float dpt = fmaf(fmaf(P.dp2, t, P.dp1), t, P.dp0);
-      bool tail = rr > P.rt;
-      ep = tail ? fmaf(G, dpt, dvt) : ep;
-      eV = tail ? vt : eV;
-      bool in = r2 < P.rc2 && r2 > 0.0f;
-      float s = in ? ep * ri : 0.0f;
-      ev += in ? eV : 0.0f;
-      ax = fmaf(s, dx, ax);
-      ay = fmaf(s, dy, ay);
-      float sz = s * dz;
-      az += sz;
-      wz = fmaf(sz, dz, wz);
-    }
+  {  // core pairs: r <= r_tail
+    const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
+    const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
+    const float c2p = P.c2p;
+    const int n = na.x;
+    chunk_loop(S.act, N, i, self, n, 0, 1, [&](const int (&j)[8], int k0) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float dx = (float)(q[e].x - qi.x);
+        const float dy = (float)(q[e].y - qi.y);
+        const float dz = (float)(q[e].z - qi.z);
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float rr = r2 * ri;
+        const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
+        const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
+        const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
+        const float ep = fmaf(G, eP, -c2p * eV);
+        const bool on = k0 + e < n;
+        const float s = on ? ep * ri : 0.0f;
+        ev += on ? eV : 0.0f;
+        ax = fmaf(s, dx, ax);
+        ay = fmaf(s, dy, ay);
+        const float sz = s * dz;
+        az += sz;
+        wz = fmaf(sz, dz, wz);
+      }
+    });
+  }
+  {  // tail pairs: r_tail < r <= r_cut
+    const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
+    const float v0 = in_vgpr(P.v0), v1 = in_vgpr(P.v1), v2 = in_vgpr(P.v2),
+                v3 = in_vgpr(P.v3);
+    const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1), d2 = in_vgpr(P.dv2);
+    const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1), p2 = in_vgpr(P.dp2);
+    const int n = na.y;
+    chunk_loop(S.act, N, i, self, n, act_chunks(S) - 1, -1,
+               [&](const int (&j)[8], int k0) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float dx = (float)(q[e].x - qi.x);
+        const float dy = (float)(q[e].y - qi.y);
+        const float dz = (float)(q[e].z - qi.z);
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float rr = r2 * ri;
+        const float t = fmaf(rr, tS, tB);
+        const float vt = fmaf(fmaf(fmaf(v3, t, v2), t, v1), t, v0);
+        const float dvt = fmaf(fmaf(d2, t, d1), t, d0);
+        const float dpt = fmaf(fmaf(p2, t, p1), t, p0);
+        const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
+        const float ep = fmaf(G, dpt, dvt);
+        const bool on = k0 + e < n;
+        const float s = on ? ep * ri : 0.0f;
+        ev += on ? vt : 0.0f;
+        ax = fmaf(s, dx, ax);
+        ay = fmaf(s, dy, ay);
+        const float sz = s * dz;
+        az += sz;
+        wz = fmaf(sz, dz, wz);
+      }
+    });
   }
   double e_i = 0.0, w_i = 0.0;
   if (valid) {
-    float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
+    const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
     fx[i] = ax;
     fy[i] = ay;
     fz[i] = az;
@@ -364,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
   }
   e_i = wave_sum(e_i);
   w_i = wave_sum(w_i);
-  if ((threadIdx.x & 63) == 0 && valid) {
+  if ((tid & 63) == 0 && valid) {
     double *pt = S.part + (i / kTile) * kNPart;
     pt[kPartE] = e_i;
     pt[kPartW] = w_i;
@@ -383,10 +576,9 @@ __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
   double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
          zi = valid ? S.z[i] : 0.0;
   double gi = valid ? g[i] : 0.0;
-  const int64_t N = S.N;
   double ax = 0, ay = 0, az = 0, ev = 0, wz = 0, rho = 0;
   for (int k = 0; k < n; ++k) {
-    int j = S.nl[(int64_t)k * N + i];
+    int j = nl_entry(S, i, k);
     double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(r > 0.0) || r > P.rc) continue;
@@ -455,8 +647,17 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
       if (M.gamma > 0.0) {
         double n0, n1, n2;
         uint32_t tag = (uint32_t)(i - S.rep_off[r]);
-        gauss3(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u, n0,
-               n1, n2);
+        if (MIXED) {  // FP32 Box-Muller on the same Philox words
+          float m0, m1, m2;
+          gauss3f(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u,
+                  m0, m1, m2);
+          n0 = m0;
+          n1 = m1;
+          n2 = m2;
+        } else {
+          gauss3(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u,
+                 n0, n1, n2);
+        }
         double sg = sqrt(kBoltz * M.T[r] / S.mass * kAccel) *
                     sqrt(1.0 - M.c1 * M.c1);
         double uz = stream_u(M, r, z, M.v_pull[r] * ((double)step + 0.5) * dt);

@@ -63,6 +63,7 @@ class WireBatch:
         self.replicas = list(replicas)
         self.pot = pot or Potential()
         self.precision = precision
+        k_cap = (int(k_cap) + 7) // 8 * 8
         self.skin, self.cell, self.k_cap = skin, cell, k_cap
         self.gamma, self.dt, self.lab_frame = gamma, dt, lab_frame
         self.n_log, self.n_slots = n_log, n_slots
@@ -142,6 +143,10 @@ class WireBatch:
         T["cell_atoms"] = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
         T["nl"] = torch.zeros(k_cap * N, dtype=torch.int32, device=dev)
         T["nn"] = torch.zeros(N, dtype=torch.int32, device=dev)
+        mixed = precision == "mixed"
+        T["act"] = torch.zeros((k_cap + 16) * N if mixed else 1, dtype=torch.int32,
+                               device=dev)
+        T["nact"] = torch.zeros(2 * N if mixed else 1, dtype=torch.int32, device=dev)
         for k in ("fx", "fy", "fz", "e_atom"):
             T[k] = torch.zeros(N, dtype=ft, device=dev)
         T["g"] = torch.zeros(N, **f64)
@@ -174,7 +179,9 @@ class WireBatch:
                             _ptr(T["qpos"]) if precision == "mixed" else None)
         self.cells = A.Cells(_ptr(T["cell_start"]), _ptr(T["cell_atoms"]))
         self.nlist = A.NList(_ptr(T["nl"]), _ptr(T["nn"]), k_cap, 0, _ptr(T["x_ref"]),
-                             _ptr(T["y_ref"]), _ptr(T["z_ref"]))
+                             _ptr(T["y_ref"]), _ptr(T["z_ref"]),
+                             _ptr(T["act"]) if mixed else None,
+                             _ptr(T["nact"]) if mixed else None)
         self.out = A.ForcesOut(_ptr(T["fx"]), _ptr(T["fy"]), _ptr(T["fz"]), _ptr(T["e_atom"]),
                                _ptr(T["g"]) if precision == "fp64" else None,
                                _ptr(T["rep_energy"]), _ptr(T["rep_wzz"]))
@@ -218,9 +225,14 @@ class WireBatch:
         A.check(rc)
 
     def resize_nlist(self, k_cap: int):
+        k_cap = (int(k_cap) + 7) // 8 * 8
         self.k_cap = k_cap
         self.t["nl"] = torch.zeros(k_cap * self.N, dtype=torch.int32, device=self.device)
         self.nlist.nl = _ptr(self.t["nl"])
+        if self.precision == "mixed":
+            self.t["act"] = torch.zeros((k_cap + 16) * self.N, dtype=torch.int32,
+                                        device=self.device)
+            self.nlist.act = _ptr(self.t["act"])
         self.nlist.k_cap = k_cap
 
     def compute_forces(self):
@@ -284,9 +296,26 @@ class WireBatch:
     def neighbor_rows(self, r: int):
         """List of neighbour slot arrays (replica-local indices) of replica r."""
         nn = self.t["nn"].cpu().numpy()
-        nl = self.t["nl"].view(self.k_cap, self.N).cpu().numpy()
+        # chunks of 8: entry k of slot i at ((k // 8) * N + i) * 8 + k % 8
+        nl = self.t["nl"].view(self.k_cap // 8, self.N, 8).cpu().numpy()
         o = int(self.rep_off[r])
-        return [np.sort(nl[:nn[o + i], o + i]) - o for i in range(int(self.n_atoms[r]))]
+        return [np.sort(nl[:, o + i, :].reshape(-1)[:nn[o + i]]) - o
+                for i in range(int(self.n_atoms[r]))]
+
+    def active_rows(self, r: int):
+        """(core, tail) active-pair index arrays of replica r (mixed only),
+        replica-local, as written by the last density pass."""
+        na = self.t["nact"].view(self.N, 2).cpu().numpy()
+        C8 = self.k_cap // 8 + 2
+        act = self.t["act"].view(C8, self.N, 8).cpu().numpy()
+        o = int(self.rep_off[r])
+        out = []
+        for i in range(int(self.n_atoms[r])):
+            nc, nt = na[o + i]
+            core = act[:, o + i, :].reshape(-1)[:nc]
+            tail = act[::-1, o + i, :].reshape(-1)[:nt]
+            out.append((core - o, tail - o))
+        return out
 
     def status(self):
         return self.t["status"].cpu().numpy().view(np.uint32)
@@ -305,3 +334,11 @@ class WireBatch:
     def mean_neighbors(self) -> float:
         nn = self.t["nn"].double()
         return float(nn.sum().item() / max(1, int(self.n_atoms.sum())))
+
+    def mean_active_pairs(self) -> float:
+        """Mean number of pairs within r_cut per real atom (mixed precision;
+        from the active list of the last density pass)."""
+        if self.precision != "mixed":
+            return float("nan")
+        na = self.t["nact"].double()
+        return float(na.sum().item() / max(1, int(self.n_atoms.sum())))

@@ -110,6 +110,24 @@ def test_neighbor_lists_are_exact_sets(precision):
         got = b.neighbor_rows(r)
         for i in range(len(ref)):
             assert np.array_equal(got[i], ref[i]), (r, i)
+    if precision == "mixed":
+        # active lists of the density pass: core 0 < r <= r_tail, tail
+        # r_tail < r <= r_cut (pairs within 1e-4 A of a boundary may fall on
+        # either side in FP32)
+        rt, rc = b.pot.r_tail, b.pot.r_cut
+        for r in range(b.R):
+            x, y, z = b.positions(r)
+            P = np.stack([x, y, z], 1)
+            for i, (core, tail) in enumerate(b.active_rows(r)):
+                d = np.sqrt(((P - P[i]) ** 2).sum(1))
+                d[i] = np.inf
+                sure_core = set(np.nonzero(d <= rt - 1e-4)[0])
+                sure_tail = set(np.nonzero((d > rt + 1e-4) & (d <= rc - 1e-4))[0])
+                maybe = set(np.nonzero((np.abs(d - rt) < 1e-4) | (np.abs(d - rc) < 1e-4))[0])
+                cs, ts = set(core.tolist()), set(tail.tolist())
+                assert len(cs) == core.size and len(ts) == tail.size
+                assert sure_core <= cs <= sure_core | maybe, (r, i)
+                assert sure_tail <= ts <= sure_tail | maybe, (r, i)
     # rows are stored in ascending cell-scan order: check determinism
     b2 = WireBatch(reps, precision)
     b2.prepare()
@@ -402,8 +420,11 @@ def test_full_size_config3_sampled():
     idx = [0, 1, 77, 200, 311, 450, 510, 511]
     worst = _sampled_parity(b, idx)
     note(f"  worst eps_F over {len(idx)} replicas: {worst:.2e}")
+    # 0.2 ps after a 298 K start on the perfect lattice, equipartition has
+    # moved about half of the kinetic energy into the potential energy and the
+    # 1/ps thermostat has only begun to restore it
     T = b.obs_at(100)[:, A.OBS_T]
-    assert np.all(np.abs(T - 298.0) < 60.0)
+    assert T.min() > 150.0 and T.max() < 320.0, (T.min(), T.max())
 
 
 def test_full_size_config5_sampled():
