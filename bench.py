@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--no-per-replica", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--drift-steps", type=int, default=0,
+                    help="also measure NVE energy drift over this many steps (FP64 D1.5xL3nm "
+                         "and mixed D3xL20nm wires at 10 K, static grips)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -190,6 +193,29 @@ def main():
                          f"L {rp.L / 10:.2f} nm), {k} FP64 steps, cell-list mode, OpenMP"}
         log(f"[bench] oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
 
+    drift = None
+    if args.drift_steps > 0:
+        drift = {}
+        for name, rp, prec in (("fp64 D1.5xL3nm", W.cfg1_plain_fp64().replicas[0], "fp64"),
+                               ("mixed D3xL20nm", W.cfg2_single_mixed().replicas[0], "mixed")):
+            rp = W.Replica(rp.D, rp.L, rp.T, 0.0, rp.seed, rp.rep_id, jitter=rp.jitter)
+            n_log = max(1, args.drift_steps // 100)
+            nb = WireBatch([rp], prec, n_log=n_log, n_slots=100, gamma=0.0)
+            nb.prepare()
+            nb.run_batch(args.drift_steps, n_log)
+            torch.cuda.synchronize()
+            ob = nb.obs()[:, 0, :]
+            ob = ob[np.argsort(ob[:, A.OBS_STEP])]
+            t_ps = ob[:, A.OBS_STEP] * nb.dt
+            etot = ob[:, A.OBS_EPOT] + ob[:, A.OBS_KE]
+            na = int(nb.n_atoms[0])
+            slope = np.polyfit(t_ps, etot, 1)[0]  # eV/ps
+            drift[name] = {"steps": args.drift_steps, "atoms": na,
+                           "drift_meV_per_atom_per_ns": slope * 1e3 * 1e3 / na,
+                           "rms_fluct_meV_per_atom": float(np.std(etot)) * 1e3 / na,
+                           "T_mean_K": float(ob[:, A.OBS_T].mean())}
+            log(f"[bench] NVE {name}: {drift[name]}")
+
     line = {
         "metric": "atom-timesteps/s, batched vs per-replica TB-SMA NVT; force-kernel % HBM peak",
         "value": value,
@@ -221,6 +247,8 @@ def main():
         "bad_replicas": bad,
         "cpu_baseline": cpu,
     }
+    if drift is not None:
+        line["nve_drift"] = drift
     print(json.dumps(line), flush=True)
 
 

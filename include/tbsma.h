@@ -175,12 +175,11 @@ typedef struct {
  * cell-scan order (cells by z, y, x; slots ascending within a cell).
  * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.
- * act, nact (MIXED only; NULL for FP64): device [(k_cap+16)*N] and [2N]
- * int32, rewritten by every density pass: the pairs of the Verlet list with
- * 0 < r <= r_cut at the current positions, in list order, in the same chunked
- * layout with C = k_cap/8 + 2 chunks per atom: the nact[2i] pairs with
- * r <= r_tail are entries k of chunks 0, 1, ... (chunk k/8); the nact[2i+1]
- * tail pairs are entries k of chunks C-1, C-2, ... (chunk C-1-k/8).
+ * amask, nact (MIXED only; NULL for FP64): device [ceil(k_cap/32)*N] and
+ * [2N] int32, rewritten by every density pass: bit k%32 of
+ * amask[(k/32)*N + i] is set when entry k of atom i's list has
+ * 0 < r <= r_cut at the current positions; nact[2i] and nact[2i+1] count
+ * those with r <= r_tail and r > r_tail.
  */
 typedef struct {
   int32_t *nl;
@@ -188,7 +187,7 @@ typedef struct {
   int32_t k_cap;
   int32_t reserved;
   double *x_ref, *y_ref, *z_ref;
-  int32_t *act;
+  int32_t *amask;
   int32_t *nact;
 } tbsma_nlist;
 
@@ -259,8 +258,10 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
  * Host-side wire builder (Simulation details, Figure 1): the [100] FCC
  * cylinder of lattice constant a, diameter D and length L with the axis
  * through an atom column; sites (i, j, k) a/2 with i+j+k even,
- * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, in (k, j, i) order; the n_grip
- * lowest planes get TBSMA_GRIP_FIXED and the n_grip highest TBSMA_GRIP_PULL.
+ * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, ordered by slabs of four planes
+ * (k/4) and, within a slab, by (i^2 + j^2, k, j, i) so that neighbouring
+ * slots share a slab and a coordination; the n_grip lowest planes get
+ * TBSMA_GRIP_FIXED and the n_grip highest TBSMA_GRIP_PULL.
  * x, y, z, flag are host arrays of capacity cap (may be NULL when cap = 0).
  * *n_out receives the atom count; TBSMA_ECAPACITY if it exceeds cap.
  */

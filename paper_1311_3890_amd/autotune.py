@@ -1,0 +1,116 @@
+"""Per-bucket launch settings chosen by short timed trials.
+
+Replicas are grouped into buckets of equal diameter and temperature class.
+For each bucket a sample of its replicas is run through the batched graph
+path for every candidate Verlet skin (with the cell edge r_cut + skin) and
+graph chunk length; the fastest setting in atom-timesteps/s is kept.  The
+skin trades list length (pair work per step) against rebuild frequency, which
+depends on temperature and diameter; the chunk length trades graph launch
+overhead against the step granularity of the host loop.  Choices are cached
+as JSON so later runs reuse them.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import asdict, dataclass
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from .engine import WireBatch
+
+
+@dataclass
+class Choice:
+    skin: float
+    steps_per_graph: int
+    rate: float          # atom-timesteps/s of the trial
+    trials: list
+
+
+def bucket_of(rp) -> Tuple[float, str]:
+    return (float(rp.D), "cold" if rp.T < 100.0 else "warm")
+
+
+def buckets(replicas: Sequence) -> Dict[Tuple[float, str], List[int]]:
+    out: Dict[Tuple[float, str], List[int]] = {}
+    for r, rp in enumerate(replicas):
+        out.setdefault(bucket_of(rp), []).append(r)
+    return dict(sorted(out.items()))
+
+
+def _key(b) -> str:
+    return f"D{b[0]:g}-{b[1]}"
+
+
+def _time_batch(reps, skin, spg, trial_steps, warmup, precision, r_cut=7.0):
+    wb = WireBatch(reps, precision, skin=skin, cell=max(8.0, r_cut + skin), n_log=spg)
+    wb.prepare()
+    wb.run_batch(warmup, spg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wb.run_batch(trial_steps, spg)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = float(wb.n_atoms.sum()) * trial_steps / dt
+    del wb
+    return rate
+
+
+def tune(replicas: Sequence, precision: str = "mixed", *,
+         skins=(0.6, 0.8, 1.0, 1.2), chunks=(25, 50), sample: int = 32,
+         trial_steps: int = 100, warmup: int = 100, cache: str | None = None,
+         log=print) -> Dict[str, Choice]:
+    """Best (skin, steps_per_graph) per bucket of `replicas`."""
+    cached = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            cached = json.load(fh)
+    result: Dict[str, Choice] = {}
+    for b, idx in buckets(replicas).items():
+        k = _key(b)
+        if k in cached:
+            result[k] = Choice(**cached[k])
+            continue
+        pick = np.linspace(0, len(idx) - 1, min(sample, len(idx))).round().astype(int)
+        reps = [replicas[idx[p]] for p in pick]
+        trials = []
+        for skin in skins:
+            for spg in chunks:
+                rate = _time_batch(reps, skin, spg, trial_steps, warmup, precision)
+                trials.append((skin, spg, rate))
+                log(f"[autotune] {k}: skin {skin} chunk {spg}: {rate:.3e} atom-steps/s")
+        skin, spg, rate = max(trials, key=lambda t: t[2])
+        result[k] = Choice(skin, spg, rate, trials)
+    if cache:
+        merged = dict(cached)
+        merged.update({k: asdict(v) for k, v in result.items()})
+        with open(cache, "w") as fh:
+            json.dump(merged, fh, indent=1)
+    return result
+
+
+class BucketRun:
+    """The replicas of a workload as one WireBatch per bucket, each with its
+    tuned settings, advanced in turn."""
+
+    def __init__(self, replicas: Sequence, choices: Dict[str, Choice],
+                 precision: str = "mixed", n_log: int = 100, r_cut: float = 7.0):
+        self.parts = []
+        for b, idx in buckets(replicas).items():
+            c = choices[_key(b)]
+            wb = WireBatch([replicas[r] for r in idx], precision, skin=c.skin,
+                           cell=max(8.0, r_cut + c.skin), n_log=n_log)
+            self.parts.append((_key(b), idx, c, wb))
+        self.n_atoms = sum(int(wb.n_atoms.sum()) for _, _, _, wb in self.parts)
+
+    def prepare(self):
+        for _, _, _, wb in self.parts:
+            wb.prepare()
+
+    def run(self, n: int):
+        for _, _, c, wb in self.parts:
+            wb.run_batch(n, c.steps_per_graph)

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "tbsma.h"
@@ -198,7 +199,7 @@ void attach_lists(Dev &d, const tbsma_cells *c, const tbsma_nlist *n) {
     d.xr = n->x_ref;
     d.yr = n->y_ref;
     d.zr = n->z_ref;
-    d.act = n->act;
+    d.amask = n->amask;
     d.nact = n->nact;
   }
 }
@@ -333,7 +334,7 @@ int check_lists(const tbsma_params *p, const tbsma_cells *c,
             n->k_cap < 8 || n->k_cap % 8))
     return fail(TBSMA_EINVAL,
                 "neighbour-list arrays missing or k_cap not a multiple of 8");
-  if (n && p->precision == TBSMA_MIXED && (!n->act || !n->nact))
+  if (n && p->precision == TBSMA_MIXED && (!n->amask || !n->nact))
     return fail(TBSMA_EINVAL, "mixed precision needs the active-pair list");
   return TBSMA_OK;
 }
@@ -353,7 +354,7 @@ void enqueue_step(const tbsma_params *p, const Dev &d, const DevMD &M,
   double rl = p->r_cut + p->skin;
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_cells(d, s);
-  launch_nlist(d, rl * rl, s);
+  launch_nlist(d, mixed, rl, s);
   launch_forces(d, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
   launch_integrate_b(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_reduce_step(d, M, s);
@@ -376,10 +377,19 @@ int finish_run(const Dev &d, const tbsma_md *m, hipStream_t s) {
   return TBSMA_OK;
 }
 
-struct GraphCache {
-  std::mutex mu;
+// Instantiated step graphs, keyed by every argument they were captured with
+// (pointers, sizes, constants, stream, device); the least recently used one
+// is dropped beyond kGraphs entries.
+constexpr size_t kGraphs = 16;
+struct GraphEntry {
   std::vector<char> key;
   hipGraphExec_t exec = nullptr;
+  uint64_t used = 0;
+};
+struct GraphCache {
+  std::mutex mu;
+  std::vector<GraphEntry> entries;
+  uint64_t clock = 0;
 };
 GraphCache g_graph;
 
@@ -433,22 +443,40 @@ int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
   while ((double)layers * h < L) ++layers;
   int64_t m = (int64_t)floor(D / a) + 1;
   int64_t n = 0;
-  for (int64_t k = 0; k < layers; ++k) {
-    uint8_t fl = k < n_grip ? TBSMA_GRIP_FIXED
-                 : k >= layers - n_grip ? TBSMA_GRIP_PULL
-                                        : TBSMA_DYN;
-    for (int64_t j = -m; j <= m; ++j)
-      for (int64_t i = -m; i <= m; ++i) {
-        if ((i + j + k) & 1) continue;
-        if ((double)(i * i + j * j) > rad2) continue;
-        if (n < cap) {
-          x[n] = (double)i * h;
-          y[n] = (double)j * h;
-          z[n] = (double)k * h;
-          flag[n] = fl;
+  // slabs of four planes; within a slab by distance from the axis, then
+  // plane, row, column: neighbouring slots share a slab and a coordination
+  struct Site {
+    int64_t r2, k, j, i;
+    bool operator<(const Site &o) const {
+      if (r2 != o.r2) return r2 < o.r2;
+      if (k != o.k) return k < o.k;
+      if (j != o.j) return j < o.j;
+      return i < o.i;
+    }
+  };
+  std::vector<Site> slab;
+  for (int64_t k0 = 0; k0 < layers; k0 += 4) {
+    slab.clear();
+    for (int64_t k = k0; k < k0 + 4 && k < layers; ++k)
+      for (int64_t j = -m; j <= m; ++j)
+        for (int64_t i = -m; i <= m; ++i) {
+          if ((i + j + k) & 1) continue;
+          if ((double)(i * i + j * j) > rad2) continue;
+          slab.push_back(Site{i * i + j * j, k, j, i});
         }
-        ++n;
+    std::sort(slab.begin(), slab.end());
+    for (const Site &st : slab) {
+      const uint8_t fl = st.k < n_grip ? TBSMA_GRIP_FIXED
+                         : st.k >= layers - n_grip ? TBSMA_GRIP_PULL
+                                                   : TBSMA_DYN;
+      if (n < cap) {
+        x[n] = (double)st.i * h;
+        y[n] = (double)st.j * h;
+        z[n] = (double)st.k * h;
+        flag[n] = fl;
       }
+      ++n;
+    }
   }
   *n_out = n;
   if (n > cap) return fail(TBSMA_ECAPACITY, "wire has %lld atoms", (long long)n);
@@ -506,8 +534,9 @@ int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
   d.all = 1;
   double rl = prm->r_cut + prm->skin;
   launch_fill_u32(reinterpret_cast<uint32_t *>(d.nnmax), 1, 0u, s);
-  launch_nlist(d, rl * rl, s);
-  if (prm->precision == TBSMA_MIXED) launch_quantise(d, s);
+  const bool mixed = prm->precision == TBSMA_MIXED;
+  if (mixed) launch_quantise(d, s);
+  launch_nlist(d, mixed, rl, s);
   HIPCHK(hipGetLastError());
   if (need_cap) {
     HIPCHK(hipStreamSynchronize(s));
@@ -622,11 +651,10 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     append(key, &dev, sizeof(dev));
-    if (!g_graph.exec || key != g_graph.key) {
-      if (g_graph.exec) {
-        (void)hipGraphExecDestroy(g_graph.exec);
-        g_graph.exec = nullptr;
-      }
+    GraphEntry *hit = nullptr;
+    for (GraphEntry &e : g_graph.entries)
+      if (e.key == key) hit = &e;
+    if (!hit) {
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       for (int32_t k = 0; k < steps_per_graph; ++k)
@@ -634,18 +662,27 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
       hipError_t ce = hipStreamEndCapture(s, &graph);
       if (ce != hipSuccess)
         return fail(TBSMA_EHIP, "graph capture: %s", hipGetErrorString(ce));
-      hipError_t ie = hipGraphInstantiate(&g_graph.exec, graph, nullptr,
-                                          nullptr, 0);
+      hipGraphExec_t exec = nullptr;
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        g_graph.exec = nullptr;
+      if (ie != hipSuccess)
         return fail(TBSMA_EHIP, "graph instantiate: %s",
                     hipGetErrorString(ie));
+      if (g_graph.entries.size() >= kGraphs) {
+        auto lru = std::min_element(
+            g_graph.entries.begin(), g_graph.entries.end(),
+            [](const GraphEntry &a, const GraphEntry &b) {
+              return a.used < b.used;
+            });
+        (void)hipGraphExecDestroy(lru->exec);
+        g_graph.entries.erase(lru);
       }
-      g_graph.key = key;
+      g_graph.entries.push_back(GraphEntry{key, exec, 0});
+      hit = &g_graph.entries.back();
     }
+    hit->used = ++g_graph.clock;
     for (int64_t c = 0; c < chunks; ++c)
-      HIPCHK(hipGraphLaunch(g_graph.exec, s));
+      HIPCHK(hipGraphLaunch(hit->exec, s));
   }
   for (int64_t k = 0; k < rest; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
   return finish_run(d, md, s);

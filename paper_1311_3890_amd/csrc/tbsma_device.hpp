@@ -61,7 +61,7 @@ struct Dev {
   // cells and lists
   int32_t *cell_start, *cell_atoms;
   int32_t *nl, *nn;
-  int32_t *act, *nact;          // active-pair list [k_cap*N], counts [2N]
+  int32_t *amask, *nact;        // active-pair bits [k_cap/32*N], counts [2N]
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace

@@ -27,7 +27,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 __global__ void k_set_step(int64_t *step, int64_t v) { *step = v; }
 
 // Quantised copy of the positions (mixed precision): q = rint((x - o) 2^qbits)
-// about the centre o of the replica's grid; w keeps its value.
+// about the centre o of the replica's grid.
 __device__ __forceinline__ int quant1(double v, double o, double qs,
                                       bool &out) {
   double t = rint((v - o) * qs);
@@ -44,10 +44,11 @@ __device__ __forceinline__ void quantise(const Dev &S, int r, int64_t i,
   const int32_t *gd = S.grid_dim + 3 * r;
   const double *lo = S.grid_lo + 3 * r;
   double hc = 0.5 * S.cell;
-  int4 q = S.qpos[i];
+  int4 q;
   q.x = quant1(x, lo[0] + hc * gd[0], S.qscale, out);
   q.y = quant1(y, lo[1] + hc * gd[1], S.qscale, out);
   q.z = quant1(z, lo[2] + hc * gd[2], S.qscale, out);
+  q.w = 0;  // g_i of these positions: written by the next density pass
   S.qpos[i] = q;
 }
 
@@ -254,13 +255,18 @@ __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
 }
 
 // ---------------------------------------------------------------------------
-// Verlet lists: scan the 27 cells around the atom's cell (FP64 distances)
+// Verlet lists: scan the 27 cells around the atom's cell
 // ---------------------------------------------------------------------------
 // One lane per atom, advancing through its candidates in a wave-uniform loop
 // (one candidate per lane per step, cells in z, y, x order, slots ascending
 // within a cell), so that the list is written in whole chunks through a
-// ring.  Rows longer than k_cap are truncated and reported.
-__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2) {
+// ring.  Rows longer than k_cap are truncated and reported.  Distances are
+// FP64 in FP64 mode; in mixed precision they come from the quantised
+// positions (one 16-byte gather, exact integer differences), compared with
+// (r_cut + skin)^2 in quanta^2 (rl2q).
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
+                                                  float rl2q) {
   __shared__ int32_t ring_lds[16 * kBlock];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= S.N) return;  // whole wavefronts (N is a multiple of 64)
@@ -276,6 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2) {
   const int cy = cell_coord(yi, lo[1], S.inv_cell, gd[1], out);
   const int cz = cell_coord(zi, lo[2], S.inv_cell, gd[2], out);
   const int32_t *start = S.cell_start + S.cell_off[r] + r;
+  const int4 qi = MIXED ? S.qpos[i] : make_int4(0, 0, 0, 0);
   Ring ring{ring_lds + threadIdx.x, 0, 0};
   int total = 0, cc = -1;
   int32_t s = 0, e = 0;
@@ -301,8 +308,18 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2) {
     if (live) {
       const int32_t j = S.cell_atoms[s++];
       if (j != (int32_t)i) {
-        const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
-        if (dx * dx + dy * dy + dz * dz < rl2) {
+        bool near;
+        if (MIXED) {
+          const int4 qj = S.qpos[j];
+          const float dx = (float)(qj.x - qi.x);
+          const float dy = (float)(qj.y - qi.y);
+          const float dz = (float)(qj.z - qi.z);
+          near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q;
+        } else {
+          const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+          near = dx * dx + dy * dy + dz * dz < rl2;
+        }
+        if (near) {
           if (total < S.k_cap) ring.push(j);
           ++total;
         }
@@ -340,20 +357,12 @@ __device__ __forceinline__ int4 gather_q(const int4 *qp, int j) {
                                          ((uint32_t)j << 4));
 }
 
-// Chunks of the active list: core entries from chunk 0 upwards, tail
-// entries from chunk act_chunks-1 downwards; act_chunks = k_cap/8 + 2 holds
-// both, since nc + nt <= k_cap.
-__device__ __forceinline__ int act_chunks(const Dev &S) {
-  return (S.k_cap >> 3) + 2;
-}
-
-// One lane per atom.  Besides rho_i, the pass writes the pairs of the
-// Verlet list with 0 < r <= r_cut at the current positions into the active
-// lists, in list order: r <= r_tail ("core") and r_tail < r ("tail"), with
-// their counts in nact[2i], nact[2i+1].
+// One lane per atom.  Besides rho_i, the pass marks the pairs of the Verlet
+// list with 0 < r <= r_cut at the current positions: bit k%32 of
+// amask[(k/32)*N + i] is set for active entry k.  Words are written at
+// wave-uniform points as coalesced 256-byte stores; nact[2i], nact[2i+1]
+// count the active pairs with r <= r_tail and r > r_tail.
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
-  __shared__ int32_t ring_c[16 * kBlock];
-  __shared__ int32_t ring_t[16 * kBlock];
   const int64_t b0 = xcd_block() * kBlock;
   const int tid = threadIdx.x;
   const int64_t i = b0 + tid;
@@ -363,18 +372,21 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   const int n = valid ? S.nn[i] : 0;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
+  uint32_t *__restrict__ amask = reinterpret_cast<uint32_t *>(S.amask);
   const float aF = in_vgpr(P.aF), bF = in_vgpr(P.bF);
   const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
   const float f0 = in_vgpr(P.f0), f1 = in_vgpr(P.f1), f2 = in_vgpr(P.f2),
               f3 = in_vgpr(P.f3);
   const float rc2 = P.rc2, rt = P.rt;
-  const int64_t tc0 = act_chunks(S) - 1;
-  Ring rc{ring_c + tid, 0, 0}, rtl{ring_t + tid, 0, 0};
   float rho = 0.0f;
-  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+  int nc = 0, nt = 0;
+  uint32_t word = 0u;
+  int last_k0 = -8;
+  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int k0) {
     int4 q[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+    uint32_t bits = 0u;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float dx = (float)(q[e].x - qi.x);
@@ -389,20 +401,23 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
       f = tail ? ft : f;
       const bool in = r2 < rc2 && r2 > 0.0f;
       rho += in ? f : 0.0f;
-      if (in) {
-        if (tail) rtl.push(j[e]);
-        else rc.push(j[e]);
-      }
+      bits |= in ? 1u << e : 0u;
+      nc += (in && !tail) ? 1 : 0;
+      nt += (in && tail) ? 1 : 0;
     }
-    rc.flush(S.act, N, i, 0, 1);
-    rtl.flush(S.act, N, i, tc0, -1);
+    word |= bits << (k0 & 31);
+    if ((k0 & 31) == 24) {  // k0 is uniform: a whole word per lane
+      amask[(int64_t)(k0 >> 5) * N + i] = word;
+      word = 0u;
+    }
+    last_k0 = k0;
   });
-  rc.finish(S.act, N, i, 0, 1);
-  rtl.finish(S.act, N, i, tc0, -1);
+  if (last_k0 >= 0 && (last_k0 & 31) != 24)
+    amask[(int64_t)(last_k0 >> 5) * N + i] = word;
   if (valid) {
     const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
     S.qpos[i].w = __float_as_int(g);
-    reinterpret_cast<int2 *>(S.nact)[i] = make_int2(rc.cnt, rtl.cnt);
+    reinterpret_cast<int2 *>(S.nact)[i] = make_int2(nc, nt);
   }
 }
 
@@ -455,95 +470,117 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // ---------------------------------------------------------------------------
 // pass 2: forces, per-atom energies, per-tile sums of E and of the zz virial
 // ---------------------------------------------------------------------------
-// Over the active lists of pass 1: core pairs with the exponential forms of
-// eqs 1-2 only, tail pairs with the cubic tail only.  Per pair:
-// E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, E_i += V(r),
-// w_i += E'_ij dz^2 / (2r).
+// Each lane walks its Verlet list chunk by chunk and, using the active-pair
+// mask of pass 1, appends the pairs within r_cut to a per-lane LDS ring;
+// rounds then evaluate 8 ring entries per lane, so that lanes stay busy with
+// in-range pairs whatever their share of pairs beyond r_cut.  The ring holds
+// 16 entries: it is refilled while it holds fewer than 8, by at most 8 per
+// chunk.  Chunks are prefetched two ahead.  Per pair (core: exponentials of
+// eqs 1-2; tail: the cubic tails): E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2,
+// F_i += E'_ij d/r, E_i += V(r), w_i += E'_ij dz^2 / (2r); the sums run in
+// Verlet-list order.
 __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         float *fx, float *fy,
                                                         float *fz,
                                                         float *eat) {
+  __shared__ int32_t ring_lds[16 * kBlock];
   const int64_t b0 = xcd_block() * kBlock;
   const int tid = threadIdx.x;
   const int64_t i = b0 + tid;
   const bool valid = i < S.N;
   const int self = valid ? (int)i : 0;
   const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  const int2 na = valid ? reinterpret_cast<const int2 *>(S.nact)[i]
-                        : make_int2(0, 0);
+  const int n = valid ? S.nn[i] : 0;
+  const int nch = (n + 7) >> 3;
   const float gi = __int_as_float(qi.w);
   const float hgi = 0.5f * gi;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
+  const uint32_t *__restrict__ amask =
+      reinterpret_cast<const uint32_t *>(S.amask);
+  const int32_t *__restrict__ nl = S.nl;
+  int32_t *ring = ring_lds + tid;
+  const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
+  const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
+  const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
+  const float v0 = in_vgpr(P.v0), v1 = in_vgpr(P.v1), v2 = in_vgpr(P.v2),
+              v3 = in_vgpr(P.v3);
+  const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1), d2 = in_vgpr(P.dv2);
+  const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1), p2 = in_vgpr(P.dp2);
+  const float c2p = P.c2p, rt = P.rt;
+
+  // chunk queue: A = chunk p, B = chunk p+1 (indices and their 8 mask bits)
+  int4 a0, a1, c0, c1;
+  uint32_t ma = 0u, mb = 0u;
+  auto load_chunk = [&](int c, int4 &x0, int4 &x1, uint32_t &m) {
+    m = 0u;
+    if (c < nch) {
+      const int4 *p = reinterpret_cast<const int4 *>(nl + cl8(N, i, c));
+      x0 = p[0];
+      x1 = p[1];
+      m = (amask[(int64_t)(c >> 2) * N + i] >>
+           ((c & 3) * 8)) & 0xFFu;
+    }
+  };
+  load_chunk(0, a0, a1, ma);
+  load_chunk(1, c0, c1, mb);
+  int p = 0, cnt = 0, head = 0;
+  auto refill = [&]() {
+    while (cnt - head < 8 && p < nch) {
+      const int js[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if ((ma >> e) & 1u) {
+          ring[(cnt & 15) * kBlock] = js[e];
+          ++cnt;
+        }
+      }
+      a0 = c0;
+      a1 = c1;
+      ma = mb;
+      load_chunk(p + 2, c0, c1, mb);
+      ++p;
+    }
+  };
   float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
-  {  // core pairs: r <= r_tail
-    const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
-    const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
-    const float c2p = P.c2p;
-    const int n = na.x;
-    chunk_loop(S.act, N, i, self, n, 0, 1, [&](const int (&j)[8], int k0) {
-      int4 q[8];
+  for (;;) {
+    refill();
+    const int m = min(8, cnt - head);
+    if (!wave_any(m > 0)) break;
+    int4 q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+    for (int e = 0; e < 8; ++e) {
+      const int j = e < m ? ring[((head + e) & 15) * kBlock] : self;
+      q[e] = gather_q(qp, j);
+    }
+    head += m;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float dx = (float)(q[e].x - qi.x);
-        const float dy = (float)(q[e].y - qi.y);
-        const float dz = (float)(q[e].z - qi.z);
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float rr = r2 * ri;
-        const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
-        const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
-        const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
-        const float ep = fmaf(G, eP, -c2p * eV);
-        const bool on = k0 + e < n;
-        const float s = on ? ep * ri : 0.0f;
-        ev += on ? eV : 0.0f;
-        ax = fmaf(s, dx, ax);
-        ay = fmaf(s, dy, ay);
-        const float sz = s * dz;
-        az += sz;
-        wz = fmaf(sz, dz, wz);
-      }
-    });
-  }
-  {  // tail pairs: r_tail < r <= r_cut
-    const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
-    const float v0 = in_vgpr(P.v0), v1 = in_vgpr(P.v1), v2 = in_vgpr(P.v2),
-                v3 = in_vgpr(P.v3);
-    const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1), d2 = in_vgpr(P.dv2);
-    const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1), p2 = in_vgpr(P.dp2);
-    const int n = na.y;
-    chunk_loop(S.act, N, i, self, n, act_chunks(S) - 1, -1,
-               [&](const int (&j)[8], int k0) {
-      int4 q[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float dx = (float)(q[e].x - qi.x);
-        const float dy = (float)(q[e].y - qi.y);
-        const float dz = (float)(q[e].z - qi.z);
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float rr = r2 * ri;
-        const float t = fmaf(rr, tS, tB);
-        const float vt = fmaf(fmaf(fmaf(v3, t, v2), t, v1), t, v0);
-        const float dvt = fmaf(fmaf(d2, t, d1), t, d0);
-        const float dpt = fmaf(fmaf(p2, t, p1), t, p0);
-        const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
-        const float ep = fmaf(G, dpt, dvt);
-        const bool on = k0 + e < n;
-        const float s = on ? ep * ri : 0.0f;
-        ev += on ? vt : 0.0f;
-        ax = fmaf(s, dx, ax);
-        ay = fmaf(s, dy, ay);
-        const float sz = s * dz;
-        az += sz;
-        wz = fmaf(sz, dz, wz);
-      }
-    });
+    for (int e = 0; e < 8; ++e) {
+      const float dx = (float)(q[e].x - qi.x);
+      const float dy = (float)(q[e].y - qi.y);
+      const float dz = (float)(q[e].z - qi.z);
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      const float rr = r2 * ri;
+      const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
+      const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
+      const float t = fmaf(rr, tS, tB);
+      const float vt = fmaf(fmaf(fmaf(v3, t, v2), t, v1), t, v0);
+      const float dvt = fmaf(fmaf(d2, t, d1), t, d0);
+      const float dpt = fmaf(fmaf(p2, t, p1), t, p0);
+      const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
+      const bool tail = rr > rt;
+      const float ep = tail ? fmaf(G, dpt, dvt) : fmaf(G, eP, -c2p * eV);
+      const float V = tail ? vt : eV;
+      const bool on = e < m;
+      const float s = on ? ep * ri : 0.0f;
+      ev += on ? V : 0.0f;
+      ax = fmaf(s, dx, ax);
+      ay = fmaf(s, dy, ay);
+      const float sz = s * dz;
+      az += sz;
+      wz = fmaf(sz, dz, wz);
+    }
   }
   double e_i = 0.0, w_i = 0.0;
   if (valid) {
@@ -1037,8 +1074,13 @@ void launch_cells(const Dev &S, hipStream_t s) {
   k_cell_sort<<<nblk(S.C, kBlock), kBlock, 0, s>>>(S);
 }
 
-void launch_nlist(const Dev &S, double rl2, hipStream_t s) {
-  k_nlist<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl2);
+void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
+  const double rq = rl * S.qscale;
+  if (mixed)
+    k_nlist<true><<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl * rl,
+                                                       (float)(rq * rq));
+  else
+    k_nlist<false><<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl * rl, 0.0f);
 }
 
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,

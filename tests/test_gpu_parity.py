@@ -104,12 +104,19 @@ def test_neighbor_lists_are_exact_sets(precision):
     b = WireBatch(reps, precision)
     b.prepare()
     torch.cuda.synchronize()
+    rl = b.pot.r_cut + b.skin
+    # FP64 lists are exact; mixed ones compare quantised positions, so pairs
+    # within 1e-5 A of r_cut + skin may fall on either side
+    tol = 0.0 if precision == "fp64" else 1e-5
     for r in range(b.R):
         x, y, z = b.positions(r)
-        ref = brute_sets(x, y, z, b.pot.r_cut + b.skin)
+        sure = brute_sets(x, y, z, rl - tol)
+        loose = brute_sets(x, y, z, rl + tol)
         got = b.neighbor_rows(r)
-        for i in range(len(ref)):
-            assert np.array_equal(got[i], ref[i]), (r, i)
+        for i in range(len(sure)):
+            g = set(got[i].tolist())
+            assert len(g) == got[i].size
+            assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
     if precision == "mixed":
         # active lists of the density pass: core 0 < r <= r_tail, tail
         # r_tail < r <= r_cut (pairs within 1e-4 A of a boundary may fall on
@@ -118,16 +125,17 @@ def test_neighbor_lists_are_exact_sets(precision):
         for r in range(b.R):
             x, y, z = b.positions(r)
             P = np.stack([x, y, z], 1)
-            for i, (core, tail) in enumerate(b.active_rows(r)):
+            for i, (act, (nc, nt)) in enumerate(b.active_rows(r)):
                 d = np.sqrt(((P - P[i]) ** 2).sum(1))
                 d[i] = np.inf
-                sure_core = set(np.nonzero(d <= rt - 1e-4)[0])
-                sure_tail = set(np.nonzero((d > rt + 1e-4) & (d <= rc - 1e-4))[0])
-                maybe = set(np.nonzero((np.abs(d - rt) < 1e-4) | (np.abs(d - rc) < 1e-4))[0])
-                cs, ts = set(core.tolist()), set(tail.tolist())
-                assert len(cs) == core.size and len(ts) == tail.size
-                assert sure_core <= cs <= sure_core | maybe, (r, i)
-                assert sure_tail <= ts <= sure_tail | maybe, (r, i)
+                sure = set(np.nonzero(d <= rc - 1e-4)[0])
+                maybe = set(np.nonzero(np.abs(d - rc) < 1e-4)[0])
+                s = set(act.tolist())
+                assert len(s) == act.size
+                assert sure <= s <= sure | maybe, (r, i)
+                n_core = int(np.count_nonzero(d <= rt))
+                assert abs(nc - n_core) <= int(np.count_nonzero(np.abs(d - rt) < 1e-4))
+                assert nc + nt == act.size
     # rows are stored in ascending cell-scan order: check determinism
     b2 = WireBatch(reps, precision)
     b2.prepare()
