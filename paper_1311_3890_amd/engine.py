@@ -320,6 +320,32 @@ class WireBatch:
             out.append((row[bits == 1] - o, tuple(na[o + i])))
         return out
 
+    # ------------------------------------------------------------------------------------
+    # checkpoint / resume: the device state that the next step reads.  With the
+    # lists saved too, a resumed run repeats the original bit for bit (the
+    # noise is keyed by the step index, which is part of the state).
+    _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nn", "x_ref", "y_ref",
+              "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "obs", "work")
+
+    def state_dict(self):
+        return {k: self.t[k].detach().cpu().numpy().copy() for k in self._STATE}
+
+    def load_state_dict(self, st):
+        for k in self._STATE:
+            src = torch.from_numpy(np.ascontiguousarray(st[k]))
+            if src.shape != self.t[k].shape:
+                raise ValueError(f"checkpoint field {k} has shape {tuple(src.shape)}, "
+                                 f"expected {tuple(self.t[k].shape)}")
+            self.t[k].copy_(src.to(self.device))
+        torch.cuda.synchronize(self.device)
+
+    def save(self, path: str):
+        np.savez(path, **self.state_dict())
+
+    def load(self, path: str):
+        with np.load(path, allow_pickle=False) as f:
+            self.load_state_dict({k: f[k] for k in self._STATE})
+
     def status(self):
         return self.t["status"].cpu().numpy().view(np.uint32)
 

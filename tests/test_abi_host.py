@@ -93,3 +93,31 @@ def test_layout_checks():
     s2 = A.System(1, 4, 128, 10, C.cast(rep2, C.c_void_p), C.cast(cel, C.c_void_p))
     assert A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s2), C.byref(nb)) == A.EINVAL
     assert b"NULL" in A.lib().tbsma_last_error()
+
+
+def test_autotune_buckets_group_by_diameter_and_temperature():
+    import workloads as W
+    from paper_1311_3890_amd import autotune
+    wl = W.cfg4_mixed_shapes(64)
+    b = autotune.buckets(wl.replicas)
+    # diameters go round-robin by r mod 4 and temperatures by r mod 2, so each
+    # diameter comes with one temperature class
+    assert len(b) == 4
+    seen = sorted(r for idx in b.values() for r in idx)
+    assert seen == list(range(64))
+    for (D, cls), idx in b.items():
+        for r in idx:
+            assert wl.replicas[r].D == D
+            assert (wl.replicas[r].T < 100) == (cls == "cold")
+
+
+def test_workloads_are_seeded_and_snapped():
+    import workloads as W
+    a = W.cfg3_batched()
+    b = W.cfg3_batched()
+    assert [r.L for r in a.replicas] == [r.L for r in b.replicas]
+    assert len(a.replicas) == 512
+    for r in a.replicas:
+        n = r.L / (W.A_LAT / 2)
+        assert abs(n - round(n)) < 1e-9 and 50 - 2.04 <= r.L <= 400 + 2.04
+    assert len({r.seed for r in a.replicas}) == 512

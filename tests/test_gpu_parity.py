@@ -308,6 +308,23 @@ def test_graph_replay_equals_eager_bitwise():
     assert g.step_index() == e.step_index() == 100
 
 
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    reps = _three_replicas()
+    note("checkpoint / resume")
+    a = WireBatch(reps, "mixed", n_log=20)
+    a.prepare()
+    a.run_batch(60, 20)
+    path = str(tmp_path / "ck.npz")
+    a.save(path)
+    a.run_batch(60, 20)
+    b = WireBatch(reps, "mixed", n_log=20, qbits=a.qbits)
+    b.load(path)
+    assert b.step_index() == 60
+    b.run_batch(60, 20)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "obs", "status"):
+        assert torch.equal(a.t[k], b.t[k]), k
+
+
 def test_mixed_dynamics_track_fp64_oracle_forces():
     """Mixed precision over 200 steps at 298 K: the forces at the GPU's
     positions stay within eps_F <= 1e-5 of the oracle and lists get rebuilt."""
