@@ -175,11 +175,9 @@ typedef struct {
  * cell-scan order (cells by z, y, x; slots ascending within a cell).
  * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.
- * amask, nact (MIXED only; NULL for FP64): device [ceil(k_cap/32)*N] and
- * [2N] int32, rewritten by every density pass: bit k%32 of
- * amask[(k/32)*N + i] is set when entry k of atom i's list has
- * 0 < r <= r_cut at the current positions; nact[2i] and nact[2i+1] count
- * those with r <= r_tail and r > r_tail.
+ * nact (MIXED only; NULL for FP64): device [2N] int32, rewritten by every
+ * density pass: the numbers of list entries of atom i with 0 < r <= r_tail
+ * (nact[2i]) and r_tail < r <= r_cut (nact[2i+1]) at the current positions.
  */
 typedef struct {
   int32_t *nl;
@@ -187,7 +185,6 @@ typedef struct {
   int32_t k_cap;
   int32_t reserved;
   double *x_ref, *y_ref, *z_ref;
-  int32_t *amask;
   int32_t *nact;
 } tbsma_nlist;
 
@@ -258,9 +255,8 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
  * Host-side wire builder (Simulation details, Figure 1): the [100] FCC
  * cylinder of lattice constant a, diameter D and length L with the axis
  * through an atom column; sites (i, j, k) a/2 with i+j+k even,
- * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, ordered by slabs of four planes
- * (k/4) and, within a slab, by (i^2 + j^2, k, j, i) so that neighbouring
- * slots share a slab and a coordination; the n_grip lowest planes get
+ * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, in (k, j, i) order (planes along
+ * the axis, then rows, then columns); the n_grip lowest planes get
  * TBSMA_GRIP_FIXED and the n_grip highest TBSMA_GRIP_PULL.
  * x, y, z, flag are host arrays of capacity cap (may be NULL when cap = 0).
  * *n_out receives the atom count; TBSMA_ECAPACITY if it exceeds cap.

@@ -104,28 +104,13 @@ double orc_radial_eval(const orc_pot *P, int kind, double r, double *df) {
  * lattice sites (i, j, k) * a/2 with i + j + k even; the cylinder axis runs
  * along z through the atom column at x = y = 0.  A site is kept when
  * (i^2 + j^2) <= (D/a)^2 (that is, x^2 + y^2 <= (D/2)^2) and 0 <= k a/2 < L.
- * Generation order, which is also the tag order: slabs of four (002) planes
- * (k / 4) from the bottom up; within a slab, by distance from the axis
- * (i^2 + j^2), then k, j, i ascending.  Consecutive atoms therefore share a
- * slab and a similar coordination.  The lowest n_grip and highest n_grip
- * (002) planes are the rigid grips: flag 1 at the bottom (fixed), flag 2 at
- * the top (the end that is pulled); every other atom has flag 0 (dynamic).
+ * Generation order, which is also the tag order: k (z) outermost, then j (y),
+ * then i (x), ascending.  The lowest n_grip and highest n_grip (002) planes
+ * are the rigid grips: flag 1 at the bottom (fixed), flag 2 at the top (the
+ * end that is pulled); every other atom has flag 0 (dynamic).
  * Returns the number of atoms (also when cap is too small: then only the
  * count is computed and nothing is written past cap).
  */
-typedef struct {
-  int64_t r2, k, j, i;
-} orc_site;
-
-static int orc_cmp_site(const void *pa, const void *pb) {
-  const orc_site *a = (const orc_site *)pa, *b = (const orc_site *)pb;
-  if (a->r2 != b->r2) return a->r2 < b->r2 ? -1 : 1;
-  if (a->k != b->k) return a->k < b->k ? -1 : 1;
-  if (a->j != b->j) return a->j < b->j ? -1 : 1;
-  if (a->i != b->i) return a->i < b->i ? -1 : 1;
-  return 0;
-}
-
 int64_t orc_build_wire(double a, double D, double L, int n_grip,
                        double *x, double *y, double *z, uint8_t *flag,
                        int64_t cap) {
@@ -134,35 +119,25 @@ int64_t orc_build_wire(double a, double D, double L, int n_grip,
   int64_t nk = 0;
   while ((double)nk * half < L) nk++;
   int64_t m = (int64_t)floor(D / a) + 1;
-  orc_site *buf =
-      (orc_site *)malloc((size_t)(4 * (2 * m + 1) * (2 * m + 1)) * sizeof(orc_site));
   int64_t n = 0;
-  for (int64_t k0 = 0; k0 < nk; k0 += 4) {
-    int64_t cnt = 0;
-    for (int64_t k = k0; k < k0 + 4 && k < nk; k++)
-      for (int64_t j = -m; j <= m; j++)
-        for (int64_t i = -m; i <= m; i++) {
-          if (((i + j + k) % 2 + 2) % 2 != 0) continue;
-          if ((double)(i * i + j * j) > lim) continue;
-          orc_site st = {i * i + j * j, k, j, i};
-          buf[cnt++] = st;
+  for (int64_t k = 0; k < nk; k++) {
+    int fl = 0;
+    if (k < n_grip) fl = 1;
+    else if (k >= nk - n_grip) fl = 2;
+    for (int64_t j = -m; j <= m; j++) {
+      for (int64_t i = -m; i <= m; i++) {
+        if (((i + j + k) % 2 + 2) % 2 != 0) continue;
+        if ((double)(i * i + j * j) > lim) continue;
+        if (n < cap) {
+          x[n] = (double)i * half;
+          y[n] = (double)j * half;
+          z[n] = (double)k * half;
+          flag[n] = (uint8_t)fl;
         }
-    qsort(buf, (size_t)cnt, sizeof(orc_site), orc_cmp_site);
-    for (int64_t c = 0; c < cnt; c++) {
-      int64_t k = buf[c].k;
-      int fl = 0;
-      if (k < n_grip) fl = 1;
-      else if (k >= nk - n_grip) fl = 2;
-      if (n < cap) {
-        x[n] = (double)buf[c].i * half;
-        y[n] = (double)buf[c].j * half;
-        z[n] = (double)k * half;
-        flag[n] = (uint8_t)fl;
+        n++;
       }
-      n++;
     }
   }
-  free(buf);
   return n;
 }
 

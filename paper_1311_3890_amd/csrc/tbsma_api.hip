@@ -112,7 +112,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 }
 
 struct Layout {
-  size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum,
+  size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
       total;
 };
 
@@ -140,6 +140,8 @@ Layout layout(const tbsma_system *s) {
   o += 256;
   L.rsum = o;
   o += up(8 * 8 * (size_t)R);
+  L.win = o;
+  o += up(8 * (size_t)nt);
   L.total = o;
   return L;
 }
@@ -177,6 +179,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.ticket = reinterpret_cast<uint32_t *>(w + L.ticket);
   d.nnmax = reinterpret_cast<int32_t *>(w + L.nnmax);
   d.rsum = reinterpret_cast<double *>(w + L.rsum);
+  d.win = reinterpret_cast<int2 *>(w + L.win);
   d.cell = p->cell;
   d.inv_cell = 1.0 / p->cell;
   d.skin_half2 = 0.25 * p->skin * p->skin;
@@ -199,7 +202,6 @@ void attach_lists(Dev &d, const tbsma_cells *c, const tbsma_nlist *n) {
     d.xr = n->x_ref;
     d.yr = n->y_ref;
     d.zr = n->z_ref;
-    d.amask = n->amask;
     d.nact = n->nact;
   }
 }
@@ -334,8 +336,8 @@ int check_lists(const tbsma_params *p, const tbsma_cells *c,
             n->k_cap < 8 || n->k_cap % 8))
     return fail(TBSMA_EINVAL,
                 "neighbour-list arrays missing or k_cap not a multiple of 8");
-  if (n && p->precision == TBSMA_MIXED && (!n->amask || !n->nact))
-    return fail(TBSMA_EINVAL, "mixed precision needs the active-pair list");
+  if (n && p->precision == TBSMA_MIXED && !n->nact)
+    return fail(TBSMA_EINVAL, "mixed precision needs nact");
   return TBSMA_OK;
 }
 
@@ -443,40 +445,22 @@ int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
   while ((double)layers * h < L) ++layers;
   int64_t m = (int64_t)floor(D / a) + 1;
   int64_t n = 0;
-  // slabs of four planes; within a slab by distance from the axis, then
-  // plane, row, column: neighbouring slots share a slab and a coordination
-  struct Site {
-    int64_t r2, k, j, i;
-    bool operator<(const Site &o) const {
-      if (r2 != o.r2) return r2 < o.r2;
-      if (k != o.k) return k < o.k;
-      if (j != o.j) return j < o.j;
-      return i < o.i;
-    }
-  };
-  std::vector<Site> slab;
-  for (int64_t k0 = 0; k0 < layers; k0 += 4) {
-    slab.clear();
-    for (int64_t k = k0; k < k0 + 4 && k < layers; ++k)
-      for (int64_t j = -m; j <= m; ++j)
-        for (int64_t i = -m; i <= m; ++i) {
-          if ((i + j + k) & 1) continue;
-          if ((double)(i * i + j * j) > rad2) continue;
-          slab.push_back(Site{i * i + j * j, k, j, i});
+  for (int64_t k = 0; k < layers; ++k) {
+    uint8_t fl = k < n_grip ? TBSMA_GRIP_FIXED
+                 : k >= layers - n_grip ? TBSMA_GRIP_PULL
+                                        : TBSMA_DYN;
+    for (int64_t j = -m; j <= m; ++j)
+      for (int64_t i = -m; i <= m; ++i) {
+        if ((i + j + k) & 1) continue;
+        if ((double)(i * i + j * j) > rad2) continue;
+        if (n < cap) {
+          x[n] = (double)i * h;
+          y[n] = (double)j * h;
+          z[n] = (double)k * h;
+          flag[n] = fl;
         }
-    std::sort(slab.begin(), slab.end());
-    for (const Site &st : slab) {
-      const uint8_t fl = st.k < n_grip ? TBSMA_GRIP_FIXED
-                         : st.k >= layers - n_grip ? TBSMA_GRIP_PULL
-                                                   : TBSMA_DYN;
-      if (n < cap) {
-        x[n] = (double)st.i * h;
-        y[n] = (double)st.j * h;
-        z[n] = (double)st.k * h;
-        flag[n] = fl;
+        ++n;
       }
-      ++n;
-    }
   }
   *n_out = n;
   if (n > cap) return fail(TBSMA_ECAPACITY, "wire has %lld atoms", (long long)n);

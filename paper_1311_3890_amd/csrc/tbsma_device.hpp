@@ -61,7 +61,8 @@ struct Dev {
   // cells and lists
   int32_t *cell_start, *cell_atoms;
   int32_t *nl, *nn;
-  int32_t *amask, *nact;        // active-pair bits [k_cap/32*N], counts [2N]
+  int32_t *nact;                // pairs within r_cut per atom: core, tail
+  int2 *win;                    // [N/64] slot window [lo, hi) of a tile's lists
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace

@@ -286,6 +286,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
   Ring ring{ring_lds + threadIdx.x, 0, 0};
   int total = 0, cc = -1;
   int32_t s = 0, e = 0;
+  int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
   bool live = real;
   for (int it = 0;; ++it) {
     if (live) {
@@ -320,7 +321,11 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
           near = dx * dx + dy * dy + dz * dz < rl2;
         }
         if (near) {
-          if (total < S.k_cap) ring.push(j);
+          if (total < S.k_cap) {
+            ring.push(j);
+            wlo = min(wlo, j);
+            whi = max(whi, j);
+          }
           ++total;
         }
       }
@@ -328,6 +333,11 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
     if ((it & 7) == 7) ring.flush(S.nl, N, i, 0, 1);
   }
   ring.finish(S.nl, N, i, 0, 1);
+  // window of the tile's rows, [lo, hi): read by the pair passes to stage
+  // neighbour positions in LDS
+  wlo = -wave_max_i(-wlo);
+  whi = wave_max_i(whi);
+  if ((threadIdx.x & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
   if (total > S.k_cap) {
     atomicMax(S.nnmax, total);
     atomicOr(&S.wstatus[r], 1u);
@@ -357,13 +367,55 @@ __device__ __forceinline__ int4 gather_q(const int4 *qp, int j) {
                                          ((uint32_t)j << 4));
 }
 
-// One lane per atom.  Besides rho_i, the pass marks the pairs of the Verlet
-// list with 0 < r <= r_cut at the current positions: bit k%32 of
-// amask[(k/32)*N + i] is set for active entry k.  Words are written at
-// wave-uniform points as coalesced 256-byte stores; nact[2i], nact[2i+1]
-// count the active pairs with r <= r_tail and r > r_tail.
-__global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
-  const int64_t b0 = xcd_block() * kBlock;
+// Neighbour positions are gathered from LDS when the block's neighbours fit:
+// atoms are ordered along the wire, so the neighbours of the 256 slots of a
+// block lie in a short slot window [lo, hi) recorded per tile by the list
+// build; the block copies qpos[lo, hi) into LDS with coalesced loads and
+// gathers from there.  Blocks with wider windows (thick wires) gather from
+// global memory.
+constexpr int kStage = 1280;  // staged positions per block (20 KB)
+
+// Slot window of the block starting at slot b0 (union over its four tiles);
+// size 0 when some tile has no list yet.
+__device__ __forceinline__ void block_window(const Dev &S, int64_t b0,
+                                             int &lo, int &size) {
+  const int64_t t0 = b0 / kTile, nt = S.N / kTile;
+  int l = 0x7fffffff, h = 0;
+  bool ok = true;
+#pragma unroll
+  for (int t = 0; t < kBlock / kTile; ++t) {
+    if (t0 + t < nt) {
+      const int2 w = S.win[t0 + t];
+      ok = ok && w.y > w.x;
+      l = min(l, w.x);
+      h = max(h, w.y);
+    }
+  }
+  lo = l;
+  size = ok ? h - l : 0;
+}
+
+template <bool STAGED>
+__device__ __forceinline__ int4 fetch_q(const int4 *qp, const int4 *lq, int lo,
+                                        int j) {
+  if (STAGED) return lq[j - lo];
+  return gather_q(qp, j);
+}
+
+// Copies qpos[lo, lo+size) to lq (all threads of the block take part).
+__device__ __forceinline__ void stage(const Dev &S, int4 *lq, int lo,
+                                      int size) {
+  for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
+  __syncthreads();
+}
+
+// One lane per atom: rho_i over the Verlet list, g_i = 1/sqrt(rho_i) into
+// qpos[i].w; nact[2i], nact[2i+1] count the pairs with 0 < r <= r_tail and
+// r_tail < r <= r_cut.
+template <bool STAGED>
+__device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
+                                            int64_t b0, const int4 *lq,
+                                            int lo) {
   const int tid = threadIdx.x;
   const int64_t i = b0 + tid;
   const bool valid = i < S.N;
@@ -372,7 +424,6 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   const int n = valid ? S.nn[i] : 0;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
-  uint32_t *__restrict__ amask = reinterpret_cast<uint32_t *>(S.amask);
   const float aF = in_vgpr(P.aF), bF = in_vgpr(P.bF);
   const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
   const float f0 = in_vgpr(P.f0), f1 = in_vgpr(P.f1), f2 = in_vgpr(P.f2),
@@ -380,13 +431,10 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   const float rc2 = P.rc2, rt = P.rt;
   float rho = 0.0f;
   int nc = 0, nt = 0;
-  uint32_t word = 0u;
-  int last_k0 = -8;
-  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int k0) {
+  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
     int4 q[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
-    uint32_t bits = 0u;
+    for (int e = 0; e < 8; ++e) q[e] = fetch_q<STAGED>(qp, lq, lo, j[e]);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float dx = (float)(q[e].x - qi.x);
@@ -401,23 +449,27 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
       f = tail ? ft : f;
       const bool in = r2 < rc2 && r2 > 0.0f;
       rho += in ? f : 0.0f;
-      bits |= in ? 1u << e : 0u;
       nc += (in && !tail) ? 1 : 0;
       nt += (in && tail) ? 1 : 0;
     }
-    word |= bits << (k0 & 31);
-    if ((k0 & 31) == 24) {  // k0 is uniform: a whole word per lane
-      amask[(int64_t)(k0 >> 5) * N + i] = word;
-      word = 0u;
-    }
-    last_k0 = k0;
   });
-  if (last_k0 >= 0 && (last_k0 & 31) != 24)
-    amask[(int64_t)(last_k0 >> 5) * N + i] = word;
   if (valid) {
     const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
     S.qpos[i].w = __float_as_int(g);
     reinterpret_cast<int2 *>(S.nact)[i] = make_int2(nc, nt);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
+  __shared__ int4 lq[kStage];
+  const int64_t b0 = xcd_block() * kBlock;
+  int lo, size;
+  block_window(S, b0, lo, size);
+  if (size > 0 && size <= kStage) {
+    stage(S, lq, lo, size);
+    density_run<true>(S, P, b0, lq, lo);
+  } else {
+    density_run<false>(S, P, b0, lq, lo);
   }
 }
 
@@ -470,36 +522,25 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // ---------------------------------------------------------------------------
 // pass 2: forces, per-atom energies, per-tile sums of E and of the zz virial
 // ---------------------------------------------------------------------------
-// Each lane walks its Verlet list chunk by chunk and, using the active-pair
-// mask of pass 1, appends the pairs within r_cut to a per-lane LDS ring;
-// rounds then evaluate 8 ring entries per lane, so that lanes stay busy with
-// in-range pairs whatever their share of pairs beyond r_cut.  The ring holds
-// 16 entries: it is refilled while it holds fewer than 8, by at most 8 per
-// chunk.  Chunks are prefetched two ahead.  Per pair (core: exponentials of
+// One lane per atom over its Verlet list (positions staged in LDS as in
+// pass 1; q.w carries g_j).  Per pair within r_cut (core: exponentials of
 // eqs 1-2; tail: the cubic tails): E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2,
-// F_i += E'_ij d/r, E_i += V(r), w_i += E'_ij dz^2 / (2r); the sums run in
-// Verlet-list order.
-__global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
-                                                        float *fx, float *fy,
-                                                        float *fz,
-                                                        float *eat) {
-  __shared__ int32_t ring_lds[16 * kBlock];
-  const int64_t b0 = xcd_block() * kBlock;
+// F_i += E'_ij d/r, E_i += V(r), w_i += E'_ij dz^2 / (2r).
+template <bool STAGED>
+__device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
+                                          int64_t b0, const int4 *lq, int lo,
+                                          float *fx, float *fy, float *fz,
+                                          float *eat) {
   const int tid = threadIdx.x;
   const int64_t i = b0 + tid;
   const bool valid = i < S.N;
   const int self = valid ? (int)i : 0;
   const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
   const int n = valid ? S.nn[i] : 0;
-  const int nch = (n + 7) >> 3;
   const float gi = __int_as_float(qi.w);
   const float hgi = 0.5f * gi;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
-  const uint32_t *__restrict__ amask =
-      reinterpret_cast<const uint32_t *>(S.amask);
-  const int32_t *__restrict__ nl = S.nl;
-  int32_t *ring = ring_lds + tid;
   const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
   const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
   const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
@@ -507,53 +548,12 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
               v3 = in_vgpr(P.v3);
   const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1), d2 = in_vgpr(P.dv2);
   const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1), p2 = in_vgpr(P.dp2);
-  const float c2p = P.c2p, rt = P.rt;
-
-  // chunk queue: A = chunk p, B = chunk p+1 (indices and their 8 mask bits)
-  int4 a0, a1, c0, c1;
-  uint32_t ma = 0u, mb = 0u;
-  auto load_chunk = [&](int c, int4 &x0, int4 &x1, uint32_t &m) {
-    m = 0u;
-    if (c < nch) {
-      const int4 *p = reinterpret_cast<const int4 *>(nl + cl8(N, i, c));
-      x0 = p[0];
-      x1 = p[1];
-      m = (amask[(int64_t)(c >> 2) * N + i] >>
-           ((c & 3) * 8)) & 0xFFu;
-    }
-  };
-  load_chunk(0, a0, a1, ma);
-  load_chunk(1, c0, c1, mb);
-  int p = 0, cnt = 0, head = 0;
-  auto refill = [&]() {
-    while (cnt - head < 8 && p < nch) {
-      const int js[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if ((ma >> e) & 1u) {
-          ring[(cnt & 15) * kBlock] = js[e];
-          ++cnt;
-        }
-      }
-      a0 = c0;
-      a1 = c1;
-      ma = mb;
-      load_chunk(p + 2, c0, c1, mb);
-      ++p;
-    }
-  };
+  const float c2p = P.c2p, rt = P.rt, rc2 = P.rc2;
   float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
-  for (;;) {
-    refill();
-    const int m = min(8, cnt - head);
-    if (!wave_any(m > 0)) break;
+  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
     int4 q[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int j = e < m ? ring[((head + e) & 15) * kBlock] : self;
-      q[e] = gather_q(qp, j);
-    }
-    head += m;
+    for (int e = 0; e < 8; ++e) q[e] = fetch_q<STAGED>(qp, lq, lo, j[e]);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float dx = (float)(q[e].x - qi.x);
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
       const bool tail = rr > rt;
       const float ep = tail ? fmaf(G, dpt, dvt) : fmaf(G, eP, -c2p * eV);
       const float V = tail ? vt : eV;
-      const bool on = e < m;
+      const bool on = r2 < rc2 && r2 > 0.0f;
       const float s = on ? ep * ri : 0.0f;
       ev += on ? V : 0.0f;
       ax = fmaf(s, dx, ax);
@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
       az += sz;
       wz = fmaf(sz, dz, wz);
     }
-  }
+  });
   double e_i = 0.0, w_i = 0.0;
   if (valid) {
     const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
@@ -598,6 +598,22 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
     double *pt = S.part + (i / kTile) * kNPart;
     pt[kPartE] = e_i;
     pt[kPartW] = w_i;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
+                                                        float *fx, float *fy,
+                                                        float *fz,
+                                                        float *eat) {
+  __shared__ int4 lq[kStage];
+  const int64_t b0 = xcd_block() * kBlock;
+  int lo, size;
+  block_window(S, b0, lo, size);
+  if (size > 0 && size <= kStage) {
+    stage(S, lq, lo, size);
+    force_run<true>(S, P, b0, lq, lo, fx, fy, fz, eat);
+  } else {
+    force_run<false>(S, P, b0, lq, lo, fx, fy, fz, eat);
   }
 }
 

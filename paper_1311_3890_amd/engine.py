@@ -144,8 +144,6 @@ class WireBatch:
         T["nl"] = torch.zeros(k_cap * N, dtype=torch.int32, device=dev)
         T["nn"] = torch.zeros(N, dtype=torch.int32, device=dev)
         mixed = precision == "mixed"
-        T["amask"] = torch.zeros((k_cap + 31) // 32 * N if mixed else 1, dtype=torch.int32,
-                                 device=dev)
         T["nact"] = torch.zeros(2 * N if mixed else 1, dtype=torch.int32, device=dev)
         for k in ("fx", "fy", "fz", "e_atom"):
             T[k] = torch.zeros(N, dtype=ft, device=dev)
@@ -180,7 +178,6 @@ class WireBatch:
         self.cells = A.Cells(_ptr(T["cell_start"]), _ptr(T["cell_atoms"]))
         self.nlist = A.NList(_ptr(T["nl"]), _ptr(T["nn"]), k_cap, 0, _ptr(T["x_ref"]),
                              _ptr(T["y_ref"]), _ptr(T["z_ref"]),
-                             _ptr(T["amask"]) if mixed else None,
                              _ptr(T["nact"]) if mixed else None)
         self.out = A.ForcesOut(_ptr(T["fx"]), _ptr(T["fy"]), _ptr(T["fz"]), _ptr(T["e_atom"]),
                                _ptr(T["g"]) if precision == "fp64" else None,
@@ -229,10 +226,6 @@ class WireBatch:
         self.k_cap = k_cap
         self.t["nl"] = torch.zeros(k_cap * self.N, dtype=torch.int32, device=self.device)
         self.nlist.nl = _ptr(self.t["nl"])
-        if self.precision == "mixed":
-            self.t["amask"] = torch.zeros((k_cap + 31) // 32 * self.N, dtype=torch.int32,
-                                          device=self.device)
-            self.nlist.amask = _ptr(self.t["amask"])
         self.nlist.k_cap = k_cap
 
     def compute_forces(self):
@@ -302,23 +295,13 @@ class WireBatch:
         return [np.sort(nl[:, o + i, :].reshape(-1)[:nn[o + i]]) - o
                 for i in range(int(self.n_atoms[r]))]
 
-    def active_rows(self, r: int):
-        """Per atom of replica r (mixed only): the replica-local indices of the
-        list entries marked within r_cut by the last density pass, and the
-        (core, tail) counts of that pass."""
-        nn = self.t["nn"].cpu().numpy()
+    def active_counts(self, r: int):
+        """(core, tail) numbers of list entries within r_tail and within
+        (r_tail, r_cut] per atom of replica r, from the last density pass
+        (mixed precision only)."""
         na = self.t["nact"].view(self.N, 2).cpu().numpy()
-        nl = self.t["nl"].view(self.k_cap // 8, self.N, 8).cpu().numpy()
-        W = (self.k_cap + 31) // 32
-        am = self.t["amask"].view(W, self.N).cpu().numpy().view(np.uint32)
         o = int(self.rep_off[r])
-        out = []
-        for i in range(int(self.n_atoms[r])):
-            row = nl[:, o + i, :].reshape(-1)[:nn[o + i]]
-            k = np.arange(row.size)
-            bits = (am[k // 32, o + i] >> (k % 32).astype(np.uint32)) & 1
-            out.append((row[bits == 1] - o, tuple(na[o + i])))
-        return out
+        return na[o:o + int(self.n_atoms[r])].copy()
 
     # ------------------------------------------------------------------------------------
     # checkpoint / resume: the device state that the next step reads.  With the

@@ -118,24 +118,21 @@ def test_neighbor_lists_are_exact_sets(precision):
             assert len(g) == got[i].size
             assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
     if precision == "mixed":
-        # active lists of the density pass: core 0 < r <= r_tail, tail
-        # r_tail < r <= r_cut (pairs within 1e-4 A of a boundary may fall on
-        # either side in FP32)
+        # per-atom counts of pairs within r_tail and within (r_tail, r_cut]
+        # from the density pass (pairs within 1e-4 A of a boundary may fall
+        # on either side in FP32)
         rt, rc = b.pot.r_tail, b.pot.r_cut
         for r in range(b.R):
             x, y, z = b.positions(r)
             P = np.stack([x, y, z], 1)
-            for i, (act, (nc, nt)) in enumerate(b.active_rows(r)):
+            cnt = b.active_counts(r)
+            for i in range(P.shape[0]):
                 d = np.sqrt(((P - P[i]) ** 2).sum(1))
                 d[i] = np.inf
-                sure = set(np.nonzero(d <= rc - 1e-4)[0])
-                maybe = set(np.nonzero(np.abs(d - rc) < 1e-4)[0])
-                s = set(act.tolist())
-                assert len(s) == act.size
-                assert sure <= s <= sure | maybe, (r, i)
-                n_core = int(np.count_nonzero(d <= rt))
-                assert abs(nc - n_core) <= int(np.count_nonzero(np.abs(d - rt) < 1e-4))
-                assert nc + nt == act.size
+                edge_t = int(np.count_nonzero(np.abs(d - rt) < 1e-4))
+                edge_c = int(np.count_nonzero(np.abs(d - rc) < 1e-4))
+                assert abs(cnt[i, 0] - np.count_nonzero(d <= rt)) <= edge_t, (r, i)
+                assert abs(cnt[i].sum() - np.count_nonzero(d <= rc)) <= edge_c, (r, i)
     # rows are stored in ascending cell-scan order: check determinism
     b2 = WireBatch(reps, precision)
     b2.prepare()
