@@ -172,12 +172,15 @@ typedef struct {
 /*
  * Verlet lists (full: both i->j and j->i), stored in chunks of 8 entries:
  * entry k of atom i is nl[((k/8)*N + i)*8 + k%8], k < nn[i] <= k_cap, in
- * cell-scan order (cells by z, y, x; slots ascending within a cell).
+ * cell-scan order (cells by z, y, x; slots ascending within a cell).  The
+ * entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk hold
+ * 0x7fffffff.
  * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.
- * nact (MIXED only; NULL for FP64): device [2N] int32, rewritten by every
- * density pass: the numbers of list entries of atom i with 0 < r <= r_tail
- * (nact[2i]) and r_tail < r <= r_cut (nact[2i+1]) at the current positions.
+ * nact (optional, MIXED only; NULL to skip): device [2N] int32, rewritten
+ * by every density pass when given: the numbers of list entries of atom i
+ * with 0 < r <= r_tail (nact[2i]) and r_tail < r < r_cut (nact[2i+1]) at
+ * the current positions.  A diagnostic: the passes are faster without it.
  */
 typedef struct {
   int32_t *nl;

@@ -113,8 +113,18 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      total;
+      bmap, total;
 };
+
+// Blocks of the list build: ceil(tiles/4) per replica.
+int32_t block_map_size(const tbsma_system *s) {
+  int64_t nb = 0;
+  for (int r = 0; r < s->R; ++r) {
+    const int64_t nt = (s->rep_off_h[r + 1] - s->rep_off_h[r]) / TBSMA_TILE;
+    nb += (nt + 3) / 4;
+  }
+  return (int32_t)nb;
+}
 
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -142,6 +152,8 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * 8 * (size_t)R);
   L.win = o;
   o += up(8 * (size_t)nt);
+  L.bmap = o;
+  o += up(8 * (size_t)(nt / 4 + R + 1));
   L.total = o;
   return L;
 }
@@ -180,6 +192,8 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.nnmax = reinterpret_cast<int32_t *>(w + L.nnmax);
   d.rsum = reinterpret_cast<double *>(w + L.rsum);
   d.win = reinterpret_cast<int2 *>(w + L.win);
+  d.bmap = reinterpret_cast<int2 *>(w + L.bmap);
+  d.nbmap = s->R > 0 ? block_map_size(s) : 0;
   d.cell = p->cell;
   d.inv_cell = 1.0 / p->cell;
   d.skin_half2 = 0.25 * p->skin * p->skin;
@@ -260,25 +274,25 @@ PotF make_potf(const tbsma_params *p) {
   P.c2p = (float)(2.0 * p->p / p->r0);
   double w = p->r_cut - p->r_tail;
   double wi = w > 0 ? 1.0 / w : 0.0;
-  P.tS = (float)(s * wi);
-  P.tB = (float)(-p->r_tail * wi);
+  P.uS = (float)(-s * wi);
+  P.uB = (float)(p->r_cut * wi);
+  // With t = 1 - u, the Hermite cubic c0 + c1 t + c2 t^2 + c3 t^3 that meets
+  // (value c0, slope c1 per unit t) at r_tail and (0, 0) at r_cut equals
+  // u^2 (a + b u) with a = 3 c0 + c1 and b = -2 c0 - c1; its r-derivative
+  // is -u (2a + 3b u) / w.
   double cf[4], cv[4];
   hermite(xi2, 2.0 * p->q, p, cf);
   hermite(p->A, p->p, p, cv);
-  P.f0 = (float)cf[0];
-  P.f1 = (float)cf[1];
-  P.f2 = (float)cf[2];
-  P.f3 = (float)cf[3];
-  P.v0 = (float)cv[0];
-  P.v1 = (float)cv[1];
-  P.v2 = (float)cv[2];
-  P.v3 = (float)cv[3];
-  P.dv0 = (float)(2.0 * cv[1] * wi);
-  P.dv1 = (float)(4.0 * cv[2] * wi);
-  P.dv2 = (float)(6.0 * cv[3] * wi);
-  P.dp0 = (float)(-cf[1] * wi);
-  P.dp1 = (float)(-2.0 * cf[2] * wi);
-  P.dp2 = (float)(-3.0 * cf[3] * wi);
+  const double fa = 3.0 * cf[0] + cf[1], fb = -2.0 * cf[0] - cf[1];
+  const double va = 3.0 * cv[0] + cv[1], vb = -2.0 * cv[0] - cv[1];
+  P.fa = (float)fa;
+  P.fb = (float)fb;
+  P.va = (float)va;
+  P.vb = (float)vb;
+  P.dv0 = (float)(-4.0 * va * wi);
+  P.dv1 = (float)(-6.0 * vb * wi);
+  P.dp0 = (float)(2.0 * fa * wi);
+  P.dp1 = (float)(3.0 * fb * wi);
   P.wscale = (float)(0.5 * s);
   return P;
 }
@@ -336,8 +350,6 @@ int check_lists(const tbsma_params *p, const tbsma_cells *c,
             n->k_cap < 8 || n->k_cap % 8))
     return fail(TBSMA_EINVAL,
                 "neighbour-list arrays missing or k_cap not a multiple of 8");
-  if (n && p->precision == TBSMA_MIXED && !n->nact)
-    return fail(TBSMA_EINVAL, "mixed precision needs nact");
   return TBSMA_OK;
 }
 
@@ -430,6 +442,7 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
                   s);
   launch_fill_u64(reinterpret_cast<unsigned long long *>(w + L.zbmin),
                   (int64_t)sys->R * sys->max_zbins, ~0ull, s);
+  launch_block_map(make_dev(prm, sys, work), s);
   HIPCHK(hipGetLastError());
   return TBSMA_OK;
 }

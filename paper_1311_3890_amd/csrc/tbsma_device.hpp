@@ -33,11 +33,14 @@ struct PotF {
   float aF, bF;     // phi(r) = exp2(aF r + bF)
   float aV, bV;     // V(r)   = exp2(aV r + bV)
   float c2p;        // 2 p / r0
-  float tS, tB;     // t = tS r + tB on the tail
-  float f0, f1, f2, f3;   // phi on the tail: cubic in t
-  float v0, v1, v2, v3;   // V on the tail: cubic in t
-  float dv0, dv1, dv2;    // 2 V'(r) on the tail: quadratic in t
-  float dp0, dp1, dp2;    // -phi'(r) on the tail: quadratic in t
+  // The cubic tails on (r_tail, r_cut] in u = (r_cut - r)/(r_cut - r_tail),
+  // which vanish with their slope at u = 0; u is clamped at 0 beyond r_cut,
+  // so the tail expressions give exactly 0 there and need no cut-off test.
+  float uS, uB;     // u = uS r + uB
+  float fa, fb;     // phi    = u^2 (fa + fb u)
+  float va, vb;     // V      = u^2 (va + vb u)
+  float dv0, dv1;   // 2 V'(r) = u (dv0 + dv1 u)
+  float dp0, dp1;   // -phi'(r) = u (dp0 + dp1 u)
   float wscale;     // 2^-qbits / 2: converts the virial accumulator to eV
 };
 
@@ -63,6 +66,8 @@ struct Dev {
   int32_t *nl, *nn;
   int32_t *nact;                // pairs within r_cut per atom: core, tail
   int2 *win;                    // [N/64] slot window [lo, hi) of a tile's lists
+  int2 *bmap;                   // list-build blocks: first tile, tiles
+  int32_t nbmap;                // number of list-build blocks
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace

@@ -181,38 +181,50 @@ __device__ __forceinline__ int64_t cl8(int64_t N, int64_t i, int64_t chunk) {
   return (chunk * N + i) << 3;
 }
 
+// Value of the unused entries of a lane's last chunk, and a chunk made of
+// them (read by lanes whose list has ended while their wavefront goes on).
+constexpr int32_t kPadEntry = 0x7fffffff;
+__constant__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
+    kPadEntry, kPadEntry, kPadEntry, kPadEntry,
+    kPadEntry, kPadEntry, kPadEntry, kPadEntry};
+
 // Per-lane ring of 16 list entries in LDS, interleaved over the lanes of the
 // block (entry e of lane l at e * kBlock + l, so a wavefront's appends hit
 // distinct banks).  Lanes append at their own pace; at every 8th step of a
-// wave-uniform loop, each lane holding a full chunk writes it to the list as
-// one 32-byte store, so at most 7 + 8 entries are ever pending.
+// wave-uniform loop, each lane holding a full chunk writes it to its list as
+// one 32-byte store, so at most 7 + 8 entries are ever pending.  Entries
+// past the row's capacity (nch chunks) are counted but not stored.
 struct Ring {
   int32_t *lds;  // this lane's first entry
   int cnt;       // entries appended
-  int head;      // entries written to the list (a multiple of 8)
+  int head;      // entries passed on to the list (a multiple of 8)
   __device__ __forceinline__ void push(int j) {
     lds[(cnt & 15) * kBlock] = j;
     ++cnt;
   }
   __device__ __forceinline__ void store_chunk(int32_t *list, int64_t N,
-                                              int64_t i, int64_t chunk) {
-    const int32_t *e = lds + (head & 15) * kBlock;
-    int4 *dst = reinterpret_cast<int4 *>(list + cl8(N, i, chunk));
-    dst[0] = make_int4(e[0], e[kBlock], e[2 * kBlock], e[3 * kBlock]);
-    dst[1] = make_int4(e[4 * kBlock], e[5 * kBlock], e[6 * kBlock],
-                       e[7 * kBlock]);
+                                              int64_t i, int nch) {
+    if ((head >> 3) < nch) {
+      const int32_t *e = lds + (head & 15) * kBlock;
+      int4 *dst = reinterpret_cast<int4 *>(list + cl8(N, i, head >> 3));
+      dst[0] = make_int4(e[0], e[kBlock], e[2 * kBlock], e[3 * kBlock]);
+      dst[1] = make_int4(e[4 * kBlock], e[5 * kBlock], e[6 * kBlock],
+                         e[7 * kBlock]);
+    }
     head += 8;
   }
-  // chunk index of entry `head` in a list growing upwards from chunk c0
-  // (dir = +1) or downwards (dir = -1)
   __device__ __forceinline__ void flush(int32_t *list, int64_t N, int64_t i,
-                                        int64_t c0, int dir) {
-    if (cnt - head >= 8) store_chunk(list, N, i, c0 + dir * (head >> 3));
+                                        int nch) {
+    if (cnt - head >= 8) store_chunk(list, N, i, nch);
   }
-  // the last, partial chunks; entries past cnt in them are never read
+  // the last chunks; the unused entries of a partial chunk are set to
+  // kPadEntry
   __device__ __forceinline__ void finish(int32_t *list, int64_t N, int64_t i,
-                                         int64_t c0, int dir) {
-    while (cnt > head) store_chunk(list, N, i, c0 + dir * (head >> 3));
+                                         int nch) {
+    while (cnt > head) {
+      for (int e = cnt; e < head + 8; ++e) lds[(e & 15) * kBlock] = kPadEntry;
+      store_chunk(list, N, i, nch);
+    }
   }
 };
 
@@ -254,39 +266,86 @@ __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
   }
 }
 
+// Loop over the chunks of one lane's list in which every entry may be read:
+// the wavefront runs as many chunks as its longest list, a lane past its own
+// chunks reads the pad chunk, and the unused entries of a lane's last chunk
+// hold kPadEntry, so body(j[8]) gets 8 entries with no per-entry test.
+template <class F>
+__device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
+                                                  int64_t N, int64_t i, int n,
+                                                  F &&body) {
+  const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
+  const int nch = (nmax + 7) >> 3;
+  const int own = (n + 7) >> 3;
+  const int32_t *row = list + (i << 3);
+  const int64_t stride = N << 3;
+  const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
+  const int4 *p = own > 0 ? reinterpret_cast<const int4 *>(row) : pad;
+  int4 a = p[0], b = p[1];
+  for (int c = 0; c < nch; ++c) {
+    const int4 *q =
+        c + 1 < own ? reinterpret_cast<const int4 *>(row + (c + 1) * stride)
+                    : pad;
+    const int4 na = q[0], nb = q[1];
+    const int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    body(j);
+    a = na;
+    b = nb;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Verlet lists: scan the 27 cells around the atom's cell
+// Verlet lists
 // ---------------------------------------------------------------------------
-// One lane per atom, advancing through its candidates in a wave-uniform loop
-// (one candidate per lane per step, cells in z, y, x order, slots ascending
-// within a cell), so that the list is written in whole chunks through a
-// ring.  Rows longer than k_cap are truncated and reported.  Distances are
-// FP64 in FP64 mode; in mixed precision they come from the quantised
-// positions (one 16-byte gather, exact integer differences), compared with
-// (r_cut + skin)^2 in quanta^2 (rl2q).
+// One lane per atom; each lane writes its list in whole chunks through a ring
+// while its wavefront advances through candidates in a uniform loop (one
+// candidate per lane per step), so that list entries come out in ascending
+// cell order (z, y, x), slots ascending within a cell.  Rows longer than
+// k_cap are truncated and reported.  A block takes up to four tiles of one
+// replica (the block map, built once per workspace), so that a replica's
+// lists do not depend on its neighbours in the batch.
+//
+// Two ways of producing the candidates:
+//  * window scan (mixed precision): cells are slabs in z, so the cells of
+//    the z-slabs around a block's atoms are one contiguous range of the
+//    cell-sorted atom array.  The block copies the positions of that range
+//    into LDS once, as FP32 offsets from the block's first atom; every
+//    wavefront then tests its 64 atoms against the candidates of the slabs
+//    around its own atoms (LDS broadcast reads).  Taken when the range fits
+//    in LDS.
+//  * cell scan (otherwise, and in FP64 mode): each lane walks the 27 cells
+//    around its own cell, reading candidates from global memory.  Distances
+//    are FP64 in FP64 mode and exact integer differences of the quantised
+//    positions in mixed precision.
+// Both give every pair with distance below r_cut + skin (rl); since cells
+// are at least rl wide, the extra candidates of the window scan (cells of
+// the same slabs outside the 3x3 columns around an atom) are farther away
+// than that and never pass the test.  Pairs within a few 1e-6 A of rl may
+// fall on either side in the window scan (FP32 offsets); they lie beyond
+// r_cut, where every pair term is exactly zero.
+constexpr int kCand = 1536;  // window candidates staged per block (24 KB)
+
+struct ListRow {
+  Ring ring;
+  int32_t wlo, whi;  // slot window of the row
+  __device__ __forceinline__ void add(int32_t j) {
+    ring.push(j);
+    wlo = min(wlo, j);
+    whi = max(whi, j);
+  }
+};
+
 template <bool MIXED>
-__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
-                                                  float rl2q) {
-  __shared__ int32_t ring_lds[16 * kBlock];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= S.N) return;  // whole wavefronts (N is a multiple of 64)
-  const int r = S.tile_rep[i / kTile];
-  if (!rebuilds(S, r)) return;  // uniform over the wavefront
+__device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
+                                            bool real, int cx, int cy, int cz,
+                                            int4 qi, double rl2, float rl2q,
+                                            int nch, ListRow &row) {
   const int64_t N = S.N;
-  const bool real = S.flag[i] != 3;
   const int32_t *gd = S.grid_dim + 3 * r;
-  const double *lo = S.grid_lo + 3 * r;
-  const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
-  bool out = false;
-  const int cx = cell_coord(xi, lo[0], S.inv_cell, gd[0], out);
-  const int cy = cell_coord(yi, lo[1], S.inv_cell, gd[1], out);
-  const int cz = cell_coord(zi, lo[2], S.inv_cell, gd[2], out);
   const int32_t *start = S.cell_start + S.cell_off[r] + r;
-  const int4 qi = MIXED ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  Ring ring{ring_lds + threadIdx.x, 0, 0};
-  int total = 0, cc = -1;
+  const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
+  int cc = -1;
   int32_t s = 0, e = 0;
-  int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
   bool live = real;
   for (int it = 0;; ++it) {
     if (live) {
@@ -320,36 +379,182 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
           const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
           near = dx * dx + dy * dy + dz * dz < rl2;
         }
-        if (near) {
-          if (total < S.k_cap) {
-            ring.push(j);
-            wlo = min(wlo, j);
-            whi = max(whi, j);
+        if (near) row.add(j);
+      }
+    }
+    if ((it & 7) == 7) row.ring.flush(S.nl, N, i, nch);
+  }
+}
+
+// Tests this lane's atom (FP32 offset pi from the block origin) against
+// window candidates [a, b) of cand (x, y, z offsets and the slot as bits;
+// a and b uniform over the wavefront).  Candidates are read in groups of 8;
+// cand holds 8 filler entries past the window so the last group stays in
+// bounds, and entries at b or beyond are never taken.
+__device__ __forceinline__ void nlist_window(const Dev &S, int64_t i,
+                                             bool real, float4 pi,
+                                             const float4 *cand, int a, int b,
+                                             float rl2q, int nch,
+                                             ListRow &row) {
+  const int32_t self = real ? (int32_t)i : -2;
+  a = __builtin_amdgcn_readfirstlane(a);
+  b = __builtin_amdgcn_readfirstlane(b);
+  for (int t0 = a; t0 < b; t0 += 8) {
+    float4 c[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c[e] = cand[t0 + e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float dx = c[e].x - pi.x;
+      const float dy = c[e].y - pi.y;
+      const float dz = c[e].z - pi.z;
+      const int32_t j = __float_as_int(c[e].w);
+      const bool near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q &&
+                        j != self && t0 + e < b && real;
+      if (near) row.add(j);
+    }
+    row.ring.flush(S.nl, S.N, i, nch);
+  }
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
+                                                  float rl2q) {
+  __shared__ int32_t ring_lds[16 * kBlock];
+  __shared__ float4 cand[MIXED ? kCand + 8 : 1];
+  __shared__ int wzlo[kBlock / kTile], wzhi[kBlock / kTile];
+  const int tid = threadIdx.x, w = tid / kTile;
+  const int2 bm = S.bmap[blockIdx.x];  // first tile, tiles (1..4)
+  const int r = S.tile_rep[bm.x];
+  if (!rebuilds(S, r)) return;  // uniform over the block
+  const bool valid = w < bm.y;
+  const int64_t i = ((int64_t)bm.x + w) * kTile + (tid & (kTile - 1));
+  bool real = false;
+  int cx = 0, cy = 0, cz = 0;
+  int4 qi = make_int4(0, 0, 0, 0);
+  const int32_t *gd = S.grid_dim + 3 * r;
+  if (valid) {
+    real = S.flag[i] != 3;
+    const double *lo = S.grid_lo + 3 * r;
+    bool out = false;
+    cx = cell_coord(S.x[i], lo[0], S.inv_cell, gd[0], out);
+    cy = cell_coord(S.y[i], lo[1], S.inv_cell, gd[1], out);
+    cz = cell_coord(S.z[i], lo[2], S.inv_cell, gd[2], out);
+    if (MIXED) qi = S.qpos[i];
+  }
+  // z-cell range of the wavefront's real atoms (empty: lo > hi)
+  const int zlo = -wave_max_i(real ? -cz : -0x7fffffff);
+  const int zhi = wave_max_i(real ? cz : -1);
+  bool window = false;
+  int a = 0, b = 0;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (MIXED) {
+    if ((tid & (kTile - 1)) == 0) {
+      wzlo[w] = zlo;
+      wzhi[w] = zhi;
+    }
+    __syncthreads();
+    int bzlo = 0x7fffffff, bzhi = -1;
+#pragma unroll
+    for (int t = 0; t < kBlock / kTile; ++t) {
+      bzlo = min(bzlo, wzlo[t]);
+      bzhi = max(bzhi, wzhi[t]);
+    }
+    if (bzlo <= bzhi) {
+      const int gxy = gd[0] * gd[1];
+      const int32_t *start = S.cell_start + S.cell_off[r] + r;
+      const int32_t s0 = start[max(bzlo - 1, 0) * gxy];
+      const int32_t s1 = start[(min(bzhi + 1, gd[2] - 1) + 1) * gxy];
+      const int m = s1 - s0;
+      window = m <= kCand;
+      if (window) {
+        const int4 o = S.qpos[(int64_t)bm.x * kTile];
+        for (int t = tid; t < m + 8; t += kBlock) {
+          float4 c = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+          if (t < m) {
+            const int32_t j = S.cell_atoms[s0 + t];
+            const int4 q = S.qpos[j];
+            c = make_float4((float)(q.x - o.x), (float)(q.y - o.y),
+                            (float)(q.z - o.z), __int_as_float(j));
           }
-          ++total;
+          cand[t] = c;
+        }
+        pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
+                         (float)(qi.z - o.z), 0.f);
+        __syncthreads();
+        if (zlo <= zhi) {
+          a = start[max(zlo - 1, 0) * gxy] - s0;
+          b = start[(min(zhi + 1, gd[2] - 1) + 1) * gxy] - s0;
         }
       }
     }
-    if ((it & 7) == 7) ring.flush(S.nl, N, i, 0, 1);
   }
-  ring.finish(S.nl, N, i, 0, 1);
+  if (!valid) return;
+  const int64_t N = S.N;
+  const int nch = S.k_cap >> 3;
+  ListRow row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
+  if (window)
+    nlist_window(S, i, real, pi, cand, a, b, rl2q, nch, row);
+  else
+    nlist_cells<MIXED>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
+  row.ring.finish(S.nl, N, i, nch);
   // window of the tile's rows, [lo, hi): read by the pair passes to stage
   // neighbour positions in LDS
-  wlo = -wave_max_i(-wlo);
-  whi = wave_max_i(whi);
-  if ((threadIdx.x & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
+  const int32_t wlo = -wave_max_i(-row.wlo);
+  const int32_t whi = wave_max_i(row.whi);
+  if ((tid & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
+  const int total = row.ring.cnt;
   if (total > S.k_cap) {
     atomicMax(S.nnmax, total);
     atomicOr(&S.wstatus[r], 1u);
   }
   S.nn[i] = real ? min(total, S.k_cap) : 0;
-  S.xr[i] = xi;
-  S.yr[i] = yi;
-  S.zr[i] = zi;
+  S.xr[i] = S.x[i];
+  S.yr[i] = S.y[i];
+  S.zr[i] = S.z[i];
+}
+
+// Block map of the list build: for each replica, blocks of up to four of
+// its tiles, replicas in order (one block of 1024 threads; a scan over the
+// replicas of their block counts).
+__global__ void __launch_bounds__(1024) k_block_map(Dev S) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < S.R; b0 += 1024) {
+    const int r = b0 + threadIdx.x;
+    int32_t t0 = 0, nt = 0;
+    if (r < S.R) {
+      t0 = (int32_t)(S.rep_off[r] / kTile);
+      nt = (int32_t)(S.rep_off[r + 1] / kTile) - t0;
+    }
+    const int32_t v = (nt + 3) >> 2;
+    int32_t s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(s, o, 64);
+      if (lane >= o) s += t;
+    }
+    if (lane == 63) wsum[wid] = s;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wid) woff += wsum[k];
+      tot += wsum[k];
+    }
+    const int32_t ex = carry_s + woff + s - v;
+    for (int k = 0; k < v; ++k)
+      S.bmap[ex + k] = make_int2(t0 + 4 * k, min(4, nt - 4 * k));
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s += tot;
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: density rho_i -> g_i = 1/sqrt(rho_i), plus the active-pair lists
+// pass 1: density rho_i -> g_i = 1/sqrt(rho_i)
 // ---------------------------------------------------------------------------
 // Keeps a loop-invariant value in a VGPR (a VOP3 instruction reads at most
 // one scalar operand, so two uniform constants would otherwise be copied
@@ -395,24 +600,48 @@ __device__ __forceinline__ void block_window(const Dev &S, int64_t b0,
   size = ok ? h - l : 0;
 }
 
-template <bool STAGED>
-__device__ __forceinline__ int4 fetch_q(const int4 *qp, const int4 *lq, int lo,
-                                        int j) {
-  if (STAGED) return lq[j - lo];
-  return gather_q(qp, j);
+// Copies qpos[lo, lo+size) to lq[0, size) (all threads of the block take
+// part) and puts at lq[kStage] a sentinel position for the unused list
+// entries, which then contribute exactly nothing: their distance is beyond
+// r_cut, where the tail expressions vanish.  The sentinel lies 2^30 quanta
+// along x from the block's first atom; it is used only when every atom of
+// the block lies within 2^29 quanta of that atom along x, so it is at least
+// 2^29 quanta (32 A at 24 bits) from each of them and no difference
+// overflows.  Returns that condition (uniform over the block).
+__device__ __forceinline__ bool stage(const Dev &S, int4 *lq, int64_t b0,
+                                      int lo, int size) {
+  for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
+  const int4 q0 = S.qpos[b0];
+  const int64_t i = b0 + threadIdx.x;
+  const int xi = i < S.N ? S.qpos[i].x : q0.x;
+  const int64_t d = (int64_t)xi - (int64_t)q0.x;
+  const bool near = d > -(1ll << 29) && d < (1ll << 29);
+  if (threadIdx.x == 0)
+    lq[kStage] = make_int4(q0.x >= 0 ? q0.x - (1 << 30) : q0.x + (1 << 30),
+                           q0.y, q0.z, 0);
+  return __syncthreads_and(near) != 0;
 }
 
-// Copies qpos[lo, lo+size) to lq (all threads of the block take part).
-__device__ __forceinline__ void stage(const Dev &S, int4 *lq, int lo,
-                                      int size) {
-  for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
-  __syncthreads();
-}
+// LDS entry of list entry j: lq[min(j, lo + kStage) - lo] (kPadEntry -> the
+// sentinel), with the byte offset formed as min(j, jmax) * 16 - lo * 16.
+struct StagedIndex {
+  int jmax;       // lo + kStage
+  uint32_t nlo;   // -lo * 16 (mod 2^32)
+  __device__ __forceinline__ StagedIndex(int lo)
+      : jmax(lo + kStage), nlo(0u - ((uint32_t)lo << 4)) {}
+  __device__ __forceinline__ int4 get(const int4 *lq, int j) const {
+    const uint32_t off = ((uint32_t)min(j, jmax) << 4) + nlo;
+    return *reinterpret_cast<const int4 *>(
+        reinterpret_cast<const char *>(lq) + off);
+  }
+};
 
 // One lane per atom: rho_i over the Verlet list, g_i = 1/sqrt(rho_i) into
-// qpos[i].w; nact[2i], nact[2i+1] count the pairs with 0 < r <= r_tail and
-// r_tail < r <= r_cut.
-template <bool STAGED>
+// qpos[i].w.  With COUNT, nact[2i] and nact[2i+1] count the pairs with
+// 0 < r <= r_tail and r_tail < r < r_cut.  Staged: positions from LDS, the
+// unused entries hit the sentinel.  Not staged: global gathers, the unused
+// entries are replaced by the atom itself and masked (r = 0).
+template <bool STAGED, bool COUNT>
 __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
                                             int64_t b0, const int4 *lq,
                                             int lo) {
@@ -425,52 +654,65 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
   const float aF = in_vgpr(P.aF), bF = in_vgpr(P.bF);
-  const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
-  const float f0 = in_vgpr(P.f0), f1 = in_vgpr(P.f1), f2 = in_vgpr(P.f2),
-              f3 = in_vgpr(P.f3);
+  const float uS = in_vgpr(P.uS), uB = in_vgpr(P.uB);
+  const float fa = in_vgpr(P.fa), fb = in_vgpr(P.fb);
   const float rc2 = P.rc2, rt = P.rt;
   float rho = 0.0f;
   int nc = 0, nt = 0;
-  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
-    int4 q[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = fetch_q<STAGED>(qp, lq, lo, j[e]);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float dx = (float)(q[e].x - qi.x);
-      const float dy = (float)(q[e].y - qi.y);
-      const float dz = (float)(q[e].z - qi.z);
-      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const float rr = __builtin_amdgcn_sqrtf(r2);
-      float f = __builtin_amdgcn_exp2f(fmaf(aF, rr, bF));
-      const float t = fmaf(rr, tS, tB);
-      const float ft = fmaf(fmaf(fmaf(f3, t, f2), t, f1), t, f0);
-      const bool tail = rr > rt;
-      f = tail ? ft : f;
+  auto pair = [&](const int4 &q) {
+    const float dx = (float)(q.x - qi.x);
+    const float dy = (float)(q.y - qi.y);
+    const float dz = (float)(q.z - qi.z);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rr = __builtin_amdgcn_sqrtf(r2);
+    const float fc = __builtin_amdgcn_exp2f(fmaf(aF, rr, bF));
+    const float u = fmaxf(fmaf(rr, uS, uB), 0.0f);
+    const float ft = u * (u * fmaf(fb, u, fa));
+    const bool tail = rr > rt;
+    float f = tail ? ft : fc;
+    if (!STAGED) f = r2 > 0.0f ? f : 0.0f;
+    rho += f;
+    if (COUNT) {
       const bool in = r2 < rc2 && r2 > 0.0f;
-      rho += in ? f : 0.0f;
       nc += (in && !tail) ? 1 : 0;
       nt += (in && tail) ? 1 : 0;
     }
-  });
+  };
+  if (STAGED) {
+    const StagedIndex sx(lo);
+    chunk_loop_padded(S.nl, N, i, n, [&](const int (&j)[8]) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pair(q[e]);
+    });
+  } else {
+    chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pair(q[e]);
+    });
+  }
   if (valid) {
     const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
     S.qpos[i].w = __float_as_int(g);
-    reinterpret_cast<int2 *>(S.nact)[i] = make_int2(nc, nt);
+    if (COUNT) reinterpret_cast<int2 *>(S.nact)[i] = make_int2(nc, nt);
   }
 }
 
+template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
-  __shared__ int4 lq[kStage];
+  __shared__ int4 lq[kStage + 1];
   const int64_t b0 = xcd_block() * kBlock;
   int lo, size;
   block_window(S, b0, lo, size);
-  if (size > 0 && size <= kStage) {
-    stage(S, lq, lo, size);
-    density_run<true>(S, P, b0, lq, lo);
-  } else {
-    density_run<false>(S, P, b0, lq, lo);
-  }
+  if (size > 0 && size <= kStage && stage(S, lq, b0, lo, size))
+    density_run<true, COUNT>(S, P, b0, lq, lo);
+  else
+    density_run<false, COUNT>(S, P, b0, lq, lo);
 }
 
 __device__ __forceinline__ double radial_d(const PotD &P, bool dens,
@@ -523,9 +765,10 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // pass 2: forces, per-atom energies, per-tile sums of E and of the zz virial
 // ---------------------------------------------------------------------------
 // One lane per atom over its Verlet list (positions staged in LDS as in
-// pass 1; q.w carries g_j).  Per pair within r_cut (core: exponentials of
-// eqs 1-2; tail: the cubic tails): E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2,
-// F_i += E'_ij d/r, E_i += V(r), w_i += E'_ij dz^2 / (2r).
+// pass 1; q.w carries g_j).  Per pair (core r <= r_tail: exponentials of
+// eqs 1-2; tail: the cubic tails, zero from r_cut on):
+// E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, E_i += V(r),
+// w_i += E'_ij dz^2 / (2r).
 template <bool STAGED>
 __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
                                           int64_t b0, const int4 *lq, int lo,
@@ -543,45 +786,59 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   const int4 *__restrict__ qp = S.qpos;
   const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
   const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
-  const float tS = in_vgpr(P.tS), tB = in_vgpr(P.tB);
-  const float v0 = in_vgpr(P.v0), v1 = in_vgpr(P.v1), v2 = in_vgpr(P.v2),
-              v3 = in_vgpr(P.v3);
-  const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1), d2 = in_vgpr(P.dv2);
-  const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1), p2 = in_vgpr(P.dp2);
-  const float c2p = P.c2p, rt = P.rt, rc2 = P.rc2;
+  const float uS = in_vgpr(P.uS), uB = in_vgpr(P.uB);
+  const float va = in_vgpr(P.va), vb = in_vgpr(P.vb);
+  const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1);
+  const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1);
+  const float c2p = P.c2p, rt = P.rt;
   float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
-  chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
-    int4 q[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = fetch_q<STAGED>(qp, lq, lo, j[e]);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float dx = (float)(q[e].x - qi.x);
-      const float dy = (float)(q[e].y - qi.y);
-      const float dz = (float)(q[e].z - qi.z);
-      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const float ri = __builtin_amdgcn_rsqf(r2);
-      const float rr = r2 * ri;
-      const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
-      const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
-      const float t = fmaf(rr, tS, tB);
-      const float vt = fmaf(fmaf(fmaf(v3, t, v2), t, v1), t, v0);
-      const float dvt = fmaf(fmaf(d2, t, d1), t, d0);
-      const float dpt = fmaf(fmaf(p2, t, p1), t, p0);
-      const float G = fmaf(0.5f, __int_as_float(q[e].w), hgi);
-      const bool tail = rr > rt;
-      const float ep = tail ? fmaf(G, dpt, dvt) : fmaf(G, eP, -c2p * eV);
-      const float V = tail ? vt : eV;
-      const bool on = r2 < rc2 && r2 > 0.0f;
-      const float s = on ? ep * ri : 0.0f;
-      ev += on ? V : 0.0f;
-      ax = fmaf(s, dx, ax);
-      ay = fmaf(s, dy, ay);
-      const float sz = s * dz;
-      az += sz;
-      wz = fmaf(sz, dz, wz);
+  auto pair = [&](const int4 &q) {
+    const float dx = (float)(q.x - qi.x);
+    const float dy = (float)(q.y - qi.y);
+    const float dz = (float)(q.z - qi.z);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float rr = r2 * ri;
+    const float G = fmaf(0.5f, __int_as_float(q.w), hgi);
+    const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
+    const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
+    const float epc = fmaf(G, eP, -c2p * eV);
+    const float u = fmaxf(fmaf(rr, uS, uB), 0.0f);
+    const float ept = u * fmaf(G, fmaf(p1, u, p0), fmaf(d1, u, d0));
+    const float Vt = u * (u * fmaf(vb, u, va));
+    const bool tail = rr > rt;
+    float s = (tail ? ept : epc) * ri;
+    float V = tail ? Vt : eV;
+    if (!STAGED) {
+      const bool on = r2 > 0.0f;
+      s = on ? s : 0.0f;
+      V = on ? V : 0.0f;
     }
-  });
+    ev += V;
+    ax = fmaf(s, dx, ax);
+    ay = fmaf(s, dy, ay);
+    const float sz = s * dz;
+    az += sz;
+    wz = fmaf(sz, dz, wz);
+  };
+  if (STAGED) {
+    const StagedIndex sx(lo);
+    chunk_loop_padded(S.nl, N, i, n, [&](const int (&j)[8]) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pair(q[e]);
+    });
+  } else {
+    chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) pair(q[e]);
+    });
+  }
   double e_i = 0.0, w_i = 0.0;
   if (valid) {
     const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
@@ -605,16 +862,14 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         float *fx, float *fy,
                                                         float *fz,
                                                         float *eat) {
-  __shared__ int4 lq[kStage];
+  __shared__ int4 lq[kStage + 1];
   const int64_t b0 = xcd_block() * kBlock;
   int lo, size;
   block_window(S, b0, lo, size);
-  if (size > 0 && size <= kStage) {
-    stage(S, lq, lo, size);
+  if (size > 0 && size <= kStage && stage(S, lq, b0, lo, size))
     force_run<true>(S, P, b0, lq, lo, fx, fy, fz, eat);
-  } else {
+  else
     force_run<false>(S, P, b0, lq, lo, fx, fy, fz, eat);
-  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
@@ -1092,11 +1347,15 @@ void launch_cells(const Dev &S, hipStream_t s) {
 
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
   const double rq = rl * S.qscale;
+  if (S.nbmap == 0) return;
   if (mixed)
-    k_nlist<true><<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl * rl,
-                                                       (float)(rq * rq));
+    k_nlist<true><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, (float)(rq * rq));
   else
-    k_nlist<false><<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, rl * rl, 0.0f);
+    k_nlist<false><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, 0.0f);
+}
+
+void launch_block_map(const Dev &S, hipStream_t s) {
+  k_block_map<<<1, 1024, 0, s>>>(S);
 }
 
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
@@ -1104,7 +1363,10 @@ void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    hipStream_t s) {
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
-    k_density_mixed<<<nb, kBlock, 0, s>>>(S, PF);
+    if (S.nact)
+      k_density_mixed<true><<<nb, kBlock, 0, s>>>(S, PF);
+    else
+      k_density_mixed<false><<<nb, kBlock, 0, s>>>(S, PF);
     k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
                                         (float *)fz, (float *)eat);
   } else {
@@ -1119,8 +1381,10 @@ void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
                        double *g, hipStream_t s) {
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
-    if (pass == 1)
-      k_density_mixed<<<nb, kBlock, 0, s>>>(S, PF);
+    if (pass == 1 && S.nact)
+      k_density_mixed<true><<<nb, kBlock, 0, s>>>(S, PF);
+    else if (pass == 1)
+      k_density_mixed<false><<<nb, kBlock, 0, s>>>(S, PF);
     else
       k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
                                           (float *)fz, (float *)eat);

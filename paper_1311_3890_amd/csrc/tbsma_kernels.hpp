@@ -12,6 +12,7 @@ void launch_set_step(int64_t *p, int64_t v, hipStream_t s);
 void launch_quantise(const Dev &S, hipStream_t s);
 void launch_cells(const Dev &S, hipStream_t s);
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s);
+void launch_block_map(const Dev &S, hipStream_t s);
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    void *fx, void *fy, void *fz, void *eat, double *g,
                    hipStream_t s);

@@ -176,9 +176,10 @@ class WireBatch:
                                                    "vy", "vz", "z0", "flag")],
                             _ptr(T["qpos"]) if precision == "mixed" else None)
         self.cells = A.Cells(_ptr(T["cell_start"]), _ptr(T["cell_atoms"]))
+        # the per-atom pair counts are a diagnostic: the step loop runs
+        # without them, count_pairs() asks for them
         self.nlist = A.NList(_ptr(T["nl"]), _ptr(T["nn"]), k_cap, 0, _ptr(T["x_ref"]),
-                             _ptr(T["y_ref"]), _ptr(T["z_ref"]),
-                             _ptr(T["nact"]) if mixed else None)
+                             _ptr(T["y_ref"]), _ptr(T["z_ref"]), None)
         self.out = A.ForcesOut(_ptr(T["fx"]), _ptr(T["fy"]), _ptr(T["fz"]), _ptr(T["e_atom"]),
                                _ptr(T["g"]) if precision == "fp64" else None,
                                _ptr(T["rep_energy"]), _ptr(T["rep_wzz"]))
@@ -295,10 +296,23 @@ class WireBatch:
         return [np.sort(nl[:, o + i, :].reshape(-1)[:nn[o + i]]) - o
                 for i in range(int(self.n_atoms[r]))]
 
+    def count_pairs(self):
+        """Runs a density pass at the current positions that also counts,
+        per atom, the list entries with 0 < r <= r_tail and r_tail < r < r_cut
+        (mixed precision only; g_i is rewritten with the same values)."""
+        if self.precision != "mixed":
+            raise ValueError("pair counts are kept in mixed precision only")
+        nl = A.NList(self.nlist.nl, self.nlist.nn, self.nlist.k_cap, 0, self.nlist.x_ref,
+                     self.nlist.y_ref, self.nlist.z_ref, _ptr(self.t["nact"]))
+        A.check(A.lib().tbsma_forces_pass(C.byref(self.params), C.byref(self.sys), C.byref(nl),
+                                          C.byref(self.out), self.work, 1, self.stream()))
+        torch.cuda.synchronize(self.device)
+
     def active_counts(self, r: int):
         """(core, tail) numbers of list entries within r_tail and within
-        (r_tail, r_cut] per atom of replica r, from the last density pass
+        (r_tail, r_cut) per atom of replica r at the current positions
         (mixed precision only)."""
+        self.count_pairs()
         na = self.t["nact"].view(self.N, 2).cpu().numpy()
         o = int(self.rep_off[r])
         return na[o:o + int(self.n_atoms[r])].copy()
@@ -348,9 +362,10 @@ class WireBatch:
         return float(nn.sum().item() / max(1, int(self.n_atoms.sum())))
 
     def mean_active_pairs(self) -> float:
-        """Mean number of pairs within r_cut per real atom (mixed precision;
-        from the active list of the last density pass)."""
+        """Mean number of pairs within r_cut per real atom at the current
+        positions (mixed precision)."""
         if self.precision != "mixed":
             return float("nan")
+        self.count_pairs()
         na = self.t["nact"].double()
         return float(na.sum().item() / max(1, int(self.n_atoms.sum())))
