@@ -30,6 +30,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    profiler counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it
+    reads for a plain elementwise kernel of known size), or None when there is
+    no record or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+            rec = json.load(f)[kernel]
+        with open(os.path.join(ROOT, "paper_1311_3890_amd", "csrc", "tbsma_kernels.hip"),
+                  "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha or rec.get("workload") != workload:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,7 +132,8 @@ def main():
         return evs[0].elapsed_time(evs[1]) / args.pass_launches
 
     t_dens = time_pass(1)
-    t_force = time_pass(2)
+    t_force_e = time_pass(2)  # force pass with energies (logged steps)
+    t_force = time_pass(3)    # force pass as run on the other steps
     if args.copy_calibration:
         # a plain elementwise kernel that reads and writes 512 MiB each: the
         # HBM byte counters of a profiler run are scaled by what they read here
@@ -124,18 +144,21 @@ def main():
         log(f"[bench] calibration kernel: {src.numel() * 8} bytes read and written")
         del src, dst
     # bytes each kernel must move per launch (per real atom):
-    #  density: nn 4 + Verlet row 4 kbar + own position 16 + g 4 + counts 8
+    #  density: nn 4 + Verlet row 4 kbar + own position 16 + g 4
     #  force:   nn 4 + Verlet row 4 kbar + own position and g 16 + force 12
-    #           + energy 4
+    #           (+ energy 4 on logged steps)
     # (neighbour positions are staged per block and counted once per atom in
     # the own-position term)
     kact = b.mean_active_pairs()
-    bytes_force = n_real * (4.0 * kbar + 36.0)
-    bytes_dens = n_real * (4.0 * kbar + 32.0)
+    bytes_force = n_real * (4.0 * kbar + 32.0)
+    bytes_force_e = n_real * (4.0 * kbar + 36.0)
+    bytes_dens = n_real * (4.0 * kbar + 24.0)
     gbs_force = bytes_force / (t_force * 1e-3) / 1e9
+    gbs_force_e = bytes_force_e / (t_force_e * 1e-3) / 1e9
     gbs_dens = bytes_dens / (t_dens * 1e-3) / 1e9
     log(f"[bench] mean listed neighbours {kbar:.2f}, active pairs {kact:.2f}; density {t_dens * 1e3:.1f} us "
-        f"({gbs_dens:.0f} GB/s), force {t_force * 1e3:.1f} us ({gbs_force:.0f} GB/s)")
+        f"({gbs_dens:.0f} GB/s), force {t_force * 1e3:.1f} us ({gbs_force:.0f} GB/s), "
+        f"force with energies {t_force_e * 1e3:.1f} us")
 
     # ---- plain path: the same kind of replicas, one replica per launch ----------------
     pr = None
@@ -235,14 +258,18 @@ def main():
                    "steps_per_graph": S, "skin_A": b.skin, "r_cut_A": b.pot.r_cut,
                    "parallelism": "replica batch, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
+                     "traffic": counter_traffic("k_force_mixed", wl.name),
                      "kernel": "k_force_mixed",
                      "algorithmic_bytes_per_launch": bytes_force,
                      "avg_launch_us": t_force * 1e3,
                      "mean_listed_neighbours": kbar,
                      "mean_active_pairs": kact},
         "kernels": {"density": {"avg_launch_us": t_dens * 1e3, "GB/s": gbs_dens,
-                                "frac": gbs_dens / HBM_PEAK_GBS}},
+                                "frac": gbs_dens / HBM_PEAK_GBS},
+                    "force_with_energies": {"avg_launch_us": t_force_e * 1e3,
+                                            "GB/s": gbs_force_e,
+                                            "frac": gbs_force_e / HBM_PEAK_GBS}},
         "per_replica_value": pr,
         "batched_over_per_replica": (value / pr) if pr else None,
         "bad_replicas": bad,

@@ -181,6 +181,11 @@ typedef struct {
  * by every density pass when given: the numbers of list entries of atom i
  * with 0 < r <= r_tail (nact[2i]) and r_tail < r < r_cut (nact[2i+1]) at
  * the current positions.  A diagnostic: the passes are faster without it.
+ * nl_lane (MIXED; NULL for FP64): device [k_cap*N] int32, a copy of the lists
+ * written by the list build in the order the mixed pair passes read them:
+ * within each block of up to four tiles of one replica, atoms by descending
+ * list length (ties by slot), the p-th atom's list as row (block start + p)
+ * of the same chunked layout.  Opaque to the caller.
  */
 typedef struct {
   int32_t *nl;
@@ -189,6 +194,7 @@ typedef struct {
   int32_t reserved;
   double *x_ref, *y_ref, *z_ref;
   int32_t *nact;
+  int32_t *nl_lane;
 } tbsma_nlist;
 
 /*
@@ -316,10 +322,12 @@ int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
  * One of the two passes of tbsma_forces on its own, for timing and for
  * callers that keep g: pass 1 is the density pass (writes g_i), pass 2 the
  * force pass (reads the g_i of pass 1, writes forces, energies and the
- * per-tile sums; no per-replica reduction).  In MIXED precision both read the
- * quantised positions in qpos as last written by the library (every call that
- * moves atoms or builds lists keeps them current).  TBSMA_EINVAL for any other
- * pass number.
+ * per-tile sums; no per-replica reduction), pass 3 the force pass as the
+ * MIXED step loops run it on steps that are not logged (forces only; e_atom
+ * and the tile sums untouched; in FP64 the same as pass 2).  In MIXED
+ * precision all read the quantised positions in qpos as last written by the
+ * library (every call that moves atoms or builds lists keeps them current).
+ * TBSMA_EINVAL for any other pass number.
  */
 int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
                       const tbsma_nlist *nl, tbsma_forces_out *out, void *work,
@@ -333,8 +341,12 @@ int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
  * per-replica rebuild of cells and lists where some atom moved more than
  * skin/2 since the last build; both force passes; half kick; per-replica
  * reductions and observables.  Forces in `out` must hold F at the current
- * state on entry (tbsma_forces).  Synchronises at the end and returns
- * TBSMA_ECAPACITY if any list overflowed during the call.
+ * state on entry (tbsma_forces).  Forces are rewritten every step; in MIXED
+ * precision the per-atom energies e_atom (and the energy and virial behind
+ * the observables) are evaluated only on logged steps ((step+1) % n_log ==
+ * 0), so after a call e_atom belongs to the last logged step.  Synchronises
+ * at the end and returns TBSMA_ECAPACITY if any list overflowed during the
+ * call.
  */
 int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
                tbsma_nlist *nl, tbsma_forces_out *out, const tbsma_md *md,

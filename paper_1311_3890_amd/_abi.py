@@ -46,7 +46,7 @@ class Cells(C.Structure):
 
 class NList(C.Structure):
     _fields_ = [("nl", vp), ("nn", vp), ("k_cap", C.c_int32), ("reserved", C.c_int32),
-                ("x_ref", vp), ("y_ref", vp), ("z_ref", vp), ("nact", vp)]
+                ("x_ref", vp), ("y_ref", vp), ("z_ref", vp), ("nact", vp), ("nl_lane", vp)]
 
 
 class ForcesOut(C.Structure):

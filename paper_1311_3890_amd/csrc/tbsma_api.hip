@@ -113,7 +113,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      bmap, total;
+      bmap, lane_atom, nn_lane, total;
 };
 
 // Blocks of the list build: ceil(tiles/4) per replica.
@@ -154,6 +154,10 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * (size_t)nt);
   L.bmap = o;
   o += up(8 * (size_t)(nt / 4 + R + 1));
+  L.lane_atom = o;
+  o += up((size_t)s->N);
+  L.nn_lane = o;
+  o += up(4 * (size_t)s->N);
   L.total = o;
   return L;
 }
@@ -193,6 +197,8 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.rsum = reinterpret_cast<double *>(w + L.rsum);
   d.win = reinterpret_cast<int2 *>(w + L.win);
   d.bmap = reinterpret_cast<int2 *>(w + L.bmap);
+  d.lane_atom = reinterpret_cast<uint8_t *>(w + L.lane_atom);
+  d.nn_lane = reinterpret_cast<int32_t *>(w + L.nn_lane);
   d.nbmap = s->R > 0 ? block_map_size(s) : 0;
   d.cell = p->cell;
   d.inv_cell = 1.0 / p->cell;
@@ -201,6 +207,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.inv_qscale = 1.0 / d.qscale;
   d.mass = p->mass;
   d.all = 0;
+  d.energies = 1;
   return d;
 }
 
@@ -217,6 +224,7 @@ void attach_lists(Dev &d, const tbsma_cells *c, const tbsma_nlist *n) {
     d.yr = n->y_ref;
     d.zr = n->z_ref;
     d.nact = n->nact;
+    d.nl_lane = n->nl_lane;
   }
 }
 
@@ -271,7 +279,7 @@ PotF make_potf(const tbsma_params *p) {
   P.bP = (float)(log2(xi2 * 2.0 * p->q / p->r0) + 2.0 * p->q * log2e);
   P.aV = (float)(-p->p * log2e * s / p->r0);
   P.bV = (float)(log2(p->A) + p->p * log2e);
-  P.c2p = (float)(2.0 * p->p / p->r0);
+  P.bW = (float)(log2(p->A * 2.0 * p->p / p->r0) + p->p * log2e);
   double w = p->r_cut - p->r_tail;
   double wi = w > 0 ? 1.0 / w : 0.0;
   P.uS = (float)(-s * wi);
@@ -350,6 +358,8 @@ int check_lists(const tbsma_params *p, const tbsma_cells *c,
             n->k_cap < 8 || n->k_cap % 8))
     return fail(TBSMA_EINVAL,
                 "neighbour-list arrays missing or k_cap not a multiple of 8");
+  if (n && p->precision == TBSMA_MIXED && !n->nl_lane)
+    return fail(TBSMA_EINVAL, "mixed precision needs nl_lane");
   return TBSMA_OK;
 }
 
@@ -369,7 +379,11 @@ void enqueue_step(const tbsma_params *p, const Dev &d, const DevMD &M,
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_cells(d, s);
   launch_nlist(d, mixed, rl, s);
-  launch_forces(d, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
+  Dev df = d;
+  df.energies = -1;
+  df.step = M.step;
+  df.n_log = M.n_log;
+  launch_forces(df, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
   launch_integrate_b(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_reduce_step(d, M, s);
 }
@@ -579,12 +593,13 @@ int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
   if (!nl) return fail(TBSMA_EINVAL, "nlist is NULL");
   TRY(check_lists(prm, nullptr, nl));
   TRY(check_out(prm, out));
-  if (pass != 1 && pass != 2) return fail(TBSMA_EINVAL, "pass must be 1 or 2");
+  if (pass < 1 || pass > 3) return fail(TBSMA_EINVAL, "pass must be 1, 2 or 3");
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(prm, sys, work);
   attach_lists(d, nullptr, nl);
+  if (pass == 3) d.energies = 0;
   launch_force_pass(d, prm->precision == TBSMA_MIXED, pass, make_potf(prm),
                     make_potd(prm), out->fx, out->fy, out->fz, out->e_atom,
                     out->g, s);

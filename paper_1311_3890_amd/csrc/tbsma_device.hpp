@@ -32,7 +32,7 @@ struct PotF {
   float aP, bP;     // (2q/r0) phi(r) = exp2(aP r + bP)
   float aF, bF;     // phi(r) = exp2(aF r + bF)
   float aV, bV;     // V(r)   = exp2(aV r + bV)
-  float c2p;        // 2 p / r0
+  float bW;         // -2 V'(r) = (2p/r0) V(r) = exp2(aV r + bW)
   // The cubic tails on (r_tail, r_cut] in u = (r_cut - r)/(r_cut - r_tail),
   // which vanish with their slope at u = 0; u is clamped at 0 beyond r_cut,
   // so the tail expressions give exactly 0 there and need no cut-off test.
@@ -67,7 +67,16 @@ struct Dev {
   int32_t *nact;                // pairs within r_cut per atom: core, tail
   int2 *win;                    // [N/64] slot window [lo, hi) of a tile's lists
   int2 *bmap;                   // list-build blocks: first tile, tiles
+  uint8_t *lane_atom;           // [N] pair-pass lane order within a block
+  int32_t *nn_lane;             // [N] list lengths in lane order
+  int32_t *nl_lane;             // lists in lane order (CL8 layout), or NULL
   int32_t nbmap;                // number of list-build blocks
+  // when the mixed force pass computes energies and the virial: 1 always,
+  // 0 never, -1 when the step being completed is logged ((*step + 1) %
+  // n_log == 0, the step loops)
+  int32_t energies;
+  int32_t n_log;
+  const int64_t *step;
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace

@@ -489,29 +489,55 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
       }
     }
   }
-  if (!valid) return;
-  const int64_t N = S.N;
-  const int nch = S.k_cap >> 3;
-  ListRow row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
-  if (window)
-    nlist_window(S, i, real, pi, cand, a, b, rl2q, nch, row);
-  else
-    nlist_cells<MIXED>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
-  row.ring.finish(S.nl, N, i, nch);
-  // window of the tile's rows, [lo, hi): read by the pair passes to stage
-  // neighbour positions in LDS
-  const int32_t wlo = -wave_max_i(-row.wlo);
-  const int32_t whi = wave_max_i(row.whi);
-  if ((tid & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
-  const int total = row.ring.cnt;
-  if (total > S.k_cap) {
-    atomicMax(S.nnmax, total);
-    atomicOr(&S.wstatus[r], 1u);
+  int nn_i = -1;  // list length of this thread's atom (-1: no atom)
+  if (valid) {
+    const int64_t N = S.N;
+    const int nch = S.k_cap >> 3;
+    ListRow row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
+    if (window)
+      nlist_window(S, i, real, pi, cand, a, b, rl2q, nch, row);
+    else
+      nlist_cells<MIXED>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
+    row.ring.finish(S.nl, N, i, nch);
+    // window of the tile's rows, [lo, hi): read by the pair passes to stage
+    // neighbour positions in LDS
+    const int32_t wlo = -wave_max_i(-row.wlo);
+    const int32_t whi = wave_max_i(row.whi);
+    if ((tid & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
+    const int total = row.ring.cnt;
+    if (total > S.k_cap) {
+      atomicMax(S.nnmax, total);
+      atomicOr(&S.wstatus[r], 1u);
+    }
+    nn_i = real ? min(total, S.k_cap) : 0;
+    S.nn[i] = nn_i;
+    S.xr[i] = S.x[i];
+    S.yr[i] = S.y[i];
+    S.zr[i] = S.z[i];
   }
-  S.nn[i] = real ? min(total, S.k_cap) : 0;
-  S.xr[i] = S.x[i];
-  S.yr[i] = S.y[i];
-  S.zr[i] = S.z[i];
+  // lane order of the pair passes: the block's atoms by descending list
+  // length, ties by slot (keys are distinct)
+  __syncthreads();  // the ring is no longer needed
+  int32_t *key = ring_lds;
+  key[tid] = nn_i < 0 ? 0x7fffffff : ((255 - min(nn_i, 255)) << 8) | tid;
+  __syncthreads();
+  if (valid) {
+    const int32_t k = key[tid];
+    int rank = 0;
+    for (int m = 0; m < bm.y * kTile; ++m) rank += key[m] < k ? 1 : 0;
+    const int64_t row = (int64_t)bm.x * kTile + rank;
+    S.lane_atom[row] = (uint8_t)tid;
+    S.nn_lane[row] = nn_i;
+    // the row again, at the lane position (chunks this thread just wrote)
+    if (S.nl_lane) {
+      for (int c = 0; c < (nn_i + 7) >> 3; ++c) {
+        const int4 *src = reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c));
+        int4 *dst = reinterpret_cast<int4 *>(S.nl_lane + cl8(S.N, row, c));
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
+    }
+  }
 }
 
 // Block map of the list build: for each replica, blocks of up to four of
@@ -572,25 +598,51 @@ __device__ __forceinline__ int4 gather_q(const int4 *qp, int j) {
                                          ((uint32_t)j << 4));
 }
 
+// The pair passes run over the blocks of the list build (up to four tiles of
+// one replica).  Lane p of a block evaluates atom b0 + lane_atom[b0 + p]: the
+// list build orders each block's atoms by descending list length, so that the
+// lists of a wavefront have similar lengths (a wavefront runs as many steps as
+// its longest list).  Each atom's own sums run in list order whichever lane
+// takes it, so results do not depend on the assignment.
+struct PairBlock {
+  int64_t b0;  // first slot
+  int t0, nt;  // first tile, tiles
+  int p;       // this thread's position
+  bool valid;  // p < 64 nt
+  int64_t i;   // the atom this thread evaluates
+  int n;       // its list length; its list is row b0 + p of nl_lane
+};
+
+__device__ __forceinline__ PairBlock pair_block(const Dev &S) {
+  const int2 bm = S.bmap[xcd_block()];
+  PairBlock B;
+  B.t0 = bm.x;
+  B.nt = bm.y;
+  B.b0 = (int64_t)bm.x * kTile;
+  B.p = threadIdx.x;
+  B.valid = B.p < bm.y * kTile;
+  B.i = B.b0 + (B.valid ? (int)S.lane_atom[B.b0 + B.p] : 0);
+  B.n = B.valid ? S.nn_lane[B.b0 + B.p] : 0;
+  return B;
+}
+
 // Neighbour positions are gathered from LDS when the block's neighbours fit:
-// atoms are ordered along the wire, so the neighbours of the 256 slots of a
-// block lie in a short slot window [lo, hi) recorded per tile by the list
-// build; the block copies qpos[lo, hi) into LDS with coalesced loads and
-// gathers from there.  Blocks with wider windows (thick wires) gather from
-// global memory.
+// atoms are ordered along the wire, so the neighbours of a block's slots lie
+// in a short slot window [lo, hi) recorded per tile by the list build; the
+// block copies qpos[lo, hi) into LDS with coalesced loads and gathers from
+// there.  Blocks with wider windows (thick wires) gather from global memory.
 constexpr int kStage = 1280;  // staged positions per block (20 KB)
 
-// Slot window of the block starting at slot b0 (union over its four tiles);
-// size 0 when some tile has no list yet.
-__device__ __forceinline__ void block_window(const Dev &S, int64_t b0,
+// Slot window of the block (union over its tiles); size 0 when some tile has
+// no list yet.
+__device__ __forceinline__ void block_window(const Dev &S, const PairBlock &B,
                                              int &lo, int &size) {
-  const int64_t t0 = b0 / kTile, nt = S.N / kTile;
   int l = 0x7fffffff, h = 0;
   bool ok = true;
 #pragma unroll
   for (int t = 0; t < kBlock / kTile; ++t) {
-    if (t0 + t < nt) {
-      const int2 w = S.win[t0 + t];
+    if (t < B.nt) {
+      const int2 w = S.win[B.t0 + t];
       ok = ok && w.y > w.x;
       l = min(l, w.x);
       h = max(h, w.y);
@@ -608,12 +660,11 @@ __device__ __forceinline__ void block_window(const Dev &S, int64_t b0,
 // the block lies within 2^29 quanta of that atom along x, so it is at least
 // 2^29 quanta (32 A at 24 bits) from each of them and no difference
 // overflows.  Returns that condition (uniform over the block).
-__device__ __forceinline__ bool stage(const Dev &S, int4 *lq, int64_t b0,
-                                      int lo, int size) {
+__device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
+                                      const PairBlock &B, int lo, int size) {
   for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
-  const int4 q0 = S.qpos[b0];
-  const int64_t i = b0 + threadIdx.x;
-  const int xi = i < S.N ? S.qpos[i].x : q0.x;
+  const int4 q0 = S.qpos[B.b0];
+  const int xi = B.valid ? S.qpos[B.b0 + B.p].x : q0.x;
   const int64_t d = (int64_t)xi - (int64_t)q0.x;
   const bool near = d > -(1ll << 29) && d < (1ll << 29);
   if (threadIdx.x == 0)
@@ -643,14 +694,14 @@ struct StagedIndex {
 // entries are replaced by the atom itself and masked (r = 0).
 template <bool STAGED, bool COUNT>
 __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
-                                            int64_t b0, const int4 *lq,
-                                            int lo) {
-  const int tid = threadIdx.x;
-  const int64_t i = b0 + tid;
-  const bool valid = i < S.N;
+                                            const PairBlock &B,
+                                            const int4 *lq, int lo) {
+  const int64_t i = B.i;
+  const bool valid = B.valid;
   const int self = valid ? (int)i : 0;
   const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  const int n = valid ? S.nn[i] : 0;
+  const int n = B.n;
+  const int64_t row = B.b0 + B.p;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
   const float aF = in_vgpr(P.aF), bF = in_vgpr(P.bF);
@@ -680,7 +731,7 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
   };
   if (STAGED) {
     const StagedIndex sx(lo);
-    chunk_loop_padded(S.nl, N, i, n, [&](const int (&j)[8]) {
+    chunk_loop_padded(S.nl_lane, N, row, n, [&](const int (&j)[8]) {
       int4 q[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
@@ -688,7 +739,7 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
       for (int e = 0; e < 8; ++e) pair(q[e]);
     });
   } else {
-    chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+    chunk_loop(S.nl_lane, N, row, self, n, 0, 1, [&](const int (&j)[8], int) {
       int4 q[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
@@ -706,13 +757,13 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
 template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   __shared__ int4 lq[kStage + 1];
-  const int64_t b0 = xcd_block() * kBlock;
+  const PairBlock B = pair_block(S);
   int lo, size;
-  block_window(S, b0, lo, size);
-  if (size > 0 && size <= kStage && stage(S, lq, b0, lo, size))
-    density_run<true, COUNT>(S, P, b0, lq, lo);
+  block_window(S, B, lo, size);
+  if (size > 0 && size <= kStage && stage(S, lq, B, lo, size))
+    density_run<true, COUNT>(S, P, B, lq, lo);
   else
-    density_run<false, COUNT>(S, P, b0, lq, lo);
+    density_run<false, COUNT>(S, P, B, lq, lo);
 }
 
 __device__ __forceinline__ double radial_d(const PotD &P, bool dens,
@@ -767,30 +818,32 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // One lane per atom over its Verlet list (positions staged in LDS as in
 // pass 1; q.w carries g_j).  Per pair (core r <= r_tail: exponentials of
 // eqs 1-2; tail: the cubic tails, zero from r_cut on):
-// E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, E_i += V(r),
-// w_i += E'_ij dz^2 / (2r).
-template <bool STAGED>
+// E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, and with ENERGY
+// also E_i += V(r), w_i += E'_ij dz^2 / (2r).  Without ENERGY (steps whose
+// observables are not logged) e_atom and the tile sums are left unchanged.
+template <bool STAGED, bool ENERGY>
 __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
-                                          int64_t b0, const int4 *lq, int lo,
-                                          float *fx, float *fy, float *fz,
-                                          float *eat) {
+                                          const PairBlock &B, const int4 *lq,
+                                          int lo, double *lsum, float *fx,
+                                          float *fy, float *fz, float *eat) {
   const int tid = threadIdx.x;
-  const int64_t i = b0 + tid;
-  const bool valid = i < S.N;
+  const int64_t i = B.i;
+  const bool valid = B.valid;
   const int self = valid ? (int)i : 0;
   const int4 qi = valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  const int n = valid ? S.nn[i] : 0;
+  const int n = B.n;
+  const int64_t row = B.b0 + B.p;
   const float gi = __int_as_float(qi.w);
   const float hgi = 0.5f * gi;
   const int64_t N = S.N;
   const int4 *__restrict__ qp = S.qpos;
-  const float aV = in_vgpr(P.aV), bV = in_vgpr(P.bV);
+  const float aV = in_vgpr(P.aV), bW = in_vgpr(P.bW);
   const float aP = in_vgpr(P.aP), bP = in_vgpr(P.bP);
   const float uS = in_vgpr(P.uS), uB = in_vgpr(P.uB);
-  const float va = in_vgpr(P.va), vb = in_vgpr(P.vb);
   const float d0 = in_vgpr(P.dv0), d1 = in_vgpr(P.dv1);
   const float p0 = in_vgpr(P.dp0), p1 = in_vgpr(P.dp1);
-  const float c2p = P.c2p, rt = P.rt;
+  const float va = P.va, vb = P.vb, bV = P.bV;
+  const float rt = P.rt;
   float ax = 0.f, ay = 0.f, az = 0.f, ev = 0.f, wz = 0.f;
   auto pair = [&](const int4 &q) {
     const float dx = (float)(q.x - qi.x);
@@ -800,30 +853,31 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float rr = r2 * ri;
     const float G = fmaf(0.5f, __int_as_float(q.w), hgi);
-    const float eV = __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
+    // core: E' = (g_i+g_j)/2 (2q/r0) phi - (2p/r0) V
+    const float eW = __builtin_amdgcn_exp2f(fmaf(aV, rr, bW));
     const float eP = __builtin_amdgcn_exp2f(fmaf(aP, rr, bP));
-    const float epc = fmaf(G, eP, -c2p * eV);
+    const float epc = fmaf(G, eP, -eW);
     const float u = fmaxf(fmaf(rr, uS, uB), 0.0f);
     const float ept = u * fmaf(G, fmaf(p1, u, p0), fmaf(d1, u, d0));
-    const float Vt = u * (u * fmaf(vb, u, va));
     const bool tail = rr > rt;
-    float s = (tail ? ept : epc) * ri;
-    float V = tail ? Vt : eV;
-    if (!STAGED) {
-      const bool on = r2 > 0.0f;
-      s = on ? s : 0.0f;
-      V = on ? V : 0.0f;
-    }
-    ev += V;
+    const bool on = STAGED || r2 > 0.0f;
+    const float s = on ? (tail ? ept : epc) * ri : 0.0f;
     ax = fmaf(s, dx, ax);
     ay = fmaf(s, dy, ay);
-    const float sz = s * dz;
-    az += sz;
-    wz = fmaf(sz, dz, wz);
+    if (ENERGY) {
+      const float Vt = u * (u * fmaf(vb, u, va));
+      const float V = tail ? Vt : __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
+      ev += on ? V : 0.0f;
+      const float sz = s * dz;
+      az += sz;
+      wz = fmaf(sz, dz, wz);
+    } else {
+      az = fmaf(s, dz, az);
+    }
   };
   if (STAGED) {
     const StagedIndex sx(lo);
-    chunk_loop_padded(S.nl, N, i, n, [&](const int (&j)[8]) {
+    chunk_loop_padded(S.nl_lane, N, row, n, [&](const int (&j)[8]) {
       int4 q[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
@@ -831,7 +885,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
       for (int e = 0; e < 8; ++e) pair(q[e]);
     });
   } else {
-    chunk_loop(S.nl, N, i, self, n, 0, 1, [&](const int (&j)[8], int) {
+    chunk_loop(S.nl_lane, N, row, self, n, 0, 1, [&](const int (&j)[8], int) {
       int4 q[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
@@ -839,22 +893,31 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
       for (int e = 0; e < 8; ++e) pair(q[e]);
     });
   }
-  double e_i = 0.0, w_i = 0.0;
   if (valid) {
-    const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
     fx[i] = ax;
     fy[i] = ay;
     fz[i] = az;
-    eat[i] = e;
-    e_i = (double)e;
-    w_i = (double)wz * (double)P.wscale;
   }
-  e_i = wave_sum(e_i);
-  w_i = wave_sum(w_i);
-  if ((tid & 63) == 0 && valid) {
-    double *pt = S.part + (i / kTile) * kNPart;
-    pt[kPartE] = e_i;
-    pt[kPartW] = w_i;
+  if (ENERGY) {
+    // per-tile sums in slot order: each atom's values go to LDS at its slot
+    // in the block, then wavefront w sums tile t0 + w
+    if (valid) {
+      const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
+      eat[i] = e;
+      lsum[i - B.b0] = (double)e;
+      lsum[kBlock + (i - B.b0)] = (double)wz * (double)P.wscale;
+    }
+    __syncthreads();
+    const int w = tid / kTile;
+    if (w < B.nt) {
+      const double e_i = wave_sum(lsum[tid]);
+      const double w_i = wave_sum(lsum[kBlock + tid]);
+      if ((tid & 63) == 0) {
+        double *pt = S.part + (int64_t)(B.t0 + w) * kNPart;
+        pt[kPartE] = e_i;
+        pt[kPartW] = w_i;
+      }
+    }
   }
 }
 
@@ -863,13 +926,23 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         float *fz,
                                                         float *eat) {
   __shared__ int4 lq[kStage + 1];
-  const int64_t b0 = xcd_block() * kBlock;
+  __shared__ double lsum[2 * kBlock];
+  const PairBlock B = pair_block(S);
+  const bool energy =
+      S.energies > 0 || (S.energies < 0 && (*S.step + 1) % S.n_log == 0);
   int lo, size;
-  block_window(S, b0, lo, size);
-  if (size > 0 && size <= kStage && stage(S, lq, b0, lo, size))
-    force_run<true>(S, P, b0, lq, lo, fx, fy, fz, eat);
-  else
-    force_run<false>(S, P, b0, lq, lo, fx, fy, fz, eat);
+  block_window(S, B, lo, size);
+  if (size > 0 && size <= kStage && stage(S, lq, B, lo, size)) {
+    if (energy)
+      force_run<true, true>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+    else
+      force_run<true, false>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+  } else {
+    if (energy)
+      force_run<false, true>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+    else
+      force_run<false, false>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
@@ -1106,9 +1179,14 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   int64_t step = *M.step;
   int64_t n1 = step + 1;
   int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
-  double s[4];
-  block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
-  bool logstep = (n1 % M.n_log) == 0;
+  // energy and virial tile sums are current on logged steps only
+  const bool logstep = (n1 % M.n_log) == 0;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (logstep) {
+    block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
+  } else {
+    block_sum_tiles<2>(S.part, t0, t1, kPartK, s + 2, lds);
+  }
   int nb = 2 * S.grid_dim[3 * r + 2];
   unsigned long long *bmin = S.zbmin + (int64_t)r * S.max_zbins;
   unsigned long long *bmax = S.zbmax + (int64_t)r * S.max_zbins;
@@ -1119,7 +1197,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     double T = dof > 0 ? 2.0 * KE / ((double)dof * kBoltz) : 0.0;
     double D = M.v_pull[r] * (double)n1 * M.dt;
     uint32_t st = S.wstatus[r];
-    if (!isfinite(E) || !isfinite(KE)) st |= 2u;
+    if (!isfinite(E) || !isfinite(KE)) st |= 2u;  // E is 0 when not logged
     if (__longlong_as_double((long long)S.maxdisp[r]) > S.skin_half2)
       st |= 16u;
     if (logstep) {
@@ -1363,12 +1441,13 @@ void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    hipStream_t s) {
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
+    if (S.nbmap == 0) return;
     if (S.nact)
-      k_density_mixed<true><<<nb, kBlock, 0, s>>>(S, PF);
+      k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
     else
-      k_density_mixed<false><<<nb, kBlock, 0, s>>>(S, PF);
-    k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
-                                        (float *)fz, (float *)eat);
+      k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+    k_force_mixed<<<S.nbmap, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
+                                             (float *)fz, (float *)eat);
   } else {
     k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);
     k_force_fp64<<<nb, kBlock, 0, s>>>(S, PD, g, (double *)fx, (double *)fy,
@@ -1381,13 +1460,15 @@ void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
                        double *g, hipStream_t s) {
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
+    if (S.nbmap == 0) return;
     if (pass == 1 && S.nact)
-      k_density_mixed<true><<<nb, kBlock, 0, s>>>(S, PF);
+      k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
     else if (pass == 1)
-      k_density_mixed<false><<<nb, kBlock, 0, s>>>(S, PF);
+      k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
     else
-      k_force_mixed<<<nb, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
-                                          (float *)fz, (float *)eat);
+      k_force_mixed<<<S.nbmap, kBlock, 0, s>>>(S, PF, (float *)fx,
+                                               (float *)fy, (float *)fz,
+                                               (float *)eat);
   } else {
     if (pass == 1)
       k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);

@@ -142,6 +142,8 @@ class WireBatch:
         T["cell_start"] = torch.zeros(self.C + R, dtype=torch.int32, device=dev)
         T["cell_atoms"] = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
         T["nl"] = torch.zeros(k_cap * N, dtype=torch.int32, device=dev)
+        T["nl_lane"] = torch.zeros(k_cap * N if precision == "mixed" else 1, dtype=torch.int32,
+                                   device=dev)
         T["nn"] = torch.zeros(N, dtype=torch.int32, device=dev)
         mixed = precision == "mixed"
         T["nact"] = torch.zeros(2 * N if mixed else 1, dtype=torch.int32, device=dev)
@@ -179,7 +181,8 @@ class WireBatch:
         # the per-atom pair counts are a diagnostic: the step loop runs
         # without them, count_pairs() asks for them
         self.nlist = A.NList(_ptr(T["nl"]), _ptr(T["nn"]), k_cap, 0, _ptr(T["x_ref"]),
-                             _ptr(T["y_ref"]), _ptr(T["z_ref"]), None)
+                             _ptr(T["y_ref"]), _ptr(T["z_ref"]), None,
+                             _ptr(T["nl_lane"]) if mixed else None)
         self.out = A.ForcesOut(_ptr(T["fx"]), _ptr(T["fy"]), _ptr(T["fz"]), _ptr(T["e_atom"]),
                                _ptr(T["g"]) if precision == "fp64" else None,
                                _ptr(T["rep_energy"]), _ptr(T["rep_wzz"]))
@@ -227,6 +230,10 @@ class WireBatch:
         self.k_cap = k_cap
         self.t["nl"] = torch.zeros(k_cap * self.N, dtype=torch.int32, device=self.device)
         self.nlist.nl = _ptr(self.t["nl"])
+        if self.precision == "mixed":
+            self.t["nl_lane"] = torch.zeros(k_cap * self.N, dtype=torch.int32,
+                                            device=self.device)
+            self.nlist.nl_lane = _ptr(self.t["nl_lane"])
         self.nlist.k_cap = k_cap
 
     def compute_forces(self):
@@ -303,7 +310,8 @@ class WireBatch:
         if self.precision != "mixed":
             raise ValueError("pair counts are kept in mixed precision only")
         nl = A.NList(self.nlist.nl, self.nlist.nn, self.nlist.k_cap, 0, self.nlist.x_ref,
-                     self.nlist.y_ref, self.nlist.z_ref, _ptr(self.t["nact"]))
+                     self.nlist.y_ref, self.nlist.z_ref, _ptr(self.t["nact"]),
+                     self.nlist.nl_lane)
         A.check(A.lib().tbsma_forces_pass(C.byref(self.params), C.byref(self.sys), C.byref(nl),
                                           C.byref(self.out), self.work, 1, self.stream()))
         torch.cuda.synchronize(self.device)
@@ -321,7 +329,7 @@ class WireBatch:
     # checkpoint / resume: the device state that the next step reads.  With the
     # lists saved too, a resumed run repeats the original bit for bit (the
     # noise is keyed by the step index, which is part of the state).
-    _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nn", "x_ref", "y_ref",
+    _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nl_lane", "nn", "x_ref", "y_ref",
               "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "obs", "work")
 
     def state_dict(self):
