@@ -66,8 +66,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--drift-steps", type=int, default=0,
-                    help="also measure NVE energy drift over this many steps (FP64 D1.5xL3nm "
-                         "and mixed D3xL20nm wires at 10 K, static grips)")
+                    help="also measure NVE energy drift over this many steps (D1.5xL3nm and "
+                         "D3xL20nm wires at 10 K, static grips, FP64 and mixed)")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="also time the oracle on the D1.5xL3nm, D3xL20nm and D10xL100nm wires")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -143,20 +145,22 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration kernel: {src.numel() * 8} bytes read and written")
         del src, dst
-    # bytes each kernel must move per launch (per real atom):
-    #  density: nn 4 + Verlet row 4 kbar + own position 16 + g 4
-    #  force:   nn 4 + Verlet row 4 kbar + own position and g 16 + force 12
+    # bytes each kernel must move per launch (per real atom), with kp the mean
+    # length of the (pruned) lists the passes read:
+    #  density: length 4 + row 4 kp + own position 16 + g 4
+    #  force:   length 4 + row 4 kp + own position and g 16 + force 12
     #           (+ energy 4 on logged steps)
     # (neighbour positions are staged per block and counted once per atom in
     # the own-position term)
     kact = b.mean_active_pairs()
-    bytes_force = n_real * (4.0 * kbar + 32.0)
-    bytes_force_e = n_real * (4.0 * kbar + 36.0)
-    bytes_dens = n_real * (4.0 * kbar + 24.0)
+    kfull, kp = b.list_lengths()
+    bytes_force = n_real * (4.0 * kp + 32.0)
+    bytes_force_e = n_real * (4.0 * kp + 36.0)
+    bytes_dens = n_real * (4.0 * kp + 24.0)
     gbs_force = bytes_force / (t_force * 1e-3) / 1e9
     gbs_force_e = bytes_force_e / (t_force_e * 1e-3) / 1e9
     gbs_dens = bytes_dens / (t_dens * 1e-3) / 1e9
-    log(f"[bench] mean listed neighbours {kbar:.2f}, active pairs {kact:.2f}; density {t_dens * 1e3:.1f} us "
+    log(f"[bench] mean listed neighbours {kbar:.2f} (pruned lists {kp:.2f}), active pairs {kact:.2f}; density {t_dens * 1e3:.1f} us "
         f"({gbs_dens:.0f} GB/s), force {t_force * 1e3:.1f} us ({gbs_force:.0f} GB/s), "
         f"force with energies {t_force_e * 1e3:.1f} us")
 
@@ -221,6 +225,8 @@ def main():
     if args.drift_steps > 0:
         drift = {}
         for name, rp, prec in (("fp64 D1.5xL3nm", W.cfg1_plain_fp64().replicas[0], "fp64"),
+                               ("mixed D1.5xL3nm", W.cfg1_plain_fp64().replicas[0], "mixed"),
+                               ("fp64 D3xL20nm", W.cfg2_single_mixed().replicas[0], "fp64"),
                                ("mixed D3xL20nm", W.cfg2_single_mixed().replicas[0], "mixed")):
             rp = W.Replica(rp.D, rp.L, rp.T, 0.0, rp.seed, rp.rep_id, jitter=rp.jitter)
             n_log = max(1, args.drift_steps // 100)
@@ -240,6 +246,33 @@ def main():
                            "T_mean_K": float(ob[:, A.OBS_T].mean())}
             log(f"[bench] NVE {name}: {drift[name]}")
 
+    oracle_other = None
+    if args.oracle_configs and not args.no_cpu_baseline:
+        import oracle
+        oracle_other = {}
+        for name, w in (("D1.5xL3nm", W.cfg1_plain_fp64()), ("D3xL20nm", W.cfg2_single_mixed()),
+                        ("D10xL100nm", W.cfg5_large())):
+            rp = w.replicas[0]
+            x, y, z, f = oracle.build_wire(W.A_LAT, rp.D, rp.L, rp.n_grip)
+            stt = oracle.State(x, y, z, f)
+            md = oracle.MD(dt=W.DT, gamma=w.gamma, T=rp.T, v_pull=rp.v_pull,
+                           z_lo=z[f == 1].max(), z_hi=z[f == 2].min(), seed=rp.seed,
+                           rep_id=rp.rep_id)
+            pot = oracle.Pot()
+            oracle.init_state(md, stt, rp.jitter)
+            oracle.compute_forces(pot, stt, 1)
+            t0 = time.perf_counter()
+            oracle.run(pot, md, stt, 1, 1)
+            t1 = time.perf_counter() - t0
+            k = max(1, int(args.cpu_seconds / 3 / max(t1, 1e-6)))
+            t0 = time.perf_counter()
+            oracle.run(pot, md, stt, k, 1)
+            tc = time.perf_counter() - t0
+            oracle_other[name] = {"atoms": int(x.size), "steps": k,
+                                  "atom_timesteps_per_s": x.size * k / tc,
+                                  "cores": oracle.num_threads()}
+            log(f"[bench] oracle {name}: {oracle_other[name]}")
+
     line = {
         "metric": "atom-timesteps/s, batched vs per-replica TB-SMA NVT; force-kernel % HBM peak",
         "value": value,
@@ -256,6 +289,7 @@ def main():
         "config": {"workload": wl.name, "replicas": b.R, "atoms": n_real,
                    "precision": "f32 pair math, f64 integration and sums",
                    "steps_per_graph": S, "skin_A": b.skin, "r_cut_A": b.pot.r_cut,
+                   "prune_A": b.prune,
                    "parallelism": "replica batch, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
@@ -264,12 +298,19 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_force,
                      "avg_launch_us": t_force * 1e3,
                      "mean_listed_neighbours": kbar,
+                     "mean_pruned_list": kp,
                      "mean_active_pairs": kact},
         "kernels": {"density": {"avg_launch_us": t_dens * 1e3, "GB/s": gbs_dens,
                                 "frac": gbs_dens / HBM_PEAK_GBS},
                     "force_with_energies": {"avg_launch_us": t_force_e * 1e3,
                                             "GB/s": gbs_force_e,
-                                            "frac": gbs_force_e / HBM_PEAK_GBS}},
+                                            "frac": gbs_force_e / HBM_PEAK_GBS},
+                    # both passes of a step: (8 kbar + 56) bytes per atom
+                    "density_plus_force": {
+                        "avg_us": (t_dens + t_force) * 1e3,
+                        "GB/s": (bytes_dens + bytes_force) / ((t_dens + t_force) * 1e-3) / 1e9,
+                        "frac": (bytes_dens + bytes_force) / ((t_dens + t_force) * 1e-3) / 1e9
+                        / HBM_PEAK_GBS}},
         "per_replica_value": pr,
         "batched_over_per_replica": (value / pr) if pr else None,
         "bad_replicas": bad,
@@ -277,6 +318,8 @@ def main():
     }
     if drift is not None:
         line["nve_drift"] = drift
+    if oracle_other is not None:
+        line["oracle_other_configs"] = oracle_other
     print(json.dumps(line), flush=True)
 
 

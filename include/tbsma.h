@@ -105,6 +105,12 @@ extern "C" {
  *  qbits            MIXED only: positions are quantised to 2^-qbits A about
  *                   the centre of each replica's grid (16 <= qbits <= 24);
  *                   the grid half-extent must stay below 2^(31-qbits) A.
+ *  prune            MIXED only: half-width d (A) of the pruned lists the pair
+ *                   passes read, 0 <= d <= skin/2 (0: no pruning).  Each list
+ *                   is pruned to the pairs within r_cut + 2d, and pruned again
+ *                   from the full list whenever some atom of the replica has
+ *                   moved more than d since the last pruning, so no pair
+ *                   within r_cut is ever left out.
  */
 typedef struct {
   double A, xi, p, q, r0;
@@ -114,6 +120,7 @@ typedef struct {
   double mass;
   int32_t precision;
   int32_t qbits;
+  double prune;
 } tbsma_params;
 
 /*
@@ -181,11 +188,12 @@ typedef struct {
  * by every density pass when given: the numbers of list entries of atom i
  * with 0 < r <= r_tail (nact[2i]) and r_tail < r < r_cut (nact[2i+1]) at
  * the current positions.  A diagnostic: the passes are faster without it.
- * nl_lane (MIXED; NULL for FP64): device [k_cap*N] int32, a copy of the lists
- * written by the list build in the order the mixed pair passes read them:
- * within each block of up to four tiles of one replica, atoms by descending
- * list length (ties by slot), the p-th atom's list as row (block start + p)
- * of the same chunked layout.  Opaque to the caller.
+ * nl_lane (MIXED; NULL for FP64): device [k_cap*N] int32, the lists as the
+ * mixed pair passes read them: within each block of up to four tiles of one
+ * replica, atoms by descending list length (ties by slot), the p-th atom's
+ * list as row (block start + p) of the same chunked layout, pruned to the
+ * pairs within r_cut + 2 prune (see tbsma_params).  Written by the list
+ * build and by the pruning in the step loops; opaque to the caller.
  */
 typedef struct {
   int32_t *nl;
@@ -364,6 +372,15 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
                     tbsma_cells *cells, tbsma_nlist *nl,
                     tbsma_forces_out *out, const tbsma_md *md, void *work,
                     int64_t n_steps, int32_t steps_per_graph, void *stream);
+
+/*
+ * Diagnostics of the lists: out_host[0] = sum over atoms of nn (the Verlet
+ * lists), out_host[1] = sum of the lengths of the lists the mixed pair passes
+ * read (pruned; equal to out_host[0] in FP64).  Synchronises.
+ */
+int tbsma_list_stats(const tbsma_params *prm, const tbsma_system *sys,
+                     const tbsma_nlist *nl, void *work, int64_t *out_host,
+                     void *stream);
 
 /*
  * Diagnostics of the random numbers: for tag = 0 .. n-1 writes the four

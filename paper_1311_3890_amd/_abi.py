@@ -29,7 +29,7 @@ class Params(C.Structure):
     _fields_ = [("A", C.c_double), ("xi", C.c_double), ("p", C.c_double), ("q", C.c_double),
                 ("r0", C.c_double), ("r_tail", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("cell", C.c_double), ("mass", C.c_double),
-                ("precision", C.c_int32), ("qbits", C.c_int32)]
+                ("precision", C.c_int32), ("qbits", C.c_int32), ("prune", C.c_double)]
 
 
 class System(C.Structure):
@@ -78,6 +78,7 @@ SIGNATURES = {
                              vp, C.c_int64, vp]),
     "tbsma_run_batch": (C.c_int, [P(Params), P(System), P(Cells), P(NList), P(ForcesOut),
                                   P(MD), vp, C.c_int64, C.c_int32, vp]),
+    "tbsma_list_stats": (C.c_int, [P(Params), P(System), P(NList), vp, P(C.c_int64), vp]),
     "tbsma_rng_fill": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int64,
                                  vp, vp, vp]),
     "tbsma_last_error": (C.c_char_p, []),

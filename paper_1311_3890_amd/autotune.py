@@ -114,3 +114,71 @@ class BucketRun:
     def run(self, n: int):
         for _, _, c, wb in self.parts:
             wb.run_batch(n, c.steps_per_graph)
+
+
+def _pass_us(wb, p: int, n: int = 10) -> float:
+    """Average launch time (us) of force pass p on wb's current state, HIP
+    events on the launch stream."""
+    import ctypes as C
+    from . import _abi as A
+    lib = A.lib()
+    args = (C.byref(wb.params), C.byref(wb.sys), C.byref(wb.nlist), C.byref(wb.out), wb.work)
+    A.check(lib.tbsma_forces_pass(*args, p, wb.stream()))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(n):
+        A.check(lib.tbsma_forces_pass(*args, p, wb.stream()))
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n * 1e3
+
+
+def main(argv=None):
+    """Tunes the buckets of a workload, then times each bucket's batch with its
+    chosen settings; prints one JSON object."""
+    import argparse
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--workload", default="cfg4", choices=sorted(W.CONFIGS))
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--sample", type=int, default=32)
+    ap.add_argument("--trial-steps", type=int, default=100)
+    ap.add_argument("--cache", default=None, help="JSON file of earlier choices")
+    a = ap.parse_args(argv)
+    log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    wl = W.CONFIGS[a.workload]()
+    choices = tune(wl.replicas, wl.precision, sample=a.sample, trial_steps=a.trial_steps,
+                   warmup=a.warmup, cache=a.cache, log=log)
+    run = BucketRun(wl.replicas, choices, wl.precision)
+    run.prepare()
+    out = {"workload": wl.name, "atoms": run.n_atoms, "steps": a.steps, "buckets": {}}
+    total_s = 0.0
+    for k, idx, c, wb in run.parts:
+        wb.run_batch(a.warmup, c.steps_per_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wb.run_batch(a.steps, c.steps_per_graph)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total_s += dt
+        n = int(wb.n_atoms.sum())
+        kbar = wb.mean_neighbors()
+        t3 = _pass_us(wb, 3)
+        out["buckets"][k] = {
+            "replicas": len(idx), "atoms": n, "skin_A": c.skin,
+            "steps_per_graph": c.steps_per_graph,
+            "atom_timesteps_per_s": n * a.steps / dt,
+            "mean_listed_neighbours": kbar,
+            "force_pass_us": t3,
+            "force_pass_GB_per_s": n * (4.0 * kbar + 32.0) / (t3 * 1e-6) / 1e9}
+        log(f"[autotune] {k}: {out['buckets'][k]}")
+    out["atom_timesteps_per_s"] = run.n_atoms * a.steps / total_s
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -73,6 +73,8 @@ int check_params(const tbsma_params *p) {
     return fail(TBSMA_EINVAL, "unknown precision %d", p->precision);
   if (p->precision == TBSMA_MIXED && (p->qbits < 16 || p->qbits > 24))
     return fail(TBSMA_EINVAL, "qbits %d outside 16..24", p->qbits);
+  if (!(p->prune >= 0 && p->prune <= 0.5 * p->skin))
+    return fail(TBSMA_EINVAL, "prune must be in [0, skin/2]");
   return TBSMA_OK;
 }
 
@@ -112,8 +114,8 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 }
 
 struct Layout {
-  size_t maxdisp, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      bmap, lane_atom, nn_lane, total;
+  size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
+      bmap, lane_atom, nn_lane, qprune, atom_lane, stats, total;
 };
 
 // Blocks of the list build: ceil(tiles/4) per replica.
@@ -132,8 +134,8 @@ Layout layout(const tbsma_system *s) {
   Layout L;
   size_t o = 0;
   int64_t R = s->R, nt = s->N / TBSMA_TILE;
-  L.maxdisp = o;
-  o += up(8 * (size_t)R);
+  L.rflag = o;
+  o += up(4 * (size_t)R);
   L.cnt = o;
   o += up(4 * (size_t)s->C);
   L.part = o;
@@ -158,6 +160,12 @@ Layout layout(const tbsma_system *s) {
   o += up((size_t)s->N);
   L.nn_lane = o;
   o += up(4 * (size_t)s->N);
+  L.qprune = o;
+  o += up(16 * (size_t)s->N);
+  L.atom_lane = o;
+  o += up((size_t)s->N);
+  L.stats = o;
+  o += 256;
   L.total = o;
   return L;
 }
@@ -186,7 +194,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.qpos = reinterpret_cast<int4 *>(s->qpos);
   Layout L = layout(s);
   char *w = static_cast<char *>(work);
-  d.maxdisp = reinterpret_cast<unsigned long long *>(w + L.maxdisp);
+  d.rflag = reinterpret_cast<uint32_t *>(w + L.rflag);
   d.cnt = reinterpret_cast<int32_t *>(w + L.cnt);
   d.part = reinterpret_cast<double *>(w + L.part);
   d.zbmin = reinterpret_cast<unsigned long long *>(w + L.zbmin);
@@ -199,6 +207,20 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.bmap = reinterpret_cast<int2 *>(w + L.bmap);
   d.lane_atom = reinterpret_cast<uint8_t *>(w + L.lane_atom);
   d.nn_lane = reinterpret_cast<int32_t *>(w + L.nn_lane);
+  d.qprune = reinterpret_cast<int4 *>(w + L.qprune);
+  d.atom_lane = reinterpret_cast<uint8_t *>(w + L.atom_lane);
+  d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
+  if (p->precision == TBSMA_MIXED) {
+    // a pair is kept when its quantised distance is below r_cut + 2d, with
+    // a margin of 1e-5 A for rounding of positions to quanta and of r^2 to
+    // FP32; without pruning every listed pair is kept
+    const double q = ldexp(1.0, p->qbits);
+    const double rp = p->prune > 0 ? p->r_cut + 2.0 * p->prune + 1e-5
+                                   : p->r_cut + p->skin + 1.0;
+    d.pruning = p->prune > 0 ? 1 : 0;
+    d.prune_r2q = (float)(rp * rp * q * q);
+    d.prune_d2q = (float)(p->prune * p->prune * q * q);
+  }
   d.nbmap = s->R > 0 ? block_map_size(s) : 0;
   d.cell = p->cell;
   d.inv_cell = 1.0 / p->cell;
@@ -379,6 +401,7 @@ void enqueue_step(const tbsma_params *p, const Dev &d, const DevMD &M,
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_cells(d, s);
   launch_nlist(d, mixed, rl, s);
+  if (mixed) launch_prune(d, s);
   Dev df = d;
   df.energies = -1;
   df.step = M.step;
@@ -698,6 +721,30 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   }
   for (int64_t k = 0; k < rest; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
   return finish_run(d, md, s);
+}
+
+int tbsma_list_stats(const tbsma_params *prm, const tbsma_system *sys,
+                     const tbsma_nlist *nl, void *work, int64_t *out_host,
+                     void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!nl || !out_host || !work)
+    return fail(TBSMA_EINVAL, "nlist, work or out_host is NULL");
+  TRY(check_lists(prm, nullptr, nl));
+  out_host[0] = out_host[1] = 0;
+  if (sys->R == 0) return TBSMA_OK;
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, nullptr, nl);
+  launch_list_stats(d, prm->precision == TBSMA_MIXED, s);
+  HIPCHK(hipGetLastError());
+  unsigned long long h[2];
+  HIPCHK(hipMemcpyAsync(h, d.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out_host[0] = (int64_t)h[0];
+  out_host[1] = (int64_t)h[1];
+  return TBSMA_OK;
 }
 
 int tbsma_rng_fill(uint64_t seed, uint32_t rep_id, uint64_t step,

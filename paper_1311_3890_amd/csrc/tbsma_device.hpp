@@ -70,6 +70,13 @@ struct Dev {
   uint8_t *lane_atom;           // [N] pair-pass lane order within a block
   int32_t *nn_lane;             // [N] list lengths in lane order
   int32_t *nl_lane;             // lists in lane order (CL8 layout), or NULL
+  // pruning of the lane-ordered lists (mixed precision)
+  int32_t pruning;              // 1 when enabled
+  float prune_r2q;              // (r_cut + 2d)^2 + margin, quanta^2
+  float prune_d2q;              // d^2, quanta^2
+  int4 *qprune;                 // [N] quantised positions at the last pruning
+  uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
+  unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
@@ -80,7 +87,9 @@ struct Dev {
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace
-  unsigned long long *maxdisp;  // [R] bits of max |x - x_ref|^2 (>= 0)
+  uint32_t *rflag;              // [R] bit 0: some atom moved more than skin/2
+                                // since the list build; bit 1: more than the
+                                // pruning half-width since the last pruning
   int32_t *cnt;                 // [C]
   double *part;                 // [N/64 * kNPart]
   unsigned long long *zbmin, *zbmax;  // [R * max_zbins] ordered keys of z
@@ -115,6 +124,12 @@ __device__ __forceinline__ int64_t xcd_block() {
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -207,7 +222,12 @@ __device__ __forceinline__ double dkey_inv(unsigned long long k) {
 }
 
 __device__ __forceinline__ bool rebuilds(const Dev &S, int r) {
-  return S.all || __longlong_as_double((long long)S.maxdisp[r]) > S.skin_half2;
+  return S.all || (S.rflag[r] & 1u);
+}
+
+// Whether replica r's pruned lists must be pruned again this step.
+__device__ __forceinline__ bool prunes(const Dev &S, int r) {
+  return S.pruning && (S.rflag[r] & 2u);
 }
 
 // Cell coordinate along one axis, clamped to the grid (clamping keeps the

@@ -38,7 +38,7 @@ __device__ __forceinline__ int quant1(double v, double o, double qs,
   return (int)t;
 }
 
-__device__ __forceinline__ void quantise(const Dev &S, int r, int64_t i,
+__device__ __forceinline__ int4 quantise(const Dev &S, int r, int64_t i,
                                          double x, double y, double z,
                                          bool &out) {
   const int32_t *gd = S.grid_dim + 3 * r;
@@ -50,6 +50,7 @@ __device__ __forceinline__ void quantise(const Dev &S, int r, int64_t i,
   q.z = quant1(z, lo[2] + hc * gd[2], S.qscale, out);
   q.w = 0;  // g_i of these positions: written by the next density pass
   S.qpos[i] = q;
+  return q;
 }
 
 __global__ void __launch_bounds__(kBlock) k_quantise(Dev S) {
@@ -417,12 +418,46 @@ __device__ __forceinline__ void nlist_window(const Dev &S, int64_t i,
   }
 }
 
+// Copies atom i's list (nl, by atom, n entries) to row `row` of nl_lane,
+// keeping the pairs whose current quantised distance is below the pruning
+// radius (all of them when pruning is off); returns the number kept.  Each
+// lane works on its own row through its ring.
+template <class Fetch>
+__device__ __forceinline__ int prune_row(const Dev &S, int64_t i, int64_t row,
+                                         int n, int32_t *ring_lane,
+                                         Fetch &&fetch) {
+  Ring ring{ring_lane, 0, 0};
+  const int4 qi = S.qpos[i];
+  const int nch = S.k_cap >> 3;
+  const float rp2 = S.prune_r2q;
+  for (int c = 0; c < (n + 7) >> 3; ++c) {
+    const int4 *src = reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c));
+    const int4 a = src[0], b = src[1];
+    const int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int4 q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = fetch(c * 8 + e < n ? j[e] : (int)i);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float dx = (float)(q[e].x - qi.x);
+      const float dy = (float)(q[e].y - qi.y);
+      const float dz = (float)(q[e].z - qi.z);
+      if (c * 8 + e < n && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
+        ring.push(j[e]);
+    }
+    ring.flush(S.nl_lane, S.N, row, nch);
+  }
+  ring.finish(S.nl_lane, S.N, row, nch);
+  return ring.cnt;
+}
+
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
                                                   float rl2q) {
   __shared__ int32_t ring_lds[16 * kBlock];
   __shared__ float4 cand[MIXED ? kCand + 8 : 1];
   __shared__ int wzlo[kBlock / kTile], wzhi[kBlock / kTile];
+  __shared__ int32_t key[kBlock];
   const int tid = threadIdx.x, w = tid / kTile;
   const int2 bm = S.bmap[blockIdx.x];  // first tile, tiles (1..4)
   const int r = S.tile_rep[bm.x];
@@ -517,8 +552,6 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
   }
   // lane order of the pair passes: the block's atoms by descending list
   // length, ties by slot (keys are distinct)
-  __syncthreads();  // the ring is no longer needed
-  int32_t *key = ring_lds;
   key[tid] = nn_i < 0 ? 0x7fffffff : ((255 - min(nn_i, 255)) << 8) | tid;
   __syncthreads();
   if (valid) {
@@ -527,15 +560,13 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
     for (int m = 0; m < bm.y * kTile; ++m) rank += key[m] < k ? 1 : 0;
     const int64_t row = (int64_t)bm.x * kTile + rank;
     S.lane_atom[row] = (uint8_t)tid;
-    S.nn_lane[row] = nn_i;
-    // the row again, at the lane position (chunks this thread just wrote)
+    S.atom_lane[i] = (uint8_t)rank;
+    // the row again at the lane position, pruned (mixed precision; its
+    // chunks were just written by this thread)
     if (S.nl_lane) {
-      for (int c = 0; c < (nn_i + 7) >> 3; ++c) {
-        const int4 *src = reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c));
-        int4 *dst = reinterpret_cast<int4 *>(S.nl_lane + cl8(S.N, row, c));
-        dst[0] = src[0];
-        dst[1] = src[1];
-      }
+      S.nn_lane[row] = prune_row(S, i, row, nn_i, ring_lds + tid,
+                                 [&](int j) { return S.qpos[j]; });
+      S.qprune[i] = S.qpos[i];
     }
   }
 }
@@ -686,6 +717,84 @@ struct StagedIndex {
         reinterpret_cast<const char *>(lq) + off);
   }
 };
+
+// Pruning of the lane-ordered lists of the replicas in which some atom has
+// moved more than the pruning half-width since their lists were last pruned
+// (and that are not rebuilt this step, which prunes too).  Lanes take the
+// block's atoms in slot order, so the full rows are read coalesced; each
+// lane writes its kept entries to its atom's lane-ordered row.  Positions
+// come from LDS as in the pair passes when the block's window fits.
+__global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
+  __shared__ int32_t ring_lds[16 * kBlock];
+  __shared__ int4 lq[kStage + 1];
+  const PairBlock B = pair_block(S);
+  const int r = S.tile_rep[B.t0];
+  if (rebuilds(S, r) || !prunes(S, r)) return;  // uniform over the block
+  int lo, size;
+  block_window(S, B, lo, size);
+  const bool staged = size > 0 && size <= kStage && stage(S, lq, B, lo, size);
+  const int64_t i = B.b0 + B.p;
+  const int n = B.valid ? S.nn[i] : 0;
+  const int64_t row = B.b0 + (B.valid ? (int)S.atom_lane[i] : 0);
+  const int4 qi = B.valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+  const float rp2 = S.prune_r2q;
+  const int nch = S.k_cap >> 3;
+  Ring ring{ring_lds + threadIdx.x, 0, 0};
+  auto keep = [&](const int4 &q, int j, bool in) {
+    const float dx = (float)(q.x - qi.x);
+    const float dy = (float)(q.y - qi.y);
+    const float dz = (float)(q.z - qi.z);
+    if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2) ring.push(j);
+  };
+  if (staged) {
+    // the row in batches of kPruneBatch chunks, all loaded before any is
+    // used: the stores of the ring's flushes then overlap the positions'
+    // LDS reads instead of delaying the next list loads (loads and stores
+    // retire in order)
+    constexpr int kPruneBatch = 7;
+    const StagedIndex sx(lo);
+    const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
+    const int own = (n + 7) >> 3;
+    const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
+    for (int c0 = 0; c0 < (nmax + 7) >> 3; c0 += kPruneBatch) {
+      int4 buf[2 * kPruneBatch];
+#pragma unroll
+      for (int k = 0; k < kPruneBatch; ++k) {
+        const int4 *src =
+            c0 + k < own
+                ? reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c0 + k))
+                : pad;
+        buf[2 * k] = src[0];
+        buf[2 * k + 1] = src[1];
+      }
+#pragma unroll
+      for (int k = 0; k < kPruneBatch; ++k) {
+        const int j[8] = {buf[2 * k].x,     buf[2 * k].y,     buf[2 * k].z,
+                          buf[2 * k].w,     buf[2 * k + 1].x, buf[2 * k + 1].y,
+                          buf[2 * k + 1].z, buf[2 * k + 1].w};
+        int4 q[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) keep(q[e], j[e], j[e] != kPadEntry);
+        ring.flush(S.nl_lane, S.N, row, nch);
+      }
+    }
+  } else {
+    chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
+      int4 q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) keep(q[e], j[e], k0 + e < n);
+      ring.flush(S.nl_lane, S.N, row, nch);
+    });
+  }
+  if (!B.valid) return;
+  ring.finish(S.nl_lane, S.N, row, nch);
+  S.nn_lane[row] = ring.cnt;
+  S.qprune[i] = qi;
+}
 
 // One lane per atom: rho_i over the Verlet list, g_i = 1/sqrt(rho_i) into
 // qpos[i].w.  With COUNT, nact[2i] and nact[2i+1] count the pairs with
@@ -1014,6 +1123,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
   const double dt = M.dt, hdt = 0.5 * dt;
   uint8_t f = valid ? S.flag[i] : 3;
   double disp2 = 0.0;
+  float pd2 = 0.0f;  // |q - qprune|^2 (quanta^2) when pruning
   if (f != 3) {
     double x = S.x[i], y = S.y[i], z = S.z[i];
     double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
@@ -1071,16 +1181,25 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
     }
     if (MIXED) {
       bool out = false;
-      quantise(S, r, i, x, y, z, out);
+      const int4 q = quantise(S, r, i, x, y, z, out);
       if (out) atomicOr(&S.wstatus[r], 4u);
+      if (S.pruning) {
+        const int4 p = S.qprune[i];
+        const float ex = (float)(q.x - p.x), ey = (float)(q.y - p.y),
+                    ez = (float)(q.z - p.z);
+        pd2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+        if (out) pd2 = 3.0e38f;
+      }
     }
     double ex = x - S.xr[i], ey = y - S.yr[i], ez = z - S.zr[i];
     disp2 = ex * ex + ey * ey + ez * ez;
     if (!(disp2 == disp2)) disp2 = 1.0e300;  // NaN forces a rebuild
   }
-  disp2 = wave_max(disp2);
-  if ((threadIdx.x & 63) == 0 && valid)
-    atomicMax(&S.maxdisp[r], (unsigned long long)__double_as_longlong(disp2));
+  // per-replica flags (a NaN displacement counts as far)
+  const bool far = !(disp2 <= S.skin_half2);
+  const bool pfar = MIXED && S.pruning && !(pd2 <= S.prune_d2q);
+  const uint32_t m = (wave_any(far) ? 1u : 0u) | (wave_any(pfar) ? 2u : 0u);
+  if ((threadIdx.x & 63) == 0 && valid && m) atomicOr(&S.rflag[r], m);
 }
 
 template <typename FT>
@@ -1198,8 +1317,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     double D = M.v_pull[r] * (double)n1 * M.dt;
     uint32_t st = S.wstatus[r];
     if (!isfinite(E) || !isfinite(KE)) st |= 2u;  // E is 0 when not logged
-    if (__longlong_as_double((long long)S.maxdisp[r]) > S.skin_half2)
-      st |= 16u;
+    if (S.rflag[r] & 1u) st |= 16u;
     if (logstep) {
       double gap = 0.0, pmax = 0.0;
       bool have = false;
@@ -1226,7 +1344,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     }
     M.status[r] |= st;
     S.wstatus[r] = 0u;
-    S.maxdisp[r] = 0ull;
+    S.rflag[r] = 0u;
   }
   __syncthreads();
   if (logstep) {
@@ -1430,6 +1548,43 @@ void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
     k_nlist<true><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, (float)(rq * rq));
   else
     k_nlist<false><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, 0.0f);
+}
+
+// Sums of the full and of the lane-ordered list lengths (diagnostics).
+__global__ void __launch_bounds__(kBlock) k_list_stats(Dev S, int mixed) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  long long a = 0, b = 0;
+  if (i < S.N) {
+    a = S.nn[i];
+    b = mixed ? S.nn_lane[i] : a;
+  }
+  __shared__ long long ls[2][kBlock / kTile];
+  a = wave_sum_ll(a);
+  b = wave_sum_ll(b);
+  if ((threadIdx.x & 63) == 0) {
+    ls[0][threadIdx.x / kTile] = a;
+    ls[1][threadIdx.x / kTile] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long sa = 0, sb = 0;
+    for (int w = 0; w < kBlock / kTile; ++w) {
+      sa += ls[0][w];
+      sb += ls[1][w];
+    }
+    atomicAdd(&S.stats[0], (unsigned long long)sa);
+    atomicAdd(&S.stats[1], (unsigned long long)sb);
+  }
+}
+
+void launch_list_stats(const Dev &S, bool mixed, hipStream_t s) {
+  k_fill_u64<<<1, 64, 0, s>>>(S.stats, 2, 0ull);
+  k_list_stats<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, mixed ? 1 : 0);
+}
+
+void launch_prune(const Dev &S, hipStream_t s) {
+  if (S.nbmap == 0 || !S.pruning || !S.nl_lane) return;
+  k_prune<<<S.nbmap, kBlock, 0, s>>>(S);
 }
 
 void launch_block_map(const Dev &S, hipStream_t s) {

@@ -13,6 +13,8 @@ void launch_quantise(const Dev &S, hipStream_t s);
 void launch_cells(const Dev &S, hipStream_t s);
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s);
 void launch_block_map(const Dev &S, hipStream_t s);
+void launch_prune(const Dev &S, hipStream_t s);
+void launch_list_stats(const Dev &S, bool mixed, hipStream_t s);
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    void *fx, void *fy, void *fz, void *eat, double *g,
                    hipStream_t s);

@@ -59,7 +59,7 @@ class WireBatch:
                  cell: float = 8.0, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
                  n_log: int = 100, n_slots: int = 64, strain_max: float = 0.5,
                  lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
-                 device=None, wires=None, qbits: int | None = None):
+                 device=None, wires=None, qbits: int | None = None, prune: float = 0.15):
         self.replicas = list(replicas)
         self.pot = pot or Potential()
         self.precision = precision
@@ -165,9 +165,11 @@ class WireBatch:
         T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
         T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
         # --- ABI structs -------------------------------------------------------------------
+        self.prune = float(prune) if precision == "mixed" else 0.0
         self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
                                self.pot.r_tail, self.pot.r_cut, skin, cell, MASS_AU,
-                               A.MIXED if precision == "mixed" else A.FP64, self.qbits)
+                               A.MIXED if precision == "mixed" else A.FP64, self.qbits,
+                               self.prune)
         self._rep_off_h = (C.c_int64 * (R + 1))(*self.rep_off.tolist())
         self._cell_off_h = (C.c_int64 * (R + 1))(*self.cell_off.tolist())
         self.sys = A.System(R, self.max_zbins, N, self.C,
@@ -368,6 +370,15 @@ class WireBatch:
     def mean_neighbors(self) -> float:
         nn = self.t["nn"].double()
         return float(nn.sum().item() / max(1, int(self.n_atoms.sum())))
+
+    def list_lengths(self):
+        """(mean Verlet-list length, mean length of the lists the pair passes
+        read) per real atom; they differ in mixed precision with pruning."""
+        out = (C.c_int64 * 2)()
+        A.check(A.lib().tbsma_list_stats(C.byref(self.params), C.byref(self.sys),
+                                         C.byref(self.nlist), self.work, out, self.stream()))
+        n = max(1, int(self.n_atoms.sum()))
+        return out[0] / n, out[1] / n
 
     def mean_active_pairs(self) -> float:
         """Mean number of pairs within r_cut per real atom at the current

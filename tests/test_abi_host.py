@@ -60,7 +60,8 @@ def test_wire_builder_capacity_and_errors():
 
 
 def _params(**kw):
-    p = A.Params(0.2061, 1.790, 10.229, 4.036, 2.884, 6.5, 7.0, 1.0, 8.0, 196.96657, A.MIXED, 21)
+    p = A.Params(0.2061, 1.790, 10.229, 4.036, 2.884, 6.5, 7.0, 1.0, 8.0, 196.96657, A.MIXED, 21,
+                 0.15)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -72,6 +73,8 @@ def _params(**kw):
     (dict(qbits=30), b"qbits"),
     (dict(precision=7), b"precision"),
     (dict(cell=20.0), b"cell/2"),
+    (dict(prune=0.6), b"prune"),
+    (dict(prune=-0.1), b"prune"),
 ])
 def test_parameter_checks(kw, msg):
     sysm = A.System()

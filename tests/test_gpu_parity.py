@@ -291,6 +291,25 @@ def test_batched_equals_one_replica_at_a_time_bitwise():
         assert np.array_equal(b.obs_at(120)[r], s.obs_at(120)[0])
 
 
+def test_pruned_lists_leave_trajectories_unchanged_bitwise():
+    """The pair passes read lists pruned to r_cut + 2d and re-pruned when an
+    atom moves more than d; the pairs they drop contribute exactly zero, so
+    the trajectory equals the one on full lists bit for bit (several
+    prunings and rebuilds happen at 298 K in 300 steps)."""
+    reps = _three_replicas()
+    note("pruned vs full lists, 300 steps mixed")
+    a = WireBatch(reps, "mixed", n_log=50, prune=0.1)
+    a.prepare()
+    a.run_batch(300, steps_per_graph=50)
+    b = WireBatch(reps, "mixed", n_log=50, prune=0.0, qbits=a.qbits)
+    b.prepare()
+    b.run_batch(300, steps_per_graph=50)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz"):
+        assert torch.equal(a.t[k], b.t[k]), k
+    assert torch.equal(a.t["obs"], b.t["obs"])
+    assert np.all(a.status() & A.ST_REBUILT)
+
+
 def test_graph_replay_equals_eager_bitwise():
     reps = _three_replicas()
     note("graph vs eager, 100 steps")
