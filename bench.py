@@ -68,6 +68,10 @@ def main():
     ap.add_argument("--drift-steps", type=int, default=0,
                     help="also measure NVE energy drift over this many steps (D1.5xL3nm and "
                          "D3xL20nm wires at 10 K, static grips, FP64 and mixed)")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="Verlet skin (A); default: the workload's")
+    ap.add_argument("--prune", type=float, default=None,
+                    help="pruning half-width (A); default: the workload's")
     ap.add_argument("--oracle-configs", action="store_true",
                     help="also time the oracle on the D1.5xL3nm, D3xL20nm and D10xL100nm wires")
     args = ap.parse_args()
@@ -91,8 +95,10 @@ def main():
     wl = W.CONFIGS[args.workload]()
     strain_max = 0.1 if args.workload == "cfg5" else 0.5
     log(f"[bench] workload {wl.name}: building {len(wl.replicas)} replicas")
+    skin = wl.skin if args.skin is None else args.skin
+    prune = wl.prune if args.prune is None else args.prune
     b = WireBatch(wl.replicas, wl.precision, n_log=100, strain_max=strain_max,
-                  skin=wl.skin, gamma=wl.gamma)
+                  skin=skin, prune=prune, gamma=wl.gamma)
     b.prepare()
     n_real = int(b.n_atoms.sum())
     S = args.steps_per_graph

@@ -2,12 +2,14 @@
 
 Replicas are grouped into buckets of equal diameter and temperature class.
 For each bucket a sample of its replicas is run through the batched graph
-path for every candidate Verlet skin (with the cell edge r_cut + skin) and
-graph chunk length; the fastest setting in atom-timesteps/s is kept.  The
-skin trades list length (pair work per step) against rebuild frequency, which
-depends on temperature and diameter; the chunk length trades graph launch
-overhead against the step granularity of the host loop.  Choices are cached
-as JSON so later runs reuse them.
+path for every candidate Verlet skin (with the cell edge r_cut + skin),
+pruning half-width and graph chunk length; the fastest setting in
+atom-timesteps/s is kept.  The skin trades the length of the full lists
+(the work of each rebuild and pruning) against rebuild frequency, which
+depends on temperature and diameter; the pruning half-width trades the length
+of the lists the pair passes read against pruning frequency; the chunk length
+trades graph launch overhead against the step granularity of the host loop.
+Choices are cached as JSON so later runs reuse them.
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ from .engine import WireBatch
 @dataclass
 class Choice:
     skin: float
+    prune: float
     steps_per_graph: int
     rate: float          # atom-timesteps/s of the trial
     trials: list
@@ -46,8 +49,8 @@ def _key(b) -> str:
     return f"D{b[0]:g}-{b[1]}"
 
 
-def _time_batch(reps, skin, spg, trial_steps, warmup, precision, r_cut=7.0):
-    wb = WireBatch(reps, precision, skin=skin, cell=max(8.0, r_cut + skin), n_log=spg)
+def _time_batch(reps, skin, prune, spg, trial_steps, warmup, precision):
+    wb = WireBatch(reps, precision, skin=skin, prune=prune, n_log=spg)
     wb.prepare()
     wb.run_batch(warmup, spg)
     torch.cuda.synchronize()
@@ -61,10 +64,10 @@ def _time_batch(reps, skin, spg, trial_steps, warmup, precision, r_cut=7.0):
 
 
 def tune(replicas: Sequence, precision: str = "mixed", *,
-         skins=(0.6, 0.8, 1.0, 1.2), chunks=(25, 50), sample: int = 32,
-         trial_steps: int = 100, warmup: int = 100, cache: str | None = None,
-         log=print) -> Dict[str, Choice]:
-    """Best (skin, steps_per_graph) per bucket of `replicas`."""
+         skins=(1.0, 1.3, 1.6, 2.0), prunes=(0.1, 0.15, 0.2), chunks=(50,),
+         sample: int = 32, trial_steps: int = 100, warmup: int = 100,
+         cache: str | None = None, log=print) -> Dict[str, Choice]:
+    """Best (skin, prune, steps_per_graph) per bucket of `replicas`."""
     cached = {}
     if cache and os.path.exists(cache):
         with open(cache) as fh:
@@ -79,12 +82,14 @@ def tune(replicas: Sequence, precision: str = "mixed", *,
         reps = [replicas[idx[p]] for p in pick]
         trials = []
         for skin in skins:
-            for spg in chunks:
-                rate = _time_batch(reps, skin, spg, trial_steps, warmup, precision)
-                trials.append((skin, spg, rate))
-                log(f"[autotune] {k}: skin {skin} chunk {spg}: {rate:.3e} atom-steps/s")
-        skin, spg, rate = max(trials, key=lambda t: t[2])
-        result[k] = Choice(skin, spg, rate, trials)
+            for prune in (prunes if precision == "mixed" else (0.0,)):
+                for spg in chunks:
+                    rate = _time_batch(reps, skin, prune, spg, trial_steps, warmup, precision)
+                    trials.append((skin, prune, spg, rate))
+                    log(f"[autotune] {k}: skin {skin} prune {prune} chunk {spg}: "
+                        f"{rate:.3e} atom-steps/s")
+        skin, prune, spg, rate = max(trials, key=lambda t: t[3])
+        result[k] = Choice(skin, prune, spg, rate, trials)
     if cache:
         merged = dict(cached)
         merged.update({k: asdict(v) for k, v in result.items()})
@@ -98,12 +103,12 @@ class BucketRun:
     tuned settings, advanced in turn."""
 
     def __init__(self, replicas: Sequence, choices: Dict[str, Choice],
-                 precision: str = "mixed", n_log: int = 100, r_cut: float = 7.0):
+                 precision: str = "mixed", n_log: int = 100):
         self.parts = []
         for b, idx in buckets(replicas).items():
             c = choices[_key(b)]
-            wb = WireBatch([replicas[r] for r in idx], precision, skin=c.skin,
-                           cell=max(8.0, r_cut + c.skin), n_log=n_log)
+            wb = WireBatch([replicas[r] for r in idx], precision, skin=c.skin, prune=c.prune,
+                           n_log=n_log)
             self.parts.append((_key(b), idx, c, wb))
         self.n_atoms = sum(int(wb.n_atoms.sum()) for _, _, _, wb in self.parts)
 
@@ -166,15 +171,16 @@ def main(argv=None):
         dt = time.perf_counter() - t0
         total_s += dt
         n = int(wb.n_atoms.sum())
-        kbar = wb.mean_neighbors()
+        kbar, kp = wb.list_lengths()
         t3 = _pass_us(wb, 3)
         out["buckets"][k] = {
-            "replicas": len(idx), "atoms": n, "skin_A": c.skin,
+            "replicas": len(idx), "atoms": n, "skin_A": c.skin, "prune_A": c.prune,
             "steps_per_graph": c.steps_per_graph,
             "atom_timesteps_per_s": n * a.steps / dt,
             "mean_listed_neighbours": kbar,
+            "mean_pruned_list": kp,
             "force_pass_us": t3,
-            "force_pass_GB_per_s": n * (4.0 * kbar + 32.0) / (t3 * 1e-6) / 1e9}
+            "force_pass_GB_per_s": n * (4.0 * kp + 32.0) / (t3 * 1e-6) / 1e9}
         log(f"[autotune] {k}: {out['buckets'][k]}")
     out["atom_timesteps_per_s"] = run.n_atoms * a.steps / total_s
     print(json.dumps(out), flush=True)

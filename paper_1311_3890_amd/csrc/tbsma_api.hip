@@ -115,8 +115,16 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      bmap, lane_atom, nn_lane, qprune, atom_lane, stats, total;
+      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, total;
 };
+
+// Blocks of the cell sort: ceil(cells/64) per replica.
+int32_t cell_map_size(const tbsma_system *s) {
+  int64_t nb = 0;
+  for (int r = 0; r < s->R; ++r)
+    nb += (s->cell_off_h[r + 1] - s->cell_off_h[r] + 63) / 64;
+  return (int32_t)nb;
+}
 
 // Blocks of the list build: ceil(tiles/4) per replica.
 int32_t block_map_size(const tbsma_system *s) {
@@ -156,6 +164,8 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * (size_t)nt);
   L.bmap = o;
   o += up(8 * (size_t)(nt / 4 + R + 1));
+  L.cbmap = o;
+  o += up(16 * (size_t)(s->C / 64 + R + 1));
   L.lane_atom = o;
   o += up((size_t)s->N);
   L.nn_lane = o;
@@ -205,6 +215,8 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.rsum = reinterpret_cast<double *>(w + L.rsum);
   d.win = reinterpret_cast<int2 *>(w + L.win);
   d.bmap = reinterpret_cast<int2 *>(w + L.bmap);
+  d.cbmap = reinterpret_cast<int4 *>(w + L.cbmap);
+  d.ncbmap = s->R > 0 ? cell_map_size(s) : 0;
   d.lane_atom = reinterpret_cast<uint8_t *>(w + L.lane_atom);
   d.nn_lane = reinterpret_cast<int32_t *>(w + L.nn_lane);
   d.qprune = reinterpret_cast<int4 *>(w + L.qprune);

@@ -67,6 +67,8 @@ struct Dev {
   int32_t *nact;                // pairs within r_cut per atom: core, tail
   int2 *win;                    // [N/64] slot window [lo, hi) of a tile's lists
   int2 *bmap;                   // list-build blocks: first tile, tiles
+  int4 *cbmap;                  // cell-sort blocks: replica, first cell, cells
+  int32_t ncbmap;               // number of cell-sort blocks
   uint8_t *lane_atom;           // [N] pair-pass lane order within a block
   int32_t *nn_lane;             // [N] list lengths in lane order
   int32_t *nl_lane;             // lists in lane order (CL8 layout), or NULL

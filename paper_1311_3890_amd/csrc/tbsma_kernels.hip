@@ -143,33 +143,83 @@ __global__ void __launch_bounds__(kBlock) k_cell_fill(Dev S) {
   S.cell_atoms[pos] = (int32_t)i;
 }
 
-// One thread per cell: order the cell's slots ascending (the fill order is
-// not deterministic) and clear its counter for the next build.
+// Ordering of each cell's slots (the fill order is not deterministic), and
+// clearing of its counter for the next build.  Blocks of the cell map take up
+// to kSortCells cells of one replica; a wavefront takes kSortCells / 4 of
+// them in turn.  A cell of up to 64 atoms is ordered by ranks in registers
+// (lane l holds one slot and counts the smaller ones, read lane by lane);
+// larger cells by one lane's insertion sort.
+constexpr int kSortCells = 64;
+
 __global__ void __launch_bounds__(kBlock) k_cell_sort(Dev S) {
-  int64_t cg = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (cg >= S.C) return;
-  int lo = 0, hi = S.R - 1;  // replica with cell_off[r] <= cg < cell_off[r+1]
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (S.cell_off[mid] <= cg) lo = mid;
-    else hi = mid - 1;
-  }
-  int r = lo;
-  if (!rebuilds(S, r)) return;
-  int64_t c = cg - S.cell_off[r];
-  int32_t *start = S.cell_start + S.cell_off[r] + r;
-  int32_t a = start[c], e = start[c + 1];
+  const int4 cb = S.cbmap[blockIdx.x];  // replica, first cell, cells
+  const int r = cb.x;
+  if (!rebuilds(S, r)) return;  // uniform over the block
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int per = kSortCells / (kBlock / kTile);
+  const int64_t c0 = S.cell_off[r];
+  const int32_t *start = S.cell_start + c0 + r;
   int32_t *v = S.cell_atoms;
-  for (int32_t k = a + 1; k < e; ++k) {
-    int32_t key = v[k];
-    int32_t m = k - 1;
-    while (m >= a && v[m] > key) {
-      v[m + 1] = v[m];
-      --m;
+  for (int k = 0; k < per; ++k) {
+    const int c = cb.y + w * per + k;
+    if (w * per + k >= cb.z) break;  // uniform over the wavefront
+    const int32_t a = start[c], n = start[c + 1] - a;
+    if (n <= 64) {
+      const int32_t mine = lane < n ? v[a + lane] : 0x7fffffff;
+      int rank = 0;
+      for (int m = 0; m < n; ++m)
+        rank += __builtin_amdgcn_readlane(mine, m) < mine ? 1 : 0;
+      if (lane < n) v[a + rank] = mine;
+    } else if (lane == 0) {
+      for (int32_t q = a + 1; q < a + n; ++q) {
+        const int32_t key = v[q];
+        int32_t m = q - 1;
+        while (m >= a && v[m] > key) {
+          v[m + 1] = v[m];
+          --m;
+        }
+        v[m + 1] = key;
+      }
     }
-    v[m + 1] = key;
+    if (lane == 0) S.cnt[c0 + c] = 0;
   }
-  S.cnt[cg] = 0;
+}
+
+// Cell map of the sort: for each replica, blocks of up to kSortCells of its
+// cells, replicas in order (one block of 1024 threads; a scan over the
+// replicas of their block counts).
+__global__ void __launch_bounds__(1024) k_cell_map(Dev S) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < S.R; b0 += 1024) {
+    const int r = b0 + threadIdx.x;
+    const int32_t nc =
+        r < S.R ? (int32_t)(S.cell_off[r + 1] - S.cell_off[r]) : 0;
+    const int32_t v = (nc + kSortCells - 1) / kSortCells;
+    int32_t s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(s, o, 64);
+      if (lane >= o) s += t;
+    }
+    if (lane == 63) wsum[wid] = s;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wid) woff += wsum[k];
+      tot += wsum[k];
+    }
+    const int32_t ex = carry_s + woff + s - v;
+    for (int k = 0; k < v; ++k)
+      S.cbmap[ex + k] = make_int4(r, k * kSortCells,
+                                  min(kSortCells, nc - k * kSortCells), 0);
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s += tot;
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1538,7 +1588,7 @@ void launch_cells(const Dev &S, hipStream_t s) {
   k_cell_count<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
   k_cell_scan<<<S.R, 1024, 0, s>>>(S);
   k_cell_fill<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
-  k_cell_sort<<<nblk(S.C, kBlock), kBlock, 0, s>>>(S);
+  if (S.ncbmap > 0) k_cell_sort<<<S.ncbmap, kBlock, 0, s>>>(S);
 }
 
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
@@ -1589,6 +1639,7 @@ void launch_prune(const Dev &S, hipStream_t s) {
 
 void launch_block_map(const Dev &S, hipStream_t s) {
   k_block_map<<<1, 1024, 0, s>>>(S);
+  k_cell_map<<<1, 1024, 0, s>>>(S);
 }
 
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,

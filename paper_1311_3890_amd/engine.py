@@ -56,7 +56,7 @@ class WireBatch:
     """R independent [100] Au nanowires advanced together on one GPU."""
 
     def __init__(self, replicas: Sequence, precision: str = "mixed", *, skin: float = 1.0,
-                 cell: float = 8.0, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
+                 cell: float | None = None, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
                  n_log: int = 100, n_slots: int = 64, strain_max: float = 0.5,
                  lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
                  device=None, wires=None, qbits: int | None = None, prune: float = 0.15):
@@ -64,6 +64,8 @@ class WireBatch:
         self.pot = pot or Potential()
         self.precision = precision
         k_cap = (int(k_cap) + 7) // 8 * 8
+        if cell is None:  # the smallest cell the 27-cell scan allows, at least 8 A
+            cell = max(8.0, self.pot.r_cut + skin)
         self.skin, self.cell, self.k_cap = skin, cell, k_cap
         self.gamma, self.dt, self.lab_frame = gamma, dt, lab_frame
         self.n_log, self.n_slots = n_log, n_slots

@@ -452,7 +452,7 @@ def test_full_size_config3_sampled():
     graph-replayed steps, then sampled replicas against the oracle."""
     wl = W.cfg3_batched()
     note(f"cfg3 full size R={len(wl.replicas)}")
-    b = WireBatch(wl.replicas, "mixed", n_log=50)
+    b = WireBatch(wl.replicas, "mixed", n_log=50, skin=wl.skin, prune=wl.prune)
     b.prepare()
     b.run_batch(100, 50)
     torch.cuda.synchronize()
@@ -483,7 +483,7 @@ def test_full_size_config5_sampled():
 def test_config4_mixed_shapes_sampled():
     wl = W.cfg4_mixed_shapes()
     note(f"cfg4 R={len(wl.replicas)}")
-    b = WireBatch(wl.replicas, "mixed", n_log=20)
+    b = WireBatch(wl.replicas, "mixed", n_log=20, skin=wl.skin, prune=wl.prune)
     b.prepare()
     b.run_batch(40, 20)
     torch.cuda.synchronize()

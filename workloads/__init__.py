@@ -42,7 +42,8 @@ class Workload:
     precision: str      # "fp64" or "mixed"
     steps: int          # protocol length (steps)
     gamma: float = 1.0  # 1/ps
-    skin: float = 1.0   # Angstrom
+    skin: float = 1.0   # Angstrom, Verlet skin of the full lists
+    prune: float = 0.15  # Angstrom, half-width of the pruned lists (mixed)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -77,7 +78,9 @@ def cfg3_batched(n_rep: int = 512) -> Workload:
     Ls = rng.uniform(50.0, 400.0, size=n_rep)
     reps = [Replica(30.0, snap_length(float(Ls[r])), 298.0, 0.5, seed_of(r), r)
             for r in range(n_rep)]
-    return Workload(f"batched {n_rep}x D3nm L5-40nm 298K", reps, "mixed", 20000)
+    # skin 1.6 A: with pruned lists the pair work does not grow with the
+    # skin, and rebuilds become rare (measured fastest of 1.0-2.0 A)
+    return Workload(f"batched {n_rep}x D3nm L5-40nm 298K", reps, "mixed", 20000, skin=1.6)
 
 
 def cfg4_mixed_shapes(n_rep: int = 2048) -> Workload:
@@ -89,7 +92,7 @@ def cfg4_mixed_shapes(n_rep: int = 2048) -> Workload:
     rates = (0.1, 0.5, 1.0)
     reps = [Replica(Ds[r % 4], snap_length(float(Ls[r])), 10.0 if r % 2 == 0 else 298.0,
                     rates[r % 3], seed_of(r), r) for r in range(n_rep)]
-    return Workload(f"mixed-shapes {n_rep}x D1.5-3nm L3-30nm", reps, "mixed", 20000)
+    return Workload(f"mixed-shapes {n_rep}x D1.5-3nm L3-30nm", reps, "mixed", 20000, skin=1.6)
 
 
 def cfg5_large() -> Workload:
