@@ -79,6 +79,8 @@ extern "C" {
 #define TBSMA_ST_OUTSIDE 4u    /* an atom left its cell grid (still exact) */
 #define TBSMA_ST_RUPTURED 8u   /* axial gap >= r_cut found at a logged step */
 #define TBSMA_ST_REBUILT 16u   /* neighbour list rebuilt at some step */
+#define TBSMA_ST_DONE 32u      /* retired: the pulled grip moved `retire` A
+                                  past the rupture; the replica is frozen */
 
 /* observable record (tbsma_md.obs), TBSMA_NOBS doubles */
 #define TBSMA_OBS_STEP 0    /* step index of the state */
@@ -238,6 +240,15 @@ typedef struct {
  *  obs           device [n_slots * R * TBSMA_NOBS]: record of replica r at
  *                logged step s is at ((s / n_log) % n_slots) * R + r.
  *  status        device [R] uint32 status bits (OR-accumulated).
+ *  retire        grip travel (A) after the first logged step at which the
+ *                replica is ruptured, beyond which it is retired: status
+ *                TBSMA_ST_DONE, and the step loops leave its atoms, lists and
+ *                forces untouched (its record repeats at later logged steps).
+ *                0 or less: never retire.
+ *  dfail         device [R] double: grip displacement D at the first logged
+ *                step at which the replica was ruptured (its failure point;
+ *                strain D/L0, eq 4), -1 before that.  Set it to -1 when the
+ *                run starts.  May be NULL when retire <= 0.
  */
 typedef struct {
   double dt, gamma;
@@ -251,6 +262,8 @@ typedef struct {
   int64_t *step;
   double *obs;
   uint32_t *status;
+  double retire;
+  double *dfail;
 } tbsma_md;
 
 /*

@@ -18,7 +18,7 @@ NOBS = 10
 OK, EINVAL, ECAPACITY, EHIP, EDEVICE = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
 DYN, GRIP_FIXED, GRIP_PULL, PAD = 0, 1, 2, 3
-ST_OVERFLOW, ST_NONFINITE, ST_OUTSIDE, ST_RUPTURED, ST_REBUILT = 1, 2, 4, 8, 16
+ST_OVERFLOW, ST_NONFINITE, ST_OUTSIDE, ST_RUPTURED, ST_REBUILT, ST_DONE = 1, 2, 4, 8, 16, 32
 OBS_STEP, OBS_EPOT, OBS_KE, OBS_T, OBS_WZZ, OBS_SZZ, OBS_STRAIN, OBS_GAP, OBS_D, \
     OBS_STATUS = range(10)
 
@@ -58,7 +58,8 @@ class MD(C.Structure):
     _fields_ = [("dt", C.c_double), ("gamma", C.c_double), ("lab_frame", C.c_int32),
                 ("n_log", C.c_int32), ("n_slots", C.c_int32), ("reserved", C.c_int32),
                 ("T", vp), ("v_pull", vp), ("z_lo", vp), ("z_hi", vp), ("vol", vp), ("L0", vp),
-                ("seed", vp), ("dof", vp), ("step", vp), ("obs", vp), ("status", vp)]
+                ("seed", vp), ("dof", vp), ("step", vp), ("obs", vp), ("status", vp),
+                ("retire", C.c_double), ("dfail", vp)]
 
 
 P = C.POINTER

@@ -176,6 +176,7 @@ Layout layout(const tbsma_system *s) {
   o += up((size_t)s->N);
   L.stats = o;
   o += 256;
+
   L.total = o;
   return L;
 }
@@ -222,6 +223,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.qprune = reinterpret_cast<int4 *>(w + L.qprune);
   d.atom_lane = reinterpret_cast<uint8_t *>(w + L.atom_lane);
   d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
+
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
     // a margin of 1e-5 A for rounding of positions to quanta and of r^2 to
@@ -373,6 +375,8 @@ DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
   M.step = m->step;
   M.obs = m->obs;
   M.status = m->status;
+  M.retire = m->dfail ? m->retire : 0.0;
+  M.dfail = m->dfail;
   return M;
 }
 
@@ -405,11 +409,14 @@ int check_lists(const tbsma_params *p, const tbsma_cells *c,
   } while (0)
 
 // One MD step (see tbsma_step) enqueued on s.
-void enqueue_step(const tbsma_params *p, const Dev &d, const DevMD &M,
+void enqueue_step(const tbsma_params *p, const Dev &d0, const DevMD &M0,
                   const tbsma_forces_out *o, const PotF &PF, const PotD &PD,
                   hipStream_t s) {
   bool mixed = p->precision == TBSMA_MIXED;
   double rl = p->r_cut + p->skin;
+  Dev d = d0;
+  d.rstatus = M0.status;
+  const DevMD &M = M0;
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_cells(d, s);
   launch_nlist(d, mixed, rl, s);
@@ -491,6 +498,7 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
                   s);
   launch_fill_u64(reinterpret_cast<unsigned long long *>(w + L.zbmin),
                   (int64_t)sys->R * sys->max_zbins, ~0ull, s);
+
   launch_block_map(make_dev(prm, sys, work), s);
   HIPCHK(hipGetLastError());
   return TBSMA_OK;

@@ -86,6 +86,8 @@ struct Dev {
   int32_t energies;
   int32_t n_log;
   const int64_t *step;
+  // step loops only: per-replica status; retired replicas are skipped
+  const uint32_t *rstatus;
   int32_t k_cap;
   double *xr, *yr, *zr;
   // workspace
@@ -113,6 +115,8 @@ struct DevMD {
   int64_t *step;
   double *obs;
   uint32_t *status;
+  double retire;   // grip travel after rupture before retiring (<= 0: never)
+  double *dfail;   // [R] grip displacement at the first rupture (-1: none)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
@@ -225,6 +229,11 @@ __device__ __forceinline__ double dkey_inv(unsigned long long k) {
 
 __device__ __forceinline__ bool rebuilds(const Dev &S, int r) {
   return S.all || (S.rflag[r] & 1u);
+}
+
+// Whether replica r has been retired (step loops only).
+__device__ __forceinline__ bool retired(const Dev &S, int r) {
+  return S.rstatus != nullptr && (S.rstatus[r] & 32u);
 }
 
 // Whether replica r's pruned lists must be pruned again this step.

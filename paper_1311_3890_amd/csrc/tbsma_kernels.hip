@@ -917,6 +917,7 @@ template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   __shared__ int4 lq[kStage + 1];
   const PairBlock B = pair_block(S);
+  if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   int lo, size;
   block_window(S, B, lo, size);
   if (size > 0 && size <= kStage && stage(S, lq, B, lo, size))
@@ -958,6 +959,7 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
   int64_t b0 = xcd_block() * kBlock;
   int64_t i = b0 + threadIdx.x;
   bool valid = i < S.N;
+  if (valid && retired(S, S.tile_rep[i / kTile])) return;  // whole wavefront
   int n = valid ? S.nn[i] : 0;
   double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
          zi = valid ? S.z[i] : 0.0;
@@ -1087,6 +1089,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
   __shared__ int4 lq[kStage + 1];
   __shared__ double lsum[2 * kBlock];
   const PairBlock B = pair_block(S);
+  if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   const bool energy =
       S.energies > 0 || (S.energies < 0 && (*S.step + 1) % S.n_log == 0);
   int lo, size;
@@ -1112,6 +1115,7 @@ __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
   int64_t b0 = xcd_block() * kBlock;
   int64_t i = b0 + threadIdx.x;
   bool valid = i < S.N;
+  if (valid && retired(S, S.tile_rep[i / kTile])) return;  // whole wavefront
   int n = valid ? S.nn[i] : 0;
   double xi = valid ? S.x[i] : 0.0, yi = valid ? S.y[i] : 0.0,
          zi = valid ? S.z[i] : 0.0;
@@ -1169,6 +1173,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool valid = i < S.N;
   int r = valid ? S.tile_rep[i / kTile] : 0;
+  if (valid && (M.status[r] & 32u)) return;  // retired (whole wavefront)
   int64_t step = *M.step;
   const double dt = M.dt, hdt = 0.5 * dt;
   uint8_t f = valid ? S.flag[i] : 3;
@@ -1260,6 +1265,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool valid = i < S.N;
   int r = valid ? S.tile_rep[i / kTile] : 0;
+  if (valid && (M.status[r] & 32u)) return;  // retired (whole wavefront)
   int64_t step = *M.step;
   const double hdt = 0.5 * M.dt;
   uint8_t f = valid ? S.flag[i] : 3;
@@ -1350,6 +1356,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
   // energy and virial tile sums are current on logged steps only
   const bool logstep = (n1 % M.n_log) == 0;
+  const bool frozen = (M.status[r] & 32u) != 0;  // retired: record unchanged
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   if (logstep) {
     block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
@@ -1359,7 +1366,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   int nb = 2 * S.grid_dim[3 * r + 2];
   unsigned long long *bmin = S.zbmin + (int64_t)r * S.max_zbins;
   unsigned long long *bmax = S.zbmax + (int64_t)r * S.max_zbins;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !frozen) {
     double E = s[0], wzz = s[1];
     double KE = 0.5 * s[2] / kAccel, Kz = s[3] / kAccel;
     int dof = M.dof[r];
@@ -1379,6 +1386,11 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
         have = true;
       }
       if (gap >= M.r_cut) st |= 8u;
+      // retirement: `retire` A of grip travel after the first rupture
+      if (M.retire > 0.0) {
+        if ((st & 8u) && M.dfail[r] < 0.0) M.dfail[r] = D;
+        if (M.dfail[r] >= 0.0 && D >= M.dfail[r] + M.retire) st |= 32u;
+      }
       double *o = M.obs + ((n1 / M.n_log) % M.n_slots) * (int64_t)S.R * 10 +
                   (int64_t)r * 10;
       o[0] = (double)n1;
@@ -1395,6 +1407,14 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     M.status[r] |= st;
     S.wstatus[r] = 0u;
     S.rflag[r] = 0u;
+  } else if (threadIdx.x == 0 && logstep) {
+    // a retired replica repeats its last record (with its step index)
+    const int64_t k = n1 / M.n_log;
+    const double *src = M.obs + ((k - 1) % M.n_slots) * (int64_t)S.R * 10 +
+                        (int64_t)r * 10;
+    double *dst = M.obs + (k % M.n_slots) * (int64_t)S.R * 10 + (int64_t)r * 10;
+    if (k > 0)
+      for (int q = 0; q < 10; ++q) dst[q] = src[q];
   }
   __syncthreads();
   if (logstep) {

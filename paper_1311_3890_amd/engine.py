@@ -59,7 +59,8 @@ class WireBatch:
                  cell: float | None = None, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
                  n_log: int = 100, n_slots: int = 64, strain_max: float = 0.5,
                  lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
-                 device=None, wires=None, qbits: int | None = None, prune: float = 0.15):
+                 device=None, wires=None, qbits: int | None = None, prune: float = 0.15,
+                 retire: float = 0.0):
         self.replicas = list(replicas)
         self.pot = pot or Potential()
         self.precision = precision
@@ -166,6 +167,7 @@ class WireBatch:
         T["step"] = torch.zeros(1, dtype=torch.int64, device=dev)
         T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
         T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
+        T["dfail"] = torch.full((R,), -1.0, **f64)
         # --- ABI structs -------------------------------------------------------------------
         self.prune = float(prune) if precision == "mixed" else 0.0
         self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
@@ -192,7 +194,8 @@ class WireBatch:
                                _ptr(T["rep_energy"]), _ptr(T["rep_wzz"]))
         self.md = A.MD(dt, gamma, lab_frame, n_log, n_slots, 0,
                        *[_ptr(T[k]) for k in ("T", "v_pull", "z_lo", "z_hi", "vol", "L0", "seed",
-                                              "dof", "step", "obs", "status")])
+                                              "dof", "step", "obs", "status")], float(retire),
+                       _ptr(T["dfail"]))
         nb = C.c_size_t()
         A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
                                               C.byref(nb)))
@@ -334,7 +337,7 @@ class WireBatch:
     # lists saved too, a resumed run repeats the original bit for bit (the
     # noise is keyed by the step index, which is part of the state).
     _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nl_lane", "nn", "x_ref", "y_ref",
-              "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "obs", "work")
+              "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "dfail", "obs", "work")
 
     def state_dict(self):
         return {k: self.t[k].detach().cpu().numpy().copy() for k in self._STATE}

@@ -436,6 +436,42 @@ def test_rupture_gap_and_nonfinite_status():
     assert st[1] & A.ST_NONFINITE and not st[1] & A.ST_RUPTURED
 
 
+def test_retired_replica_freezes_and_the_rest_are_unaffected():
+    """A replica cut in two is ruptured at the first logged step; after
+    `retire` A more grip travel it is retired: its atoms stop moving and its
+    record repeats, while the other replica evolves exactly as it does alone."""
+    reps = [R(20.0, 40.0, T=298.0, v=0.5, r=0), R(20.0, 40.0, T=298.0, v=0.5, r=1)]
+    note("retirement after rupture, 200 steps mixed")
+    # retirement is decided at logged steps; 0.045 A sits between two of them
+    # (0.01 A apart) so that rounding of the grip travel cannot move it
+    b = WireBatch(reps, "mixed", n_log=10, retire=0.045)
+    b.prepare()
+    o, n = int(b.rep_off[0]), int(b.n_atoms[0])
+    zz = b.t["z"][o:o + n]
+    up = zz > 20.0
+    zz[up] += 9.0
+    b.t["z0"][o:o + n][up] += 9.0
+    b.compute_forces()
+    b.run_batch(100, 50)
+    st = b.status()
+    assert st[0] & A.ST_RUPTURED and st[0] & A.ST_DONE
+    assert not st[1] & (A.ST_RUPTURED | A.ST_DONE)
+    x100 = [a.copy() for a in b.positions(0)]
+    rec100 = b.obs_at(100)[0].copy()
+    b.run_batch(100, 50)
+    for a, c in zip(b.positions(0), x100):
+        assert np.array_equal(a, c)
+    assert np.array_equal(b.obs_at(200)[0], rec100)
+    # retired at the first logged step with 0.045 A of travel (0.001 A/step)
+    # after the rupture seen at step 10
+    assert rec100[A.OBS_STEP] == 60.0
+    s = WireBatch([reps[1]], "mixed", n_log=10, qbits=b.qbits, retire=0.045)
+    s.prepare()
+    s.run_batch(200, 50)
+    for a_, c_ in zip(b.positions(1) + b.velocities(1), s.positions(0) + s.velocities(0)):
+        assert np.array_equal(a_, c_)
+
+
 def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1):
     worst = 0.0
     for r in reps_to_check:
