@@ -60,25 +60,42 @@ def properties(strain, stress, status=None, eps_lin: float = 0.02) -> Dict[str, 
 
 class Recorder:
     """Keeps every observable record of a WireBatch: run() advances it in
-    chunks that fit the ring and drains the ring after each."""
+    chunks that fit the ring and drains the ring after each.  With
+    compact=True the batch is replaced, after each chunk in which a replica
+    was retired, by its compacted copy (WireBatch.compact); records stay
+    keyed by the replica's index in the original batch."""
 
     def __init__(self, batch):
         self.b = batch
-        self.rows: List[np.ndarray] = []   # [R, NOBS] per logged step
-        self.last = -1
+        self.ids = np.arange(batch.R)                # original index of each batch row
+        self.rows: List[List[np.ndarray]] = [[] for _ in range(batch.R)]
+        self.last = np.full(batch.R, -1, dtype=np.int64)
 
     def drain(self):
-        ring = self.b.obs()                # [n_slots, R, NOBS]
-        steps = ring[:, 0, A.OBS_STEP]
-        order = np.argsort(steps)
-        for slot in order:
-            st = int(steps[slot])
-            if st > self.last and st > 0:
-                # retired replicas repeat an older record: keep the slot as is
-                self.rows.append(ring[slot].copy())
-                self.last = st
+        ring = self.b.obs()                          # [n_slots, R, NOBS]
+        steps = ring[:, :, A.OBS_STEP].astype(np.int64)
+        for j, r in enumerate(self.ids):
+            # a retired replica repeats its last record: only newer steps count
+            for slot in np.argsort(steps[:, j], kind="stable"):
+                st = int(steps[slot, j])
+                if st > self.last[r] and st > 0:
+                    self.rows[r].append(ring[slot, j].copy())
+                    self.last[r] = st
 
-    def run(self, n_steps: int, steps_per_graph: int = 50):
+    def compact(self) -> bool:
+        """Drops retired replicas from the batch; False once none is left."""
+        st = np.asarray(self.b.status()).astype(np.int64)
+        keep = [j for j in range(len(self.ids)) if not st[j] & A.ST_DONE]
+        if len(keep) == len(self.ids):
+            return True
+        nb = self.b.compact(keep) if keep else None
+        self.ids = self.ids[keep]
+        if nb is None:
+            return False
+        self.b = nb
+        return True
+
+    def run(self, n_steps: int, steps_per_graph: int = 50, compact: bool = False):
         chunk = self.b.n_log * self.b.n_slots
         chunk -= chunk % steps_per_graph if chunk > steps_per_graph else 0
         done = 0
@@ -87,13 +104,16 @@ class Recorder:
             self.b.run_batch(k, steps_per_graph)
             done += k
             self.drain()
+            if compact and not self.compact():
+                break
 
     def curve(self, r: int):
-        """(strain, stress GPa, status) of replica r, one entry per logged step."""
-        if not self.rows:
+        """(strain, stress GPa, status) of original replica r, one entry per
+        logged step."""
+        if not self.rows[r]:
             return np.zeros(0), np.zeros(0), np.zeros(0, dtype=np.int64)
-        a = np.stack([row[r] for row in self.rows])
+        a = np.stack(self.rows[r])
         return a[:, A.OBS_STRAIN], a[:, A.OBS_SZZ], a[:, A.OBS_STATUS].astype(np.int64)
 
     def properties(self, eps_lin: float = 0.02):
-        return [properties(*self.curve(r), eps_lin=eps_lin) for r in range(self.b.R)]
+        return [properties(*self.curve(r), eps_lin=eps_lin) for r in range(len(self.rows))]

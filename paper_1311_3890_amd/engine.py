@@ -62,7 +62,13 @@ class WireBatch:
                  device=None, wires=None, qbits: int | None = None, prune: float = 0.15,
                  retire: float = 0.0):
         self.replicas = list(replicas)
+        if not self.replicas:
+            raise ValueError("a batch needs at least one replica")
         self.pot = pot or Potential()
+        # settings a compacted copy of this batch is built with
+        self._kw = dict(skin=skin, cell=cell, gamma=gamma, dt=dt, n_log=n_log, n_slots=n_slots,
+                        strain_max=strain_max, lab_frame=lab_frame, a=a, pot=self.pot,
+                        device=device, prune=prune, retire=retire)
         self.precision = precision
         k_cap = (int(k_cap) + 7) // 8 * 8
         if cell is None:  # the smallest cell the 27-cell scan allows, at least 8 A
@@ -360,6 +366,40 @@ class WireBatch:
 
     def status(self):
         return self.t["status"].cpu().numpy().view(np.uint32)
+
+    def compact(self, keep: Sequence[int] | None = None) -> "WireBatch | None":
+        """A new batch of the replicas in `keep` (default: those not retired),
+        in that order, or None when none is left.  Positions, velocities, grip
+        references, the step index, status, rupture displacements and the
+        observable ring carry over; cells, lists and forces are rebuilt from
+        the carried positions.  Every replica evolves independently of the
+        others, so a kept replica continues exactly as it would in this batch
+        after a list rebuild and force evaluation (build_lists and
+        compute_forces) at the same step."""
+        if keep is None:
+            st = self.status()
+            keep = [r for r in range(self.R) if not st[r] & A.ST_DONE]
+        keep = [int(r) for r in keep]
+        if not keep:
+            return None
+        if min(keep) < 0 or max(keep) >= self.R or len(set(keep)) != len(keep):
+            raise ValueError("keep must list distinct replica indices of this batch")
+        nb = WireBatch([self.replicas[r] for r in keep], self.precision,
+                       wires=[self.wires[r] for r in keep], qbits=self.qbits,
+                       k_cap=self.k_cap, **dict(self._kw, device=self.device))
+        for j, r in enumerate(keep):
+            o, oj, n = int(self.rep_off[r]), int(nb.rep_off[j]), int(self.n_atoms[r])
+            for k in ("x", "y", "z", "vx", "vy", "vz", "z0"):
+                nb.t[k][oj:oj + n].copy_(self.t[k][o:o + n])
+        idx = torch.tensor(keep, dtype=torch.int64, device=self.device)
+        nb.t["step"].copy_(self.t["step"])
+        nb.t["status"].copy_(self.t["status"][idx])
+        nb.t["dfail"].copy_(self.t["dfail"][idx])
+        ring = self.t["obs"].view(self.n_slots, self.R, A.NOBS)
+        nb.t["obs"].view(nb.n_slots, nb.R, A.NOBS).copy_(ring[:, idx])
+        nb.build_lists()
+        nb.compute_forces()
+        return nb
 
     def step_index(self) -> int:
         return int(self.t["step"].item())

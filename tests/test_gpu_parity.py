@@ -472,6 +472,39 @@ def test_retired_replica_freezes_and_the_rest_are_unaffected():
         assert np.array_equal(a_, c_)
 
 
+def test_compacted_batch_continues_the_kept_replicas_exactly():
+    """After a replica is retired, the compacted batch of the other two
+    continues them bit for bit as the full batch does after a list rebuild and
+    force evaluation at the same step; the step index, status and records
+    carry over."""
+    reps = [R(20.0, 40.0, T=298.0, v=0.5, r=k) for k in range(3)]
+    note("compaction of 3 replicas after a retirement, 100 + 100 steps mixed")
+    b = WireBatch(reps, "mixed", n_log=10, retire=0.045)
+    b.prepare()
+    o, n = int(b.rep_off[1]), int(b.n_atoms[1])
+    zz = b.t["z"][o:o + n]
+    up = zz > 20.0
+    zz[up] += 9.0
+    b.t["z0"][o:o + n][up] += 9.0
+    b.compute_forces()
+    b.run_batch(100, 50)
+    assert b.status()[1] & A.ST_DONE and not (b.status()[[0, 2]] & A.ST_DONE).any()
+    c = b.compact()
+    assert c.R == 2 and c.step_index() == 100
+    assert np.array_equal(c.status(), b.status()[[0, 2]])
+    assert np.array_equal(c.obs(), b.obs()[:, [0, 2]])
+    b.build_lists()
+    b.compute_forces()
+    b.run_batch(100, 50)
+    c.run_batch(100, 50)
+    for j, r in enumerate((0, 2)):
+        for a_, c_ in zip(b.positions(r) + b.velocities(r), c.positions(j) + c.velocities(j)):
+            assert np.array_equal(a_, c_)
+    assert np.array_equal(c.obs(), b.obs()[:, [0, 2]])
+    assert b.compact([1]).status()[0] & A.ST_DONE
+    assert WireBatch.compact(c, []) is None
+
+
 def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1):
     worst = 0.0
     for r in reps_to_check:
