@@ -42,7 +42,8 @@ class _MD(C.Structure):
     _fields_ = [("dt", C.c_double), ("gamma", C.c_double), ("T", C.c_double),
                 ("v_pull", C.c_double), ("z_lo", C.c_double), ("z_hi", C.c_double),
                 ("mass", C.c_double), ("seed", C.c_uint64), ("rep_id", C.c_uint32),
-                ("lab_frame", C.c_int32)]
+                ("lab_frame", C.c_int32), ("nh_tau", C.c_double), ("grip_step", C.c_double),
+                ("grip_hold", C.c_int64)]
 
 
 @dataclass
@@ -76,10 +77,14 @@ class MD:
     seed: int = 0
     rep_id: int = 0
     lab_frame: int = 0
+    nh_tau: float = 0.0     # > 0: Nose-Hoover thermostat (gamma must be 0)
+    grip_step: float = 0.0  # stepwise grips: displacement per side per hold (A)
+    grip_hold: int = 0      # > 0: stepwise symmetric grips, steps per hold
 
     def c(self) -> _MD:
         return _MD(self.dt, self.gamma, self.T, self.v_pull, self.z_lo, self.z_hi,
-                   self.mass, self.seed, self.rep_id, self.lab_frame)
+                   self.mass, self.seed, self.rep_id, self.lab_frame, self.nh_tau,
+                   self.grip_step, self.grip_hold)
 
 
 _lib = None
@@ -100,8 +105,9 @@ def lib():
         L.orc_radial_eval.restype = C.c_double
         L.orc_radial_eval.argtypes = [C.POINTER(_Pot), C.c_int, C.c_double, C.POINTER(C.c_double)]
         L.orc_build_wire.restype = C.c_int64
-        L.orc_build_wire.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.orc_build_wire.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                     C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64]
         L.orc_forces.restype = C.c_double
         L.orc_forces.argtypes = [C.POINTER(_Pot), C.c_int64, dp, dp, dp, C.c_int,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -122,7 +128,8 @@ def lib():
                                      C.c_double]
         L.orc_run.restype = None
         L.orc_run.argtypes = [C.POINTER(_Pot), C.POINTER(_MD), C.c_int64, dp, dp, dp, dp, dp, dp,
-                              dp, u8p, dp, dp, dp, C.c_void_p, C.c_int64, C.c_int64, C.c_int]
+                              dp, u8p, dp, dp, dp, C.c_void_p, C.c_int64, C.c_int64, C.c_int,
+                              dp, dp]
         L.orc_observe.restype = None
         L.orc_observe.argtypes = [C.POINTER(_Pot), C.POINTER(_MD), C.c_int64, dp, dp, dp, dp, dp,
                                   dp, u8p, C.c_int64, C.c_double, C.c_double, dp]
@@ -154,15 +161,18 @@ def radial(pot: Pot, kind: int, r: float):
     return f, d.value
 
 
-def build_wire(a: float, D: float, L: float, n_grip: int = 2):
+def build_wire(a: float, D: float, L: float, n_grip: int = 2, notch_layers: int = 0,
+               notch_depth: float = 0.0):
     """[100] FCC cylinder of diameter D and length L (Simulation details,
-    Figure 1).  Returns x, y, z (float64) and flag (uint8: 0 dynamic,
-    1 fixed grip, 2 pulled grip)."""
-    n = lib().orc_build_wire(a, D, L, n_grip, None, None, None, None, 0)
+    Figure 1), optionally with the ring notch of Figure 1's caption at its
+    middle.  Returns x, y, z (float64) and flag (uint8: 0 dynamic,
+    1 bottom grip, 2 top grip)."""
+    n = lib().orc_build_wire(a, D, L, n_grip, notch_layers, notch_depth, None, None, None,
+                             None, 0)
     x, y, z = (np.empty(n) for _ in range(3))
     flag = np.empty(n, dtype=np.uint8)
-    lib().orc_build_wire(a, D, L, n_grip, x.ctypes.data, y.ctypes.data, z.ctypes.data,
-                         flag.ctypes.data, n)
+    lib().orc_build_wire(a, D, L, n_grip, notch_layers, notch_depth, x.ctypes.data,
+                         y.ctypes.data, z.ctypes.data, flag.ctypes.data, n)
     return x, y, z, flag
 
 
@@ -233,10 +243,12 @@ class State:
         self.e_atom = np.zeros(n)
         self.z0 = self.z.copy()
         self.step = 0
+        self.zeta = np.zeros(1)   # Nose-Hoover friction (1/ps)
+        self.eta = np.zeros(1)    # its time integral
 
     def copy(self):
         s = State(self.x, self.y, self.z, self.flag)
-        for k in ("vx", "vy", "vz", "fx", "fy", "fz", "e_atom", "z0"):
+        for k in ("vx", "vy", "vz", "fx", "fy", "fz", "e_atom", "z0", "zeta", "eta"):
             setattr(s, k, getattr(self, k).copy())
         s.step = self.step
         return s
@@ -256,10 +268,11 @@ def compute_forces(pot: Pot, st: State, mode: int = 0):
 
 
 def run(pot: Pot, md: MD, st: State, n_steps: int, mode: int = 0):
-    """n_steps of BAOAB Langevin / velocity Verlet with grips (orc_run)."""
+    """n_steps of velocity Verlet with grips and the Langevin (BAOAB) or
+    Nose-Hoover thermostat, or none (orc_run)."""
     lib().orc_run(C.byref(pot.c()), C.byref(md.c()), st.x.size, st.x, st.y, st.z,
                   st.vx, st.vy, st.vz, st.z0, st.flag, st.fx, st.fy, st.fz,
-                  st.e_atom.ctypes.data, st.step, n_steps, mode)
+                  st.e_atom.ctypes.data, st.step, n_steps, mode, st.zeta, st.eta)
     st.step += n_steps
 
 

@@ -108,10 +108,16 @@ double orc_radial_eval(const orc_pot *P, int kind, double r, double *df) {
  * then i (x), ascending.  The lowest n_grip and highest n_grip (002) planes
  * are the rigid grips: flag 1 at the bottom (fixed), flag 2 at the top (the
  * end that is pulled); every other atom has flag 0 (dynamic).
+ * Ring notch (Simulation details; Figure 1 caption: three atoms wide, two
+ * deep), reading: with nk planes, the notch covers the notch_layers planes
+ * k = nk/2 - notch_layers/2, ..., nk/2 - notch_layers/2 + notch_layers - 1
+ * (integer division) and removes there every site whose distance from the
+ * axis exceeds D/2 - notch_depth.  notch_layers = 0: no notch.
  * Returns the number of atoms (also when cap is too small: then only the
  * count is computed and nothing is written past cap).
  */
 int64_t orc_build_wire(double a, double D, double L, int n_grip,
+                       int notch_layers, double notch_depth,
                        double *x, double *y, double *z, uint8_t *flag,
                        int64_t cap) {
   double half = 0.5 * a;
@@ -119,18 +125,24 @@ int64_t orc_build_wire(double a, double D, double L, int n_grip,
   int64_t nk = 0;
   while ((double)nk * half < L) nk++;
   int64_t m = (int64_t)floor(D / a) + 1;
+  int64_t k_n0 = nk / 2 - notch_layers / 2;
+  int64_t k_n1 = k_n0 + notch_layers; /* exclusive */
+  double rin = 0.5 * D - notch_depth;
   int64_t n = 0;
   for (int64_t k = 0; k < nk; k++) {
     int fl = 0;
     if (k < n_grip) fl = 1;
     else if (k >= nk - n_grip) fl = 2;
+    int notched = notch_layers > 0 && k >= k_n0 && k < k_n1;
     for (int64_t j = -m; j <= m; j++) {
       for (int64_t i = -m; i <= m; i++) {
         if (((i + j + k) % 2 + 2) % 2 != 0) continue;
         if ((double)(i * i + j * j) > lim) continue;
+        double xx = (double)i * half, yy = (double)j * half;
+        if (notched && sqrt(xx * xx + yy * yy) > rin) continue;
         if (n < cap) {
-          x[n] = (double)i * half;
-          y[n] = (double)j * half;
+          x[n] = xx;
+          y[n] = yy;
           z[n] = (double)k * half;
           flag[n] = (uint8_t)fl;
         }
@@ -550,13 +562,43 @@ typedef struct {
   uint64_t seed;
   uint32_t rep_id;
   int32_t lab_frame; /* 1: thermostat acts on the lab-frame velocity */
+  double nh_tau;     /* ps; > 0: Nose-Hoover thermostat (gamma must be 0) */
+  double grip_step;  /* stepwise grips: displacement of each grip per hold, A */
+  int64_t grip_hold; /* steps per hold; > 0 selects stepwise symmetric grips */
 } orc_md;
+
+/*
+ * Grips.  Continuous pulling (grip_hold = 0): the bottom grip stays, the top
+ * one moves at v_pull, so after s steps the top has moved v_pull s dt.
+ * Stepwise symmetric grips (Simulation details: both grips displaced by
+ * 0.05 A in opposite directions between 20 ps of MD), reading: each hold of
+ * grip_hold steps begins with both grips moving grip_step outwards, so after
+ * s steps each has moved grip_step * ceil(s / grip_hold).
+ * orc_grip_top / orc_grip_bottom: displacement of the top grip along +z and
+ * of the bottom grip along -z; their sum is the elongation D of eq 4.
+ */
+static double orc_grip_top(const orc_md *M, int64_t s) {
+  if (M->grip_hold > 0)
+    return M->grip_step * (double)((s + M->grip_hold - 1) / M->grip_hold);
+  return M->v_pull * (double)s * M->dt;
+}
+
+static double orc_grip_bottom(const orc_md *M, int64_t s) {
+  if (M->grip_hold > 0)
+    return M->grip_step * (double)((s + M->grip_hold - 1) / M->grip_hold);
+  return 0.0;
+}
+
+static double orc_elongation(const orc_md *M, int64_t s) {
+  return orc_grip_top(M, s) + orc_grip_bottom(M, s);
+}
 
 /* Streaming velocity of the affine stretch at axial position zz when the top
  * grip has moved by Dg: v_pull (zz - z_lo) / (z_hi - z_lo + Dg); zero in the
- * lab frame or when the grip does not move. */
+ * lab frame, when the grip does not move, or with stepwise grips (which rest
+ * between their displacements). */
 static double orc_stream_u(const orc_md *M, double zz, double Dg) {
-  if (M->lab_frame || M->v_pull == 0.0) return 0.0;
+  if (M->lab_frame || M->v_pull == 0.0 || M->grip_hold > 0) return 0.0;
   return M->v_pull * (zz - M->z_lo) / (M->z_hi - M->z_lo + Dg);
 }
 
@@ -567,7 +609,8 @@ static double orc_stream_u(const orc_md *M, double zz, double Dg) {
  * standard deviation sqrt(kB T / m) (stream 1, step 0); their centre-of-mass
  * velocity is removed and they are rescaled to exactly T with 3 N_dyn - 3
  * degrees of freedom; finally the streaming profile of the stretch at t = 0
- * is added.  Grip atoms: fixed ones at rest, moving ones at v_pull along z.
+ * is added.  Grip atoms: fixed ones at rest, moving ones at v_pull along z
+ * (at rest with stepwise grips).
  */
 void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
                     double *z, double *vx, double *vy, double *vz,
@@ -586,7 +629,7 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
   int64_t ndyn = 0;
   for (int64_t i = 0; i < n; i++) {
     vx[i] = vy[i] = vz[i] = 0.0;
-    if (flag[i] == 2) vz[i] = M->v_pull;
+    if (flag[i] == 2 && M->grip_hold == 0) vz[i] = M->v_pull;
     if (flag[i] != 0) continue;
     double g3[3];
     orc_gauss3(M->seed, M->rep_id, (uint32_t)i, 0, 1, g3);
@@ -624,35 +667,93 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
 }
 
 /*
- * n_steps of velocity Verlet (Simulation details: dt = 2 fs) with the
- * Langevin thermostat of the configurations in BAOAB order, and the rigid
- * grips of Figure 1 (Simulation details: two rigid layers at each end).
+ * Nose-Hoover thermostat (Simulation details), reading: one friction
+ * variable zeta per replica acts on the peculiar velocities w = v - u of the
+ * dynamic atoms (u the streaming velocity, see orc_stream_u):
+ *   dw/dt = F/m - zeta w,   dzeta/dt = (2K - g kB T) / Q,   Q = g kB T tau^2,
+ * with K = sum m |w|^2 / 2 and g = 3 N_dyn - 3.  With deta/dt = zeta,
+ * E_pot + K + Q zeta^2 / 2 + g kB T eta is a constant of motion while the
+ * grips rest.  The paper does not give its discretisation; this follows the
+ * symmetric Trotter splitting of the Liouville operator: a thermostat half
+ * step before the velocity Verlet step and one after it, each
+ *   zeta += dt/4 G(K);  eta += dt/2 zeta;  w *= exp(-zeta dt/2);
+ *   zeta += dt/4 G(K'),   G(K) = (2K / (g kB T) - 1) / tau^2,
+ * K' the kinetic energy after the scaling.  A replica with T <= 0 or g <= 0
+ * is left unthermostatted.  Dg: top-grip displacement (for u).
+ */
+static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
+                        double *vz, const double *z, const uint8_t *flag,
+                        double Dg, double *zeta, double *eta) {
+  int64_t ndyn = 0;
+  double w2 = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    if (flag[i] != 0) continue;
+    double wz = vz[i] - orc_stream_u(M, z[i], Dg);
+    w2 += vx[i] * vx[i] + vy[i] * vy[i] + wz * wz;
+    ndyn++;
+  }
+  double g = (double)(3 * ndyn - 3);
+  if (!(g > 0.0) || !(M->T > 0.0)) return;
+  double gkT = g * ORC_KB * M->T;
+  double tau2 = M->nh_tau * M->nh_tau;
+  double K = 0.5 * M->mass * w2 / ORC_ACC;
+  *zeta += 0.25 * M->dt * (2.0 * K / gkT - 1.0) / tau2;
+  *eta += 0.5 * M->dt * *zeta;
+  double sc = exp(-0.5 * M->dt * *zeta);
+  w2 = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    if (flag[i] != 0) continue;
+    double u = orc_stream_u(M, z[i], Dg);
+    vx[i] *= sc;
+    vy[i] *= sc;
+    vz[i] = u + sc * (vz[i] - u);
+    double wz = vz[i] - u;
+    w2 += vx[i] * vx[i] + vy[i] * vy[i] + wz * wz;
+  }
+  K = 0.5 * M->mass * w2 / ORC_ACC;
+  *zeta += 0.25 * M->dt * (2.0 * K / gkT - 1.0) / tau2;
+}
+
+/*
+ * n_steps of velocity Verlet (Simulation details: dt = 2 fs) with the rigid
+ * grips of Figure 1 (Simulation details: two rigid layers at each end) and
+ * one of three thermostats: none (gamma = 0, nh_tau = 0), the Langevin
+ * thermostat of the configurations in BAOAB order (gamma > 0), or the
+ * Nose-Hoover thermostat of the paper (nh_tau > 0, orc_nh_half).
  * Step s -> s+1, on dynamic atoms (flag 0):
+ *   [Nose-Hoover half step at the positions of step s]
  *   B: v += dt/2 F/m;  A: x += dt/2 v;
- *   O: v = u + c1 (v - u) + c2 sqrt(kB T/m) n,  c1 = exp(-gamma dt),
- *      c2 = sqrt(1 - c1^2), u the streaming velocity at mid-step (zero in the
- *      lab frame), n from the counter (tag, s, rep_id, stream 0);
+ *   O (Langevin only): v = u + c1 (v - u) + c2 sqrt(kB T/m) n,
+ *      c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2), u the streaming velocity at
+ *      mid-step (zero in the lab frame), n from the counter (tag, s, rep_id,
+ *      stream 0);
  *   A: x += dt/2 v;
- * grips: fixed ones stay at their reference z0 (x, y unchanged) with v = 0;
- * moving ones sit at z0 + v_pull (s+1) dt with v = v_pull along z;
- * then forces at the new positions and B: v += dt/2 F/m.
+ * grips (orc_grip_top, orc_grip_bottom): bottom ones at z0 minus the bottom
+ * displacement after s+1 steps, top ones at z0 plus the top displacement
+ * (x, y unchanged), with v = 0 except v_z = v_pull on top when pulling
+ * continuously; then forces at the new positions, B: v += dt/2 F/m, and
+ * [Nose-Hoover half step at the positions of step s+1].
  * On entry fx, fy, fz hold F at step0; on return F at step0 + n_steps and
- * e_atom (may be NULL) the per-atom energies there.
+ * e_atom (may be NULL) the per-atom energies there.  zeta, eta: the
+ * Nose-Hoover variables, read and updated (only used when nh_tau > 0).
  * mode: 0 brute force, 1 cell list (orc_forces).
  */
 void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
              double *y, double *z, double *vx, double *vy, double *vz,
              const double *z0, const uint8_t *flag, double *fx, double *fy,
              double *fz, double *e_atom, int64_t step0, int64_t n_steps,
-             int mode) {
+             int mode, double *zeta, double *eta) {
   const double dt = M->dt;
   const double ac = ORC_ACC / M->mass; /* eV/A per amu -> A/ps^2 */
   const double c1 = exp(-M->gamma * dt);
   const double c2 = sqrt(1.0 - c1 * c1);
   const double sig = sqrt(ORC_KB * M->T / M->mass * ORC_ACC);
+  const int nh = M->nh_tau > 0.0;
   for (int64_t s = step0; s < step0 + n_steps; s++) {
     double Dmid = M->v_pull * ((double)s + 0.5) * dt;
-    double Dnew = M->v_pull * (double)(s + 1) * dt;
+    double top = orc_grip_top(M, s + 1), bottom = orc_grip_bottom(M, s + 1);
+    if (nh)
+      orc_nh_half(M, n, vx, vy, vz, z, flag, orc_grip_top(M, s), zeta, eta);
     for (int64_t i = 0; i < n; i++) {
       if (flag[i] == 0) {
         vx[i] += 0.5 * dt * ac * fx[i];
@@ -673,12 +774,12 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
         y[i] += 0.5 * dt * vy[i];
         z[i] += 0.5 * dt * vz[i];
       } else if (flag[i] == 1) {
-        z[i] = z0[i];
+        z[i] = z0[i] - bottom;
         vx[i] = vy[i] = vz[i] = 0.0;
       } else if (flag[i] == 2) {
-        z[i] = z0[i] + Dnew;
+        z[i] = z0[i] + top;
         vx[i] = vy[i] = 0.0;
-        vz[i] = M->v_pull;
+        vz[i] = M->grip_hold > 0 ? 0.0 : M->v_pull;
       }
     }
     orc_forces(P, n, x, y, z, mode, NULL, e_atom, fx, fy, fz, NULL);
@@ -688,6 +789,7 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
       vy[i] += 0.5 * dt * ac * fy[i];
       vz[i] += 0.5 * dt * ac * fz[i];
     }
+    if (nh) orc_nh_half(M, n, vx, vy, vz, z, flag, top, zeta, eta);
   }
 }
 
@@ -703,11 +805,12 @@ static int orc_cmp_double(const void *a, const void *b) {
  *  2 T (K), dof = 3 N_dyn - 3     3 -W_zz = 1/2 sum_i sum_j E'_ij dz^2 / r (eV)
  *  4 sigma_zz (GPa)               5 strain D/L0 (eq 4)
  *  6 largest empty axial gap between consecutive atoms (A)
- *  7 D, the displacement of the pulled grip (A)
+ *  7 D, the elongation: the sum of both grips' displacements (A)
  * Readings: eq 5's kinetic term is read as m v_z,i^2 (the printed v_x,i v_x,j
  * is a typo), with peculiar velocities v - u (u the streaming profile, zero in
  * the lab frame) over dynamic atoms; V is the constant hard-sphere volume
- * passed in; eq 4's L - L0 is the grip displacement D = v_pull s dt.
+ * passed in; eq 4's L - L0 is the elongation D (v_pull s dt when pulling
+ * continuously, orc_elongation).
  */
 void orc_observe(const orc_pot *P, const orc_md *M, int64_t n,
                  const double *x, const double *y, const double *z,
@@ -716,7 +819,7 @@ void orc_observe(const orc_pot *P, const orc_md *M, int64_t n,
                  double out[8]) {
   double w6[6];
   double ep = orc_forces(P, n, x, y, z, 1, NULL, NULL, NULL, NULL, NULL, w6);
-  double Dg = M->v_pull * (double)step * M->dt;
+  double Dg = orc_grip_top(M, step);
   double ke = 0.0, kz = 0.0;
   int64_t ndyn = 0;
   for (int64_t i = 0; i < n; i++) {
@@ -743,9 +846,9 @@ void orc_observe(const orc_pot *P, const orc_md *M, int64_t n,
   out[2] = dof > 0 ? 2.0 * ke / ((double)dof * ORC_KB) : 0.0;
   out[3] = -w6[2];
   out[4] = (-w6[2] - kz) / vol * ORC_EVA3_GPA;
-  out[5] = Dg / L0;
+  out[5] = orc_elongation(M, step) / L0;
   out[6] = gap;
-  out[7] = Dg;
+  out[7] = orc_elongation(M, step);
 }
 
 int orc_num_threads(void) {

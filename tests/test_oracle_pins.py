@@ -409,3 +409,127 @@ def test_observe_gap_and_stress_sign():
     assert obs2[4] > 0
     st3 = oracle.State(x, y, z * 0.98, f)
     assert oracle.observe(AU, md, st3, 1000.0, 40.8)[4] < obs2[4]
+
+
+# --- the paper's protocol: Nose-Hoover thermostat, stepwise grips, notch ----
+def _nh_extended_energy(st, md, kb, acc):
+    dyn = st.flag == 0
+    g = 3 * int(dyn.sum()) - 3
+    m = oracle.MASS_AU
+    ke = 0.5 * m * (st.vx[dyn] ** 2 + st.vy[dyn] ** 2 + st.vz[dyn] ** 2).sum() / acc
+    gkT = g * kb * md.T
+    Q = gkT * md.nh_tau ** 2
+    return st.e_atom.sum() + ke + 0.5 * Q * st.zeta[0] ** 2 + gkT * st.eta[0], ke, g
+
+
+def test_nose_hoover_conserves_its_extended_energy():
+    """With resting grips, E_pot + K + Q zeta^2/2 + g kB T eta is a constant
+    of the Nose-Hoover equations; a wire started at twice the target
+    temperature is driven towards it while that sum stays put."""
+    kb, acc, _ = oracle.constants()
+    st, md = small_wire_state(600.0, v_pull=0.0, gamma=0.0)
+    md.T, md.nh_tau = 300.0, 0.1
+    h0, _, g = _nh_extended_energy(st, md, kb, acc)
+    hs, Ts = [], []
+    for _ in range(30):
+        oracle.run(AU, md, st, 50, 1)
+        h, ke, _ = _nh_extended_energy(st, md, kb, acc)
+        hs.append(h)
+        Ts.append(2 * ke / (g * kb))
+    n = st.x.size
+    hs = np.array(hs)
+    assert np.abs(hs - h0).max() / n < 2e-5          # eV/atom
+    assert abs(np.polyfit(np.arange(hs.size), hs, 1)[0]) / n < 2e-7
+    assert abs(st.zeta[0]) > 0 and st.eta[0] != 0
+    # the kinetic temperature leaves 600 K and ends near the 300 K target
+    assert abs(np.mean(Ts[15:]) - 300.0) < 40.0
+
+
+def test_nose_hoover_free_gas_converges_to_its_ode():
+    """Non-interacting atoms (spacing > r_cut): all velocities share one
+    scale, so K and zeta follow dK/dt = -2 zeta K, dzeta/dt =
+    (2K/(g kB T) - 1)/tau^2, solved here by scipy.  The splitting must
+    converge to that solution at second order in dt."""
+    from scipy.integrate import solve_ivp
+    kb, acc, _ = oracle.constants()
+    g1 = np.arange(3) * 20.0
+    X, Y, Z = np.meshgrid(g1, g1, g1, indexing="ij")
+    x, y, z = X.ravel(), Y.ravel(), Z.ravel()
+    f = np.zeros(x.size, np.uint8)
+    rng = np.random.default_rng(5)
+    v0 = rng.normal(size=(x.size, 3)) * 3.0
+    m = oracle.MASS_AU
+    n_dof = 3 * x.size - 3
+    T, tau, t_end = 200.0, 0.2, 0.8
+    K0 = 0.5 * m * (v0 ** 2).sum() / acc
+    gkT = n_dof * kb * T
+
+    def rhs(_, s):
+        K, zeta = s
+        return [-2.0 * zeta * K, (2.0 * K / gkT - 1.0) / tau ** 2]
+
+    ref = solve_ivp(rhs, (0.0, t_end), [K0, 0.0], rtol=1e-12, atol=1e-14).y[:, -1]
+    errs = []
+    for dt in (0.004, 0.002):
+        st = oracle.State(x, y, z, f)
+        st.vx, st.vy, st.vz = (v0[:, k].copy() for k in range(3))
+        oracle.compute_forces(AU, st, 0)
+        assert np.abs(st.fx).max() == 0.0
+        md = oracle.MD(dt=dt, gamma=0.0, T=T, v_pull=0.0, nh_tau=tau)
+        oracle.run(AU, md, st, int(round(t_end / dt)), 0)
+        K = 0.5 * m * (st.vx ** 2 + st.vy ** 2 + st.vz ** 2).sum() / acc
+        errs.append((abs(K / ref[0] - 1.0), abs(st.zeta[0] - ref[1])))
+    assert errs[1][0] < 2e-4 and errs[1][1] < 2e-3
+    for k in range(2):
+        assert 3.0 < errs[0][k] / errs[1][k] < 5.0   # second order
+
+
+def test_nose_hoover_with_infinite_mass_is_velocity_verlet():
+    st, md = small_wire_state(300.0, v_pull=0.0, gamma=0.0)
+    st2 = st.copy()
+    md2 = oracle.MD(**{**md.__dict__, "nh_tau": 1e12})
+    oracle.run(AU, md, st, 40, 0)
+    oracle.run(AU, md2, st2, 40, 0)
+    assert np.abs(st.vx - st2.vx).max() < 1e-12 and np.abs(st.z - st2.z).max() < 1e-12
+
+
+def test_stepwise_symmetric_grips():
+    """Each hold begins with both grips moving grip_step outwards; they rest
+    in between, and the elongation D of eq 4 is the sum of both moves."""
+    x = np.array([0.0, 50.0, 100.0])
+    st = oracle.State(x, np.zeros(3), np.array([0.0, 10.0, 20.0]),
+                      np.array([0, 1, 2], np.uint8))
+    md = oracle.MD(gamma=0.0, v_pull=0.7, z_lo=10.0, z_hi=20.0, grip_step=0.05, grip_hold=25)
+    oracle.compute_forces(AU, st, 0)
+    for n_done, moves in ((1, 1), (25, 1), (26, 2), (75, 3), (76, 4)):
+        oracle.run(AU, md, st, n_done - st.step, 0)
+        assert st.z[1] == 10.0 - 0.05 * moves and st.z[2] == 20.0 + 0.05 * moves
+        assert st.vz[1] == 0.0 and st.vz[2] == 0.0
+        obs = oracle.observe(AU, md, st, 1.0, 10.0)
+        assert abs(obs[7] - 0.1 * moves) < 1e-15 and abs(obs[5] - 0.01 * moves) < 1e-15
+
+
+def test_ring_notch_geometry():
+    """The notch of Figure 1: three middle (002) planes lose exactly the sites
+    farther than D/2 - depth from the axis; nothing else changes."""
+    a, D, L = 4.08, 31.0, 204.0
+    x, y, z, f = oracle.build_wire(a, D, L, 2)
+    xn, yn, zn, fn = oracle.build_wire(a, D, L, 2, notch_layers=3, notch_depth=a)
+    key = lambda X, Y, Z: set(zip(np.round(X / (a / 2)).astype(int),
+                                  np.round(Y / (a / 2)).astype(int),
+                                  np.round(Z / (a / 2)).astype(int)))
+    full, notched = key(x, y, z), key(xn, yn, zn)
+    assert notched < full
+    planes = np.unique(np.round(z / (a / 2)).astype(int))
+    mid = planes.size // 2
+    ks = set(planes[mid - 1:mid + 2].tolist())
+    rin = D / 2 - a
+    want = {(i, j, k) for i, j, k in full
+            if k in ks and math.hypot(i * a / 2, j * a / 2) > rin}
+    assert full - notched == want and len(want) > 0
+    # every removed plane keeps its core; the notch sits mid-wire
+    for k in ks:
+        assert any(kk == k for _, _, kk in notched)
+    zc = np.mean([k * a / 2 for k in ks])
+    assert abs(zc - 0.5 * z.max()) <= a / 2
+    assert np.array_equal(np.unique(fn), [0, 1, 2])
