@@ -223,7 +223,8 @@ typedef struct {
 
 /*
  * Dynamics settings and observables.
- *  dt, gamma     time step (ps) and Langevin friction (1/ps; 0 = NVE).
+ *  dt, gamma     time step (ps) and Langevin friction (1/ps; 0 = no Langevin
+ *                thermostat).
  *  lab_frame     0: the thermostat acts on the velocity relative to the
  *                affine stretching profile u(z) = v_pull (z - z_lo) /
  *                (z_hi - z_lo + D); 1: on the lab-frame velocity.
@@ -249,6 +250,30 @@ typedef struct {
  *                step at which the replica was ruptured (its failure point;
  *                strain D/L0, eq 4), -1 before that.  Set it to -1 when the
  *                run starts.  May be NULL when retire <= 0.
+ *  nh_tau        Nose-Hoover thermostat (Simulation details) when > 0 (ps;
+ *                needs gamma = 0): one friction zeta per replica acting on
+ *                the peculiar velocities of the dynamic atoms,
+ *                dzeta/dt = (2K / (g kB T) - 1) / nh_tau^2 (g = dof[r]),
+ *                integrated by the symmetric Trotter splitting: a thermostat
+ *                half step before and after each velocity Verlet step.
+ *                Replicas with T <= 0 or dof <= 0 are not thermostatted.
+ *  nh_xi         device [R] double: zeta (1/ps) at the current step, read
+ *                and updated by the step loops (zero it to start).  Needed
+ *                when nh_tau > 0.
+ *  nh_eta        device [R] double or NULL: the time integral of zeta, with
+ *                which E_pot + K + Q zeta^2/2 + g kB T eta (Q = g kB T
+ *                nh_tau^2) is conserved while the grips rest.
+ *                Each step-loop call starts from the velocities as they are
+ *                (it sums the kinetic energy afresh), so runs split into
+ *                different calls agree to rounding, not bit for bit.
+ *  grip_step, grip_hold
+ *                grip_hold > 0 selects the stepwise symmetric grips of
+ *                Simulation details: each hold of grip_hold steps begins with
+ *                the TBSMA_GRIP_FIXED atoms moving grip_step (A) along -z and
+ *                the TBSMA_GRIP_PULL atoms grip_step along +z; grips rest in
+ *                between and v_pull is not used.  grip_hold = 0: the bottom
+ *                grip rests and the top one moves at v_pull.  The elongation
+ *                D of eq 4 is the sum of both grips' travel.
  */
 typedef struct {
   double dt, gamma;
@@ -264,6 +289,11 @@ typedef struct {
   uint32_t *status;
   double retire;
   double *dfail;
+  double nh_tau;
+  double *nh_xi;
+  double *nh_eta;
+  double grip_step;
+  int64_t grip_hold;
 } tbsma_md;
 
 /*
@@ -288,10 +318,15 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
  * i^2 + j^2 <= (D/a)^2 and 0 <= k a/2 < L, in (k, j, i) order (planes along
  * the axis, then rows, then columns); the n_grip lowest planes get
  * TBSMA_GRIP_FIXED and the n_grip highest TBSMA_GRIP_PULL.
+ * Ring notch (Figure 1: three atoms wide, two deep): of the K planes, planes
+ * K/2 - notch_layers/2 ... K/2 - notch_layers/2 + notch_layers - 1 (integer
+ * division) lose every site farther than D/2 - notch_depth (A) from the
+ * axis; notch_layers = 0 builds no notch.
  * x, y, z, flag are host arrays of capacity cap (may be NULL when cap = 0).
  * *n_out receives the atom count; TBSMA_ECAPACITY if it exceeds cap.
  */
-int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
+int tbsma_build_wire(double a, double D, double L, int32_t n_grip,
+                     int32_t notch_layers, double notch_depth, double *x,
                      double *y, double *z, uint8_t *flag, int64_t cap,
                      int64_t *n_out);
 
@@ -301,8 +336,8 @@ int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
  * (Philox stream 2); dynamic atoms get Maxwell-Boltzmann velocities at T[r]
  * (stream 1), minus their centre-of-mass velocity, rescaled to exactly T[r]
  * over dof[r], plus the stretching profile at t = 0; fixed grips are at rest
- * and pulled grips move at v_pull.  Sets z0 = z and *step = 0.  Synchronises
- * the stream.
+ * and pulled grips move at v_pull (rest with stepwise grips).  Sets z0 = z
+ * and *step = 0.  Synchronises the stream.
  */
 int tbsma_init_state(const tbsma_params *prm, tbsma_system *sys,
                      const tbsma_md *md, void *work, double jitter,
@@ -356,13 +391,18 @@ int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
 
 /*
  * n_steps MD steps of every replica, one launch per kernel per step (the
- * plain path; with R = 1 it is one replica per launch).  Each step: half
- * kick, half drift, Langevin O step (noise counter (tag, step, rep_id, 0)),
- * half drift, grips placed at z0 (fixed) or z0 + v_pull (step+1) dt (pulled);
+ * plain path; with R = 1 it is one replica per launch).  Each step:
+ * [Nose-Hoover half step], half kick, half drift, Langevin O step (noise
+ * counter (tag, step, rep_id, 0)), half drift, grips placed at z0 minus the
+ * bottom grip's travel (TBSMA_GRIP_FIXED) or z0 plus the top grip's travel
+ * (TBSMA_GRIP_PULL) after step+1 steps;
  * per-replica rebuild of cells and lists where some atom moved more than
  * skin/2 since the last build; both force passes; half kick; per-replica
  * reductions and observables.  Forces in `out` must hold F at the current
- * state on entry (tbsma_forces).  Forces are rewritten every step; in MIXED
+ * state on entry (tbsma_forces).  With Nose-Hoover, the half step that ends
+ * one step and the one that begins the next act as one velocity scale, and
+ * the last end-of-step half step is applied when the call ends.  Forces are
+ * rewritten every step; in MIXED
  * precision the per-atom energies e_atom (and the energy and virial behind
  * the observables) are evaluated only on logged steps ((step+1) % n_log ==
  * 0), so after a call e_atom belongs to the last logged step.  Synchronises

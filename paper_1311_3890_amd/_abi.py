@@ -59,15 +59,16 @@ class MD(C.Structure):
                 ("n_log", C.c_int32), ("n_slots", C.c_int32), ("reserved", C.c_int32),
                 ("T", vp), ("v_pull", vp), ("z_lo", vp), ("z_hi", vp), ("vol", vp), ("L0", vp),
                 ("seed", vp), ("dof", vp), ("step", vp), ("obs", vp), ("status", vp),
-                ("retire", C.c_double), ("dfail", vp)]
+                ("retire", C.c_double), ("dfail", vp), ("nh_tau", C.c_double), ("nh_xi", vp),
+                ("nh_eta", vp), ("grip_step", C.c_double), ("grip_hold", C.c_int64)]
 
 
 P = C.POINTER
 SIGNATURES = {
     "tbsma_workspace_query": (C.c_int, [P(Params), P(System), P(C.c_size_t)]),
     "tbsma_workspace_init": (C.c_int, [P(Params), P(System), vp, vp]),
-    "tbsma_build_wire": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, vp, vp, vp,
-                                   vp, C.c_int64, P(C.c_int64)]),
+    "tbsma_build_wire": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                   C.c_double, vp, vp, vp, vp, C.c_int64, P(C.c_int64)]),
     "tbsma_init_state": (C.c_int, [P(Params), P(System), P(MD), vp, C.c_double, vp]),
     "tbsma_build_cells": (C.c_int, [P(Params), P(System), P(Cells), vp, vp]),
     "tbsma_neighbors": (C.c_int, [P(Params), P(System), P(Cells), P(NList), vp,

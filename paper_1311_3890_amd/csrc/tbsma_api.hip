@@ -115,7 +115,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, total;
+      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, total;
 };
 
 // Blocks of the cell sort: ceil(cells/64) per replica.
@@ -176,6 +176,8 @@ Layout layout(const tbsma_system *s) {
   o += up((size_t)s->N);
   L.stats = o;
   o += 256;
+  L.nhw = o;
+  o += up(8 * 5 * (size_t)R);
 
   L.total = o;
   return L;
@@ -223,6 +225,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.qprune = reinterpret_cast<int4 *>(w + L.qprune);
   d.atom_lane = reinterpret_cast<uint8_t *>(w + L.atom_lane);
   d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
+  d.nhw = reinterpret_cast<double *>(w + L.nhw);
 
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
@@ -351,6 +354,15 @@ int check_md(const tbsma_md *m, int R) {
                 !m->L0 || !m->seed || !m->dof || !m->step || !m->obs ||
                 !m->status))
     return fail(TBSMA_EINVAL, "a device array of md is NULL");
+  if (!(m->nh_tau >= 0) || !std::isfinite(m->nh_tau))
+    return fail(TBSMA_EINVAL, "nh_tau must be finite and >= 0");
+  if (m->nh_tau > 0 && m->gamma > 0)
+    return fail(TBSMA_EINVAL, "Langevin (gamma > 0) and Nose-Hoover "
+                "(nh_tau > 0) exclude each other");
+  if (m->nh_tau > 0 && R > 0 && !m->nh_xi)
+    return fail(TBSMA_EINVAL, "Nose-Hoover needs nh_xi");
+  if (m->grip_hold < 0 || !std::isfinite(m->grip_step))
+    return fail(TBSMA_EINVAL, "need grip_hold >= 0 and a finite grip_step");
   return TBSMA_OK;
 }
 
@@ -377,6 +389,11 @@ DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
   M.status = m->status;
   M.retire = m->dfail ? m->retire : 0.0;
   M.dfail = m->dfail;
+  M.nh_tau = m->nh_tau;
+  M.nh_xi = m->nh_xi;
+  M.nh_eta = m->nh_eta;
+  M.grip_step = m->grip_hold > 0 ? m->grip_step : 0.0;
+  M.grip_hold = m->grip_hold;
   return M;
 }
 
@@ -504,25 +521,37 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
   return TBSMA_OK;
 }
 
-int tbsma_build_wire(double a, double D, double L, int32_t n_grip, double *x,
+int tbsma_build_wire(double a, double D, double L, int32_t n_grip,
+                     int32_t notch_layers, double notch_depth, double *x,
                      double *y, double *z, uint8_t *flag, int64_t cap,
                      int64_t *n_out) {
   if (!(a > 0) || !(D >= 0) || !(L >= 0) || n_grip < 0 || !n_out)
     return fail(TBSMA_EINVAL, "bad wire arguments");
+  if (notch_layers < 0 || !(notch_depth >= 0))
+    return fail(TBSMA_EINVAL, "need notch_layers >= 0 and notch_depth >= 0");
   double h = 0.5 * a;
   double rad2 = (D / a) * (D / a);
   int64_t layers = 0;
   while ((double)layers * h < L) ++layers;
   int64_t m = (int64_t)floor(D / a) + 1;
+  // ring notch: planes [k0, k0 + notch_layers) around the middle plane lose
+  // the sites farther than D/2 - notch_depth from the axis
+  const int64_t k0 = layers / 2 - notch_layers / 2;
+  const double r_in = 0.5 * D - notch_depth;
   int64_t n = 0;
   for (int64_t k = 0; k < layers; ++k) {
     uint8_t fl = k < n_grip ? TBSMA_GRIP_FIXED
                  : k >= layers - n_grip ? TBSMA_GRIP_PULL
                                         : TBSMA_DYN;
+    const bool notch = k >= k0 && k < k0 + notch_layers;
     for (int64_t j = -m; j <= m; ++j)
       for (int64_t i = -m; i <= m; ++i) {
         if ((i + j + k) & 1) continue;
         if ((double)(i * i + j * j) > rad2) continue;
+        if (notch) {
+          const double px = (double)i * h, py = (double)j * h;
+          if (std::sqrt(px * px + py * py) > r_in) continue;
+        }
         if (n < cap) {
           x[n] = (double)i * h;
           y[n] = (double)j * h;
@@ -668,7 +697,9 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   DevMD M = make_devmd(prm, md);
   PotF PF = make_potf(prm);
   PotD PD = make_potd(prm);
+  if (M.nh_tau > 0) launch_nh_begin(d, M, s);
   for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
+  if (M.nh_tau > 0) launch_nh_finish(d, M, s);
   return finish_run(d, md, s);
 }
 
@@ -694,6 +725,7 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   PotD PD = make_potd(prm);
   int64_t chunks = n_steps / steps_per_graph;
   int64_t rest = n_steps % steps_per_graph;
+  if (M.nh_tau > 0) launch_nh_begin(d, M, s);
   if (chunks > 0) {
     std::lock_guard<std::mutex> lk(g_graph.mu);
     std::vector<char> key;
@@ -740,6 +772,7 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
       HIPCHK(hipGraphLaunch(hit->exec, s));
   }
   for (int64_t k = 0; k < rest; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
+  if (M.nh_tau > 0) launch_nh_finish(d, M, s);
   return finish_run(d, md, s);
 }
 

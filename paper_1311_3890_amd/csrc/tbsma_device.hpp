@@ -101,6 +101,7 @@ struct Dev {
   uint32_t *ticket;             // [1]
   int32_t *nnmax;               // [1]
   double *rsum;                 // [R * 8] per-replica scratch sums
+  double *nhw;                  // [R * 5] Nose-Hoover step state (kNh*)
   // parameters used on the device
   double cell, inv_cell, skin_half2, qscale, inv_qscale, mass;
   int32_t all;                  // 1: rebuild every replica
@@ -117,7 +118,59 @@ struct DevMD {
   uint32_t *status;
   double retire;   // grip travel after rupture before retiring (<= 0: never)
   double *dfail;   // [R] grip displacement at the first rupture (-1: none)
+  double nh_tau;   // Nose-Hoover relaxation time (ps); 0: not used
+  double *nh_xi;   // [R] thermostat friction zeta (1/ps) at the current step
+  double *nh_eta;  // [R] its time integral, or NULL
+  double grip_step;   // stepwise grips: move of each grip per hold (A)
+  int64_t grip_hold;  // steps per hold; 0: continuous pulling at v_pull
 };
+
+// Per-replica Nose-Hoover state in the workspace (DevMD::nh_tau > 0), at
+// offsets of Dev::nhw + 5 r:
+constexpr int kNhPend = 0;  // velocity scale the next first half kick applies
+constexpr int kNhEnd = 1;   // scale of the last end-of-step half step, still
+                            // to be applied when the call ends (1: none)
+constexpr int kNhZeta = 2;  // zeta and eta after the next step's first
+constexpr int kNhEta = 3;   //   thermostat half step
+constexpr int kNhTop = 4;   // top-grip travel at which kNhEnd was taken
+
+// Grips.  Continuous pulling (grip_hold = 0): the bottom grip rests and the
+// top one moves at v_pull.  Stepwise symmetric grips (Simulation details):
+// each hold of grip_hold steps begins with both grips moving grip_step
+// outwards.  Travel after n steps of the top grip (+z) and the bottom grip
+// (-z); their sum is the elongation D of eq 4.
+__device__ __forceinline__ double grip_top(const DevMD &M, int r, int64_t n) {
+  if (M.grip_hold > 0)
+    return M.grip_step * (double)((n + M.grip_hold - 1) / M.grip_hold);
+  return M.v_pull[r] * (double)n * M.dt;
+}
+__device__ __forceinline__ double grip_bottom(const DevMD &M, int64_t n) {
+  if (M.grip_hold > 0)
+    return M.grip_step * (double)((n + M.grip_hold - 1) / M.grip_hold);
+  return 0.0;
+}
+__device__ __forceinline__ double elongation(const DevMD &M, int r,
+                                             int64_t n) {
+  return grip_top(M, r, n) + grip_bottom(M, n);
+}
+
+// One Nose-Hoover thermostat half step (dt/2) of replica r for the kinetic
+// energy K (eV) of its peculiar velocities: zeta += dt/4 G(K); eta += dt/2
+// zeta; scale s = exp(-zeta dt/2); K *= s^2; zeta += dt/4 G(K), with
+// G(K) = (2K / (g kB T) - 1) / tau^2.  Returns s (1 when g kB T <= 0: such a
+// replica is left unthermostatted).
+__device__ __forceinline__ double nh_half(const DevMD &M, int r, double &zeta,
+                                          double &eta, double &K) {
+  const double gkT = (double)M.dof[r] * kBoltz * M.T[r];
+  if (!(gkT > 0.0)) return 1.0;
+  const double tau2 = M.nh_tau * M.nh_tau;
+  zeta += 0.25 * M.dt * (2.0 * K / gkT - 1.0) / tau2;
+  eta += 0.5 * M.dt * zeta;
+  const double s = exp(-0.5 * M.dt * zeta);
+  K *= s * s;
+  zeta += 0.25 * M.dt * (2.0 * K / gkT - 1.0) / tau2;
+  return s;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
 // that each XCD works on one contiguous range of tiles, which keeps the

@@ -1161,7 +1161,7 @@ __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
 __device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
                                            double D) {
   double vp = M.v_pull[r];
-  if (M.lab_frame || vp == 0.0) return 0.0;
+  if (M.lab_frame || vp == 0.0 || M.grip_hold > 0) return 0.0;
   return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
 }
 
@@ -1183,6 +1183,15 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
     double x = S.x[i], y = S.y[i], z = S.z[i];
     double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
     if (f == 0) {
+      if (M.nh_tau > 0.0) {
+        // the thermostat half steps that end the last step and begin this
+        // one, as one scale of the peculiar velocity
+        const double sc = S.nhw[5 * r + kNhPend];
+        const double u0 = stream_u(M, r, z, grip_top(M, r, step));
+        vx *= sc;
+        vy *= sc;
+        vz = u0 + sc * (vz - u0);
+      }
       double ac = hdt * kAccel / S.mass;
       vx += ac * (double)fx[i];
       vy += ac * (double)fy[i];
@@ -1221,18 +1230,17 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
       S.vy[i] = vy;
       S.vz[i] = vz;
     } else if (f == 1) {
-      z = S.z0[i];
+      z = S.z0[i] - grip_bottom(M, step + 1);
       S.z[i] = z;
       S.vx[i] = 0.0;
       S.vy[i] = 0.0;
       S.vz[i] = 0.0;
     } else {
-      double vp = M.v_pull[r];
-      z = S.z0[i] + vp * (double)(step + 1) * dt;
+      z = S.z0[i] + grip_top(M, r, step + 1);
       S.z[i] = z;
       S.vx[i] = 0.0;
       S.vy[i] = 0.0;
-      S.vz[i] = vp;
+      S.vz[i] = M.grip_hold > 0 ? 0.0 : M.v_pull[r];
     }
     if (MIXED) {
       bool out = false;
@@ -1281,8 +1289,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
       S.vx[i] = vx;
       S.vy[i] = vy;
       S.vz[i] = vz;
-      double D = M.v_pull[r] * (double)(step + 1) * M.dt;
-      double wv = vz - stream_u(M, r, z, D);
+      double wv = vz - stream_u(M, r, z, grip_top(M, r, step + 1));
       k2 = S.mass * (vx * vx + vy * vy + wv * wv);
       kz = S.mass * wv * wv;
     }
@@ -1369,9 +1376,27 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   if (threadIdx.x == 0 && !frozen) {
     double E = s[0], wzz = s[1];
     double KE = 0.5 * s[2] / kAccel, Kz = s[3] / kAccel;
+    if (M.nh_tau > 0.0) {
+      // thermostat half step that ends this step (its scale is applied by
+      // the next step's first kick, or when the call ends), then the one
+      // that begins the next step
+      double *w = S.nhw + 5 * r;
+      double zeta = w[kNhZeta], eta = w[kNhEta];
+      const double sb = nh_half(M, r, zeta, eta, KE);
+      Kz *= sb * sb;
+      M.nh_xi[r] = zeta;
+      if (M.nh_eta) M.nh_eta[r] = eta;
+      double K2 = KE;
+      const double sa = nh_half(M, r, zeta, eta, K2);
+      w[kNhPend] = sb * sa;
+      w[kNhEnd] = sb;
+      w[kNhZeta] = zeta;
+      w[kNhEta] = eta;
+      w[kNhTop] = grip_top(M, r, n1);
+    }
     int dof = M.dof[r];
     double T = dof > 0 ? 2.0 * KE / ((double)dof * kBoltz) : 0.0;
-    double D = M.v_pull[r] * (double)n1 * M.dt;
+    double D = elongation(M, r, n1);
     uint32_t st = S.wstatus[r];
     if (!isfinite(E) || !isfinite(KE)) st |= 2u;  // E is 0 when not logged
     if (S.rflag[r] & 1u) st |= 16u;
@@ -1436,6 +1461,62 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
 }
 
 // ---------------------------------------------------------------------------
+// Nose-Hoover thermostat: the first half step of a call's first step, and
+// the last end-of-step scale applied when the call ends.  Inside a call the
+// two half steps between consecutive steps are folded into kNhPend.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_nh_begin(Dev S, DevMD M) {
+  __shared__ double lds[256];
+  const int r = blockIdx.x;
+  double *w = S.nhw + 5 * r;
+  if (M.status[r] & 32u) {  // retired: nothing pending (uniform per block)
+    if (threadIdx.x == 0) {
+      w[kNhPend] = 1.0;
+      w[kNhEnd] = 1.0;
+    }
+    return;
+  }
+  const int64_t step = *M.step;
+  const double top = grip_top(M, r, step);
+  double k2 = 0.0;
+  for (int64_t i = S.rep_off[r] + threadIdx.x; i < S.rep_off[r + 1];
+       i += blockDim.x) {
+    if (S.flag[i] != 0) continue;
+    const double vx = S.vx[i], vy = S.vy[i];
+    const double wz = S.vz[i] - stream_u(M, r, S.z[i], top);
+    k2 += S.mass * (vx * vx + vy * vy + wz * wz);
+  }
+  lds[threadIdx.x] = k2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double K = 0.5 * lds[0] / kAccel;
+    double zeta = M.nh_xi[r], eta = M.nh_eta ? M.nh_eta[r] : 0.0;
+    w[kNhPend] = nh_half(M, r, zeta, eta, K);
+    w[kNhEnd] = 1.0;
+    w[kNhZeta] = zeta;
+    w[kNhEta] = eta;
+    w[kNhTop] = top;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_nh_finish(Dev S, DevMD M) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= S.N || S.flag[i] != 0) return;
+  const int r = S.tile_rep[i / kTile];
+  const double *w = S.nhw + 5 * r;
+  const double sb = w[kNhEnd];
+  if (sb == 1.0) return;
+  const double u = stream_u(M, r, S.z[i], w[kNhTop]);
+  S.vx[i] *= sb;
+  S.vy[i] *= sb;
+  S.vz[i] = u + sb * (S.vz[i] - u);
+}
+
+// ---------------------------------------------------------------------------
 // initial state
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
@@ -1466,7 +1547,7 @@ __global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
       sy = vy;
       sz = vz;
       cn = 1.0;
-    } else if (f == 2) {
+    } else if (f == 2 && M.grip_hold == 0) {
       vz = M.v_pull[r];
     }
     S.vx[i] = vx;
@@ -1735,6 +1816,14 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
 
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {
   k_reduce_step<<<S.R, 256, 0, s>>>(S, M);
+}
+
+void launch_nh_begin(const Dev &S, const DevMD &M, hipStream_t s) {
+  k_nh_begin<<<S.R, 256, 0, s>>>(S, M);
+}
+
+void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s) {
+  k_nh_finish<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, M);
 }
 
 void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,

@@ -30,6 +30,8 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
                         const void *fx, const void *fy, const void *fz,
                         hipStream_t s);
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s);
+void launch_nh_begin(const Dev &S, const DevMD &M, hipStream_t s);
+void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s);
 void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
                  hipStream_t s);
 void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,

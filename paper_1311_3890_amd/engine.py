@@ -38,17 +38,21 @@ def _ptr(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
-def build_wire_host(a: float, D: float, L: float, n_grip: int = 2):
-    """Host-side wire geometry from libtbsma (tbsma_build_wire)."""
+def build_wire_host(a: float, D: float, L: float, n_grip: int = 2, notch_layers: int = 0,
+                    notch_depth: float = 0.0):
+    """Host-side wire geometry from libtbsma (tbsma_build_wire), optionally
+    with the ring notch of Figure 1 at mid-length."""
     lib = A.lib()
     n = C.c_int64()
-    rc = lib.tbsma_build_wire(a, D, L, n_grip, None, None, None, None, 0, C.byref(n))
+    rc = lib.tbsma_build_wire(a, D, L, n_grip, notch_layers, notch_depth, None, None, None,
+                              None, 0, C.byref(n))
     if rc not in (A.OK, A.ECAPACITY):
         A.check(rc)
     x, y, z = (np.empty(n.value) for _ in range(3))
     f = np.empty(n.value, dtype=np.uint8)
-    A.check(lib.tbsma_build_wire(a, D, L, n_grip, x.ctypes.data, y.ctypes.data,
-                                 z.ctypes.data, f.ctypes.data, n.value, C.byref(n)))
+    A.check(lib.tbsma_build_wire(a, D, L, n_grip, notch_layers, notch_depth, x.ctypes.data,
+                                 y.ctypes.data, z.ctypes.data, f.ctypes.data, n.value,
+                                 C.byref(n)))
     return x, y, z, f
 
 
@@ -60,15 +64,21 @@ class WireBatch:
                  n_log: int = 100, n_slots: int = 64, strain_max: float = 0.5,
                  lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
                  device=None, wires=None, qbits: int | None = None, prune: float = 0.15,
-                 retire: float = 0.0):
+                 retire: float = 0.0, nh_tau: float = 0.0, grip_step: float = 0.0,
+                 grip_hold: int = 0, notch: tuple | None = None):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
         self.pot = pot or Potential()
+        if nh_tau > 0 and gamma > 0:
+            raise ValueError("the Nose-Hoover thermostat (nh_tau > 0) needs gamma = 0")
         # settings a compacted copy of this batch is built with
         self._kw = dict(skin=skin, cell=cell, gamma=gamma, dt=dt, n_log=n_log, n_slots=n_slots,
                         strain_max=strain_max, lab_frame=lab_frame, a=a, pot=self.pot,
-                        device=device, prune=prune, retire=retire)
+                        device=device, prune=prune, retire=retire, nh_tau=nh_tau,
+                        grip_step=grip_step, grip_hold=grip_hold, notch=notch)
+        self.nh_tau, self.grip_step, self.grip_hold = float(nh_tau), float(grip_step), int(grip_hold)
+        self.notch = notch
         self.precision = precision
         k_cap = (int(k_cap) + 7) // 8 * 8
         if cell is None:  # the smallest cell the 27-cell scan allows, at least 8 A
@@ -82,8 +92,9 @@ class WireBatch:
         R = len(self.replicas)
         self.R = R
         # --- host geometry and layout -------------------------------------------------
+        nl_, nd_ = notch if notch is not None else (0, 0.0)
         self.wires = wires if wires is not None else [
-            build_wire_host(a, rp.D, rp.L, rp.n_grip) for rp in self.replicas]
+            build_wire_host(a, rp.D, rp.L, rp.n_grip, nl_, nd_) for rp in self.replicas]
         self.n_atoms = np.array([w[0].size for w in self.wires], dtype=np.int64)
         pad = (self.n_atoms + A.TILE - 1) // A.TILE * A.TILE
         self.rep_off = np.zeros(R + 1, dtype=np.int64)
@@ -97,7 +108,9 @@ class WireBatch:
             gxy = int(math.ceil((rp.D + 2 * margin) / cell))
             gz = int(math.ceil((rp.L * (1.0 + strain_max) + 2 * margin) / cell))
             gdim[r] = (gxy, gxy, gz)
-            glo[r] = (-0.5 * gxy * cell, -0.5 * gxy * cell, -margin)
+            # symmetric grips stretch the wire both ways
+            below = 0.5 * strain_max * rp.L if grip_hold > 0 else 0.0
+            glo[r] = (-0.5 * gxy * cell, -0.5 * gxy * cell, -margin - below)
         self.grid_dim, self.grid_lo = gdim, glo
         ncell = gdim.prod(axis=1).astype(np.int64)
         self.cell_off = np.zeros(R + 1, dtype=np.int64)
@@ -174,6 +187,8 @@ class WireBatch:
         T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
         T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
         T["dfail"] = torch.full((R,), -1.0, **f64)
+        T["nh_xi"] = torch.zeros(R, **f64)
+        T["nh_eta"] = torch.zeros(R, **f64)
         # --- ABI structs -------------------------------------------------------------------
         self.prune = float(prune) if precision == "mixed" else 0.0
         self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
@@ -201,7 +216,8 @@ class WireBatch:
         self.md = A.MD(dt, gamma, lab_frame, n_log, n_slots, 0,
                        *[_ptr(T[k]) for k in ("T", "v_pull", "z_lo", "z_hi", "vol", "L0", "seed",
                                               "dof", "step", "obs", "status")], float(retire),
-                       _ptr(T["dfail"]))
+                       _ptr(T["dfail"]), self.nh_tau, _ptr(T["nh_xi"]), _ptr(T["nh_eta"]),
+                       self.grip_step, self.grip_hold)
         nb = C.c_size_t()
         A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
                                               C.byref(nb)))
@@ -343,7 +359,8 @@ class WireBatch:
     # lists saved too, a resumed run repeats the original bit for bit (the
     # noise is keyed by the step index, which is part of the state).
     _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nl_lane", "nn", "x_ref", "y_ref",
-              "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "dfail", "obs", "work")
+              "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "dfail", "nh_xi",
+              "nh_eta", "obs", "work")
 
     def state_dict(self):
         return {k: self.t[k].detach().cpu().numpy().copy() for k in self._STATE}
@@ -395,6 +412,8 @@ class WireBatch:
         nb.t["step"].copy_(self.t["step"])
         nb.t["status"].copy_(self.t["status"][idx])
         nb.t["dfail"].copy_(self.t["dfail"][idx])
+        nb.t["nh_xi"].copy_(self.t["nh_xi"][idx])
+        nb.t["nh_eta"].copy_(self.t["nh_eta"][idx])
         ring = self.t["obs"].view(self.n_slots, self.R, A.NOBS)
         nb.t["obs"].view(nb.n_slots, nb.R, A.NOBS).copy_(ring[:, idx])
         nb.build_lists()

@@ -47,16 +47,29 @@ def test_host_wire_builder_equals_oracle(D, L):
 def test_wire_builder_capacity_and_errors():
     lib = A.lib()
     n = C.c_int64()
-    assert lib.tbsma_build_wire(4.08, 15.0, 30.0, 2, None, None, None, None, 0,
+    assert lib.tbsma_build_wire(4.08, 15.0, 30.0, 2, 0, 0.0, None, None, None, None, 0,
                                 C.byref(n)) == A.ECAPACITY
     assert n.value == 336
-    assert lib.tbsma_build_wire(-1.0, 15.0, 30.0, 2, None, None, None, None, 0,
+    assert lib.tbsma_build_wire(-1.0, 15.0, 30.0, 2, 0, 0.0, None, None, None, None, 0,
                                 C.byref(n)) == A.EINVAL
     assert b"bad wire" in lib.tbsma_last_error()
     # empty wire
-    assert lib.tbsma_build_wire(4.08, 15.0, 0.0, 2, None, None, None, None, 0,
+    assert lib.tbsma_build_wire(4.08, 15.0, 0.0, 2, 0, 0.0, None, None, None, None, 0,
                                 C.byref(n)) == A.OK
     assert n.value == 0
+    assert lib.tbsma_build_wire(4.08, 15.0, 30.0, 2, -1, 0.0, None, None, None, None, 0,
+                                C.byref(n)) == A.EINVAL
+    assert b"notch" in lib.tbsma_last_error()
+
+
+@pytest.mark.parametrize("D,L,layers,depth", [(31.0, 204.0, 3, 4.08), (15.0, 30.6, 2, 2.04),
+                                               (20.0, 40.8, 5, 100.0)])
+def test_notched_wire_builder_equals_oracle(D, L, layers, depth):
+    x, y, z, f = build_wire_host(4.08, D, L, 2, layers, depth)
+    xo, yo, zo, fo = oracle.build_wire(4.08, D, L, 2, layers, depth)
+    assert x.size == xo.size < build_wire_host(4.08, D, L, 2)[0].size
+    assert np.array_equal(x, xo) and np.array_equal(y, yo) and np.array_equal(z, zo)
+    assert np.array_equal(f, fo)
 
 
 def _params(**kw):
@@ -124,3 +137,36 @@ def test_workloads_are_seeded_and_snapped():
         n = r.L / (W.A_LAT / 2)
         assert abs(n - round(n)) < 1e-9 and 50 - 2.04 <= r.L <= 400 + 2.04
     assert len({r.seed for r in a.replicas}) == 512
+
+
+def _dummy_step_args(R=1, **md_kw):
+    """Structures that pass every host-side check up to the dynamics
+    settings; their device pointers are placeholders that the checks only
+    compare with NULL (nothing runs: the checks fail first)."""
+    ph = C.c_void_p(0x1000)
+    rep = (C.c_int64 * (R + 1))(*[64 * r for r in range(R + 1)])
+    cel = (C.c_int64 * (R + 1))(*[8 * r for r in range(R + 1)])
+    s = A.System(R, 4, 64 * R, 8 * R, C.cast(rep, C.c_void_p), C.cast(cel, C.c_void_p),
+                 *([ph] * 14), ph)
+    cells = A.Cells(ph, ph)
+    nl = A.NList(ph, ph, 8, 0, ph, ph, ph, None, ph)
+    out = A.ForcesOut(ph, ph, ph, ph, None, ph, ph)
+    md = A.MD(0.002, 0.0, 0, 10, 4, 0, *([ph] * 11), 0.0, None)
+    for k, v in md_kw.items():
+        setattr(md, k, v)
+    return s, cells, nl, out, md, (rep, cel)
+
+
+@pytest.mark.parametrize("R,kw,msg", [
+    (0, dict(gamma=1.0, nh_tau=0.1), b"exclude"),
+    (0, dict(nh_tau=-1.0), b"nh_tau"),
+    (1, dict(nh_tau=0.1), b"nh_xi"),
+    (0, dict(grip_hold=-5), b"grip_hold"),
+    (0, dict(grip_hold=10, grip_step=float("nan")), b"grip_step"),
+])
+def test_dynamics_setting_checks(R, kw, msg):
+    s, cells, nl, out, md, keep = _dummy_step_args(R, **kw)
+    rc = A.lib().tbsma_step(C.byref(_params()), C.byref(s), C.byref(cells), C.byref(nl),
+                            C.byref(out), C.byref(md), None, 1, None)
+    assert rc == A.EINVAL
+    assert msg in A.lib().tbsma_last_error()

@@ -47,13 +47,21 @@ def orc_state(b: WireBatch, r: int):
     n = int(b.n_atoms[r])
     st.z0 = b.t["z0"][o:o + n].cpu().numpy().copy()
     st.step = b.step_index()
+    st.zeta[0] = float(b.t["nh_xi"][r])
+    st.eta[0] = float(b.t["nh_eta"][r])
     return st
 
 
 def orc_md(b: WireBatch, r: int):
     rp = b.replicas[r]
     return oracle.MD(dt=b.dt, gamma=b.gamma, T=rp.T, v_pull=rp.v_pull, z_lo=b.z_lo[r],
-                     z_hi=b.z_hi[r], seed=rp.seed, rep_id=rp.rep_id, lab_frame=b.lab_frame)
+                     z_hi=b.z_hi[r], seed=rp.seed, rep_id=rp.rep_id, lab_frame=b.lab_frame,
+                     nh_tau=b.nh_tau, grip_step=b.grip_step, grip_hold=b.grip_hold)
+
+
+# the paper's protocol: Nose-Hoover, stepwise symmetric grips (short holds so
+# that tests see several moves), ring notch three planes wide, a deep
+PROTOCOL = dict(gamma=0.0, nh_tau=0.1, grip_step=0.05, grip_hold=20, notch=(3, 4.08))
 
 
 def R(D, L, T=10.0, v=0.5, r=0, jitter=0.0):
@@ -246,6 +254,80 @@ def test_step_fp64_lockstep_with_oracle():
         assert abs(ob[k_gpu] - orf[k_or]) <= 1e-9 * max(1.0, abs(orf[k_or])), (k_gpu, ob, orf)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paper_protocol_lockstep_with_oracle(precision):
+    """Nose-Hoover at 298 K, stepwise symmetric grips and a notched wire:
+    positions, velocities, zeta and eta follow the oracle step for step
+    (FP64 to rounding; mixed within its force error), and the elongation and
+    strain of the records are the grips' travel."""
+    rp = R(20.0, 40.0, T=298.0, v=0.0, r=3, jitter=0.01)
+    note(f"paper protocol lockstep {precision}, 60 steps")
+    b = WireBatch([rp], precision, n_log=10, **PROTOCOL)
+    b.prepare()
+    torch.cuda.synchronize()
+    st = orc_state(b, 0)
+    assert st.x.size == oracle.build_wire(4.08, rp.D, rp.L, 2, 3, 4.08)[0].size
+    oracle.compute_forces(AU, st, 0)
+    md = orc_md(b, 0)
+    # mixed: FP32 pair terms (eps_F ~ 1e-6) against the FP64 oracle
+    tol_x, tol_v, tol_z, tol_e = ((1e-11, 1e-9, 1e-9, 1e-11) if precision == "fp64"
+                                  else (1e-4, 1e-2, 1e-3, 1e-5))
+    for k in range(6):
+        b.step(10)
+        oracle.run(AU, md, st, 10, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+        dzeta = abs(float(b.t["nh_xi"][0]) - st.zeta[0])
+        deta = abs(float(b.t["nh_eta"][0]) - st.eta[0])
+        note(f"  after {10 * (k + 1)} steps: |dx| {dx:.2e} |dv| {dv:.2e} "
+             f"|dzeta| {dzeta:.2e} |deta| {deta:.2e}")
+        assert dx < tol_x and dv < tol_v
+        assert dzeta < tol_z and deta < tol_e
+    assert abs(st.zeta[0]) > 1e-3
+    ob = b.obs_at(60)[0]
+    orf = oracle.observe(AU, md, st, b.vol[0], b.L0[0])
+    assert ob[A.OBS_D] == orf[7] and abs(ob[A.OBS_D] - 2 * 0.05 * 3) < 1e-15
+    assert abs(ob[A.OBS_STRAIN] - orf[5]) < 1e-15
+    for k_gpu, k_or in ((A.OBS_EPOT, 0), (A.OBS_KE, 1), (A.OBS_T, 2), (A.OBS_WZZ, 3)):
+        tol = 1e-9 if precision == "fp64" else 1e-4
+        assert abs(ob[k_gpu] - orf[k_or]) <= tol * max(1.0, abs(orf[k_or])), (k_gpu, ob, orf)
+    # the grips rest between moves and sit at z0 -+ 3 moves after 60 steps
+    f = b.flags(0)
+    z0 = b.t["z0"][:int(b.n_atoms[0])].cpu().numpy()
+    assert np.all(z[f == A.GRIP_FIXED] == z0[f == A.GRIP_FIXED] - 0.05 * 3)
+    assert np.all(z[f == A.GRIP_PULL] == z0[f == A.GRIP_PULL] + 0.05 * 3)
+    assert np.all(b.velocities(0)[2][f != 0] == 0.0)
+
+
+def test_nose_hoover_extended_energy_is_conserved_in_mixed_precision():
+    """Resting grips, Nose-Hoover from 600 K towards 300 K in the batched
+    graph loop: E_pot + K + Q zeta^2/2 + g kB T eta stays within the mixed
+    force error while the temperature relaxes."""
+    kb, _, _ = oracle.constants()
+    rp = R(20.0, 40.0, T=600.0, v=0.0, r=4, jitter=0.01)
+    note("nose-hoover invariant, mixed, 2000 steps")
+    b = WireBatch([rp], "mixed", n_log=100, gamma=0.0, nh_tau=0.1, grip_step=0.0,
+                  grip_hold=1000)
+    b.prepare()
+    b.t["T"].fill_(300.0)  # drawn at 600 K, thermostatted towards 300 K
+    g = int(b.dof[0])
+    Q = g * kb * 300.0 * 0.1 ** 2
+    hs, Ts = [], []
+    for _ in range(20):
+        b.run_batch(100, 50)
+        ob = b.obs_at(b.step_index())[0]
+        xi, eta = float(b.t["nh_xi"][0]), float(b.t["nh_eta"][0])
+        hs.append(ob[A.OBS_EPOT] + ob[A.OBS_KE] + 0.5 * Q * xi ** 2 + g * kb * 300.0 * eta)
+        Ts.append(ob[A.OBS_T])
+    n = int(b.n_atoms[0])
+    hs = np.array(hs)
+    note(f"  H spread {np.ptp(hs) / n:.2e} eV/atom, T {Ts[0]:.0f} -> {np.mean(Ts[10:]):.0f} K")
+    assert np.ptp(hs) / n < 5e-5
+    assert abs(np.mean(Ts[10:]) - 300.0) < 40.0
+
+
 def test_config1_end_to_end_forces_every_step():
     """Config 1: 1000 FP64 steps at 10 K with the top grip pulled at 0.5 A/ps;
     forces and energies checked against the oracle at every step."""
@@ -276,14 +358,18 @@ def _three_replicas():
             R(30.0, 16.0, T=298.0, v=0.1, r=2)]
 
 
-def test_batched_equals_one_replica_at_a_time_bitwise():
+VARIANTS = pytest.mark.parametrize("kw", [{}, PROTOCOL], ids=["langevin", "protocol"])
+
+
+@VARIANTS
+def test_batched_equals_one_replica_at_a_time_bitwise(kw):
     reps = _three_replicas()
-    note("batched vs alone, 120 steps mixed")
-    b = WireBatch(reps, "mixed", n_log=40)
+    note(f"batched vs alone, 120 steps mixed {kw}")
+    b = WireBatch(reps, "mixed", n_log=40, **kw)
     b.prepare()
     b.run_batch(120, steps_per_graph=40)
     for r, rp in enumerate(reps):
-        s = WireBatch([rp], "mixed", n_log=40, qbits=b.qbits)
+        s = WireBatch([rp], "mixed", n_log=40, qbits=b.qbits, **kw)
         s.prepare()
         s.step(120)
         for a_, b_ in zip(b.positions(r) + b.velocities(r), s.positions(0) + s.velocities(0)):
@@ -310,13 +396,14 @@ def test_pruned_lists_leave_trajectories_unchanged_bitwise():
     assert np.all(a.status() & A.ST_REBUILT)
 
 
-def test_graph_replay_equals_eager_bitwise():
+@VARIANTS
+def test_graph_replay_equals_eager_bitwise(kw):
     reps = _three_replicas()
-    note("graph vs eager, 100 steps")
-    g = WireBatch(reps, "mixed", n_log=25)
+    note(f"graph vs eager, 100 steps {kw}")
+    g = WireBatch(reps, "mixed", n_log=25, **kw)
     g.prepare()
     g.run_batch(100, steps_per_graph=30)  # 3 replays + 10 eager steps
-    e = WireBatch(reps, "mixed", n_log=25)
+    e = WireBatch(reps, "mixed", n_log=25, **kw)
     e.prepare()
     e.step(100)
     assert torch.equal(g.t["x"], e.t["x"]) and torch.equal(g.t["vz"], e.t["vz"])
@@ -324,20 +411,21 @@ def test_graph_replay_equals_eager_bitwise():
     assert g.step_index() == e.step_index() == 100
 
 
-def test_checkpoint_resume_is_bitwise(tmp_path):
+@VARIANTS
+def test_checkpoint_resume_is_bitwise(tmp_path, kw):
     reps = _three_replicas()
-    note("checkpoint / resume")
-    a = WireBatch(reps, "mixed", n_log=20)
+    note(f"checkpoint / resume {kw}")
+    a = WireBatch(reps, "mixed", n_log=20, **kw)
     a.prepare()
     a.run_batch(60, 20)
     path = str(tmp_path / "ck.npz")
     a.save(path)
     a.run_batch(60, 20)
-    b = WireBatch(reps, "mixed", n_log=20, qbits=a.qbits)
+    b = WireBatch(reps, "mixed", n_log=20, qbits=a.qbits, **kw)
     b.load(path)
     assert b.step_index() == 60
     b.run_batch(60, 20)
-    for k in ("x", "y", "z", "vx", "vy", "vz", "obs", "status"):
+    for k in ("x", "y", "z", "vx", "vy", "vz", "obs", "status", "nh_xi", "nh_eta"):
         assert torch.equal(a.t[k], b.t[k]), k
 
 
