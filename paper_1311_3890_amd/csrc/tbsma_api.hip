@@ -442,8 +442,12 @@ void enqueue_step(const tbsma_params *p, const Dev &d0, const DevMD &M0,
   df.energies = -1;
   df.step = M.step;
   df.n_log = M.n_log;
-  launch_forces(df, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
-  launch_integrate_b(d, M, mixed, o->fx, o->fy, o->fz, s);
+  if (mixed) {
+    launch_forces_kick(df, M, PF, o->fx, o->fy, o->fz, o->e_atom, s);
+  } else {
+    launch_forces(df, mixed, PF, PD, o->fx, o->fy, o->fz, o->e_atom, o->g, s);
+    launch_integrate_b(d, M, mixed, o->fx, o->fy, o->fz, s);
+  }
   launch_reduce_step(d, M, s);
 }
 

@@ -154,6 +154,16 @@ __device__ __forceinline__ double elongation(const DevMD &M, int r,
   return grip_top(M, r, n) + grip_bottom(M, n);
 }
 
+// Streaming velocity of the affine stretch at axial position z when the top
+// grip has travelled D; zero in the lab frame, when the grip rests, and with
+// stepwise grips.
+__device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
+                                           double D) {
+  double vp = M.v_pull[r];
+  if (M.lab_frame || vp == 0.0 || M.grip_hold > 0) return 0.0;
+  return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
+}
+
 // One Nose-Hoover thermostat half step (dt/2) of replica r for the kinetic
 // energy K (eV) of its peculiar velocities: zeta += dt/4 G(K); eta += dt/2
 // zeta; scale s = exp(-zeta dt/2); K *= s^2; zeta += dt/4 G(K), with

@@ -232,12 +232,38 @@ __device__ __forceinline__ int64_t cl8(int64_t N, int64_t i, int64_t chunk) {
   return (chunk * N + i) << 3;
 }
 
-// Value of the unused entries of a lane's last chunk, and a chunk made of
-// them (read by lanes whose list has ended while their wavefront goes on).
+// Value of the unused entries of a lane's last chunk of the Verlet lists
+// (nl), and a chunk made of them (read by lanes whose list has ended while
+// their wavefront goes on).
 constexpr int32_t kPadEntry = 0x7fffffff;
 __constant__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
     kPadEntry, kPadEntry, kPadEntry, kPadEntry,
     kPadEntry, kPadEntry, kPadEntry, kPadEntry};
+
+// The lists the pair passes read (nl_lane) hold byte offsets (j - lo) * 16
+// of each neighbour j from the start lo of its block's slot window (the
+// union of the windows [lo, hi) of the block's tiles, fixed between list
+// builds), so that a block whose window is staged in LDS reads a neighbour
+// at the entry itself.  Unused entries hold kPadStaged in blocks whose
+// window fits in LDS, which addresses the sentinel after the staged
+// positions, and kPadWide in the others; both are at least 16 times the
+// window size.
+constexpr int kStage = 1280;  // staged positions per block (20 KB)
+constexpr int32_t kPadStaged = kStage * 16;
+constexpr int32_t kPadWide = (int32_t)0xFFFFFFF0u;
+__constant__ __attribute__((aligned(16))) int32_t kPadChunkStaged[8] = {
+    kPadStaged, kPadStaged, kPadStaged, kPadStaged,
+    kPadStaged, kPadStaged, kPadStaged, kPadStaged};
+
+__device__ __forceinline__ int32_t pad_of_window(int size) {
+  return size > 0 && size <= kStage ? kPadStaged : kPadWide;
+}
+
+// Entry of neighbour j in a block whose window starts at lo (j >= lo; slot
+// counts are below 2^28 in mixed precision, so it fits 32 bits unsigned).
+__device__ __forceinline__ int32_t list_entry(int j, int lo) {
+  return (int32_t)((uint32_t)(j - lo) << 4);
+}
 
 // Per-lane ring of 16 list entries in LDS, interleaved over the lanes of the
 // block (entry e of lane l at e * kBlock + l, so a wavefront's appends hit
@@ -268,12 +294,11 @@ struct Ring {
                                         int nch) {
     if (cnt - head >= 8) store_chunk(list, N, i, nch);
   }
-  // the last chunks; the unused entries of a partial chunk are set to
-  // kPadEntry
+  // the last chunks; the unused entries of a partial chunk are set to pad
   __device__ __forceinline__ void finish(int32_t *list, int64_t N, int64_t i,
-                                         int nch) {
+                                         int nch, int32_t pad = kPadEntry) {
     while (cnt > head) {
-      for (int e = cnt; e < head + 8; ++e) lds[(e & 15) * kBlock] = kPadEntry;
+      for (int e = cnt; e < head + 8; ++e) lds[(e & 15) * kBlock] = pad;
       store_chunk(list, N, i, nch);
     }
   }
@@ -319,18 +344,20 @@ __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
 
 // Loop over the chunks of one lane's list in which every entry may be read:
 // the wavefront runs as many chunks as its longest list, a lane past its own
-// chunks reads the pad chunk, and the unused entries of a lane's last chunk
-// hold kPadEntry, so body(j[8]) gets 8 entries with no per-entry test.
+// chunks reads the pad chunk padc, and the unused entries of a lane's last
+// chunk hold the same pad value, so body(j[8]) gets 8 entries with no
+// per-entry test.
 template <class F>
 __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
                                                   int64_t N, int64_t i, int n,
+                                                  const int32_t *padc,
                                                   F &&body) {
   const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
   const int nch = (nmax + 7) >> 3;
   const int own = (n + 7) >> 3;
   const int32_t *row = list + (i << 3);
   const int64_t stride = N << 3;
-  const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
+  const int4 *pad = reinterpret_cast<const int4 *>(padc);
   const int4 *p = own > 0 ? reinterpret_cast<const int4 *>(row) : pad;
   int4 a = p[0], b = p[1];
   for (int c = 0; c < nch; ++c) {
@@ -468,14 +495,15 @@ __device__ __forceinline__ void nlist_window(const Dev &S, int64_t i,
   }
 }
 
-// Copies atom i's list (nl, by atom, n entries) to row `row` of nl_lane,
+// Copies atom i's list (nl, by atom, n entries) to row `row` of nl_lane as
+// offsets from the block's window start lo (pad: the block's pad value),
 // keeping the pairs whose current quantised distance is below the pruning
 // radius (all of them when pruning is off); returns the number kept.  Each
 // lane works on its own row through its ring.
 template <class Fetch>
 __device__ __forceinline__ int prune_row(const Dev &S, int64_t i, int64_t row,
-                                         int n, int32_t *ring_lane,
-                                         Fetch &&fetch) {
+                                         int n, int32_t *ring_lane, int lo,
+                                         int32_t pad, Fetch &&fetch) {
   Ring ring{ring_lane, 0, 0};
   const int4 qi = S.qpos[i];
   const int nch = S.k_cap >> 3;
@@ -493,11 +521,11 @@ __device__ __forceinline__ int prune_row(const Dev &S, int64_t i, int64_t row,
       const float dy = (float)(q[e].y - qi.y);
       const float dz = (float)(q[e].z - qi.z);
       if (c * 8 + e < n && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
-        ring.push(j[e]);
+        ring.push(list_entry(j[e], lo));
     }
     ring.flush(S.nl_lane, S.N, row, nch);
   }
-  ring.finish(S.nl_lane, S.N, row, nch);
+  ring.finish(S.nl_lane, S.N, row, nch, pad);
   return ring.cnt;
 }
 
@@ -508,6 +536,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
   __shared__ float4 cand[MIXED ? kCand + 8 : 1];
   __shared__ int wzlo[kBlock / kTile], wzhi[kBlock / kTile];
   __shared__ int32_t key[kBlock];
+  __shared__ int2 twin[kBlock / kTile];
   const int tid = threadIdx.x, w = tid / kTile;
   const int2 bm = S.bmap[blockIdx.x];  // first tile, tiles (1..4)
   const int r = S.tile_rep[bm.x];
@@ -588,7 +617,10 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
     // neighbour positions in LDS
     const int32_t wlo = -wave_max_i(-row.wlo);
     const int32_t whi = wave_max_i(row.whi);
-    if ((tid & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
+    if ((tid & 63) == 0) {
+      S.win[i / kTile] = make_int2(wlo, whi + 1);
+      twin[w] = make_int2(wlo, whi + 1);
+    }
     const int total = row.ring.cnt;
     if (total > S.k_cap) {
       atomicMax(S.nnmax, total);
@@ -614,7 +646,14 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
     // the row again at the lane position, pruned (mixed precision; its
     // chunks were just written by this thread)
     if (S.nl_lane) {
-      S.nn_lane[row] = prune_row(S, i, row, nn_i, ring_lds + tid,
+      // the block's window, as the pair passes will compute it from win
+      int blo = 0x7fffffff, bhi = 0;
+      for (int t = 0; t < bm.y; ++t) {
+        blo = min(blo, twin[t].x);
+        bhi = max(bhi, twin[t].y);
+      }
+      S.nn_lane[row] = prune_row(S, i, row, nn_i, ring_lds + tid, blo,
+                                 pad_of_window(bhi - blo),
                                  [&](int j) { return S.qpos[j]; });
       S.qprune[i] = S.qpos[i];
     }
@@ -712,8 +751,6 @@ __device__ __forceinline__ PairBlock pair_block(const Dev &S) {
 // in a short slot window [lo, hi) recorded per tile by the list build; the
 // block copies qpos[lo, hi) into LDS with coalesced loads and gathers from
 // there.  Blocks with wider windows (thick wires) gather from global memory.
-constexpr int kStage = 1280;  // staged positions per block (20 KB)
-
 // Slot window of the block (union over its tiles); size 0 when some tile has
 // no list yet.
 __device__ __forceinline__ void block_window(const Dev &S, const PairBlock &B,
@@ -768,6 +805,25 @@ struct StagedIndex {
   }
 };
 
+// Staged position at byte offset e of lq (an entry of nl_lane).
+__device__ __forceinline__ int4 lds_at(const int4 *lq, int32_t e) {
+  return *reinterpret_cast<const int4 *>(reinterpret_cast<const char *>(lq) +
+                                         (uint32_t)e);
+}
+
+// Slot of an entry of nl_lane in a block that is not staged: lo + e/16, or
+// self for a pad entry (self then adds nothing: its distance is 0).
+struct ListDecode {
+  int lo;
+  uint32_t lim;  // 16 * window size; pad entries are at least this
+  int self;
+  __device__ __forceinline__ ListDecode(int lo_, int size, int self_)
+      : lo(size > 0 ? lo_ : 0), lim((uint32_t)size << 4), self(self_) {}
+  __device__ __forceinline__ int operator()(int32_t e) const {
+    return (uint32_t)e < lim ? lo + (int)((uint32_t)e >> 4) : self;
+  }
+};
+
 // Pruning of the lane-ordered lists of the replicas in which some atom has
 // moved more than the pruning half-width since their lists were last pruned
 // (and that are not rebuilt this step, which prunes too).  Lanes take the
@@ -789,12 +845,14 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
   const int4 qi = B.valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
   const float rp2 = S.prune_r2q;
   const int nch = S.k_cap >> 3;
+  const int base = size > 0 ? lo : 0;  // entries are offsets from base
   Ring ring{ring_lds + threadIdx.x, 0, 0};
   auto keep = [&](const int4 &q, int j, bool in) {
     const float dx = (float)(q.x - qi.x);
     const float dy = (float)(q.y - qi.y);
     const float dz = (float)(q.z - qi.z);
-    if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2) ring.push(j);
+    if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
+      ring.push(list_entry(j, base));
   };
   if (staged) {
     // the row in batches of kPruneBatch chunks, all loaded before any is
@@ -841,7 +899,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
     });
   }
   if (!B.valid) return;
-  ring.finish(S.nl_lane, S.N, row, nch);
+  ring.finish(S.nl_lane, S.N, row, nch, pad_of_window(size));
   S.nn_lane[row] = ring.cnt;
   S.qprune[i] = qi;
 }
@@ -854,7 +912,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 template <bool STAGED, bool COUNT>
 __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
                                             const PairBlock &B,
-                                            const int4 *lq, int lo) {
+                                            const int4 *lq, int lo, int size) {
   const int64_t i = B.i;
   const bool valid = B.valid;
   const int self = valid ? (int)i : 0;
@@ -889,22 +947,24 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
     }
   };
   if (STAGED) {
-    const StagedIndex sx(lo);
-    chunk_loop_padded(S.nl_lane, N, row, n, [&](const int (&j)[8]) {
-      int4 q[8];
+    chunk_loop_padded(S.nl_lane, N, row, n, kPadChunkStaged,
+                      [&](const int (&e)[8]) {
+                        int4 q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+                        for (int k = 0; k < 8; ++k) q[k] = lds_at(lq, e[k]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) pair(q[e]);
-    });
+                        for (int k = 0; k < 8; ++k) pair(q[k]);
+                      });
   } else {
-    chunk_loop(S.nl_lane, N, row, self, n, 0, 1, [&](const int (&j)[8], int) {
-      int4 q[8];
+    const ListDecode dec(lo, size, self);
+    chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
+               [&](const int (&e)[8], int) {
+                 int4 q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+                 for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
 #pragma unroll
-      for (int e = 0; e < 8; ++e) pair(q[e]);
-    });
+                 for (int k = 0; k < 8; ++k) pair(q[k]);
+               });
   }
   if (valid) {
     const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
@@ -921,9 +981,9 @@ __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   int lo, size;
   block_window(S, B, lo, size);
   if (size > 0 && size <= kStage && stage(S, lq, B, lo, size))
-    density_run<true, COUNT>(S, P, B, lq, lo);
+    density_run<true, COUNT>(S, P, B, lq, lo, size);
   else
-    density_run<false, COUNT>(S, P, B, lq, lo);
+    density_run<false, COUNT>(S, P, B, lq, lo, size);
 }
 
 __device__ __forceinline__ double radial_d(const PotD &P, bool dens,
@@ -982,11 +1042,19 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // E'_ij = 2V'(r) - (g_i+g_j) phi'(r)/2, F_i += E'_ij d/r, and with ENERGY
 // also E_i += V(r), w_i += E'_ij dz^2 / (2r).  Without ENERGY (steps whose
 // observables are not logged) e_atom and the tile sums are left unchanged.
-template <bool STAGED, bool ENERGY>
+//
+// With KICK (the mixed step loops) the pass also ends the step for its atoms:
+// the second half kick v += dt/2 F/m of the dynamic atoms, their kinetic
+// partial sums and, on logged steps, the axial bins of the rupture gap.
+// These are the same operations, in the same order and precision, as
+// k_integrate_b, so the results do not depend on which of the two ran.
+template <bool STAGED, bool ENERGY, bool KICK>
 __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
-                                          const PairBlock &B, const int4 *lq,
-                                          int lo, double *lsum, float *fx,
-                                          float *fy, float *fz, float *eat) {
+                                          const DevMD &M, const PairBlock &B,
+                                          const int4 *lq, int lo, int size,
+                                          double *lsum,
+                                          float *fx, float *fy, float *fz,
+                                          float *eat) {
   const int tid = threadIdx.x;
   const int64_t i = B.i;
   const bool valid = B.valid;
@@ -1037,57 +1105,114 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
     }
   };
   if (STAGED) {
-    const StagedIndex sx(lo);
-    chunk_loop_padded(S.nl_lane, N, row, n, [&](const int (&j)[8]) {
-      int4 q[8];
+    chunk_loop_padded(S.nl_lane, N, row, n, kPadChunkStaged,
+                      [&](const int (&e)[8]) {
+                        int4 q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+                        for (int k = 0; k < 8; ++k) q[k] = lds_at(lq, e[k]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) pair(q[e]);
-    });
+                        for (int k = 0; k < 8; ++k) pair(q[k]);
+                      });
   } else {
-    chunk_loop(S.nl_lane, N, row, self, n, 0, 1, [&](const int (&j)[8], int) {
-      int4 q[8];
+    const ListDecode dec(lo, size, self);
+    chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
+               [&](const int (&e)[8], int) {
+                 int4 q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = gather_q(qp, j[e]);
+                 for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
 #pragma unroll
-      for (int e = 0; e < 8; ++e) pair(q[e]);
-    });
+                 for (int k = 0; k < 8; ++k) pair(q[k]);
+               });
   }
   if (valid) {
     fx[i] = ax;
     fy[i] = ay;
     fz[i] = az;
   }
-  if (ENERGY) {
+  double k2 = 0.0, kz = 0.0;
+  if (KICK && valid) {
+    const int r = S.tile_rep[B.t0];
+    const int64_t step = *M.step;
+    const uint8_t f = S.flag[i];
+    if (f != 3) {
+      const double z = S.z[i];
+      if (f == 0) {
+        const double ac = 0.5 * M.dt * kAccel / S.mass;
+        const double vx = S.vx[i] + ac * (double)ax;
+        const double vy = S.vy[i] + ac * (double)ay;
+        const double vz = S.vz[i] + ac * (double)az;
+        S.vx[i] = vx;
+        S.vy[i] = vy;
+        S.vz[i] = vz;
+        const double wv = vz - stream_u(M, r, z, grip_top(M, r, step + 1));
+        k2 = S.mass * (vx * vx + vy * vy + wv * wv);
+        kz = S.mass * wv * wv;
+      }
+      if (((step + 1) % M.n_log) == 0) {
+        // axial bins of width cell/2 for the rupture gap
+        const int nb = 2 * S.grid_dim[3 * r + 2];
+        const double t = floor((z - S.grid_lo[3 * r + 2]) * 2.0 * S.inv_cell);
+        const int b = t >= 0.0 ? (t < (double)nb ? (int)t : nb - 1) : 0;
+        const unsigned long long kk = dkey(z);
+        atomicMin(&S.zbmin[(int64_t)r * S.max_zbins + b], kk);
+        atomicMax(&S.zbmax[(int64_t)r * S.max_zbins + b], kk);
+      }
+    }
+  }
+  float e = 0.0f;
+  if (ENERGY && valid) {
+    e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
+    eat[i] = e;
+  }
+  if (ENERGY || KICK) {
     // per-tile sums in slot order: each atom's values go to LDS at its slot
-    // in the block, then wavefront w sums tile t0 + w
+    // in the block, then wavefront w sums tile t0 + w.  lsum shares its LDS
+    // with the staged positions, which every wavefront must have finished
+    // reading first.
+    __syncthreads();
     if (valid) {
-      const float e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
-      eat[i] = e;
-      lsum[i - B.b0] = (double)e;
-      lsum[kBlock + (i - B.b0)] = (double)wz * (double)P.wscale;
+      if (ENERGY) {
+        lsum[i - B.b0] = (double)e;
+        lsum[kBlock + (i - B.b0)] = (double)wz * (double)P.wscale;
+      }
+      if (KICK) {
+        lsum[2 * kBlock + (i - B.b0)] = k2;
+        lsum[3 * kBlock + (i - B.b0)] = kz;
+      }
     }
     __syncthreads();
     const int w = tid / kTile;
     if (w < B.nt) {
-      const double e_i = wave_sum(lsum[tid]);
-      const double w_i = wave_sum(lsum[kBlock + tid]);
-      if ((tid & 63) == 0) {
-        double *pt = S.part + (int64_t)(B.t0 + w) * kNPart;
-        pt[kPartE] = e_i;
-        pt[kPartW] = w_i;
+      double *pt = S.part + (int64_t)(B.t0 + w) * kNPart;
+      if (ENERGY) {
+        const double e_i = wave_sum(lsum[tid]);
+        const double w_i = wave_sum(lsum[kBlock + tid]);
+        if ((tid & 63) == 0) {
+          pt[kPartE] = e_i;
+          pt[kPartW] = w_i;
+        }
+      }
+      if (KICK) {
+        const double k_i = wave_sum(lsum[2 * kBlock + tid]);
+        const double kz_i = wave_sum(lsum[3 * kBlock + tid]);
+        if ((tid & 63) == 0) {
+          pt[kPartK] = k_i;
+          pt[kPartKz] = kz_i;
+        }
       }
     }
   }
 }
 
+template <bool KICK>
 __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
-                                                        float *fx, float *fy,
-                                                        float *fz,
+                                                        DevMD M, float *fx,
+                                                        float *fy, float *fz,
                                                         float *eat) {
   __shared__ int4 lq[kStage + 1];
-  __shared__ double lsum[2 * kBlock];
+  // per-tile sums after the pair loop, in the staged positions' LDS
+  static_assert(4 * kBlock * sizeof(double) <= sizeof(lq), "lsum fits");
+  double *lsum = reinterpret_cast<double *>(lq);
   const PairBlock B = pair_block(S);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   const bool energy =
@@ -1096,14 +1221,15 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
   block_window(S, B, lo, size);
   if (size > 0 && size <= kStage && stage(S, lq, B, lo, size)) {
     if (energy)
-      force_run<true, true>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+      force_run<true, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
     else
-      force_run<true, false>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+      force_run<true, false, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
   } else {
     if (energy)
-      force_run<false, true>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+      force_run<false, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
     else
-      force_run<false, false>(S, P, B, lq, lo, lsum, fx, fy, fz, eat);
+      force_run<false, false, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz,
+                                    eat);
   }
 }
 
@@ -1158,12 +1284,6 @@ __global__ void __launch_bounds__(kBlock) k_force_fp64(Dev S, PotD P,
 // ---------------------------------------------------------------------------
 // integrator (BAOAB + grips) and per-replica reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
-                                           double D) {
-  double vp = M.v_pull[r];
-  if (M.lab_frame || vp == 0.0 || M.grip_hold > 0) return 0.0;
-  return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
-}
 
 template <typename FT, bool MIXED>
 __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
@@ -1753,13 +1873,25 @@ void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
       k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
     else
       k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-    k_force_mixed<<<S.nbmap, kBlock, 0, s>>>(S, PF, (float *)fx, (float *)fy,
-                                             (float *)fz, (float *)eat);
+    k_force_mixed<false><<<S.nbmap, kBlock, 0, s>>>(
+        S, PF, DevMD{}, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
   } else {
     k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);
     k_force_fp64<<<nb, kBlock, 0, s>>>(S, PD, g, (double *)fx, (double *)fy,
                                        (double *)fz, (double *)eat);
   }
+}
+
+void launch_forces_kick(const Dev &S, const DevMD &M, const PotF &PF,
+                        void *fx, void *fy, void *fz, void *eat,
+                        hipStream_t s) {
+  if (S.nbmap == 0) return;
+  if (S.nact)
+    k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+  else
+    k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+  k_force_mixed<true><<<S.nbmap, kBlock, 0, s>>>(
+      S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
 }
 
 void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
@@ -1773,9 +1905,9 @@ void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
     else if (pass == 1)
       k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
     else
-      k_force_mixed<<<S.nbmap, kBlock, 0, s>>>(S, PF, (float *)fx,
-                                               (float *)fy, (float *)fz,
-                                               (float *)eat);
+      k_force_mixed<false><<<S.nbmap, kBlock, 0, s>>>(
+          S, PF, DevMD{}, (float *)fx, (float *)fy, (float *)fz,
+          (float *)eat);
   } else {
     if (pass == 1)
       k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);

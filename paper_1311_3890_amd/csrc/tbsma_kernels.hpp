@@ -18,6 +18,11 @@ void launch_list_stats(const Dev &S, bool mixed, hipStream_t s);
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    void *fx, void *fy, void *fz, void *eat, double *g,
                    hipStream_t s);
+// Both mixed pair passes of a step-loop step, the force pass ending with the
+// second half kick and kinetic sums (replaces launch_integrate_b).
+void launch_forces_kick(const Dev &S, const DevMD &M, const PotF &PF,
+                        void *fx, void *fy, void *fz, void *eat,
+                        hipStream_t s);
 void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
                        const PotD &PD, void *fx, void *fy, void *fz, void *eat,
                        double *g, hipStream_t s);
