@@ -43,7 +43,8 @@ class _MD(C.Structure):
                 ("v_pull", C.c_double), ("z_lo", C.c_double), ("z_hi", C.c_double),
                 ("mass", C.c_double), ("seed", C.c_uint64), ("rep_id", C.c_uint32),
                 ("lab_frame", C.c_int32), ("nh_tau", C.c_double), ("grip_step", C.c_double),
-                ("grip_hold", C.c_int64)]
+                ("grip_hold", C.c_int64), ("T_start", C.c_double), ("ramp_begin", C.c_int64),
+                ("ramp_steps", C.c_int64)]
 
 
 @dataclass
@@ -80,11 +81,15 @@ class MD:
     nh_tau: float = 0.0     # > 0: Nose-Hoover thermostat (gamma must be 0)
     grip_step: float = 0.0  # stepwise grips: displacement per side per hold (A)
     grip_hold: int = 0      # > 0: stepwise symmetric grips, steps per hold
+    T_start: float = 0.0    # temperature ramp from T_start at step ramp_begin
+    ramp_begin: int = 0     # to T at ramp_begin + ramp_steps (0: no ramp)
+    ramp_steps: int = 0
 
     def c(self) -> _MD:
         return _MD(self.dt, self.gamma, self.T, self.v_pull, self.z_lo, self.z_hi,
                    self.mass, self.seed, self.rep_id, self.lab_frame, self.nh_tau,
-                   self.grip_step, self.grip_hold)
+                   self.grip_step, self.grip_hold, self.T_start, self.ramp_begin,
+                   self.ramp_steps)
 
 
 _lib = None
@@ -133,6 +138,8 @@ def lib():
         L.orc_observe.restype = None
         L.orc_observe.argtypes = [C.POINTER(_Pot), C.POINTER(_MD), C.c_int64, dp, dp, dp, dp, dp,
                                   dp, u8p, C.c_int64, C.c_double, C.c_double, dp]
+        L.orc_target_temperature.restype = C.c_double
+        L.orc_target_temperature.argtypes = [C.POINTER(_MD), C.c_double]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -282,6 +289,11 @@ def observe(pot: Pot, md: MD, st: State, vol: float, L0: float):
     lib().orc_observe(C.byref(pot.c()), C.byref(md.c()), st.x.size, st.x, st.y, st.z,
                       st.vx, st.vy, st.vz, st.flag, st.step, vol, L0, out)
     return out
+
+
+def target_temperature(md: MD, t: float) -> float:
+    """Target temperature at time t (in steps) of the thermostats (ramp)."""
+    return lib().orc_target_temperature(C.byref(md.c()), float(t))
 
 
 def num_threads() -> int:

@@ -565,7 +565,27 @@ typedef struct {
   double nh_tau;     /* ps; > 0: Nose-Hoover thermostat (gamma must be 0) */
   double grip_step;  /* stepwise grips: displacement of each grip per hold, A */
   int64_t grip_hold; /* steps per hold; > 0 selects stepwise symmetric grips */
+  double T_start;    /* temperature ramp: target T_start at ramp_begin ... */
+  int64_t ramp_begin; /* ... rising linearly to T over ramp_steps steps; */
+  int64_t ramp_steps; /* ramp_steps = 0: the target is T throughout */
 } orc_md;
+
+/*
+ * Target temperature at time t (in steps) (Simulation details: the
+ * equilibration ramps the temperature from 0.01 K to the target value),
+ * reading: linear in time from T_start at step ramp_begin to T at step
+ * ramp_begin + ramp_steps, constant outside.  The thermostats take it at the
+ * time of each operation: the Langevin O step at mid-step, the Nose-Hoover
+ * half steps at the start and the end of the step, the initial velocities at
+ * step 0.
+ */
+static double orc_target_T(const orc_md *M, double t) {
+  if (M->ramp_steps <= 0) return M->T;
+  double f = (t - (double)M->ramp_begin) / (double)M->ramp_steps;
+  if (f < 0.0) f = 0.0;
+  if (f > 1.0) f = 1.0;
+  return M->T_start + (M->T - M->T_start) * f;
+}
 
 /*
  * Grips.  Continuous pulling (grip_hold = 0): the bottom grip stays, the top
@@ -591,6 +611,10 @@ static double orc_grip_bottom(const orc_md *M, int64_t s) {
 
 static double orc_elongation(const orc_md *M, int64_t s) {
   return orc_grip_top(M, s) + orc_grip_bottom(M, s);
+}
+
+double orc_target_temperature(const orc_md *M, double t) {
+  return orc_target_T(M, t);
 }
 
 /* Streaming velocity of the affine stretch at axial position zz when the top
@@ -624,7 +648,8 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
       z[i] += jitter * (2.0 * u[2] - 1.0);
     }
   }
-  double sig = sqrt(ORC_KB * M->T / M->mass * ORC_ACC);
+  const double T0 = orc_target_T(M, 0.0);
+  double sig = sqrt(ORC_KB * T0 / M->mass * ORC_ACC);
   double px = 0, py = 0, pz = 0;
   int64_t ndyn = 0;
   for (int64_t i = 0; i < n; i++) {
@@ -656,7 +681,7 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
   int64_t dof = 3 * ndyn - 3;
   double scale = 0.0;
   if (s2 > 0.0 && dof > 0)
-    scale = sqrt((double)dof * ORC_KB * M->T / (M->mass * s2 / ORC_ACC));
+    scale = sqrt((double)dof * ORC_KB * T0 / (M->mass * s2 / ORC_ACC));
   for (int64_t i = 0; i < n; i++) {
     if (flag[i] != 0) continue;
     vx[i] *= scale;
@@ -679,11 +704,12 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
  *   zeta += dt/4 G(K);  eta += dt/2 zeta;  w *= exp(-zeta dt/2);
  *   zeta += dt/4 G(K'),   G(K) = (2K / (g kB T) - 1) / tau^2,
  * K' the kinetic energy after the scaling.  A replica with T <= 0 or g <= 0
- * is left unthermostatted.  Dg: top-grip displacement (for u).
+ * is left unthermostatted.  Dg: top-grip displacement (for u); Tt: the
+ * target temperature at the time of the half step.
  */
 static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
                         double *vz, const double *z, const uint8_t *flag,
-                        double Dg, double *zeta, double *eta) {
+                        double Dg, double Tt, double *zeta, double *eta) {
   int64_t ndyn = 0;
   double w2 = 0.0;
   for (int64_t i = 0; i < n; i++) {
@@ -693,8 +719,8 @@ static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
     ndyn++;
   }
   double g = (double)(3 * ndyn - 3);
-  if (!(g > 0.0) || !(M->T > 0.0)) return;
-  double gkT = g * ORC_KB * M->T;
+  if (!(g > 0.0) || !(Tt > 0.0)) return;
+  double gkT = g * ORC_KB * Tt;
   double tau2 = M->nh_tau * M->nh_tau;
   double K = 0.5 * M->mass * w2 / ORC_ACC;
   *zeta += 0.25 * M->dt * (2.0 * K / gkT - 1.0) / tau2;
@@ -719,7 +745,8 @@ static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
  * grips of Figure 1 (Simulation details: two rigid layers at each end) and
  * one of three thermostats: none (gamma = 0, nh_tau = 0), the Langevin
  * thermostat of the configurations in BAOAB order (gamma > 0), or the
- * Nose-Hoover thermostat of the paper (nh_tau > 0, orc_nh_half).
+ * Nose-Hoover thermostat of the paper (nh_tau > 0, orc_nh_half), each at
+ * the target temperature of orc_target_T.
  * Step s -> s+1, on dynamic atoms (flag 0):
  *   [Nose-Hoover half step at the positions of step s]
  *   B: v += dt/2 F/m;  A: x += dt/2 v;
@@ -747,13 +774,15 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
   const double ac = ORC_ACC / M->mass; /* eV/A per amu -> A/ps^2 */
   const double c1 = exp(-M->gamma * dt);
   const double c2 = sqrt(1.0 - c1 * c1);
-  const double sig = sqrt(ORC_KB * M->T / M->mass * ORC_ACC);
   const int nh = M->nh_tau > 0.0;
   for (int64_t s = step0; s < step0 + n_steps; s++) {
     double Dmid = M->v_pull * ((double)s + 0.5) * dt;
     double top = orc_grip_top(M, s + 1), bottom = orc_grip_bottom(M, s + 1);
+    const double sig =
+        sqrt(ORC_KB * orc_target_T(M, (double)s + 0.5) / M->mass * ORC_ACC);
     if (nh)
-      orc_nh_half(M, n, vx, vy, vz, z, flag, orc_grip_top(M, s), zeta, eta);
+      orc_nh_half(M, n, vx, vy, vz, z, flag, orc_grip_top(M, s),
+                  orc_target_T(M, (double)s), zeta, eta);
     for (int64_t i = 0; i < n; i++) {
       if (flag[i] == 0) {
         vx[i] += 0.5 * dt * ac * fx[i];
@@ -789,7 +818,9 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
       vy[i] += 0.5 * dt * ac * fy[i];
       vz[i] += 0.5 * dt * ac * fz[i];
     }
-    if (nh) orc_nh_half(M, n, vx, vy, vz, z, flag, top, zeta, eta);
+    if (nh)
+      orc_nh_half(M, n, vx, vy, vz, z, flag, top,
+                  orc_target_T(M, (double)(s + 1)), zeta, eta);
   }
 }
 

@@ -533,3 +533,39 @@ def test_ring_notch_geometry():
     zc = np.mean([k * a / 2 for k in ks])
     assert abs(zc - 0.5 * z.max()) <= a / 2
     assert np.array_equal(np.unique(fn), [0, 1, 2])
+
+
+def test_temperature_ramp_target_and_tracking():
+    """Equilibration ramp: the target rises linearly from T_start to T over
+    the ramp and is constant outside it; initial velocities are drawn at the
+    target of step 0; a Nose-Hoover wire follows the ramp."""
+    kb, acc, _ = oracle.constants()
+    md = oracle.MD(T=300.0, T_start=20.0, ramp_begin=100, ramp_steps=400)
+    for t, want in ((0, 20.0), (100, 20.0), (300, 160.0), (500, 300.0), (900, 300.0),
+                    (100.5, 20.0 + 280.0 * 0.5 / 400)):
+        assert abs(oracle.target_temperature(md, t) - want) < 1e-12
+    assert oracle.target_temperature(oracle.MD(T=77.0), 12345) == 77.0
+    x, y, z, f = oracle.build_wire(4.08, 15.0, 30.6, 2)
+    st = oracle.State(x, y, z, f)
+    md = oracle.MD(T=300.0, T_start=50.0, ramp_begin=0, ramp_steps=1500, gamma=0.0,
+                   nh_tau=0.1, v_pull=0.0, z_lo=z[f == 1].max(), z_hi=z[f == 2].min(),
+                   seed=7, rep_id=3)
+    oracle.init_state(md, st, 0.0)
+    dyn = st.flag == 0
+    g = 3 * int(dyn.sum()) - 3
+    m = oracle.MASS_AU
+
+    def temp():
+        ke = 0.5 * m * (st.vx[dyn] ** 2 + st.vy[dyn] ** 2 + st.vz[dyn] ** 2).sum() / acc
+        return 2 * ke / (g * kb)
+
+    assert abs(temp() - 50.0) < 1e-9
+    oracle.compute_forces(AU, st, 1)
+    Ts = []
+    for _ in range(40):
+        oracle.run(AU, md, st, 50, 1)
+        Ts.append(temp())
+    # the second half of the ramp averages near its mean target (~240 K),
+    # the hold after it near 300 K
+    assert abs(np.mean(Ts[15:30]) - 238.0) < 45.0
+    assert abs(np.mean(Ts[32:]) - 300.0) < 45.0
