@@ -274,6 +274,14 @@ typedef struct {
  *                between and v_pull is not used.  grip_hold = 0: the bottom
  *                grip rests and the top one moves at v_pull.  The elongation
  *                D of eq 4 is the sum of both grips' travel.
+ *  T_start, ramp_begin, ramp_steps
+ *                temperature ramp of the equilibration (Simulation details):
+ *                when ramp_steps > 0 the target temperature of replica r at
+ *                time t (in steps) is T_start[r] + (T[r] - T_start[r]) *
+ *                clamp((t - ramp_begin) / ramp_steps, 0, 1) (T_start: device
+ *                [R] double); otherwise it is T[r].  The Langevin O step takes
+ *                it at mid-step, the Nose-Hoover half steps at the start and
+ *                end of the step, tbsma_init_state at step 0.
  */
 typedef struct {
   double dt, gamma;
@@ -294,6 +302,9 @@ typedef struct {
   double *nh_eta;
   double grip_step;
   int64_t grip_hold;
+  const double *T_start;
+  int64_t ramp_begin;
+  int64_t ramp_steps;
 } tbsma_md;
 
 /*

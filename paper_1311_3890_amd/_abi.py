@@ -60,7 +60,8 @@ class MD(C.Structure):
                 ("T", vp), ("v_pull", vp), ("z_lo", vp), ("z_hi", vp), ("vol", vp), ("L0", vp),
                 ("seed", vp), ("dof", vp), ("step", vp), ("obs", vp), ("status", vp),
                 ("retire", C.c_double), ("dfail", vp), ("nh_tau", C.c_double), ("nh_xi", vp),
-                ("nh_eta", vp), ("grip_step", C.c_double), ("grip_hold", C.c_int64)]
+                ("nh_eta", vp), ("grip_step", C.c_double), ("grip_hold", C.c_int64),
+                ("T_start", vp), ("ramp_begin", C.c_int64), ("ramp_steps", C.c_int64)]
 
 
 P = C.POINTER

@@ -363,6 +363,10 @@ int check_md(const tbsma_md *m, int R) {
     return fail(TBSMA_EINVAL, "Nose-Hoover needs nh_xi");
   if (m->grip_hold < 0 || !std::isfinite(m->grip_step))
     return fail(TBSMA_EINVAL, "need grip_hold >= 0 and a finite grip_step");
+  if (m->ramp_steps < 0)
+    return fail(TBSMA_EINVAL, "ramp_steps must be >= 0");
+  if (m->ramp_steps > 0 && R > 0 && !m->T_start)
+    return fail(TBSMA_EINVAL, "a temperature ramp needs T_start");
   return TBSMA_OK;
 }
 
@@ -394,6 +398,9 @@ DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
   M.nh_eta = m->nh_eta;
   M.grip_step = m->grip_hold > 0 ? m->grip_step : 0.0;
   M.grip_hold = m->grip_hold;
+  M.T_start = m->T_start;
+  M.ramp_begin = m->ramp_begin;
+  M.ramp_steps = m->T_start ? m->ramp_steps : 0;
   return M;
 }
 

@@ -123,6 +123,9 @@ struct DevMD {
   double *nh_eta;  // [R] its time integral, or NULL
   double grip_step;   // stepwise grips: move of each grip per hold (A)
   int64_t grip_hold;  // steps per hold; 0: continuous pulling at v_pull
+  const double *T_start;  // [R] temperature ramp: T_start at ramp_begin,
+  int64_t ramp_begin;     //   rising linearly to T over ramp_steps steps
+  int64_t ramp_steps;     //   (0: the target is T throughout)
 };
 
 // Per-replica Nose-Hoover state in the workspace (DevMD::nh_tau > 0), at
@@ -164,14 +167,26 @@ __device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
   return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
 }
 
+// Target temperature of replica r at time t (in steps): linear from
+// T_start at ramp_begin to T at ramp_begin + ramp_steps, constant outside
+// (the equilibration ramp of Simulation details); T without a ramp.
+__device__ __forceinline__ double target_T(const DevMD &M, int r, double t) {
+  if (M.ramp_steps <= 0) return M.T[r];
+  double f = (t - (double)M.ramp_begin) / (double)M.ramp_steps;
+  if (f < 0.0) f = 0.0;
+  if (f > 1.0) f = 1.0;
+  return M.T_start[r] + (M.T[r] - M.T_start[r]) * f;
+}
+
 // One Nose-Hoover thermostat half step (dt/2) of replica r for the kinetic
-// energy K (eV) of its peculiar velocities: zeta += dt/4 G(K); eta += dt/2
-// zeta; scale s = exp(-zeta dt/2); K *= s^2; zeta += dt/4 G(K), with
-// G(K) = (2K / (g kB T) - 1) / tau^2.  Returns s (1 when g kB T <= 0: such a
-// replica is left unthermostatted).
-__device__ __forceinline__ double nh_half(const DevMD &M, int r, double &zeta,
-                                          double &eta, double &K) {
-  const double gkT = (double)M.dof[r] * kBoltz * M.T[r];
+// energy K (eV) of its peculiar velocities at target temperature Tt:
+// zeta += dt/4 G(K); eta += dt/2 zeta; scale s = exp(-zeta dt/2); K *= s^2;
+// zeta += dt/4 G(K), with G(K) = (2K / (g kB Tt) - 1) / tau^2.  Returns s
+// (1 when g kB Tt <= 0: such a replica is left unthermostatted).
+__device__ __forceinline__ double nh_half(const DevMD &M, int r, double Tt,
+                                          double &zeta, double &eta,
+                                          double &K) {
+  const double gkT = (double)M.dof[r] * kBoltz * Tt;
   if (!(gkT > 0.0)) return 1.0;
   const double tau2 = M.nh_tau * M.nh_tau;
   zeta += 0.25 * M.dt * (2.0 * K / gkT - 1.0) / tau2;

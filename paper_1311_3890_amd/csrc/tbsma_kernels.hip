@@ -1333,7 +1333,8 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
           gauss3(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u,
                  n0, n1, n2);
         }
-        double sg = sqrt(kBoltz * M.T[r] / S.mass * kAccel) *
+        double sg = sqrt(kBoltz * target_T(M, r, (double)step + 0.5) /
+                         S.mass * kAccel) *
                     sqrt(1.0 - M.c1 * M.c1);
         double uz = stream_u(M, r, z, M.v_pull[r] * ((double)step + 0.5) * dt);
         vx = M.c1 * vx + sg * n0;
@@ -1502,12 +1503,13 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
       // that begins the next step
       double *w = S.nhw + 5 * r;
       double zeta = w[kNhZeta], eta = w[kNhEta];
-      const double sb = nh_half(M, r, zeta, eta, KE);
+      const double Tn = target_T(M, r, (double)n1);
+      const double sb = nh_half(M, r, Tn, zeta, eta, KE);
       Kz *= sb * sb;
       M.nh_xi[r] = zeta;
       if (M.nh_eta) M.nh_eta[r] = eta;
       double K2 = KE;
-      const double sa = nh_half(M, r, zeta, eta, K2);
+      const double sa = nh_half(M, r, Tn, zeta, eta, K2);
       w[kNhPend] = sb * sa;
       w[kNhEnd] = sb;
       w[kNhZeta] = zeta;
@@ -1615,7 +1617,7 @@ __global__ void __launch_bounds__(256) k_nh_begin(Dev S, DevMD M) {
   if (threadIdx.x == 0) {
     double K = 0.5 * lds[0] / kAccel;
     double zeta = M.nh_xi[r], eta = M.nh_eta ? M.nh_eta[r] : 0.0;
-    w[kNhPend] = nh_half(M, r, zeta, eta, K);
+    w[kNhPend] = nh_half(M, r, target_T(M, r, (double)step), zeta, eta, K);
     w[kNhEnd] = 1.0;
     w[kNhZeta] = zeta;
     w[kNhEta] = eta;
@@ -1657,7 +1659,7 @@ __global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
     }
     double vx = 0, vy = 0, vz = 0;
     if (f == 0) {
-      double sg = sqrt(kBoltz * M.T[r] / S.mass * kAccel);
+      double sg = sqrt(kBoltz * target_T(M, r, 0.0) / S.mass * kAccel);
       double n0, n1, n2;
       gauss3(M.seed[r], rid, tag, 0, 1u, n0, n1, n2);
       vx = sg * n0;
@@ -1707,7 +1709,7 @@ __global__ void __launch_bounds__(256) k_init_reduce(Dev S, DevMD M,
       int dof = M.dof[r];
       double s2 = s[0];
       rs[3] = (s2 > 0.0 && dof > 0)
-                  ? sqrt((double)dof * kBoltz * M.T[r] /
+                  ? sqrt((double)dof * kBoltz * target_T(M, r, 0.0) /
                          (S.mass * s2 / kAccel))
                   : 0.0;
     }

@@ -65,7 +65,8 @@ class WireBatch:
                  lab_frame: int = 0, a: float = 4.08, pot: Potential | None = None,
                  device=None, wires=None, qbits: int | None = None, prune: float = 0.15,
                  retire: float = 0.0, nh_tau: float = 0.0, grip_step: float = 0.0,
-                 grip_hold: int = 0, notch: tuple | None = None):
+                 grip_hold: int = 0, notch: tuple | None = None, T_start=None,
+                 ramp_begin: int = 0, ramp_steps: int = 0):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
@@ -76,7 +77,8 @@ class WireBatch:
         self._kw = dict(skin=skin, cell=cell, gamma=gamma, dt=dt, n_log=n_log, n_slots=n_slots,
                         strain_max=strain_max, lab_frame=lab_frame, a=a, pot=self.pot,
                         device=device, prune=prune, retire=retire, nh_tau=nh_tau,
-                        grip_step=grip_step, grip_hold=grip_hold, notch=notch)
+                        grip_step=grip_step, grip_hold=grip_hold, notch=notch,
+                        T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps)
         self.nh_tau, self.grip_step, self.grip_hold = float(nh_tau), float(grip_step), int(grip_hold)
         self.notch = notch
         self.precision = precision
@@ -187,6 +189,11 @@ class WireBatch:
         T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
         T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
         T["dfail"] = torch.full((R,), -1.0, **f64)
+        # target temperatures at the start of a ramp (scalar or per replica)
+        t0 = np.broadcast_to(np.asarray(T_start if T_start is not None else
+                                        [rp.T for rp in self.replicas], dtype=np.float64), (R,))
+        T["T_start"] = torch.tensor(np.ascontiguousarray(t0), **f64)
+        self.ramp_begin, self.ramp_steps = int(ramp_begin), int(ramp_steps)
         T["nh_xi"] = torch.zeros(R, **f64)
         T["nh_eta"] = torch.zeros(R, **f64)
         # --- ABI structs -------------------------------------------------------------------
@@ -217,7 +224,8 @@ class WireBatch:
                        *[_ptr(T[k]) for k in ("T", "v_pull", "z_lo", "z_hi", "vol", "L0", "seed",
                                               "dof", "step", "obs", "status")], float(retire),
                        _ptr(T["dfail"]), self.nh_tau, _ptr(T["nh_xi"]), _ptr(T["nh_eta"]),
-                       self.grip_step, self.grip_hold)
+                       self.grip_step, self.grip_hold, _ptr(T["T_start"]), self.ramp_begin,
+                       self.ramp_steps)
         nb = C.c_size_t()
         A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
                                               C.byref(nb)))
@@ -403,7 +411,9 @@ class WireBatch:
             raise ValueError("keep must list distinct replica indices of this batch")
         nb = WireBatch([self.replicas[r] for r in keep], self.precision,
                        wires=[self.wires[r] for r in keep], qbits=self.qbits,
-                       k_cap=self.k_cap, **dict(self._kw, device=self.device))
+                       k_cap=self.k_cap,
+                       **dict(self._kw, device=self.device,
+                              T_start=self.t["T_start"].cpu().numpy()[keep]))
         for j, r in enumerate(keep):
             o, oj, n = int(self.rep_off[r]), int(nb.rep_off[j]), int(self.n_atoms[r])
             for k in ("x", "y", "z", "vx", "vy", "vz", "z0"):

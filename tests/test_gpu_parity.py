@@ -56,7 +56,9 @@ def orc_md(b: WireBatch, r: int):
     rp = b.replicas[r]
     return oracle.MD(dt=b.dt, gamma=b.gamma, T=rp.T, v_pull=rp.v_pull, z_lo=b.z_lo[r],
                      z_hi=b.z_hi[r], seed=rp.seed, rep_id=rp.rep_id, lab_frame=b.lab_frame,
-                     nh_tau=b.nh_tau, grip_step=b.grip_step, grip_hold=b.grip_hold)
+                     nh_tau=b.nh_tau, grip_step=b.grip_step, grip_hold=b.grip_hold,
+                     T_start=float(b.t["T_start"][r]), ramp_begin=b.ramp_begin,
+                     ramp_steps=b.ramp_steps)
 
 
 # the paper's protocol: Nose-Hoover, stepwise symmetric grips (short holds so
@@ -254,15 +256,17 @@ def test_step_fp64_lockstep_with_oracle():
         assert abs(ob[k_gpu] - orf[k_or]) <= 1e-9 * max(1.0, abs(orf[k_or])), (k_gpu, ob, orf)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_paper_protocol_lockstep_with_oracle(precision):
+@pytest.mark.parametrize("precision,ramp", [("fp64", False), ("mixed", False), ("fp64", True)])
+def test_paper_protocol_lockstep_with_oracle(precision, ramp):
     """Nose-Hoover at 298 K, stepwise symmetric grips and a notched wire:
     positions, velocities, zeta and eta follow the oracle step for step
     (FP64 to rounding; mixed within its force error), and the elongation and
-    strain of the records are the grips' travel."""
+    strain of the records are the grips' travel.  With ramp, the target
+    rises from 100 K to 298 K between steps 5 and 45."""
     rp = R(20.0, 40.0, T=298.0, v=0.0, r=3, jitter=0.01)
-    note(f"paper protocol lockstep {precision}, 60 steps")
-    b = WireBatch([rp], precision, n_log=10, **PROTOCOL)
+    note(f"paper protocol lockstep {precision} ramp={ramp}, 60 steps")
+    rkw = dict(T_start=100.0, ramp_begin=5, ramp_steps=40) if ramp else {}
+    b = WireBatch([rp], precision, n_log=10, **PROTOCOL, **rkw)
     b.prepare()
     torch.cuda.synchronize()
     st = orc_state(b, 0)
@@ -299,6 +303,32 @@ def test_paper_protocol_lockstep_with_oracle(precision):
     assert np.all(z[f == A.GRIP_FIXED] == z0[f == A.GRIP_FIXED] - 0.05 * 3)
     assert np.all(z[f == A.GRIP_PULL] == z0[f == A.GRIP_PULL] + 0.05 * 3)
     assert np.all(b.velocities(0)[2][f != 0] == 0.0)
+
+
+def test_langevin_with_temperature_ramp_lockstep_with_oracle():
+    """BAOAB Langevin at a ramped target (mid-step noise amplitude), FP64,
+    continuous pulling: the same trajectory as the oracle."""
+    rp = R(20.0, 30.0, T=298.0, v=0.5, r=6, jitter=0.01)
+    note("langevin ramp lockstep fp64, 40 steps")
+    b = WireBatch([rp], "fp64", n_log=10, T_start=20.0, ramp_begin=0, ramp_steps=30)
+    b.prepare()
+    torch.cuda.synchronize()
+    st = orc_state(b, 0)
+    md = orc_md(b, 0)
+    x0, y0, z0, f0 = oracle.build_wire(4.08, rp.D, rp.L, 2)
+    st0 = oracle.State(x0, y0, z0, f0)
+    oracle.init_state(md, st0, rp.jitter)
+    assert np.abs(stackF((st.vx, st.vy, st.vz)) - stackF((st0.vx, st0.vy, st0.vz))).max() < 1e-12
+    oracle.compute_forces(AU, st, 0)
+    for k in range(4):
+        b.step(10)
+        oracle.run(AU, md, st, 10, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+        note(f"  after {10 * (k + 1)} steps: |dx| {dx:.2e} |dv| {dv:.2e}")
+        assert dx < 1e-11 and dv < 1e-9
 
 
 def test_nose_hoover_extended_energy_is_conserved_in_mixed_precision():
