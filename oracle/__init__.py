@@ -44,7 +44,8 @@ class _MD(C.Structure):
                 ("mass", C.c_double), ("seed", C.c_uint64), ("rep_id", C.c_uint32),
                 ("lab_frame", C.c_int32), ("nh_tau", C.c_double), ("grip_step", C.c_double),
                 ("grip_hold", C.c_int64), ("T_start", C.c_double), ("ramp_begin", C.c_int64),
-                ("ramp_steps", C.c_int64)]
+                ("ramp_steps", C.c_int64), ("baro_mass", C.c_double), ("baro_load", C.c_double),
+                ("baro_damp", C.c_double)]
 
 
 @dataclass
@@ -84,12 +85,15 @@ class MD:
     T_start: float = 0.0    # temperature ramp from T_start at step ramp_begin
     ramp_begin: int = 0     # to T at ramp_begin + ramp_steps (0: no ramp)
     ramp_steps: int = 0
+    baro_mass: float = 0.0  # > 0: axial barostat on the grip separation (amu)
+    baro_load: float = 0.0  # outward pull on each grip (eV/A)
+    baro_damp: float = 0.0  # friction on the barostat coordinate (1/ps)
 
     def c(self) -> _MD:
         return _MD(self.dt, self.gamma, self.T, self.v_pull, self.z_lo, self.z_hi,
                    self.mass, self.seed, self.rep_id, self.lab_frame, self.nh_tau,
                    self.grip_step, self.grip_hold, self.T_start, self.ramp_begin,
-                   self.ramp_steps)
+                   self.ramp_steps, self.baro_mass, self.baro_load, self.baro_damp)
 
 
 _lib = None
@@ -134,10 +138,10 @@ def lib():
         L.orc_run.restype = None
         L.orc_run.argtypes = [C.POINTER(_Pot), C.POINTER(_MD), C.c_int64, dp, dp, dp, dp, dp, dp,
                               dp, u8p, dp, dp, dp, C.c_void_p, C.c_int64, C.c_int64, C.c_int,
-                              dp, dp]
+                              dp, dp, dp]
         L.orc_observe.restype = None
         L.orc_observe.argtypes = [C.POINTER(_Pot), C.POINTER(_MD), C.c_int64, dp, dp, dp, dp, dp,
-                                  dp, u8p, C.c_int64, C.c_double, C.c_double, dp]
+                                  dp, u8p, C.c_int64, C.c_double, C.c_double, dp, dp]
         L.orc_target_temperature.restype = C.c_double
         L.orc_target_temperature.argtypes = [C.POINTER(_MD), C.c_double]
         L.orc_num_threads.restype = C.c_int
@@ -252,10 +256,11 @@ class State:
         self.step = 0
         self.zeta = np.zeros(1)   # Nose-Hoover friction (1/ps)
         self.eta = np.zeros(1)    # its time integral
+        self.piston = np.zeros(2)  # barostat: grip travel s (A) and ds/dt
 
     def copy(self):
         s = State(self.x, self.y, self.z, self.flag)
-        for k in ("vx", "vy", "vz", "fx", "fy", "fz", "e_atom", "z0", "zeta", "eta"):
+        for k in ("vx", "vy", "vz", "fx", "fy", "fz", "e_atom", "z0", "zeta", "eta", "piston"):
             setattr(s, k, getattr(self, k).copy())
         s.step = self.step
         return s
@@ -279,7 +284,7 @@ def run(pot: Pot, md: MD, st: State, n_steps: int, mode: int = 0):
     Nose-Hoover thermostat, or none (orc_run)."""
     lib().orc_run(C.byref(pot.c()), C.byref(md.c()), st.x.size, st.x, st.y, st.z,
                   st.vx, st.vy, st.vz, st.z0, st.flag, st.fx, st.fy, st.fz,
-                  st.e_atom.ctypes.data, st.step, n_steps, mode, st.zeta, st.eta)
+                  st.e_atom.ctypes.data, st.step, n_steps, mode, st.zeta, st.eta, st.piston)
     st.step += n_steps
 
 
@@ -287,7 +292,7 @@ def observe(pot: Pot, md: MD, st: State, vol: float, L0: float):
     """E_pot, KE, T, -W_zz, sigma_zz (GPa), strain, max axial gap, D."""
     out = np.zeros(8)
     lib().orc_observe(C.byref(pot.c()), C.byref(md.c()), st.x.size, st.x, st.y, st.z,
-                      st.vx, st.vy, st.vz, st.flag, st.step, vol, L0, out)
+                      st.vx, st.vy, st.vz, st.flag, st.step, vol, L0, st.piston, out)
     return out
 
 

@@ -568,6 +568,9 @@ typedef struct {
   double T_start;    /* temperature ramp: target T_start at ramp_begin ... */
   int64_t ramp_begin; /* ... rising linearly to T over ramp_steps steps; */
   int64_t ramp_steps; /* ramp_steps = 0: the target is T throughout */
+  double baro_mass;  /* amu; > 0: axial barostat on the grip separation */
+  double baro_load;  /* eV/A: outward pull on each grip (0: zero stress) */
+  double baro_damp;  /* 1/ps: friction on the barostat coordinate */
 } orc_md;
 
 /*
@@ -622,7 +625,9 @@ double orc_target_temperature(const orc_md *M, double t) {
  * lab frame, when the grip does not move, or with stepwise grips (which rest
  * between their displacements). */
 static double orc_stream_u(const orc_md *M, double zz, double Dg) {
-  if (M->lab_frame || M->v_pull == 0.0 || M->grip_hold > 0) return 0.0;
+  if (M->lab_frame || M->v_pull == 0.0 || M->grip_hold > 0 ||
+      M->baro_mass > 0.0)
+    return 0.0;
   return M->v_pull * (zz - M->z_lo) / (M->z_hi - M->z_lo + Dg);
 }
 
@@ -654,7 +659,8 @@ void orc_init_state(const orc_md *M, int64_t n, double *x, double *y,
   int64_t ndyn = 0;
   for (int64_t i = 0; i < n; i++) {
     vx[i] = vy[i] = vz[i] = 0.0;
-    if (flag[i] == 2 && M->grip_hold == 0) vz[i] = M->v_pull;
+    if (flag[i] == 2 && M->grip_hold == 0 && M->baro_mass == 0.0)
+      vz[i] = M->v_pull;
     if (flag[i] != 0) continue;
     double g3[3];
     orc_gauss3(M->seed, M->rep_id, (uint32_t)i, 0, 1, g3);
@@ -741,6 +747,33 @@ static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
 }
 
 /*
+ * Axial barostat (Simulation details: the equilibration holds zero pressure
+ * along [100] with a Nose-Hoover barostat).  Reading: the wire is finite and
+ * held by rigid grips, so the length the barostat controls is the grip
+ * separation.  Both grips move by s, outwards, from their reference
+ * positions; s is an extended coordinate of mass W (baro_mass) whose
+ * equation of motion is
+ *   W d2s/dt2 = Q + 2 F_load,   Q = -dE/ds = sum_top F_z - sum_bottom F_z,
+ * F_load (baro_load) the outward pull on each grip: zero for zero axial
+ * stress.  E_pot + K + W (ds/dt)^2 / 2 - 2 F_load s is then a constant of
+ * motion without thermostat.  Atoms are not rescaled: the grips pass the
+ * load to the wire.  Integrated with the particles by velocity Verlet.  The
+ * barostat coordinate exchanges energy with the wire only through the grips,
+ * so an optional friction gamma_b (baro_damp) relaxes it: ds/dt is
+ * multiplied by exp(-gamma_b dt/2) before its first and after its second
+ * half kick of each step.  The piston then settles where Q = -2 F_load.
+ */
+static double orc_grip_force(int64_t n, const uint8_t *flag,
+                             const double *fz) {
+  double q = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    if (flag[i] == 2) q += fz[i];
+    else if (flag[i] == 1) q -= fz[i];
+  }
+  return q;
+}
+
+/*
  * n_steps of velocity Verlet (Simulation details: dt = 2 fs) with the rigid
  * grips of Figure 1 (Simulation details: two rigid layers at each end) and
  * one of three thermostats: none (gamma = 0, nh_tau = 0), the Langevin
@@ -749,40 +782,55 @@ static void orc_nh_half(const orc_md *M, int64_t n, double *vx, double *vy,
  * the target temperature of orc_target_T.
  * Step s -> s+1, on dynamic atoms (flag 0):
  *   [Nose-Hoover half step at the positions of step s]
+ *   [barostat: ds/dt *= exp(-gamma_b dt/2); ds/dt += dt/2 (Q + 2 F_load)/W
+ *    with the forces of step s; s += dt ds/dt]
  *   B: v += dt/2 F/m;  A: x += dt/2 v;
  *   O (Langevin only): v = u + c1 (v - u) + c2 sqrt(kB T/m) n,
  *      c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2), u the streaming velocity at
  *      mid-step (zero in the lab frame), n from the counter (tag, s, rep_id,
  *      stream 0);
  *   A: x += dt/2 v;
- * grips (orc_grip_top, orc_grip_bottom): bottom ones at z0 minus the bottom
- * displacement after s+1 steps, top ones at z0 plus the top displacement
- * (x, y unchanged), with v = 0 except v_z = v_pull on top when pulling
- * continuously; then forces at the new positions, B: v += dt/2 F/m, and
- * [Nose-Hoover half step at the positions of step s+1].
+ * grips: bottom ones at z0 minus the bottom grip's travel, top ones at z0
+ * plus the top grip's travel (x, y unchanged): orc_grip_top/orc_grip_bottom
+ * after s+1 steps, or the barostat's s; v = 0 except v_z = v_pull on top
+ * when pulling continuously; then forces at the new positions,
+ * B: v += dt/2 F/m, [barostat: ds/dt += dt/2 (Q + 2 F_load)/W with the new
+ * forces; ds/dt *= exp(-gamma_b dt/2)] and [Nose-Hoover half step at the
+ * positions of step s+1].
  * On entry fx, fy, fz hold F at step0; on return F at step0 + n_steps and
  * e_atom (may be NULL) the per-atom energies there.  zeta, eta: the
- * Nose-Hoover variables, read and updated (only used when nh_tau > 0).
+ * Nose-Hoover variables (used when nh_tau > 0); piston: s and ds/dt of the
+ * barostat (used when baro_mass > 0); all read and updated.
  * mode: 0 brute force, 1 cell list (orc_forces).
  */
 void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
              double *y, double *z, double *vx, double *vy, double *vz,
              const double *z0, const uint8_t *flag, double *fx, double *fy,
              double *fz, double *e_atom, int64_t step0, int64_t n_steps,
-             int mode, double *zeta, double *eta) {
+             int mode, double *zeta, double *eta, double *piston) {
   const double dt = M->dt;
   const double ac = ORC_ACC / M->mass; /* eV/A per amu -> A/ps^2 */
   const double c1 = exp(-M->gamma * dt);
   const double c2 = sqrt(1.0 - c1 * c1);
   const int nh = M->nh_tau > 0.0;
+  const int baro = M->baro_mass > 0.0;
+  const double acb = baro ? ORC_ACC / M->baro_mass : 0.0;
+  const double damp = exp(-0.5 * M->baro_damp * dt);
   for (int64_t s = step0; s < step0 + n_steps; s++) {
     double Dmid = M->v_pull * ((double)s + 0.5) * dt;
-    double top = orc_grip_top(M, s + 1), bottom = orc_grip_bottom(M, s + 1);
     const double sig =
         sqrt(ORC_KB * orc_target_T(M, (double)s + 0.5) / M->mass * ORC_ACC);
     if (nh)
       orc_nh_half(M, n, vx, vy, vz, z, flag, orc_grip_top(M, s),
                   orc_target_T(M, (double)s), zeta, eta);
+    if (baro) {
+      const double q = orc_grip_force(n, flag, fz) + 2.0 * M->baro_load;
+      piston[1] *= damp;
+      piston[1] += 0.5 * dt * acb * q;
+      piston[0] += dt * piston[1];
+    }
+    double top = baro ? piston[0] : orc_grip_top(M, s + 1);
+    double bottom = baro ? piston[0] : orc_grip_bottom(M, s + 1);
     for (int64_t i = 0; i < n; i++) {
       if (flag[i] == 0) {
         vx[i] += 0.5 * dt * ac * fx[i];
@@ -808,7 +856,7 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
       } else if (flag[i] == 2) {
         z[i] = z0[i] + top;
         vx[i] = vy[i] = 0.0;
-        vz[i] = M->grip_hold > 0 ? 0.0 : M->v_pull;
+        vz[i] = (M->grip_hold > 0 || baro) ? 0.0 : M->v_pull;
       }
     }
     orc_forces(P, n, x, y, z, mode, NULL, e_atom, fx, fy, fz, NULL);
@@ -817,6 +865,11 @@ void orc_run(const orc_pot *P, const orc_md *M, int64_t n, double *x,
       vx[i] += 0.5 * dt * ac * fx[i];
       vy[i] += 0.5 * dt * ac * fy[i];
       vz[i] += 0.5 * dt * ac * fz[i];
+    }
+    if (baro) {
+      const double q = orc_grip_force(n, flag, fz) + 2.0 * M->baro_load;
+      piston[1] += 0.5 * dt * acb * q;
+      piston[1] *= damp;
     }
     if (nh)
       orc_nh_half(M, n, vx, vy, vz, z, flag, top,
@@ -841,13 +894,14 @@ static int orc_cmp_double(const void *a, const void *b) {
  * is a typo), with peculiar velocities v - u (u the streaming profile, zero in
  * the lab frame) over dynamic atoms; V is the constant hard-sphere volume
  * passed in; eq 4's L - L0 is the elongation D (v_pull s dt when pulling
- * continuously, orc_elongation).
+ * continuously, orc_elongation; twice the piston's s with the barostat,
+ * piston may be NULL otherwise).
  */
 void orc_observe(const orc_pot *P, const orc_md *M, int64_t n,
                  const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz,
                  const uint8_t *flag, int64_t step, double vol, double L0,
-                 double out[8]) {
+                 const double *piston, double out[8]) {
   double w6[6];
   double ep = orc_forces(P, n, x, y, z, 1, NULL, NULL, NULL, NULL, NULL, w6);
   double Dg = orc_grip_top(M, step);
@@ -877,9 +931,11 @@ void orc_observe(const orc_pot *P, const orc_md *M, int64_t n,
   out[2] = dof > 0 ? 2.0 * ke / ((double)dof * ORC_KB) : 0.0;
   out[3] = -w6[2];
   out[4] = (-w6[2] - kz) / vol * ORC_EVA3_GPA;
-  out[5] = orc_elongation(M, step) / L0;
+  const double D = M->baro_mass > 0.0 ? 2.0 * piston[0]
+                                      : orc_elongation(M, step);
+  out[5] = D / L0;
   out[6] = gap;
-  out[7] = orc_elongation(M, step);
+  out[7] = D;
 }
 
 int orc_num_threads(void) {

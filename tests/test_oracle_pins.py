@@ -569,3 +569,79 @@ def test_temperature_ramp_target_and_tracking():
     # the hold after it near 300 K
     assert abs(np.mean(Ts[15:30]) - 238.0) < 45.0
     assert abs(np.mean(Ts[32:]) - 300.0) < 45.0
+
+
+# --- equilibration barostat: the grip separation as an extended coordinate --
+def _piston_wire(T, **md_kw):
+    x, y, z, f = oracle.build_wire(4.08, 15.0, 30.6, 2)
+    st = oracle.State(x, y, z, f)
+    md = oracle.MD(T=T, v_pull=0.0, z_lo=z[f == 1].max(), z_hi=z[f == 2].min(), seed=11,
+                   rep_id=2, **md_kw)
+    oracle.init_state(md, st, 0.0)
+    oracle.compute_forces(AU, st, 1)
+    return st, md
+
+
+def test_barostat_force_is_minus_the_energy_slope():
+    """The barostat's generalized force Q = sum_top F_z - sum_bottom F_z is
+    -dE/ds for both grips moved outwards by s (central differences)."""
+    x, y, z, f = oracle.build_wire(4.08, 15.0, 30.6, 2)
+    z = z + np.random.default_rng(1).normal(scale=0.05, size=z.size)
+    r = oracle.forces(AU, x, y, z, 0)
+    q = r["fz"][f == 2].sum() - r["fz"][f == 1].sum()
+    h = 1e-5
+    e = lambda s: oracle.forces(AU, x, y, np.where(f == 2, z + s, np.where(f == 1, z - s, z)),
+                                0)["E"]
+    assert abs((e(-h) - e(h)) / (2 * h) - q) < 1e-6 * max(1.0, abs(q))
+
+
+def test_barostat_conserves_energy_with_the_piston():
+    """Without thermostat, E_pot + K + W (ds/dt)^2/2 stays constant while the
+    free grips move (the freshly cut wire is not at zero axial stress)."""
+    kb, acc, _ = oracle.constants()
+    W = 3000.0
+    st, md = _piston_wire(50.0, gamma=0.0, baro_mass=W)
+    m = oracle.MASS_AU
+
+    def h():
+        ke = 0.5 * m * (st.vx ** 2 + st.vy ** 2 + st.vz ** 2).sum() / acc
+        return st.e_atom.sum() + ke + 0.5 * W * st.piston[1] ** 2 / acc
+
+    h0 = h()
+    hs, ss = [], []
+    for _ in range(30):
+        oracle.run(AU, md, st, 50, 1)
+        hs.append(h())
+        ss.append(st.piston[0])
+    n = st.x.size
+    assert np.ptp(ss) > 0.02
+    assert np.abs(np.array(hs) - h0).max() / n < 2e-5
+    f = st.flag
+    z0 = st.z0
+    assert np.allclose(st.z[f == 2], z0[f == 2] + st.piston[0], atol=1e-12)
+    assert np.allclose(st.z[f == 1], z0[f == 1] - st.piston[0], atol=1e-12)
+    obs = oracle.observe(AU, md, st, 1.0, 30.6)
+    assert abs(obs[7] - 2 * st.piston[0]) < 1e-15
+
+
+def test_barostat_settles_at_the_load():
+    """A damped piston on a cold Nose-Hoover wire settles where the grips'
+    net force balances the load (Q = -2 F_load): the mean Q at rest is a
+    small fraction of the cut wire's initial Q, and an outward load leaves
+    the wire longer."""
+    runs = {}
+    for load in (0.0, 1.0):
+        st, md = _piston_wire(5.0, gamma=0.0, nh_tau=0.05, baro_mass=500.0, baro_load=load,
+                              baro_damp=5.0)
+        q = lambda: st.fz[st.flag == 2].sum() - st.fz[st.flag == 1].sum()
+        q0 = q()
+        qs, ss = [], []
+        for k in range(60):
+            oracle.run(AU, md, st, 50, 1)
+            if k >= 40:
+                qs.append(q())
+                ss.append(st.piston[0])
+        runs[load] = (q0, np.mean(qs), np.mean(ss))
+    for load, (q0, qm, _) in runs.items():
+        assert abs(qm + 2 * load) < 0.1 * abs(q0), (load, q0, qm)
+    assert runs[1.0][2] > runs[0.0][2] + 0.01
