@@ -282,6 +282,20 @@ typedef struct {
  *                [R] double); otherwise it is T[r].  The Langevin O step takes
  *                it at mid-step, the Nose-Hoover half steps at the start and
  *                end of the step, tbsma_init_state at step 0.
+ *  baro_mass, baro_load, baro_damp, baro_s
+ *                axial barostat of the equilibration (Simulation details:
+ *                zero pressure along [100]), on the grip separation: when
+ *                baro_mass > 0 (amu; needs grip_hold = 0; v_pull is not
+ *                used) both grips move outwards by s[r], an extended
+ *                coordinate with baro_mass d2s/dt2 = Q + 2 baro_load, where
+ *                Q = sum_top F_z - sum_bottom F_z = -dE/ds and baro_load
+ *                (eV/A) is the outward pull on each grip (0: zero axial
+ *                load), integrated by velocity Verlet with the atoms; ds/dt
+ *                is multiplied by exp(-baro_damp dt/2) (baro_damp in 1/ps)
+ *                before its first and after its second half kick of each
+ *                step.  baro_s: device [2R] double, s and ds/dt of each
+ *                replica, read and updated (zero them to start; the grips
+ *                must then sit at z0).  The elongation D is 2 s.
  */
 typedef struct {
   double dt, gamma;
@@ -305,6 +319,10 @@ typedef struct {
   const double *T_start;
   int64_t ramp_begin;
   int64_t ramp_steps;
+  double baro_mass;
+  double baro_load;
+  double baro_damp;
+  double *baro_s;
 } tbsma_md;
 
 /*

@@ -61,7 +61,9 @@ class MD(C.Structure):
                 ("seed", vp), ("dof", vp), ("step", vp), ("obs", vp), ("status", vp),
                 ("retire", C.c_double), ("dfail", vp), ("nh_tau", C.c_double), ("nh_xi", vp),
                 ("nh_eta", vp), ("grip_step", C.c_double), ("grip_hold", C.c_int64),
-                ("T_start", vp), ("ramp_begin", C.c_int64), ("ramp_steps", C.c_int64)]
+                ("T_start", vp), ("ramp_begin", C.c_int64), ("ramp_steps", C.c_int64),
+                ("baro_mass", C.c_double), ("baro_load", C.c_double), ("baro_damp", C.c_double),
+                ("baro_s", vp)]
 
 
 P = C.POINTER

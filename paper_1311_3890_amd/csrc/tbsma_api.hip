@@ -115,7 +115,8 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
-      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, total;
+      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
+      total;
 };
 
 // Blocks of the cell sort: ceil(cells/64) per replica.
@@ -178,6 +179,8 @@ Layout layout(const tbsma_system *s) {
   o += 256;
   L.nhw = o;
   o += up(8 * 5 * (size_t)R);
+  L.baw = o;
+  o += up(8 * 2 * (size_t)R);
 
   L.total = o;
   return L;
@@ -226,6 +229,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.atom_lane = reinterpret_cast<uint8_t *>(w + L.atom_lane);
   d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
   d.nhw = reinterpret_cast<double *>(w + L.nhw);
+  d.baw = reinterpret_cast<double *>(w + L.baw);
 
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
@@ -367,6 +371,16 @@ int check_md(const tbsma_md *m, int R) {
     return fail(TBSMA_EINVAL, "ramp_steps must be >= 0");
   if (m->ramp_steps > 0 && R > 0 && !m->T_start)
     return fail(TBSMA_EINVAL, "a temperature ramp needs T_start");
+  if (!(m->baro_mass >= 0) || !std::isfinite(m->baro_mass) ||
+      !std::isfinite(m->baro_load) || !(m->baro_damp >= 0) ||
+      !std::isfinite(m->baro_damp))
+    return fail(TBSMA_EINVAL, "need finite baro_mass >= 0, baro_load and "
+                "baro_damp >= 0");
+  if (m->baro_mass > 0 && m->grip_hold > 0)
+    return fail(TBSMA_EINVAL, "the barostat and stepwise grips exclude each "
+                "other");
+  if (m->baro_mass > 0 && R > 0 && !m->baro_s)
+    return fail(TBSMA_EINVAL, "the barostat needs baro_s");
   return TBSMA_OK;
 }
 
@@ -401,6 +415,10 @@ DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
   M.T_start = m->T_start;
   M.ramp_begin = m->ramp_begin;
   M.ramp_steps = m->T_start ? m->ramp_steps : 0;
+  M.baro_mass = m->baro_s ? m->baro_mass : 0.0;
+  M.baro_load = m->baro_load;
+  M.baro_damp = m->baro_damp;
+  M.baro_s = m->baro_s;
   return M;
 }
 
@@ -708,7 +726,9 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   DevMD M = make_devmd(prm, md);
   PotF PF = make_potf(prm);
   PotD PD = make_potd(prm);
-  if (M.nh_tau > 0) launch_nh_begin(d, M, s);
+  const bool mixed = prm->precision == TBSMA_MIXED;
+  if (M.nh_tau > 0 || M.baro_mass > 0)
+    launch_step_begin(d, M, mixed, out->fz, s);
   for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
   if (M.nh_tau > 0) launch_nh_finish(d, M, s);
   return finish_run(d, md, s);
@@ -736,7 +756,8 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   PotD PD = make_potd(prm);
   int64_t chunks = n_steps / steps_per_graph;
   int64_t rest = n_steps % steps_per_graph;
-  if (M.nh_tau > 0) launch_nh_begin(d, M, s);
+  if (M.nh_tau > 0 || M.baro_mass > 0)
+    launch_step_begin(d, M, prm->precision == TBSMA_MIXED, out->fz, s);
   if (chunks > 0) {
     std::lock_guard<std::mutex> lk(g_graph.mu);
     std::vector<char> key;

@@ -17,6 +17,7 @@ constexpr int kPartW = 1;   // sum of w_i = 1/2 sum_j E'_ij dz^2 / r
 constexpr int kPartK = 2;   // sum over dynamic atoms of m |v - u|^2
 constexpr int kPartKz = 3;  // sum over dynamic atoms of m (v_z - u_z)^2
 constexpr int kPartA = 4;   // init: sum v_x, v_y, v_z, count (4..7)
+constexpr int kPartQ = 4;   // steps: barostat force sum_top F_z - sum_bottom F_z
 
 // Physical constants: k_B (eV/K) and 1 eV/(A amu) in A/ps^2, from the SI
 // values of the electronvolt and the atomic mass unit.
@@ -102,6 +103,7 @@ struct Dev {
   int32_t *nnmax;               // [1]
   double *rsum;                 // [R * 8] per-replica scratch sums
   double *nhw;                  // [R * 5] Nose-Hoover step state (kNh*)
+  double *baw;                  // [R * 2] barostat step state (kBa*)
   // parameters used on the device
   double cell, inv_cell, skin_half2, qscale, inv_qscale, mass;
   int32_t all;                  // 1: rebuild every replica
@@ -126,7 +128,17 @@ struct DevMD {
   const double *T_start;  // [R] temperature ramp: T_start at ramp_begin,
   int64_t ramp_begin;     //   rising linearly to T over ramp_steps steps
   int64_t ramp_steps;     //   (0: the target is T throughout)
+  double baro_mass;       // axial barostat on the grip separation (amu; 0: off)
+  double baro_load;       // outward pull on each grip (eV/A)
+  double baro_damp;       // friction on the barostat coordinate (1/ps)
+  double *baro_s;         // [2R] grip travel s (A) and ds/dt (A/ps)
 };
+
+// Per-replica barostat state in the workspace (DevMD::baro_mass > 0), at
+// Dev::baw + 2 r: the grip travel the next step places the grips at, and
+// ds/dt after that step's first half kick.
+constexpr int kBaS = 0;
+constexpr int kBaV = 1;
 
 // Per-replica Nose-Hoover state in the workspace (DevMD::nh_tau > 0), at
 // offsets of Dev::nhw + 5 r:
@@ -163,7 +175,8 @@ __device__ __forceinline__ double elongation(const DevMD &M, int r,
 __device__ __forceinline__ double stream_u(const DevMD &M, int r, double z,
                                            double D) {
   double vp = M.v_pull[r];
-  if (M.lab_frame || vp == 0.0 || M.grip_hold > 0) return 0.0;
+  if (M.lab_frame || vp == 0.0 || M.grip_hold > 0 || M.baro_mass > 0.0)
+    return 0.0;
   return vp * (z - M.z_lo[r]) / (M.z_hi[r] - M.z_lo[r] + D);
 }
 
@@ -176,6 +189,18 @@ __device__ __forceinline__ double target_T(const DevMD &M, int r, double t) {
   if (f < 0.0) f = 0.0;
   if (f > 1.0) f = 1.0;
   return M.T_start[r] + (M.T[r] - M.T_start[r]) * f;
+}
+
+// Axial barostat (Simulation details: zero pressure along [100] during the
+// equilibration).  The grip separation is the coordinate it controls: both
+// grips move outwards by s, an extended coordinate of mass W with
+// W d2s/dt2 = Q + 2 F_load, Q = sum_top F_z - sum_bottom F_z = -dE/ds, and an
+// optional friction gamma_b applied as exp(-gamma_b dt/2) before the first
+// and after the second half kick of ds/dt in each step (velocity Verlet).
+// Half kick of ds/dt for the grip force Q:
+__device__ __forceinline__ double baro_kick(const DevMD &M, double sdot,
+                                            double Q) {
+  return sdot + 0.5 * M.dt * (kAccel / M.baro_mass) * (Q + 2.0 * M.baro_load);
 }
 
 // One Nose-Hoover thermostat half step (dt/2) of replica r for the kinetic

@@ -1129,11 +1129,13 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
     fy[i] = ay;
     fz[i] = az;
   }
-  double k2 = 0.0, kz = 0.0;
+  double k2 = 0.0, kz = 0.0, gq = 0.0;
+  const bool baro = KICK && M.baro_mass > 0.0;
   if (KICK && valid) {
     const int r = S.tile_rep[B.t0];
     const int64_t step = *M.step;
     const uint8_t f = S.flag[i];
+    if (baro) gq = f == 2 ? (double)az : f == 1 ? -(double)az : 0.0;
     if (f != 3) {
       const double z = S.z[i];
       if (f == 0) {
@@ -1179,6 +1181,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
         lsum[2 * kBlock + (i - B.b0)] = k2;
         lsum[3 * kBlock + (i - B.b0)] = kz;
       }
+      if (baro) lsum[4 * kBlock + (i - B.b0)] = gq;
     }
     __syncthreads();
     const int w = tid / kTile;
@@ -1200,6 +1203,10 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
           pt[kPartKz] = kz_i;
         }
       }
+      if (baro) {
+        const double q_i = wave_sum(lsum[4 * kBlock + tid]);
+        if ((tid & 63) == 0) pt[kPartQ] = q_i;
+      }
     }
   }
 }
@@ -1211,7 +1218,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         float *eat) {
   __shared__ int4 lq[kStage + 1];
   // per-tile sums after the pair loop, in the staged positions' LDS
-  static_assert(4 * kBlock * sizeof(double) <= sizeof(lq), "lsum fits");
+  static_assert(5 * kBlock * sizeof(double) <= sizeof(lq), "lsum fits");
   double *lsum = reinterpret_cast<double *>(lq);
   const PairBlock B = pair_block(S);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
@@ -1351,17 +1358,19 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
       S.vy[i] = vy;
       S.vz[i] = vz;
     } else if (f == 1) {
-      z = S.z0[i] - grip_bottom(M, step + 1);
+      z = S.z0[i] - (M.baro_mass > 0.0 ? S.baw[2 * r + kBaS]
+                                       : grip_bottom(M, step + 1));
       S.z[i] = z;
       S.vx[i] = 0.0;
       S.vy[i] = 0.0;
       S.vz[i] = 0.0;
     } else {
-      z = S.z0[i] + grip_top(M, r, step + 1);
+      const bool free = M.baro_mass > 0.0;
+      z = S.z0[i] + (free ? S.baw[2 * r + kBaS] : grip_top(M, r, step + 1));
       S.z[i] = z;
       S.vx[i] = 0.0;
       S.vy[i] = 0.0;
-      S.vz[i] = M.grip_hold > 0 ? 0.0 : M.v_pull[r];
+      S.vz[i] = (M.grip_hold > 0 || free) ? 0.0 : M.v_pull[r];
     }
     if (MIXED) {
       bool out = false;
@@ -1400,6 +1409,11 @@ __global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
   uint8_t f = valid ? S.flag[i] : 3;
   double k2 = 0.0, kz = 0.0;
   bool logstep = ((step + 1) % M.n_log) == 0;
+  const bool baro = M.baro_mass > 0.0;
+  const double gq = !baro ? 0.0
+                    : f == 2 ? (double)fz[i]
+                    : f == 1 ? -(double)fz[i]
+                             : 0.0;
   if (f != 3) {
     double z = S.z[i];
     if (f == 0) {
@@ -1426,10 +1440,12 @@ __global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
   }
   k2 = wave_sum(k2);
   kz = wave_sum(kz);
+  const double q = baro ? wave_sum(gq) : 0.0;
   if ((threadIdx.x & 63) == 0 && valid) {
     double *pt = S.part + (i / kTile) * kNPart;
     pt[kPartK] = k2;
     pt[kPartKz] = kz;
+    if (baro) pt[kPartQ] = q;
   }
 }
 
@@ -1477,7 +1493,7 @@ __global__ void __launch_bounds__(256) k_reduce_forces(Dev S, double *rep_e,
 // End of a step, one workgroup per replica: sums, observables, status, and
 // (last workgroup to finish) the step index.
 __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
-  __shared__ double lds[4 * 256];
+  __shared__ double lds[5 * 256];
   int r = blockIdx.x;
   int64_t step = *M.step;
   int64_t n1 = step + 1;
@@ -1485,11 +1501,19 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   // energy and virial tile sums are current on logged steps only
   const bool logstep = (n1 % M.n_log) == 0;
   const bool frozen = (M.status[r] & 32u) != 0;  // retired: record unchanged
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  // (each sum is the same whichever other entries are summed with it)
+  const bool baro = M.baro_mass > 0.0;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (logstep) {
-    block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
+    if (baro)
+      block_sum_tiles<5>(S.part, t0, t1, kPartE, s, lds);
+    else
+      block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
   } else {
-    block_sum_tiles<2>(S.part, t0, t1, kPartK, s + 2, lds);
+    if (baro)
+      block_sum_tiles<3>(S.part, t0, t1, kPartK, s + 2, lds);
+    else
+      block_sum_tiles<2>(S.part, t0, t1, kPartK, s + 2, lds);
   }
   int nb = 2 * S.grid_dim[3 * r + 2];
   unsigned long long *bmin = S.zbmin + (int64_t)r * S.max_zbins;
@@ -1519,6 +1543,21 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     int dof = M.dof[r];
     double T = dof > 0 ? 2.0 * KE / ((double)dof * kBoltz) : 0.0;
     double D = elongation(M, r, n1);
+    if (baro) {
+      // barostat: second half kick of ds/dt with the grip force of the new
+      // positions, then the first half kick and the drift of the next step
+      double *bw = S.baw + 2 * r;
+      const double Q = s[4];
+      const double damp = exp(-0.5 * M.baro_damp * M.dt);
+      const double sn = bw[kBaS];
+      const double vn = baro_kick(M, bw[kBaV], Q) * damp;
+      M.baro_s[2 * r] = sn;
+      M.baro_s[2 * r + 1] = vn;
+      const double vh = baro_kick(M, vn * damp, Q);
+      bw[kBaV] = vh;
+      bw[kBaS] = sn + M.dt * vh;
+      D = 2.0 * sn;
+    }
     uint32_t st = S.wstatus[r];
     if (!isfinite(E) || !isfinite(KE)) st |= 2u;  // E is 0 when not logged
     if (S.rflag[r] & 1u) st |= 16u;
@@ -1587,41 +1626,76 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
 // the last end-of-step scale applied when the call ends.  Inside a call the
 // two half steps between consecutive steps are folded into kNhPend.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_nh_begin(Dev S, DevMD M) {
+// The start of a step-loop call: the first Nose-Hoover half step, from the
+// kinetic energy of the velocities as they are; the barostat's first half
+// kick and drift, from the grip force of the forces in `out` (summed per tile
+// and per replica exactly as the step loops sum it).
+template <typename FT>
+__global__ void __launch_bounds__(256) k_step_begin(Dev S, DevMD M,
+                                                    const FT *fz) {
   __shared__ double lds[256];
   const int r = blockIdx.x;
-  double *w = S.nhw + 5 * r;
-  if (M.status[r] & 32u) {  // retired: nothing pending (uniform per block)
-    if (threadIdx.x == 0) {
-      w[kNhPend] = 1.0;
-      w[kNhEnd] = 1.0;
-    }
-    return;
-  }
+  const bool gone = (M.status[r] & 32u) != 0;  // retired (uniform per block)
   const int64_t step = *M.step;
-  const double top = grip_top(M, r, step);
-  double k2 = 0.0;
-  for (int64_t i = S.rep_off[r] + threadIdx.x; i < S.rep_off[r + 1];
-       i += blockDim.x) {
-    if (S.flag[i] != 0) continue;
-    const double vx = S.vx[i], vy = S.vy[i];
-    const double wz = S.vz[i] - stream_u(M, r, S.z[i], top);
-    k2 += S.mass * (vx * vx + vy * vy + wz * wz);
+  if (M.nh_tau > 0.0) {
+    double *w = S.nhw + 5 * r;
+    if (gone) {  // nothing pending
+      if (threadIdx.x == 0) {
+        w[kNhPend] = 1.0;
+        w[kNhEnd] = 1.0;
+      }
+    } else {
+      const double top = grip_top(M, r, step);
+      double k2 = 0.0;
+      for (int64_t i = S.rep_off[r] + threadIdx.x; i < S.rep_off[r + 1];
+           i += blockDim.x) {
+        if (S.flag[i] != 0) continue;
+        const double vx = S.vx[i], vy = S.vy[i];
+        const double wz = S.vz[i] - stream_u(M, r, S.z[i], top);
+        k2 += S.mass * (vx * vx + vy * vy + wz * wz);
+      }
+      lds[threadIdx.x] = k2;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        double K = 0.5 * lds[0] / kAccel;
+        double zeta = M.nh_xi[r], eta = M.nh_eta ? M.nh_eta[r] : 0.0;
+        w[kNhPend] =
+            nh_half(M, r, target_T(M, r, (double)step), zeta, eta, K);
+        w[kNhEnd] = 1.0;
+        w[kNhZeta] = zeta;
+        w[kNhEta] = eta;
+        w[kNhTop] = top;
+      }
+      __syncthreads();
+    }
   }
-  lds[threadIdx.x] = k2;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+  if (M.baro_mass > 0.0 && !gone) {
+    const int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
+    const int lane = threadIdx.x & 63;
+    for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += blockDim.x >> 6) {
+      const int64_t i = t * kTile + lane;
+      const uint8_t f = S.flag[i];
+      const double g = f == 2   ? (double)fz[i]
+                       : f == 1 ? -(double)fz[i]
+                                : 0.0;
+      const double q = wave_sum(g);
+      if (lane == 0) S.part[t * kNPart + kPartQ] = q;
+    }
+    __threadfence_block();
     __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double K = 0.5 * lds[0] / kAccel;
-    double zeta = M.nh_xi[r], eta = M.nh_eta ? M.nh_eta[r] : 0.0;
-    w[kNhPend] = nh_half(M, r, target_T(M, r, (double)step), zeta, eta, K);
-    w[kNhEnd] = 1.0;
-    w[kNhZeta] = zeta;
-    w[kNhEta] = eta;
-    w[kNhTop] = top;
+    double Q;
+    block_sum_tiles<1>(S.part, t0, t1, kPartQ, &Q, lds);
+    if (threadIdx.x == 0) {
+      double *bw = S.baw + 2 * r;
+      const double damp = exp(-0.5 * M.baro_damp * M.dt);
+      const double vh = baro_kick(M, M.baro_s[2 * r + 1] * damp, Q);
+      bw[kBaV] = vh;
+      bw[kBaS] = M.baro_s[2 * r] + M.dt * vh;
+    }
   }
 }
 
@@ -1952,8 +2026,12 @@ void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {
   k_reduce_step<<<S.R, 256, 0, s>>>(S, M);
 }
 
-void launch_nh_begin(const Dev &S, const DevMD &M, hipStream_t s) {
-  k_nh_begin<<<S.R, 256, 0, s>>>(S, M);
+void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
+                       const void *fz, hipStream_t s) {
+  if (mixed)
+    k_step_begin<float><<<S.R, 256, 0, s>>>(S, M, (const float *)fz);
+  else
+    k_step_begin<double><<<S.R, 256, 0, s>>>(S, M, (const double *)fz);
 }
 
 void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s) {

@@ -35,7 +35,10 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
                         const void *fx, const void *fy, const void *fz,
                         hipStream_t s);
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s);
-void launch_nh_begin(const Dev &S, const DevMD &M, hipStream_t s);
+// Start of a step-loop call: Nose-Hoover and barostat state from the
+// current velocities and forces.
+void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
+                       const void *fz, hipStream_t s);
 void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s);
 void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
                  hipStream_t s);

@@ -66,7 +66,8 @@ class WireBatch:
                  device=None, wires=None, qbits: int | None = None, prune: float = 0.15,
                  retire: float = 0.0, nh_tau: float = 0.0, grip_step: float = 0.0,
                  grip_hold: int = 0, notch: tuple | None = None, T_start=None,
-                 ramp_begin: int = 0, ramp_steps: int = 0):
+                 ramp_begin: int = 0, ramp_steps: int = 0, baro_mass: float = 0.0,
+                 baro_load: float = 0.0, baro_damp: float = 0.0):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
@@ -78,7 +79,10 @@ class WireBatch:
                         strain_max=strain_max, lab_frame=lab_frame, a=a, pot=self.pot,
                         device=device, prune=prune, retire=retire, nh_tau=nh_tau,
                         grip_step=grip_step, grip_hold=grip_hold, notch=notch,
-                        T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps)
+                        T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps,
+                        baro_mass=baro_mass, baro_load=baro_load, baro_damp=baro_damp)
+        self.baro_mass, self.baro_load = float(baro_mass), float(baro_load)
+        self.baro_damp = float(baro_damp)
         self.nh_tau, self.grip_step, self.grip_hold = float(nh_tau), float(grip_step), int(grip_hold)
         self.notch = notch
         self.precision = precision
@@ -111,7 +115,7 @@ class WireBatch:
             gz = int(math.ceil((rp.L * (1.0 + strain_max) + 2 * margin) / cell))
             gdim[r] = (gxy, gxy, gz)
             # symmetric grips stretch the wire both ways
-            below = 0.5 * strain_max * rp.L if grip_hold > 0 else 0.0
+            below = 0.5 * strain_max * rp.L if grip_hold > 0 or baro_mass > 0 else 0.0
             glo[r] = (-0.5 * gxy * cell, -0.5 * gxy * cell, -margin - below)
         self.grid_dim, self.grid_lo = gdim, glo
         ncell = gdim.prod(axis=1).astype(np.int64)
@@ -194,6 +198,7 @@ class WireBatch:
                                         [rp.T for rp in self.replicas], dtype=np.float64), (R,))
         T["T_start"] = torch.tensor(np.ascontiguousarray(t0), **f64)
         self.ramp_begin, self.ramp_steps = int(ramp_begin), int(ramp_steps)
+        T["baro_s"] = torch.zeros(2 * R, **f64)
         T["nh_xi"] = torch.zeros(R, **f64)
         T["nh_eta"] = torch.zeros(R, **f64)
         # --- ABI structs -------------------------------------------------------------------
@@ -225,7 +230,8 @@ class WireBatch:
                                               "dof", "step", "obs", "status")], float(retire),
                        _ptr(T["dfail"]), self.nh_tau, _ptr(T["nh_xi"]), _ptr(T["nh_eta"]),
                        self.grip_step, self.grip_hold, _ptr(T["T_start"]), self.ramp_begin,
-                       self.ramp_steps)
+                       self.ramp_steps, self.baro_mass, self.baro_load, self.baro_damp,
+                       _ptr(T["baro_s"]))
         nb = C.c_size_t()
         A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
                                               C.byref(nb)))
@@ -368,7 +374,7 @@ class WireBatch:
     # noise is keyed by the step index, which is part of the state).
     _STATE = ("x", "y", "z", "vx", "vy", "vz", "z0", "qpos", "nl", "nl_lane", "nn", "x_ref", "y_ref",
               "z_ref", "fx", "fy", "fz", "e_atom", "g", "step", "status", "dfail", "nh_xi",
-              "nh_eta", "obs", "work")
+              "nh_eta", "baro_s", "obs", "work")
 
     def state_dict(self):
         return {k: self.t[k].detach().cpu().numpy().copy() for k in self._STATE}
@@ -424,6 +430,7 @@ class WireBatch:
         nb.t["dfail"].copy_(self.t["dfail"][idx])
         nb.t["nh_xi"].copy_(self.t["nh_xi"][idx])
         nb.t["nh_eta"].copy_(self.t["nh_eta"][idx])
+        nb.t["baro_s"].view(nb.R, 2).copy_(self.t["baro_s"].view(self.R, 2)[idx])
         ring = self.t["obs"].view(self.n_slots, self.R, A.NOBS)
         nb.t["obs"].view(nb.n_slots, nb.R, A.NOBS).copy_(ring[:, idx])
         nb.build_lists()

@@ -163,6 +163,9 @@ def _dummy_step_args(R=1, **md_kw):
     (1, dict(nh_tau=0.1), b"nh_xi"),
     (0, dict(grip_hold=-5), b"grip_hold"),
     (0, dict(grip_hold=10, grip_step=float("nan")), b"grip_step"),
+    (0, dict(baro_mass=100.0, grip_hold=10), b"exclude"),
+    (0, dict(baro_mass=-1.0), b"baro_mass"),
+    (1, dict(baro_mass=100.0), b"baro_s"),
 ])
 def test_dynamics_setting_checks(R, kw, msg):
     s, cells, nl, out, md, keep = _dummy_step_args(R, **kw)

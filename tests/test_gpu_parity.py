@@ -49,6 +49,7 @@ def orc_state(b: WireBatch, r: int):
     st.step = b.step_index()
     st.zeta[0] = float(b.t["nh_xi"][r])
     st.eta[0] = float(b.t["nh_eta"][r])
+    st.piston[:] = b.t["baro_s"][2 * r:2 * r + 2].cpu().numpy()
     return st
 
 
@@ -58,12 +59,18 @@ def orc_md(b: WireBatch, r: int):
                      z_hi=b.z_hi[r], seed=rp.seed, rep_id=rp.rep_id, lab_frame=b.lab_frame,
                      nh_tau=b.nh_tau, grip_step=b.grip_step, grip_hold=b.grip_hold,
                      T_start=float(b.t["T_start"][r]), ramp_begin=b.ramp_begin,
-                     ramp_steps=b.ramp_steps)
+                     ramp_steps=b.ramp_steps, baro_mass=b.baro_mass, baro_load=b.baro_load,
+                     baro_damp=b.baro_damp)
 
 
 # the paper's protocol: Nose-Hoover, stepwise symmetric grips (short holds so
 # that tests see several moves), ring notch three planes wide, a deep
 PROTOCOL = dict(gamma=0.0, nh_tau=0.1, grip_step=0.05, grip_hold=20, notch=(3, 4.08))
+# its equilibration: Nose-Hoover with a temperature ramp and the axial
+# barostat on the grip separation (a light, damped piston so that tests see
+# it move)
+EQUIL = dict(gamma=0.0, nh_tau=0.1, notch=(3, 4.08), T_start=50.0, ramp_begin=0,
+             ramp_steps=60, baro_mass=300.0, baro_load=0.0, baro_damp=2.0)
 
 
 def R(D, L, T=10.0, v=0.5, r=0, jitter=0.0):
@@ -305,6 +312,42 @@ def test_paper_protocol_lockstep_with_oracle(precision, ramp):
     assert np.all(b.velocities(0)[2][f != 0] == 0.0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_equilibration_barostat_lockstep_with_oracle(precision):
+    """The equilibration protocol (Nose-Hoover on a temperature ramp and the
+    axial barostat on the grip separation): atoms, thermostat and barostat
+    variables follow the oracle step for step; the records carry D = 2 s."""
+    rp = R(20.0, 40.0, T=298.0, v=0.0, r=8, jitter=0.01)
+    note(f"equilibration lockstep {precision}, 60 steps")
+    b = WireBatch([rp], precision, n_log=10, **EQUIL)
+    b.prepare()
+    torch.cuda.synchronize()
+    st = orc_state(b, 0)
+    oracle.compute_forces(AU, st, 0)
+    md = orc_md(b, 0)
+    tol_x, tol_v, tol_s = ((1e-11, 1e-9, 1e-10) if precision == "fp64" else (1e-4, 1e-2, 1e-3))
+    for k in range(6):
+        b.step(10)
+        oracle.run(AU, md, st, 10, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+        ps = b.t["baro_s"][:2].cpu().numpy()
+        ds = np.abs(ps - st.piston).max()
+        note(f"  after {10 * (k + 1)} steps: |dx| {dx:.2e} |dv| {dv:.2e} |ds| {ds:.2e} "
+             f"s {ps[0]:.4f} ds/dt {ps[1]:.4f}")
+        assert dx < tol_x and dv < tol_v and ds < tol_s
+    assert abs(st.piston[0]) > 1e-3  # the piston moved
+    ob = b.obs_at(60)[0]
+    assert abs(ob[A.OBS_D] - 2 * float(b.t["baro_s"][0])) < 1e-15
+    f = b.flags(0)
+    z0 = b.t["z0"][:int(b.n_atoms[0])].cpu().numpy()
+    s = float(b.t["baro_s"][0])
+    assert np.allclose(z[f == A.GRIP_PULL], z0[f == A.GRIP_PULL] + s, atol=1e-12)
+    assert np.allclose(z[f == A.GRIP_FIXED], z0[f == A.GRIP_FIXED] - s, atol=1e-12)
+
+
 def test_langevin_with_temperature_ramp_lockstep_with_oracle():
     """BAOAB Langevin at a ramped target (mid-step noise amplitude), FP64,
     continuous pulling: the same trajectory as the oracle."""
@@ -388,7 +431,8 @@ def _three_replicas():
             R(30.0, 16.0, T=298.0, v=0.1, r=2)]
 
 
-VARIANTS = pytest.mark.parametrize("kw", [{}, PROTOCOL], ids=["langevin", "protocol"])
+VARIANTS = pytest.mark.parametrize("kw", [{}, PROTOCOL, EQUIL],
+                                   ids=["langevin", "protocol", "equilibration"])
 
 
 @VARIANTS
@@ -455,7 +499,7 @@ def test_checkpoint_resume_is_bitwise(tmp_path, kw):
     b.load(path)
     assert b.step_index() == 60
     b.run_batch(60, 20)
-    for k in ("x", "y", "z", "vx", "vy", "vz", "obs", "status", "nh_xi", "nh_eta"):
+    for k in ("x", "y", "z", "vx", "vy", "vz", "obs", "status", "nh_xi", "nh_eta", "baro_s"):
         assert torch.equal(a.t[k], b.t[k]), k
 
 
