@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-replica", action="store_true")
+    ap.add_argument("--no-protocols", action="store_true",
+                    help="skip the timing of the paper's elongation and equilibration "
+                         "protocols on the same replicas")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--drift-steps", type=int, default=0,
@@ -200,6 +203,44 @@ def main():
         log(f"[bench] one replica per launch ({len(idx)} replicas): {pr:.4e} atom-steps/s; "
             f"with a graph per replica {prg:.4e}; batched/plain = {value / pr:.1f}x")
 
+    # ---- the paper's protocols on the same replicas -------------------------------------
+    # (not the headline: the workload's thermostat is Langevin with continuous pulling)
+    cfg = {"replicas": b.R, "skin_A": b.skin, "r_cut_A": b.pot.r_cut, "prune_A": b.prune}
+    protocols = None
+    if not args.no_protocols:
+        del b
+        torch.cuda.empty_cache()
+        protocols = {}
+        K2 = args.steps
+        for name, kw in (
+                ("elongation: Nose-Hoover (tau 0.1 ps), grips moved 0.05 A per 20 ps, "
+                 "ring notch 3 planes x 4.08 A",
+                 dict(gamma=0.0, nh_tau=0.1, grip_step=0.05, grip_hold=10000,
+                      notch=(3, W.A_LAT))),
+                ("equilibration: Nose-Hoover on a 0.01 K -> T ramp over 400 ps, axial "
+                 "barostat on the grip separation (W 1e4 amu, 1/ps friction)",
+                 dict(gamma=0.0, nh_tau=0.1, T_start=0.01, ramp_begin=0, ramp_steps=200000,
+                      baro_mass=1.0e4, baro_damp=1.0))):
+            pb = WireBatch(wl.replicas, wl.precision, n_log=100, strain_max=strain_max,
+                           skin=skin, prune=prune, **kw)
+            pb.prepare()
+            pb.run_batch(args.warmup, S)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pb.run_batch(K2, S)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pms = e0.elapsed_time(e1)
+            pn = int(pb.n_atoms.sum())
+            protocols[name] = {"atoms": pn, "steps": K2, "ms_per_step": pms / K2,
+                               "atom_timesteps_per_s": pn * K2 / (pms * 1e-3),
+                               "bad_replicas": int(np.count_nonzero(
+                                   pb.status() & (A.ST_NONFINITE | A.ST_OVERFLOW)))}
+            log(f"[bench] {name}: {protocols[name]}")
+            del pb
+            torch.cuda.empty_cache()
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample, this host's cores ---------
     cpu = None
     if not args.no_cpu_baseline:
@@ -292,10 +333,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "replicas": b.R, "atoms": n_real,
+        "config": {"workload": wl.name, "replicas": cfg["replicas"], "atoms": n_real,
                    "precision": "f32 pair math, f64 integration and sums",
-                   "steps_per_graph": S, "skin_A": b.skin, "r_cut_A": b.pot.r_cut,
-                   "prune_A": b.prune,
+                   "steps_per_graph": S, "skin_A": cfg["skin_A"], "r_cut_A": cfg["r_cut_A"],
+                   "prune_A": cfg["prune_A"],
                    "parallelism": "replica batch, 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
@@ -322,6 +363,8 @@ def main():
         "bad_replicas": bad,
         "cpu_baseline": cpu,
     }
+    if protocols is not None:
+        line["protocols"] = protocols
     if drift is not None:
         line["nve_drift"] = drift
     if oracle_other is not None:

@@ -281,8 +281,9 @@ def test_paper_protocol_lockstep_with_oracle(precision, ramp):
     oracle.compute_forces(AU, st, 0)
     md = orc_md(b, 0)
     # mixed: FP32 pair terms (eps_F ~ 1e-6) against the FP64 oracle
+    # (measured: about 3e-7, 4e-6, 8e-6 and 4e-7 after 60 mixed steps)
     tol_x, tol_v, tol_z, tol_e = ((1e-11, 1e-9, 1e-9, 1e-11) if precision == "fp64"
-                                  else (1e-4, 1e-2, 1e-3, 1e-5))
+                                  else (1e-5, 1e-4, 1e-4, 1e-5))
     for k in range(6):
         b.step(10)
         oracle.run(AU, md, st, 10, 0)
@@ -325,7 +326,8 @@ def test_equilibration_barostat_lockstep_with_oracle(precision):
     st = orc_state(b, 0)
     oracle.compute_forces(AU, st, 0)
     md = orc_md(b, 0)
-    tol_x, tol_v, tol_s = ((1e-11, 1e-9, 1e-10) if precision == "fp64" else (1e-4, 1e-2, 1e-3))
+    # (measured in mixed precision: about 6e-7, 4e-6 and 3e-5 after 60 steps)
+    tol_x, tol_v, tol_s = ((1e-11, 1e-9, 1e-10) if precision == "fp64" else (1e-5, 1e-4, 5e-4))
     for k in range(6):
         b.step(10)
         oracle.run(AU, md, st, 10, 0)
