@@ -398,6 +398,41 @@ class WireBatch:
     def status(self):
         return self.t["status"].cpu().numpy().view(np.uint32)
 
+    _DYNAMICS = {"gamma": float, "nh_tau": float, "grip_step": float, "grip_hold": int,
+                 "baro_mass": float, "baro_load": float, "baro_damp": float,
+                 "ramp_begin": int, "ramp_steps": int, "retire": float}
+
+    def set_dynamics(self, **kw):
+        """Changes dynamics settings between calls (the protocol's phases):
+        any of gamma, nh_tau, grip_step, grip_hold, baro_mass, baro_load,
+        baro_damp, ramp_begin, ramp_steps, retire.  The library checks the
+        combination at the next call."""
+        for k, v in kw.items():
+            if k not in self._DYNAMICS:
+                raise ValueError(f"not a dynamics setting: {k}")
+            v = self._DYNAMICS[k](v)
+            setattr(self.md, k, v)
+            setattr(self, k, v)
+            self._kw[k] = v
+
+    def rebase(self):
+        """Makes the current state the start of a new stretch: grip
+        references z0 = z, step index 0, initial lengths L0 grown by the
+        barostat's elongation 2 s (which is then zeroed), status, rupture
+        marks and records cleared.  Grips then rest where they are unless
+        the settings move them (v_pull is zeroed)."""
+        self.t["z0"].copy_(self.t["z"])
+        s = self.t["baro_s"].view(self.R, 2)
+        self.t["L0"].add_(2.0 * s[:, 0])
+        s.zero_()
+        self.t["v_pull"].zero_()
+        self.t["step"].zero_()
+        self.t["status"].zero_()
+        self.t["dfail"].fill_(-1.0)
+        self.t["obs"].zero_()
+        torch.cuda.synchronize(self.device)
+        self.L0 = self.t["L0"].cpu().numpy().copy()
+
     def compact(self, keep: Sequence[int] | None = None) -> "WireBatch | None":
         """A new batch of the replicas in `keep` (default: those not retired),
         in that order, or None when none is left.  Positions, velocities, grip
@@ -431,6 +466,8 @@ class WireBatch:
         nb.t["nh_xi"].copy_(self.t["nh_xi"][idx])
         nb.t["nh_eta"].copy_(self.t["nh_eta"][idx])
         nb.t["baro_s"].view(nb.R, 2).copy_(self.t["baro_s"].view(self.R, 2)[idx])
+        for k in ("T", "T_start", "v_pull", "L0"):  # may differ from the replicas'
+            nb.t[k].copy_(self.t[k][idx])
         ring = self.t["obs"].view(self.n_slots, self.R, A.NOBS)
         nb.t["obs"].view(nb.n_slots, nb.R, A.NOBS).copy_(ring[:, idx])
         nb.build_lists()

@@ -669,6 +669,32 @@ def test_compacted_batch_continues_the_kept_replicas_exactly():
     assert WireBatch.compact(c, []) is None
 
 
+def test_paper_protocol_runs_to_failure_and_reports_properties():
+    """Equilibration (barostat at 0.01 K), ramp and hold, then stepwise
+    elongation until every replica has failed and been retired (fast
+    settings: 0.05 A per grip every 20 steps); the curves and properties
+    come out per original replica."""
+    from paper_1311_3890_amd import protocol
+    reps = [R(15.0, 30.0, T=300.0, v=0.0, r=k) for k in range(3)]
+    note("paper protocol end to end, 3 x D1.5 L3 nm")
+    proto = protocol.Protocol(baro_steps=300, ramp_steps=300, hold_steps=200, baro_mass=300.0,
+                              baro_damp=5.0, grip_step=0.05, grip_hold=20, max_steps=20000,
+                              retire=1.0, n_log=20, steps_per_graph=20)
+    res = protocol.run(reps, proto, log=note)
+    for r in range(len(reps)):
+        eps, sig, st = res.recorder.curve(r)
+        p = res.properties[r]
+        note(f"  replica {r}: {eps.size} records, L0 {res.L0[r]:.2f} A, E {p['E']:.1f} GPa, "
+             f"sigma_y {p['sigma_y']:.2f} GPa at {p['eps_y']:.3f}, eps_f {p['eps_f']:.3f}")
+        assert st[-1] & A.ST_DONE and st[-1] & A.ST_RUPTURED
+        # strain grows by 2 grip steps per hold, measured from the equilibrated length
+        d = np.diff(eps)
+        step = 2 * 0.05 / res.L0[r]
+        assert np.all(np.isclose(d, 0.0, atol=1e-12) | np.isclose(d, step, rtol=1e-9))
+        assert p["E"] > 0 and p["sigma_y"] > 0 and 0 < p["eps_y"] < p["eps_f"]
+    assert len(res.recorder.ids) == 0  # all retired and compacted away
+
+
 def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1):
     worst = 0.0
     for r in reps_to_check:
