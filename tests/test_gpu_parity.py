@@ -695,14 +695,22 @@ def test_paper_protocol_runs_to_failure_and_reports_properties():
     assert len(res.recorder.ids) == 0  # all retired and compacted away
 
 
-def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1):
+def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1, etol=1e-6):
+    """eps_F of the sampled replicas, and the relative error of their
+    energies (per-atom e_i summed, and the record of the current step, which
+    must be a logged one) against the oracle at the GPU's positions."""
     worst = 0.0
+    rec = b.obs_at(b.step_index())
+    assert b.step_index() % b.n_log == 0
     for r in reps_to_check:
         x, y, z = b.positions(r)
         ref = oracle.forces(AU, x, y, z, mode)
         e = eps_F(stackF(b.forces(r)), stackF((ref["fx"], ref["fy"], ref["fz"])))
         worst = max(worst, e)
         assert e <= tol, r
+        E = float(np.sum(b.energies(r)))
+        assert abs(E - ref["E"]) <= etol * abs(ref["E"]), (r, E, ref["E"])
+        assert abs(rec[r][A.OBS_EPOT] - ref["E"]) <= etol * abs(ref["E"]), (r, rec[r], ref["E"])
     return worst
 
 
