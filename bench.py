@@ -174,7 +174,7 @@ def main():
         f"force with energies {t_force_e * 1e3:.1f} us")
 
     # ---- plain path: the same kind of replicas, one replica per launch ----------------
-    pr = None
+    pr = prg = None
     if not args.no_per_replica:
         idx = np.linspace(0, b.R - 1, min(args.per_replica, b.R)).round().astype(int)
         atoms_steps = 0.0
@@ -262,8 +262,15 @@ def main():
         t0 = time.perf_counter()
         oracle.run(pot, md, stt, k, 1)
         tc = time.perf_counter() - t0
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh
+                                  if ln.startswith("model name")), None)
+        except OSError:
+            pass
         cpu = {"value": x.size * k / tc, "unit": "atom-timesteps/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model,
                "sample": f"replica 0 of the workload ({x.size} atoms, D {rp.D / 10:.1f} nm x "
                          f"L {rp.L / 10:.2f} nm), {k} FP64 steps, cell-list mode, OpenMP"}
         log(f"[bench] oracle: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
@@ -359,6 +366,7 @@ def main():
                         "frac": (bytes_dens + bytes_force) / ((t_dens + t_force) * 1e-3) / 1e9
                         / HBM_PEAK_GBS}},
         "per_replica_value": pr,
+        "per_replica_graph_value": prg,
         "batched_over_per_replica": (value / pr) if pr else None,
         "bad_replicas": bad,
         "cpu_baseline": cpu,
