@@ -57,7 +57,30 @@ def build_wire_host(a: float, D: float, L: float, n_grip: int = 2, notch_layers:
 
 
 class WireBatch:
-    """R independent [100] Au nanowires advanced together on one GPU."""
+    """R independent [100] Au nanowires advanced together on one GPU.
+
+    replicas      objects with D, L (A), T (K), v_pull (A/ps), seed, rep_id,
+                  n_grip and jitter (workloads.Replica).
+    precision     "mixed" (FP32 pair terms, FP64 state and sums) or "fp64".
+    skin, cell    Verlet skin and cell edge (A; cell defaults to the smallest
+                  allowed, at least 8 A); k_cap: list capacity (grows on
+                  overflow at build_lists).
+    prune         half-width d of the pair lists' pruning (mixed; 0: off).
+    gamma         Langevin friction (1/ps); nh_tau > 0 selects Nose-Hoover
+                  instead (gamma must then be 0).
+    dt, n_log, n_slots  time step (ps), logging interval and record ring.
+    strain_max    strain the cell grids leave room for.
+    lab_frame     1: the Langevin O step acts on lab-frame velocities.
+    grip_step, grip_hold  stepwise symmetric grips (grip_hold > 0).
+    notch         (planes, depth in A) of the ring notch, or None.
+    T_start, ramp_begin, ramp_steps  temperature ramp (ramp_steps > 0).
+    baro_mass, baro_load, baro_damp  axial barostat on the grip separation
+                  (baro_mass > 0).
+    retire        grip travel (A) after the first rupture before a replica is
+                  retired (0: never).
+    qbits         position quantum 2^-qbits A (mixed; default from the grid).
+    The settings mean what include/tbsma.h says of tbsma_md and tbsma_params.
+    """
 
     def __init__(self, replicas: Sequence, precision: str = "mixed", *, skin: float = 1.0,
                  cell: float | None = None, k_cap: int = 176, gamma: float = 1.0, dt: float = 0.002,
