@@ -505,6 +505,26 @@ def test_checkpoint_resume_is_bitwise(tmp_path, kw):
         assert torch.equal(a.t[k], b.t[k]), k
 
 
+def test_barostat_runs_split_into_calls_repeat_bit_for_bit():
+    """Without Nose-Hoover every call boundary is invisible: the barostat's
+    grip force is re-formed at a call's start by the same sums the steps
+    form, so 100 steps in one call equal 60 + 40 in two (Langevin, graph
+    chunks of different lengths)."""
+    reps = _three_replicas()
+    note("barostat split calls, 100 steps mixed")
+    kw = dict(gamma=1.0, baro_mass=300.0, baro_damp=2.0, T_start=50.0, ramp_steps=80)
+    a = WireBatch(reps, "mixed", n_log=20, **kw)
+    a.prepare()
+    a.run_batch(100, 50)
+    b = WireBatch(reps, "mixed", n_log=20, qbits=a.qbits, **kw)
+    b.prepare()
+    b.run_batch(60, 20)
+    b.run_batch(40, 20)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "baro_s", "obs"):
+        assert torch.equal(a.t[k], b.t[k]), k
+    assert float(a.t["baro_s"].abs().max()) > 0
+
+
 def test_mixed_dynamics_track_fp64_oracle_forces():
     """Mixed precision over 200 steps at 298 K: the forces at the GPU's
     positions stay within eps_F <= 1e-5 of the oracle and lists get rebuilt."""
