@@ -194,8 +194,10 @@ typedef struct {
  * mixed pair passes read them: within each block of up to four tiles of one
  * replica, atoms by descending list length (ties by slot), the p-th atom's
  * list as row (block start + p) of the same chunked layout, pruned to the
- * pairs within r_cut + 2 prune (see tbsma_params).  Written by the list
- * build and by the pruning in the step loops; opaque to the caller.
+ * pairs within r_cut + 2 prune (see tbsma_params), each entry encoded as
+ * the byte offset 16 (j - lo) of neighbour j from the start lo of the
+ * block's slot window.  Written by the list build and by the pruning in the
+ * step loops; opaque to the caller (save and restore it as a whole).
  */
 typedef struct {
   int32_t *nl;
