@@ -645,3 +645,28 @@ def test_barostat_settles_at_the_load():
     for load, (q0, qm, _) in runs.items():
         assert abs(qm + 2 * load) < 0.1 * abs(q0), (load, q0, qm)
     assert runs[1.0][2] > runs[0.0][2] + 0.01
+
+
+def test_philox_matches_rocrand():
+    """The oracle's Philox4x32-10 words equal those of rocRAND's own
+    header-only generator (compiled here, run on the host) for the counters
+    (tag, lo32(step), rep_id, stream) the method uses."""
+    import ctypes as C
+    lib_path = os.path.join(os.path.dirname(__file__), "rocrand_ref", "librocrand_ref.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("the rocRAND reference is compiled by __graft_entry__.build()")
+    rr = C.CDLL(lib_path)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        seed = int(rng.integers(0, 2 ** 63))
+        rep, stream = int(rng.integers(0, 2 ** 32)), int(rng.integers(0, 3))
+        step = int(rng.integers(0, 2 ** 40))
+        n = 16
+        out = np.zeros(4 * n, np.uint32)
+        rr.rocrand_philox_words(C.c_uint64(seed), C.c_uint32(rep), C.c_uint64(step),
+                                C.c_uint32(stream), C.c_int64(n),
+                                out.ctypes.data_as(C.c_void_p))
+        for t in range(n):
+            w = oracle.philox4x32_10([t, step & 0xffffffff, rep, stream],
+                                     [seed & 0xffffffff, seed >> 32])
+            assert list(w) == list(out[4 * t:4 * t + 4]), (seed, rep, step, stream, t)
