@@ -594,6 +594,33 @@ def test_degenerate_systems():
                                 C.byref(b.out), b.work, None) == A.OK
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_atom_outside_its_grid_is_reported_and_kept_exact(precision):
+    """An atom moved 20 A beyond its replica's cell grid is binned into a
+    border cell (the lists stay exact) and raises TBSMA_ST_OUTSIDE for that
+    replica only; its neighbour replica evolves exactly as without it."""
+    reps = [R(15.0, 24.0, T=298.0, v=0.5, r=0), R(15.0, 24.0, T=298.0, v=0.5, r=1)]
+    note(f"atom outside the grid, {precision}")
+    a = WireBatch(reps, precision, n_log=10)
+    a.prepare()
+    o, k = int(a.rep_off[1]), int(a.n_atoms[1]) // 2  # a dynamic atom mid-wire
+    assert a.flags(1)[k] == 0
+    a.t["x"][o + k] = float(a.grid_lo[1][0]) - 20.0
+    a.build_lists()
+    a.compute_forces()
+    a.step(20)
+    st = a.status()
+    assert st[1] & A.ST_OUTSIDE and not st[0] & A.ST_OUTSIDE
+    assert not np.any(st & A.ST_NONFINITE)
+    fx, fy, fz = a.forces(1)
+    assert fx[k] == 0.0 and fy[k] == 0.0 and fz[k] == 0.0  # nobody within r_cut
+    b = WireBatch([reps[0]], precision, n_log=10, qbits=a.qbits)
+    b.prepare()
+    b.step(20)
+    for p_, q_ in zip(a.positions(0) + a.velocities(0), b.positions(0) + b.velocities(0)):
+        assert np.array_equal(p_, q_)
+
+
 def test_rupture_gap_and_nonfinite_status():
     reps = [R(15.0, 40.0, r=0), R(15.0, 40.0, r=1)]
     note("rupture gap + NaN status")
