@@ -85,3 +85,53 @@ def run(replicas: Sequence, proto: Protocol = Protocol(), precision: str = "mixe
     rec.run(proto.max_steps, spg, compact=proto.compact)
     props = rec.properties()
     return Result(rec, L0, props)
+
+
+def summary(result: Result) -> dict:
+    """Ensemble statistics of the properties (mean and standard deviation
+    over the replicas that failed), as in Table 3."""
+    out = {}
+    props = result.properties
+    failed = [p for p in props if np.isfinite(p["eps_f"])]
+    for k in ("E", "sigma_y", "eps_y", "eps_f", "eps_after_yield"):
+        v = np.array([p[k] for p in failed], dtype=float)
+        out[k] = {"mean": float(v.mean()) if v.size else float("nan"),
+                  "std": float(v.std(ddof=1)) if v.size > 1 else float("nan")}
+    out["replicas"] = len(props)
+    out["failed"] = len(failed)
+    return out
+
+
+def main(argv=None):
+    """Runs the protocol on an ensemble of identical wires with distinct
+    velocity seeds and prints the per-replica properties and their ensemble
+    statistics as one JSON object.  --fast shortens every phase (a
+    demonstration; the paper's protocol is the default)."""
+    import argparse
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--diameter", type=float, default=31.0, help="A")
+    ap.add_argument("--length", type=float, default=204.0, help="A")
+    ap.add_argument("--T", type=float, default=298.0, help="K")
+    ap.add_argument("--replicas", type=int, default=16)
+    ap.add_argument("--fast", action="store_true")
+    a = ap.parse_args(argv)
+    reps = [W.Replica(a.diameter, W.snap_length(a.length), a.T, 0.0, W.seed_of(r), r)
+            for r in range(a.replicas)]
+    proto = Protocol()
+    if a.fast:
+        proto = Protocol(baro_steps=2000, ramp_steps=4000, hold_steps=2000, grip_hold=200,
+                         max_steps=400000, retire=2.0, n_log=200)
+    log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    res = run(reps, proto, log=log)
+    print(json.dumps({"protocol": proto.__dict__, "L0": res.L0.tolist(),
+                      "properties": res.properties, "summary": summary(res)},
+                     default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -112,3 +112,14 @@ def test_recorder_compaction_keeps_records_by_original_index():
         e, _, s = rec.curve(r)
         assert np.array_equal(e, np.arange(5, end + 1, 5) / 1000.0 + r / 10.0)
         assert s[-1] & A.ST_DONE
+
+
+def test_protocol_summary_over_failed_replicas():
+    from paper_1311_3890_amd import protocol as P
+    props = [dict(E=80.0, sigma_y=4.0, eps_y=0.05, eps_f=0.30, eps_after_yield=0.25),
+             dict(E=90.0, sigma_y=5.0, eps_y=0.07, eps_f=0.40, eps_after_yield=0.33),
+             dict(E=99.0, sigma_y=9.0, eps_y=0.09, eps_f=math.nan, eps_after_yield=math.nan)]
+    s = P.summary(P.Result(None, np.zeros(3), props))
+    assert s["replicas"] == 3 and s["failed"] == 2
+    assert abs(s["E"]["mean"] - 85.0) < 1e-12 and abs(s["E"]["std"] - math.sqrt(50.0)) < 1e-12
+    assert abs(s["eps_f"]["mean"] - 0.35) < 1e-12
