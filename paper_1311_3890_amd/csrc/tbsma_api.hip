@@ -116,7 +116,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
       bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
-      total;
+      wl, total;
 };
 
 // Blocks of the cell sort: ceil(cells/64) per replica.
@@ -181,6 +181,8 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * 5 * (size_t)R);
   L.baw = o;
   o += up(8 * 2 * (size_t)R);
+  L.wl = o;  // two counts, the tiles, the list-build blocks
+  o += up(4 * (size_t)(2 + nt + nt / 4 + R + 1));
 
   L.total = o;
   return L;
@@ -230,6 +232,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
   d.nhw = reinterpret_cast<double *>(w + L.nhw);
   d.baw = reinterpret_cast<double *>(w + L.baw);
+  d.wl = reinterpret_cast<int32_t *>(w + L.wl);
 
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
@@ -462,7 +465,6 @@ void enqueue_step(const tbsma_params *p, const Dev &d0, const DevMD &M0,
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
   launch_cells(d, s);
   launch_nlist(d, mixed, rl, s);
-  if (mixed) launch_prune(d, s);
   Dev df = d;
   df.energies = -1;
   df.step = M.step;

@@ -81,6 +81,10 @@ struct Dev {
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
+  int32_t *wl;                  // work lists of a step (mixed precision):
+                                // [0] tiles to rebuild, [1] blocks to prune,
+                                // the tiles from wl + 2, the blocks (bmap
+                                // entries) from wl + 2 + N/64
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
   // n_log == 0, the step loops)

@@ -5,6 +5,8 @@
 // One thread per atom slot; a wavefront (64 lanes) is one tile of slots and
 // never straddles two replicas, so per-replica sums are exact per wave and
 // need no atomics.  Kernels over slots use 256-thread blocks.
+#include <algorithm>
+
 #include "tbsma_device.hpp"
 #include "tbsma_kernels.hpp"
 
@@ -265,28 +267,30 @@ __device__ __forceinline__ int32_t list_entry(int j, int lo) {
   return (int32_t)((uint32_t)(j - lo) << 4);
 }
 
-// Per-lane ring of 16 list entries in LDS, interleaved over the lanes of the
-// block (entry e of lane l at e * kBlock + l, so a wavefront's appends hit
-// distinct banks).  Lanes append at their own pace; at every 8th step of a
-// wave-uniform loop, each lane holding a full chunk writes it to its list as
-// one 32-byte store, so at most 7 + 8 entries are ever pending.  Entries
-// past the row's capacity (nch chunks) are counted but not stored.
-struct Ring {
+// Per-lane ring of 16 list entries in LDS, interleaved over the STRIDE
+// threads of the block (entry e of lane l at e * STRIDE + l, so a
+// wavefront's appends hit distinct banks).  Lanes append at their own pace;
+// at every 8th step of a wave-uniform loop, each lane holding a full chunk
+// writes it to its list as one 32-byte store, so at most 7 + 8 entries are
+// ever pending.  Entries past the row's capacity (nch chunks) are counted
+// but not stored.
+template <int STRIDE>
+struct RingT {
   int32_t *lds;  // this lane's first entry
   int cnt;       // entries appended
   int head;      // entries passed on to the list (a multiple of 8)
   __device__ __forceinline__ void push(int j) {
-    lds[(cnt & 15) * kBlock] = j;
+    lds[(cnt & 15) * STRIDE] = j;
     ++cnt;
   }
   __device__ __forceinline__ void store_chunk(int32_t *list, int64_t N,
                                               int64_t i, int nch) {
     if ((head >> 3) < nch) {
-      const int32_t *e = lds + (head & 15) * kBlock;
+      const int32_t *e = lds + (head & 15) * STRIDE;
       int4 *dst = reinterpret_cast<int4 *>(list + cl8(N, i, head >> 3));
-      dst[0] = make_int4(e[0], e[kBlock], e[2 * kBlock], e[3 * kBlock]);
-      dst[1] = make_int4(e[4 * kBlock], e[5 * kBlock], e[6 * kBlock],
-                         e[7 * kBlock]);
+      dst[0] = make_int4(e[0], e[STRIDE], e[2 * STRIDE], e[3 * STRIDE]);
+      dst[1] = make_int4(e[4 * STRIDE], e[5 * STRIDE], e[6 * STRIDE],
+                         e[7 * STRIDE]);
     }
     head += 8;
   }
@@ -298,11 +302,12 @@ struct Ring {
   __device__ __forceinline__ void finish(int32_t *list, int64_t N, int64_t i,
                                          int nch, int32_t pad = kPadEntry) {
     while (cnt > head) {
-      for (int e = cnt; e < head + 8; ++e) lds[(e & 15) * kBlock] = pad;
+      for (int e = cnt; e < head + 8; ++e) lds[(e & 15) * STRIDE] = pad;
       store_chunk(list, N, i, nch);
     }
   }
 };
+using Ring = RingT<kBlock>;
 
 __device__ __forceinline__ bool wave_any(bool p) {
   return __ballot(p) != 0ull;
@@ -403,8 +408,9 @@ __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
 // r_cut, where every pair term is exactly zero.
 constexpr int kCand = 1536;  // window candidates staged per block (24 KB)
 
-struct ListRow {
-  Ring ring;
+template <int STRIDE>
+struct ListRowT {
+  RingT<STRIDE> ring;
   int32_t wlo, whi;  // slot window of the row
   __device__ __forceinline__ void add(int32_t j) {
     ring.push(j);
@@ -413,11 +419,11 @@ struct ListRow {
   }
 };
 
-template <bool MIXED>
+template <bool MIXED, class Row>
 __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
                                             bool real, int cx, int cy, int cz,
                                             int4 qi, double rl2, float rl2q,
-                                            int nch, ListRow &row) {
+                                            int nch, Row &row) {
   const int64_t N = S.N;
   const int32_t *gd = S.grid_dim + 3 * r;
   const int32_t *start = S.cell_start + S.cell_off[r] + r;
@@ -466,18 +472,21 @@ __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
 
 // Tests this lane's atom (FP32 offset pi from the block origin) against
 // window candidates [a, b) of cand (x, y, z offsets and the slot as bits;
-// a and b uniform over the wavefront).  Candidates are read in groups of 8;
-// cand holds 8 filler entries past the window so the last group stays in
-// bounds, and entries at b or beyond are never taken.
-__device__ __forceinline__ void nlist_window(const Dev &S, int64_t i,
-                                             bool real, float4 pi,
-                                             const float4 *cand, int a, int b,
-                                             float rl2q, int nch,
-                                             ListRow &row) {
+// a and b uniform over the wavefront) and calls near(j) for each candidate
+// j within the list radius, in candidate order.  Candidates are read in
+// groups of 8, and this wavefront takes groups q, q + nq, q + 2 nq, ... of
+// the range (nq wavefronts share the scan of one tile).  cand holds 8
+// filler entries past the window so the last group stays in bounds, and
+// entries at b or beyond are never taken.
+template <class F>
+__device__ __forceinline__ void window_scan(int64_t i, bool real, float4 pi,
+                                            const float4 *cand, int a, int b,
+                                            float rl2q, int q, int nq,
+                                            F &&near) {
   const int32_t self = real ? (int32_t)i : -2;
   a = __builtin_amdgcn_readfirstlane(a);
   b = __builtin_amdgcn_readfirstlane(b);
-  for (int t0 = a; t0 < b; t0 += 8) {
+  for (int t0 = a + 8 * q; t0 < b; t0 += 8 * nq) {
     float4 c[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) c[e] = cand[t0 + e];
@@ -487,140 +496,54 @@ __device__ __forceinline__ void nlist_window(const Dev &S, int64_t i,
       const float dy = c[e].y - pi.y;
       const float dz = c[e].z - pi.z;
       const int32_t j = __float_as_int(c[e].w);
-      const bool near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q &&
-                        j != self && t0 + e < b && real;
-      if (near) row.add(j);
+      if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q && j != self &&
+          t0 + e < b && real)
+        near(j);
     }
-    row.ring.flush(S.nl, S.N, i, nch);
   }
 }
 
-// Copies atom i's list (nl, by atom, n entries) to row `row` of nl_lane as
-// offsets from the block's window start lo (pad: the block's pad value),
-// keeping the pairs whose current quantised distance is below the pruning
-// radius (all of them when pruning is off); returns the number kept.  Each
-// lane works on its own row through its ring.
-template <class Fetch>
-__device__ __forceinline__ int prune_row(const Dev &S, int64_t i, int64_t row,
-                                         int n, int32_t *ring_lane, int lo,
-                                         int32_t pad, Fetch &&fetch) {
-  Ring ring{ring_lane, 0, 0};
-  const int4 qi = S.qpos[i];
-  const int nch = S.k_cap >> 3;
-  const float rp2 = S.prune_r2q;
-  for (int c = 0; c < (n + 7) >> 3; ++c) {
-    const int4 *src = reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c));
-    const int4 a = src[0], b = src[1];
-    const int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    int4 q[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = fetch(c * 8 + e < n ? j[e] : (int)i);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float dx = (float)(q[e].x - qi.x);
-      const float dy = (float)(q[e].y - qi.y);
-      const float dz = (float)(q[e].z - qi.z);
-      if (c * 8 + e < n && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
-        ring.push(list_entry(j[e], lo));
-    }
-    ring.flush(S.nl_lane, S.N, row, nch);
-  }
-  ring.finish(S.nl_lane, S.N, row, nch, pad);
-  return ring.cnt;
+// Lane order of the pair passes: the block's atoms by descending list
+// length, ties by slot (keys are distinct).  key[t] is set by every thread
+// t < kBlock; returns this thread's rank among the block's nt tiles.
+__device__ __forceinline__ int lane_rank(const int32_t *key, int t, int nt) {
+  const int32_t k = key[t];
+  int rank = 0;
+  for (int m = 0; m < nt * kTile; ++m) rank += key[m] < k ? 1 : 0;
+  return rank;
+}
+__device__ __forceinline__ int32_t lane_key(int nn_i, int t) {
+  return nn_i < 0 ? 0x7fffffff : ((255 - min(nn_i, 255)) << 8) | t;
 }
 
-template <bool MIXED>
-__global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
-                                                  float rl2q) {
+// FP64 list build: one lane per atom, the 27-cell walk with FP64 distances.
+__global__ void __launch_bounds__(kBlock) k_nlist_fp64(Dev S, double rl2) {
   __shared__ int32_t ring_lds[16 * kBlock];
-  __shared__ float4 cand[MIXED ? kCand + 8 : 1];
-  __shared__ int wzlo[kBlock / kTile], wzhi[kBlock / kTile];
   __shared__ int32_t key[kBlock];
-  __shared__ int2 twin[kBlock / kTile];
   const int tid = threadIdx.x, w = tid / kTile;
   const int2 bm = S.bmap[blockIdx.x];  // first tile, tiles (1..4)
   const int r = S.tile_rep[bm.x];
   if (!rebuilds(S, r)) return;  // uniform over the block
   const bool valid = w < bm.y;
   const int64_t i = ((int64_t)bm.x + w) * kTile + (tid & (kTile - 1));
-  bool real = false;
-  int cx = 0, cy = 0, cz = 0;
-  int4 qi = make_int4(0, 0, 0, 0);
-  const int32_t *gd = S.grid_dim + 3 * r;
-  if (valid) {
-    real = S.flag[i] != 3;
-    const double *lo = S.grid_lo + 3 * r;
-    bool out = false;
-    cx = cell_coord(S.x[i], lo[0], S.inv_cell, gd[0], out);
-    cy = cell_coord(S.y[i], lo[1], S.inv_cell, gd[1], out);
-    cz = cell_coord(S.z[i], lo[2], S.inv_cell, gd[2], out);
-    if (MIXED) qi = S.qpos[i];
-  }
-  // z-cell range of the wavefront's real atoms (empty: lo > hi)
-  const int zlo = -wave_max_i(real ? -cz : -0x7fffffff);
-  const int zhi = wave_max_i(real ? cz : -1);
-  bool window = false;
-  int a = 0, b = 0;
-  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (MIXED) {
-    if ((tid & (kTile - 1)) == 0) {
-      wzlo[w] = zlo;
-      wzhi[w] = zhi;
-    }
-    __syncthreads();
-    int bzlo = 0x7fffffff, bzhi = -1;
-#pragma unroll
-    for (int t = 0; t < kBlock / kTile; ++t) {
-      bzlo = min(bzlo, wzlo[t]);
-      bzhi = max(bzhi, wzhi[t]);
-    }
-    if (bzlo <= bzhi) {
-      const int gxy = gd[0] * gd[1];
-      const int32_t *start = S.cell_start + S.cell_off[r] + r;
-      const int32_t s0 = start[max(bzlo - 1, 0) * gxy];
-      const int32_t s1 = start[(min(bzhi + 1, gd[2] - 1) + 1) * gxy];
-      const int m = s1 - s0;
-      window = m <= kCand;
-      if (window) {
-        const int4 o = S.qpos[(int64_t)bm.x * kTile];
-        for (int t = tid; t < m + 8; t += kBlock) {
-          float4 c = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-          if (t < m) {
-            const int32_t j = S.cell_atoms[s0 + t];
-            const int4 q = S.qpos[j];
-            c = make_float4((float)(q.x - o.x), (float)(q.y - o.y),
-                            (float)(q.z - o.z), __int_as_float(j));
-          }
-          cand[t] = c;
-        }
-        pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
-                         (float)(qi.z - o.z), 0.f);
-        __syncthreads();
-        if (zlo <= zhi) {
-          a = start[max(zlo - 1, 0) * gxy] - s0;
-          b = start[(min(zhi + 1, gd[2] - 1) + 1) * gxy] - s0;
-        }
-      }
-    }
-  }
   int nn_i = -1;  // list length of this thread's atom (-1: no atom)
   if (valid) {
+    const bool real = S.flag[i] != 3;
+    const int32_t *gd = S.grid_dim + 3 * r;
+    const double *lo = S.grid_lo + 3 * r;
+    bool out = false;
+    const int cx = cell_coord(S.x[i], lo[0], S.inv_cell, gd[0], out);
+    const int cy = cell_coord(S.y[i], lo[1], S.inv_cell, gd[1], out);
+    const int cz = cell_coord(S.z[i], lo[2], S.inv_cell, gd[2], out);
     const int64_t N = S.N;
     const int nch = S.k_cap >> 3;
-    ListRow row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
-    if (window)
-      nlist_window(S, i, real, pi, cand, a, b, rl2q, nch, row);
-    else
-      nlist_cells<MIXED>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
+    ListRowT<kBlock> row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
+    nlist_cells<false>(S, i, r, real, cx, cy, cz, make_int4(0, 0, 0, 0), rl2,
+                       0.0f, nch, row);
     row.ring.finish(S.nl, N, i, nch);
-    // window of the tile's rows, [lo, hi): read by the pair passes to stage
-    // neighbour positions in LDS
     const int32_t wlo = -wave_max_i(-row.wlo);
     const int32_t whi = wave_max_i(row.whi);
-    if ((tid & 63) == 0) {
-      S.win[i / kTile] = make_int2(wlo, whi + 1);
-      twin[w] = make_int2(wlo, whi + 1);
-    }
+    if ((tid & 63) == 0) S.win[i / kTile] = make_int2(wlo, whi + 1);
     const int total = row.ring.cnt;
     if (total > S.k_cap) {
       atomicMax(S.nnmax, total);
@@ -632,31 +555,220 @@ __global__ void __launch_bounds__(kBlock) k_nlist(Dev S, double rl2,
     S.yr[i] = S.y[i];
     S.zr[i] = S.z[i];
   }
-  // lane order of the pair passes: the block's atoms by descending list
-  // length, ties by slot (keys are distinct)
-  key[tid] = nn_i < 0 ? 0x7fffffff : ((255 - min(nn_i, 255)) << 8) | tid;
+  key[tid] = lane_key(nn_i, tid);
   __syncthreads();
   if (valid) {
-    const int32_t k = key[tid];
-    int rank = 0;
-    for (int m = 0; m < bm.y * kTile; ++m) rank += key[m] < k ? 1 : 0;
-    const int64_t row = (int64_t)bm.x * kTile + rank;
-    S.lane_atom[row] = (uint8_t)tid;
+    const int rank = lane_rank(key, tid, bm.y);
+    S.lane_atom[(int64_t)bm.x * kTile + rank] = (uint8_t)tid;
     S.atom_lane[i] = (uint8_t)rank;
-    // the row again at the lane position, pruned (mixed precision; its
-    // chunks were just written by this thread)
-    if (S.nl_lane) {
-      // the block's window, as the pair passes will compute it from win
-      int blo = 0x7fffffff, bhi = 0;
-      for (int t = 0; t < bm.y; ++t) {
-        blo = min(blo, twin[t].x);
-        bhi = max(bhi, twin[t].y);
-      }
-      S.nn_lane[row] = prune_row(S, i, row, nn_i, ring_lds + tid, blo,
-                                 pad_of_window(bhi - blo),
-                                 [&](int j) { return S.qpos[j]; });
-      S.qprune[i] = S.qpos[i];
+  }
+}
+
+// Work lists of a step (mixed precision), so that the list build and the
+// pruning launch a fixed, small grid whatever the number of replicas that
+// rebuild or prune: the tiles of the replicas whose lists are rebuilt, and
+// the list-build blocks (block-map entries) of the replicas whose
+// lane-ordered lists are rebuilt or pruned, replicas in order.  wl[0] and
+// wl[1] hold the two counts; the tiles follow from wl + 2 and the blocks
+// from wl + 2 + N/64.  One block of 1024 threads; a scan over the replicas.
+__global__ void __launch_bounds__(1024) k_worklist(Dev S) {
+  __shared__ int32_t wsum[3][16];
+  __shared__ int32_t carry[3];
+  __shared__ int4 info[1024];  // first tile, tiles listed, first block, blocks listed
+  __shared__ int2 off[1024];   // offsets in the tile and block lists
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int32_t *tiles = S.wl + 2;
+  int32_t *blocks = S.wl + 2 + S.N / kTile;
+  if (tid < 3) carry[tid] = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < S.R; b0 += 1024) {
+    const int r = b0 + tid;
+    int32_t t0 = 0, nt = 0;
+    bool reb = false, upd = false;
+    if (r < S.R) {
+      t0 = (int32_t)(S.rep_off[r] / kTile);
+      nt = (int32_t)(S.rep_off[r + 1] / kTile) - t0;
+      reb = rebuilds(S, r);
+      upd = reb || prunes(S, r);
     }
+    const int32_t nb = (nt + 3) >> 2;  // its blocks in the block map
+    const int32_t v[3] = {reb ? nt : 0, upd ? nb : 0, nb};
+    int32_t sc[3], ex[3], tot[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int32_t x = v[k];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+      }
+      sc[k] = x;
+      if (lane == 63) wsum[k][wid] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int32_t woff = 0, t = 0;
+      for (int m = 0; m < 16; ++m) {
+        if (m < wid) woff += wsum[k][m];
+        t += wsum[k][m];
+      }
+      ex[k] = carry[k] + woff + sc[k] - v[k];
+      tot[k] = t;
+    }
+    info[tid] = make_int4(t0, v[0], ex[2], v[1]);
+    off[tid] = make_int2(ex[0], ex[1]);
+    __syncthreads();
+    // each wavefront writes the entries of every 16th replica of the chunk
+    const int nr = min(1024, S.R - b0);
+    for (int k = wid; k < nr; k += 16) {
+      const int4 f = info[k];
+      const int2 o = off[k];
+      for (int x = lane; x < f.y; x += 64) tiles[o.x + x] = f.x + x;
+      for (int x = lane; x < f.w; x += 64) blocks[o.y + x] = f.z + x;
+    }
+    __syncthreads();
+    if (tid < 3) carry[tid] += tot[tid];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    S.wl[0] = carry[0];
+    S.wl[1] = carry[1];
+  }
+}
+
+// Mixed-precision list build, one tile per block and work item (the tiles
+// of the work list).  The block's kNlWaves wavefronts share the scan of
+// the tile's candidates, the cell-sorted atoms of the z-slabs around its
+// atoms: wavefront q takes every kNlWaves-th group of 8.  So the rebuild of
+// a single replica, which would leave most of the GPU idle, spreads over
+// every compute unit and is not bound by one wavefront's walk over the
+// ~1000 candidates.  The scan runs twice: the first pass counts each
+// share's pairs, the second writes them at their final entries, share q
+// after shares 0..q-1.  A row is thus the pairs in candidate order within
+// each share, shares in order, whatever the timing.  When the slabs exceed
+// LDS, wavefront 0 walks the 27 cells around each atom alone.  The
+// lane-ordered, pruned rows are made by the pruning kernel.
+constexpr int kNlWaves = kBlock / kTile;
+
+__global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
+                                                        float rl2q) {
+  __shared__ int32_t ring_lds[16 * kTile];
+  __shared__ float4 cand[kCand + 8];
+  __shared__ int32_t qcnt[kNlWaves][kTile];
+  __shared__ int2 qwin[kNlWaves];
+  const int tid = threadIdx.x;
+  const int q = tid / kTile;  // share of the candidate scan
+  const int lane = tid & (kTile - 1);
+  const int ntl = S.wl[0];
+  const int32_t *tiles = S.wl + 2;
+  const int64_t N = S.N;
+  const int nch = S.k_cap >> 3;
+  for (int it = blockIdx.x; it < ntl; it += gridDim.x) {  // uniform
+    const int tile = tiles[it];
+    const int r = S.tile_rep[tile];
+    const int64_t i = (int64_t)tile * kTile + lane;
+    const bool real = S.flag[i] != 3;
+    const int32_t *gd = S.grid_dim + 3 * r;
+    const double *lo = S.grid_lo + 3 * r;
+    bool out = false;
+    const int cx = cell_coord(S.x[i], lo[0], S.inv_cell, gd[0], out);
+    const int cy = cell_coord(S.y[i], lo[1], S.inv_cell, gd[1], out);
+    const int cz = cell_coord(S.z[i], lo[2], S.inv_cell, gd[2], out);
+    const int4 qi = S.qpos[i];
+    // z-cell range of the tile's real atoms (empty: lo > hi); the same in
+    // every wavefront of the block
+    const int zlo = -wave_max_i(real ? -cz : -0x7fffffff);
+    const int zhi = wave_max_i(real ? cz : -1);
+    bool window = false;  // uniform over the block
+    int m = 0;
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (zlo <= zhi) {
+      const int gxy = gd[0] * gd[1];
+      const int32_t *start = S.cell_start + S.cell_off[r] + r;
+      const int32_t s0 = start[max(zlo - 1, 0) * gxy];
+      const int32_t s1 = start[(min(zhi + 1, gd[2] - 1) + 1) * gxy];
+      m = s1 - s0;
+      window = m <= kCand;
+      if (window) {
+        const int4 o = S.qpos[(int64_t)tile * kTile];
+        for (int t = tid; t < m + 8; t += kBlock) {
+          float4 c = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+          if (t < m) {
+            const int32_t j = S.cell_atoms[s0 + t];
+            const int4 qj = S.qpos[j];
+            c = make_float4((float)(qj.x - o.x), (float)(qj.y - o.y),
+                            (float)(qj.z - o.z), __int_as_float(j));
+          }
+          cand[t] = c;
+        }
+        pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
+                         (float)(qi.z - o.z), 0.f);
+      }
+    }
+    __syncthreads();
+    int cnt = 0;
+    int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
+    if (window) {
+      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, [&](int32_t j) {
+        ++cnt;
+        wlo = min(wlo, j);
+        whi = max(whi, j);
+      });
+    } else if (q == 0) {
+      ListRowT<kTile> row{RingT<kTile>{ring_lds + lane, 0, 0}, (int32_t)i,
+                          (int32_t)i};
+      nlist_cells<true>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
+      row.ring.finish(S.nl, N, i, nch);
+      cnt = row.ring.cnt;
+      wlo = row.wlo;
+      whi = row.whi;
+    }
+    qcnt[q][lane] = cnt;
+    const int32_t wl = -wave_max_i(-wlo);
+    const int32_t wh = wave_max_i(whi);
+    if (lane == 0) qwin[q] = make_int2(wl, wh);
+    __syncthreads();
+    int total = 0, before = 0;  // entries of all shares, of shares 0..q-1
+#pragma unroll
+    for (int k = 0; k < kNlWaves; ++k) {
+      const int c = qcnt[k][lane];
+      before += k < q ? c : 0;
+      total += c;
+    }
+    if (window) {
+      int e = before;
+      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, [&](int32_t j) {
+        if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
+        ++e;
+      });
+      // the unused entries of the row's last chunk
+      if (q == kNlWaves - 1 && total < S.k_cap)
+        for (int f = total; f < ((total + 7) & ~7); ++f)
+          S.nl[cl8(N, i, f >> 3) + (f & 7)] = kPadEntry;
+    }
+    if (q == 0) {
+      if (total > S.k_cap) {
+        atomicMax(S.nnmax, total);
+        atomicOr(&S.wstatus[r], 1u);
+      }
+      S.nn[i] = real ? min(total, S.k_cap) : 0;
+      S.xr[i] = S.x[i];
+      S.yr[i] = S.y[i];
+      S.zr[i] = S.z[i];
+    }
+    // slot window [lo, hi) of the tile's rows: read by the pair passes to
+    // stage neighbour positions in LDS
+    if (tid == 0) {
+      int2 tw = qwin[0];
+#pragma unroll
+      for (int k = 1; k < kNlWaves; ++k) {
+        tw.x = min(tw.x, qwin[k].x);
+        tw.y = max(tw.y, qwin[k].y);
+      }
+      S.win[tile] = make_int2(tw.x, tw.y + 1);
+    }
+    __syncthreads();  // cand, qcnt and qwin serve the next tile
   }
 }
 
@@ -824,84 +936,113 @@ struct ListDecode {
   }
 };
 
-// Pruning of the lane-ordered lists of the replicas in which some atom has
-// moved more than the pruning half-width since their lists were last pruned
-// (and that are not rebuilt this step, which prunes too).  Lanes take the
-// block's atoms in slot order, so the full rows are read coalesced; each
-// lane writes its kept entries to its atom's lane-ordered row.  Positions
-// come from LDS as in the pair passes when the block's window fits.
+// Lane-ordered, pruned rows (nl_lane) of the list-build blocks of the work
+// list: blocks of replicas whose lists were just rebuilt, which first take
+// their lane order from the new list lengths, and of replicas in which some
+// atom has moved more than the pruning half-width since their lists were
+// last pruned.  Lanes take the block's atoms in slot order, so the full
+// rows are read coalesced; each lane writes its kept entries to its atom's
+// lane-ordered row.  Positions come from LDS as in the pair passes when the
+// block's window fits.
 __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
   __shared__ int32_t ring_lds[16 * kBlock];
   __shared__ int4 lq[kStage + 1];
-  const PairBlock B = pair_block(S);
-  const int r = S.tile_rep[B.t0];
-  if (rebuilds(S, r) || !prunes(S, r)) return;  // uniform over the block
-  int lo, size;
-  block_window(S, B, lo, size);
-  const bool staged = size > 0 && size <= kStage && stage(S, lq, B, lo, size);
-  const int64_t i = B.b0 + B.p;
-  const int n = B.valid ? S.nn[i] : 0;
-  const int64_t row = B.b0 + (B.valid ? (int)S.atom_lane[i] : 0);
-  const int4 qi = B.valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
-  const float rp2 = S.prune_r2q;
-  const int nch = S.k_cap >> 3;
-  const int base = size > 0 ? lo : 0;  // entries are offsets from base
-  Ring ring{ring_lds + threadIdx.x, 0, 0};
-  auto keep = [&](const int4 &q, int j, bool in) {
-    const float dx = (float)(q.x - qi.x);
-    const float dy = (float)(q.y - qi.y);
-    const float dz = (float)(q.z - qi.z);
-    if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
-      ring.push(list_entry(j, base));
-  };
-  if (staged) {
-    // the row in batches of kPruneBatch chunks, all loaded before any is
-    // used: the stores of the ring's flushes then overlap the positions'
-    // LDS reads instead of delaying the next list loads (loads and stores
-    // retire in order)
-    constexpr int kPruneBatch = 7;
-    const StagedIndex sx(lo);
-    const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
-    const int own = (n + 7) >> 3;
-    const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
-    for (int c0 = 0; c0 < (nmax + 7) >> 3; c0 += kPruneBatch) {
-      int4 buf[2 * kPruneBatch];
-#pragma unroll
-      for (int k = 0; k < kPruneBatch; ++k) {
-        const int4 *src =
-            c0 + k < own
-                ? reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c0 + k))
-                : pad;
-        buf[2 * k] = src[0];
-        buf[2 * k + 1] = src[1];
-      }
-#pragma unroll
-      for (int k = 0; k < kPruneBatch; ++k) {
-        const int j[8] = {buf[2 * k].x,     buf[2 * k].y,     buf[2 * k].z,
-                          buf[2 * k].w,     buf[2 * k + 1].x, buf[2 * k + 1].y,
-                          buf[2 * k + 1].z, buf[2 * k + 1].w};
-        int4 q[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) keep(q[e], j[e], j[e] != kPadEntry);
-        ring.flush(S.nl_lane, S.N, row, nch);
+  __shared__ int32_t key[kBlock];
+  const int nbl = S.wl[1];
+  const int32_t *blocks = S.wl + 2 + S.N / kTile;
+  for (int it = blockIdx.x; it < nbl; it += gridDim.x) {  // uniform
+    const int2 bm = S.bmap[blocks[it]];
+    PairBlock B;
+    B.t0 = bm.x;
+    B.nt = bm.y;
+    B.b0 = (int64_t)bm.x * kTile;
+    B.p = threadIdx.x;
+    B.valid = B.p < bm.y * kTile;
+    B.i = B.b0 + B.p;
+    B.n = 0;
+    const bool rebuilt = rebuilds(S, S.tile_rep[B.t0]);  // uniform
+    int lo, size;
+    block_window(S, B, lo, size);
+    const bool staged =
+        size > 0 && size <= kStage && stage(S, lq, B, lo, size);
+    const int64_t i = B.b0 + B.p;
+    const int n = B.valid ? S.nn[i] : 0;
+    int64_t row = B.b0 + (B.valid ? (int)S.atom_lane[i] : 0);
+    if (rebuilt) {
+      // lane order of the pair passes: the block's atoms by descending list
+      // length, ties by slot
+      key[B.p] = lane_key(B.valid ? n : -1, B.p);
+      __syncthreads();
+      if (B.valid) {
+        const int rank = lane_rank(key, B.p, B.nt);
+        row = B.b0 + rank;
+        S.lane_atom[row] = (uint8_t)B.p;
+        S.atom_lane[i] = (uint8_t)rank;
       }
     }
-  } else {
-    chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
-      int4 q[8];
+    const int4 qi = B.valid ? S.qpos[i] : make_int4(0, 0, 0, 0);
+    const float rp2 = S.prune_r2q;
+    const int nch = S.k_cap >> 3;
+    const int base = size > 0 ? lo : 0;  // entries are offsets from base
+    Ring ring{ring_lds + threadIdx.x, 0, 0};
+    auto keep = [&](const int4 &q, int j, bool in) {
+      const float dx = (float)(q.x - qi.x);
+      const float dy = (float)(q.y - qi.y);
+      const float dz = (float)(q.z - qi.z);
+      if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
+        ring.push(list_entry(j, base));
+    };
+    if (staged) {
+      // the row in batches of kPruneBatch chunks, all loaded before any is
+      // used: the stores of the ring's flushes then overlap the positions'
+      // LDS reads instead of delaying the next list loads (loads and stores
+      // retire in order)
+      constexpr int kPruneBatch = 7;
+      const StagedIndex sx(lo);
+      const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
+      const int own = (n + 7) >> 3;
+      const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
+      for (int c0 = 0; c0 < (nmax + 7) >> 3; c0 += kPruneBatch) {
+        int4 buf[2 * kPruneBatch];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
+        for (int k = 0; k < kPruneBatch; ++k) {
+          const int4 *src =
+              c0 + k < own
+                  ? reinterpret_cast<const int4 *>(S.nl + cl8(S.N, i, c0 + k))
+                  : pad;
+          buf[2 * k] = src[0];
+          buf[2 * k + 1] = src[1];
+        }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) keep(q[e], j[e], k0 + e < n);
-      ring.flush(S.nl_lane, S.N, row, nch);
-    });
+        for (int k = 0; k < kPruneBatch; ++k) {
+          const int j[8] = {buf[2 * k].x,     buf[2 * k].y,     buf[2 * k].z,
+                            buf[2 * k].w,     buf[2 * k + 1].x, buf[2 * k + 1].y,
+                            buf[2 * k + 1].z, buf[2 * k + 1].w};
+          int4 q[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) keep(q[e], j[e], j[e] != kPadEntry);
+          ring.flush(S.nl_lane, S.N, row, nch);
+        }
+      }
+    } else {
+      chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
+        int4 q[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) keep(q[e], j[e], k0 + e < n);
+        ring.flush(S.nl_lane, S.N, row, nch);
+      });
+    }
+    if (B.valid) {
+      ring.finish(S.nl_lane, S.N, row, nch, pad_of_window(size));
+      S.nn_lane[row] = ring.cnt;
+      S.qprune[i] = qi;
+    }
+    __syncthreads();  // lq and key serve the next block
   }
-  if (!B.valid) return;
-  ring.finish(S.nl_lane, S.N, row, nch, pad_of_window(size));
-  S.nn_lane[row] = ring.cnt;
-  S.qprune[i] = qi;
 }
 
 // One lane per atom: rho_i over the Verlet list, g_i = 1/sqrt(rho_i) into
@@ -1888,13 +2029,24 @@ void launch_cells(const Dev &S, hipStream_t s) {
   if (S.ncbmap > 0) k_cell_sort<<<S.ncbmap, kBlock, 0, s>>>(S);
 }
 
+// Grid of the kernels that loop over a work list (list build, pruning).
+constexpr int64_t kWorkGrid = 2048;
+
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
   const double rq = rl * S.qscale;
   if (S.nbmap == 0) return;
-  if (mixed)
-    k_nlist<true><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, (float)(rq * rq));
-  else
-    k_nlist<false><<<S.nbmap, kBlock, 0, s>>>(S, rl * rl, 0.0f);
+  if (mixed) {
+    // work lists, the rows of the rebuilt replicas, then the lane-ordered
+    // rows of the rebuilt and the pruned ones
+    k_worklist<<<1, 1024, 0, s>>>(S);
+    const int64_t nt = S.N / kTile;
+    k_nlist_mixed<<<(unsigned)std::min(nt, kWorkGrid), kBlock, 0, s>>>(
+        S, rl * rl, (float)(rq * rq));
+    const int64_t nb = S.nbmap;
+    k_prune<<<(unsigned)std::min(nb, kWorkGrid), kBlock, 0, s>>>(S);
+  } else {
+    k_nlist_fp64<<<S.nbmap, kBlock, 0, s>>>(S, rl * rl);
+  }
 }
 
 // Sums of the full and of the lane-ordered list lengths (diagnostics).
@@ -1927,11 +2079,6 @@ __global__ void __launch_bounds__(kBlock) k_list_stats(Dev S, int mixed) {
 void launch_list_stats(const Dev &S, bool mixed, hipStream_t s) {
   k_fill_u64<<<1, 64, 0, s>>>(S.stats, 2, 0ull);
   k_list_stats<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, mixed ? 1 : 0);
-}
-
-void launch_prune(const Dev &S, hipStream_t s) {
-  if (S.nbmap == 0 || !S.pruning || !S.nl_lane) return;
-  k_prune<<<S.nbmap, kBlock, 0, s>>>(S);
 }
 
 void launch_block_map(const Dev &S, hipStream_t s) {

@@ -11,9 +11,11 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_set_step(int64_t *p, int64_t v, hipStream_t s);
 void launch_quantise(const Dev &S, hipStream_t s);
 void launch_cells(const Dev &S, hipStream_t s);
+// List build of the replicas that rebuild (all when S.all); in mixed
+// precision also the lane-ordered rows of those and of the replicas whose
+// lists are pruned this step.
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s);
 void launch_block_map(const Dev &S, hipStream_t s);
-void launch_prune(const Dev &S, hipStream_t s);
 void launch_list_stats(const Dev &S, bool mixed, hipStream_t s);
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
                    void *fx, void *fy, void *fz, void *eat, double *g,
