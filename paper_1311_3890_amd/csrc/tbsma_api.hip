@@ -119,11 +119,12 @@ struct Layout {
       wl, total;
 };
 
-// Blocks of the cell sort: ceil(cells/64) per replica.
+// Blocks of the cell sort: ceil(cells/kSortCells) per replica.
 int32_t cell_map_size(const tbsma_system *s) {
   int64_t nb = 0;
   for (int r = 0; r < s->R; ++r)
-    nb += (s->cell_off_h[r + 1] - s->cell_off_h[r] + 63) / 64;
+    nb += (s->cell_off_h[r + 1] - s->cell_off_h[r] + kSortCells - 1) /
+          kSortCells;
   return (int32_t)nb;
 }
 
@@ -166,7 +167,7 @@ Layout layout(const tbsma_system *s) {
   L.bmap = o;
   o += up(8 * (size_t)(nt / 4 + R + 1));
   L.cbmap = o;
-  o += up(16 * (size_t)(s->C / 64 + R + 1));
+  o += up(16 * (size_t)(s->C / kSortCells + R + 1));
   L.lane_atom = o;
   o += up((size_t)s->N);
   L.nn_lane = o;
@@ -181,8 +182,8 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * 5 * (size_t)R);
   L.baw = o;
   o += up(8 * 2 * (size_t)R);
-  L.wl = o;  // two counts, the tiles, the list-build blocks
-  o += up(4 * (size_t)(2 + nt + nt / 4 + R + 1));
+  L.wl = o;
+  o += up(4 * (size_t)work_lists_size(s->N, R, s->C));
 
   L.total = o;
   return L;
@@ -463,6 +464,7 @@ void enqueue_step(const tbsma_params *p, const Dev &d0, const DevMD &M0,
   d.rstatus = M0.status;
   const DevMD &M = M0;
   launch_integrate_a(d, M, mixed, o->fx, o->fy, o->fz, s);
+  launch_worklist(d, s);
   launch_cells(d, s);
   launch_nlist(d, mixed, rl, s);
   Dev df = d;
@@ -628,6 +630,7 @@ int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
   attach_lists(d, cells, nullptr);
   d.all = 1;
   launch_fill_u32(reinterpret_cast<uint32_t *>(d.cnt), sys->C, 0u, s);
+  launch_worklist(d, s);
   launch_cells(d, s);
   HIPCHK(hipGetLastError());
   return TBSMA_OK;
@@ -650,6 +653,7 @@ int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
   launch_fill_u32(reinterpret_cast<uint32_t *>(d.nnmax), 1, 0u, s);
   const bool mixed = prm->precision == TBSMA_MIXED;
   if (mixed) launch_quantise(d, s);
+  launch_worklist(d, s);
   launch_nlist(d, mixed, rl, s);
   HIPCHK(hipGetLastError());
   if (need_cap) {

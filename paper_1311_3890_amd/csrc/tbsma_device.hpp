@@ -9,6 +9,7 @@ namespace tbsma {
 
 constexpr int kTile = 64;   // slots per tile = one wavefront
 constexpr int kBlock = 256; // threads of every per-atom kernel
+constexpr int kSortCells = 16;  // cells per block of the cell sort
 constexpr int kNPart = 8;   // FP64 partial sums per tile
 
 // per-tile partial sums
@@ -81,10 +82,7 @@ struct Dev {
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
-  int32_t *wl;                  // work lists of a step (mixed precision):
-                                // [0] tiles to rebuild, [1] blocks to prune,
-                                // the tiles from wl + 2, the blocks (bmap
-                                // entries) from wl + 2 + N/64
+  int32_t *wl;                  // work lists of a step (see work_lists)
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
   // n_log == 0, the step loops)
@@ -332,6 +330,34 @@ __device__ __forceinline__ unsigned long long dkey(double v) {
 __device__ __forceinline__ double dkey_inv(unsigned long long k) {
   unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
   return __longlong_as_double((long long)b);
+}
+
+// Work lists of a step, written by k_worklist from the rebuild and pruning
+// flags, so that the cell, list-build and pruning kernels launch a fixed,
+// small grid whatever the number of replicas that rebuild or prune.
+// Replicas come in order in each list.
+struct WorkLists {
+  int32_t *count;    // [4] entries of the four lists
+  int32_t *tiles;    // tiles of the replicas that rebuild
+  int32_t *blocks;   // list-build blocks (bmap entries) of the replicas that
+                     // rebuild or prune
+  int32_t *reps;     // the replicas that rebuild
+  int32_t *cblocks;  // cell-sort blocks (cbmap entries) of those replicas
+};
+// Capacities: N/64 tiles, N/256 + R + 1 list-build blocks, R replicas,
+// C/kSortCells + R + 1 cell-sort blocks.
+__host__ __device__ inline int64_t work_lists_size(int64_t N, int64_t R,
+                                                   int64_t C) {
+  return 4 + N / kTile + (N / kTile / 4 + R + 1) + R + (C / kSortCells + R + 1);
+}
+__device__ __forceinline__ WorkLists work_lists(const Dev &S) {
+  WorkLists W;
+  W.count = S.wl;
+  W.tiles = S.wl + 4;
+  W.blocks = W.tiles + S.N / kTile;
+  W.reps = W.blocks + (S.N / kTile / 4 + S.R + 1);
+  W.cblocks = W.reps + S.R;
+  return W;
 }
 
 __device__ __forceinline__ bool rebuilds(const Dev &S, int r) {

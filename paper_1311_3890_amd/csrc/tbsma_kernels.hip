@@ -81,109 +81,143 @@ __device__ __forceinline__ int atom_cell(const Dev &S, int r, int64_t i,
   return (cz * gd[1] + cy) * gd[0] + cx;
 }
 
+// The cell kernels run over the work lists of the step (the tiles, the
+// replicas and the cell-sort blocks of the replicas that rebuild): a
+// wavefront takes one tile of the list at a time in the per-atom kernels.
 __global__ void __launch_bounds__(kBlock) k_cell_count(Dev S) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= S.N) return;
-  int r = S.tile_rep[i / kTile];
-  if (!rebuilds(S, r) || S.flag[i] == 3) return;
-  bool out = false;
-  int c = atom_cell(S, r, i, out);
-  atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
-  if (out) atomicOr(&S.wstatus[r], 4u);
+  const WorkLists W = work_lists(S);
+  const int n = W.count[0];
+  const int wv = threadIdx.x / kTile, lane = threadIdx.x & (kTile - 1);
+  for (int it = blockIdx.x * (kBlock / kTile) + wv; it < n;
+       it += gridDim.x * (kBlock / kTile)) {
+    const int tile = W.tiles[it];
+    const int64_t i = (int64_t)tile * kTile + lane;
+    const int r = S.tile_rep[tile];
+    if (S.flag[i] == 3) continue;
+    bool out = false;
+    const int c = atom_cell(S, r, i, out);
+    atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
+    if (out) atomicOr(&S.wstatus[r], 4u);
+  }
 }
 
-// One workgroup per replica: exclusive scan of its cell counts into
-// cell_start; the counters become fill cursors.
+// One workgroup per replica of the work list at a time: exclusive scan of
+// its cell counts into cell_start; the counters become fill cursors.
 __global__ void __launch_bounds__(1024) k_cell_scan(Dev S) {
   __shared__ int32_t wsum[16];
   __shared__ int32_t carry_s;
-  int r = blockIdx.x;
-  if (!rebuilds(S, r)) return;
-  int64_t c0 = S.cell_off[r], nc = S.cell_off[r + 1] - c0;
-  int32_t *start = S.cell_start + c0 + r;
-  int32_t base = (int32_t)S.rep_off[r];
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry_s = 0;
-  __syncthreads();
-  for (int64_t b = 0; b < nc; b += 1024) {
-    int64_t c = b + threadIdx.x;
-    int32_t v = c < nc ? S.cnt[c0 + c] : 0;
-    // inclusive wave scan
-    int32_t s = v;
+  const WorkLists W = work_lists(S);
+  const int nrep = W.count[2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int it = blockIdx.x; it < nrep; it += gridDim.x) {  // uniform
+    const int r = W.reps[it];
+    const int64_t c0 = S.cell_off[r], nc = S.cell_off[r + 1] - c0;
+    int32_t *start = S.cell_start + c0 + r;
+    const int32_t base = (int32_t)S.rep_off[r];
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < nc; b += 1024) {
+      const int64_t c = b + threadIdx.x;
+      const int32_t v = c < nc ? S.cnt[c0 + c] : 0;
+      // inclusive wave scan
+      int32_t sc = v;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int32_t t = __shfl_up(s, o, 64);
-      if (lane >= o) s += t;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(sc, o, 64);
+        if (lane >= o) sc += t;
+      }
+      if (lane == 63) wsum[wid] = sc;
+      __syncthreads();
+      int32_t woff = 0, tot = 0;
+      for (int w = 0; w < 16; ++w) {
+        if (w < wid) woff += wsum[w];
+        tot += wsum[w];
+      }
+      const int32_t ex = carry_s + woff + sc - v;
+      if (c < nc) {
+        start[c] = base + ex;
+        S.cnt[c0 + c] = base + ex;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) carry_s += tot;
+      __syncthreads();
     }
-    if (lane == 63) wsum[wid] = s;
-    __syncthreads();
-    int32_t woff = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wid) woff += wsum[w];
-      tot += wsum[w];
-    }
-    int32_t ex = carry_s + woff + s - v;
-    if (c < nc) {
-      start[c] = base + ex;
-      S.cnt[c0 + c] = base + ex;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) carry_s += tot;
-    __syncthreads();
+    if (threadIdx.x == 0) start[nc] = base + carry_s;
   }
-  if (threadIdx.x == 0) start[nc] = base + carry_s;
 }
 
 __global__ void __launch_bounds__(kBlock) k_cell_fill(Dev S) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= S.N) return;
-  int r = S.tile_rep[i / kTile];
-  if (!rebuilds(S, r) || S.flag[i] == 3) return;
-  bool out = false;
-  int c = atom_cell(S, r, i, out);
-  int32_t pos = atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
-  S.cell_atoms[pos] = (int32_t)i;
+  const WorkLists W = work_lists(S);
+  const int n = W.count[0];
+  const int wv = threadIdx.x / kTile, lane = threadIdx.x & (kTile - 1);
+  for (int it = blockIdx.x * (kBlock / kTile) + wv; it < n;
+       it += gridDim.x * (kBlock / kTile)) {
+    const int tile = W.tiles[it];
+    const int64_t i = (int64_t)tile * kTile + lane;
+    const int r = S.tile_rep[tile];
+    if (S.flag[i] == 3) continue;
+    bool out = false;
+    const int c = atom_cell(S, r, i, out);
+    const int32_t pos = atomicAdd(&S.cnt[S.cell_off[r] + c], 1);
+    S.cell_atoms[pos] = (int32_t)i;
+  }
 }
 
 // Ordering of each cell's slots (the fill order is not deterministic), and
 // clearing of its counter for the next build.  Blocks of the cell map take up
 // to kSortCells cells of one replica; a wavefront takes kSortCells / 4 of
-// them in turn.  A cell of up to 64 atoms is ordered by ranks in registers
-// (lane l holds one slot and counts the smaller ones, read lane by lane);
-// larger cells by one lane's insertion sort.
-constexpr int kSortCells = 64;
-
+// them in turn, with the starts of its cells read at once and the next
+// cell's slots loaded while a cell is ordered.  A cell of up to 64 atoms is
+// ordered by ranks in registers (lane l holds one slot and counts the
+// smaller ones, read lane by lane); larger cells by one lane's insertion
+// sort.
 __global__ void __launch_bounds__(kBlock) k_cell_sort(Dev S) {
-  const int4 cb = S.cbmap[blockIdx.x];  // replica, first cell, cells
-  const int r = cb.x;
-  if (!rebuilds(S, r)) return;  // uniform over the block
+  const WorkLists W = work_lists(S);
+  const int ncb = W.count[3];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int per = kSortCells / (kBlock / kTile);
-  const int64_t c0 = S.cell_off[r];
-  const int32_t *start = S.cell_start + c0 + r;
+  constexpr int per = kSortCells / (kBlock / kTile);
   int32_t *v = S.cell_atoms;
-  for (int k = 0; k < per; ++k) {
-    const int c = cb.y + w * per + k;
-    if (w * per + k >= cb.z) break;  // uniform over the wavefront
-    const int32_t a = start[c], n = start[c + 1] - a;
-    if (n <= 64) {
-      const int32_t mine = lane < n ? v[a + lane] : 0x7fffffff;
-      int rank = 0;
-      for (int m = 0; m < n; ++m)
-        rank += __builtin_amdgcn_readlane(mine, m) < mine ? 1 : 0;
-      if (lane < n) v[a + rank] = mine;
-    } else if (lane == 0) {
-      for (int32_t q = a + 1; q < a + n; ++q) {
-        const int32_t key = v[q];
-        int32_t m = q - 1;
-        while (m >= a && v[m] > key) {
-          v[m + 1] = v[m];
-          --m;
-        }
-        v[m + 1] = key;
+  for (int it = blockIdx.x; it < ncb; it += gridDim.x) {
+    const int4 cb = S.cbmap[W.cblocks[it]];  // replica, first cell, cells
+    const int r = cb.x;
+    const int nk = min(per, cb.z - w * per);  // this wavefront's cells
+    if (nk <= 0) continue;                    // uniform over the wavefront
+    const int64_t c0 = S.cell_off[r];
+    const int32_t *start = S.cell_start + c0 + r;
+    const int cw = cb.y + w * per;
+    // lane k <= nk: start of cell cw + k (k = nk: end of the last)
+    const int32_t st = start[cw + min(lane, nk)];
+    int32_t a = __builtin_amdgcn_readlane(st, 0);
+    int32_t e = __builtin_amdgcn_readlane(st, 1);
+    int32_t mine = (e - a <= 64 && lane < e - a) ? v[a + lane] : 0x7fffffff;
+    for (int k = 0; k < nk; ++k) {
+      int32_t an = e, en = e, nxt = 0x7fffffff;
+      if (k + 1 < nk) {
+        en = __builtin_amdgcn_readlane(st, k + 2);
+        if (en - an <= 64 && lane < en - an) nxt = v[an + lane];
       }
+      const int32_t n = e - a;
+      if (n <= 64) {
+        int rank = 0;
+        for (int m = 0; m < n; ++m)
+          rank += __builtin_amdgcn_readlane(mine, m) < mine ? 1 : 0;
+        if (lane < n) v[a + rank] = mine;
+      } else if (lane == 0) {
+        for (int32_t q = a + 1; q < a + n; ++q) {
+          const int32_t key = v[q];
+          int32_t m = q - 1;
+          while (m >= a && v[m] > key) {
+            v[m + 1] = v[m];
+            --m;
+          }
+          v[m + 1] = key;
+        }
+      }
+      if (lane == 0) S.cnt[c0 + cw + k] = 0;
+      a = an;
+      e = en;
+      mine = nxt;
     }
-    if (lane == 0) S.cnt[c0 + c] = 0;
   }
 }
 
@@ -564,38 +598,39 @@ __global__ void __launch_bounds__(kBlock) k_nlist_fp64(Dev S, double rl2) {
   }
 }
 
-// Work lists of a step (mixed precision), so that the list build and the
-// pruning launch a fixed, small grid whatever the number of replicas that
-// rebuild or prune: the tiles of the replicas whose lists are rebuilt, and
-// the list-build blocks (block-map entries) of the replicas whose
-// lane-ordered lists are rebuilt or pruned, replicas in order.  wl[0] and
-// wl[1] hold the two counts; the tiles follow from wl + 2 and the blocks
-// from wl + 2 + N/64.  One block of 1024 threads; a scan over the replicas.
+// The work lists of the step (WorkLists) from the rebuild and pruning flags
+// of every replica.  One block of 1024 threads; a scan over the replicas of
+// the entries each adds to each list, and of its blocks in the list-build
+// and cell-sort maps (replicas in order there too).
 __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
-  __shared__ int32_t wsum[3][16];
-  __shared__ int32_t carry[3];
-  __shared__ int4 info[1024];  // first tile, tiles listed, first block, blocks listed
-  __shared__ int2 off[1024];   // offsets in the tile and block lists
+  // scanned per replica: tiles, list-build blocks and cell-sort blocks
+  // listed, replica listed; its blocks in the two maps
+  constexpr int kL = 6;
+  __shared__ int32_t wsum[kL][16];
+  __shared__ int32_t carry[kL], tot[kL];
+  __shared__ int4 run[1024][3];  // per replica: (first, count, offset) x 3
+  const WorkLists W = work_lists(S);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  int32_t *tiles = S.wl + 2;
-  int32_t *blocks = S.wl + 2 + S.N / kTile;
-  if (tid < 3) carry[tid] = 0;
+  if (tid < kL) carry[tid] = 0;
   __syncthreads();
   for (int b0 = 0; b0 < S.R; b0 += 1024) {
     const int r = b0 + tid;
-    int32_t t0 = 0, nt = 0;
+    int32_t t0 = 0, nt = 0, nc = 0;
     bool reb = false, upd = false;
     if (r < S.R) {
       t0 = (int32_t)(S.rep_off[r] / kTile);
       nt = (int32_t)(S.rep_off[r + 1] / kTile) - t0;
+      nc = (int32_t)(S.cell_off[r + 1] - S.cell_off[r]);
       reb = rebuilds(S, r);
       upd = reb || prunes(S, r);
     }
-    const int32_t nb = (nt + 3) >> 2;  // its blocks in the block map
-    const int32_t v[3] = {reb ? nt : 0, upd ? nb : 0, nb};
-    int32_t sc[3], ex[3], tot[3];
+    const int32_t nb = (nt + 3) >> 2;
+    const int32_t ncb = (nc + kSortCells - 1) / kSortCells;
+    const int32_t v[kL] = {reb ? nt : 0, upd ? nb : 0, reb ? ncb : 0,
+                           reb ? 1 : 0,  nb,          ncb};
+    int32_t sc[kL];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kL; ++k) {
       int32_t x = v[k];
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -606,34 +641,43 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
       if (lane == 63) wsum[k][wid] = x;
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int32_t woff = 0, t = 0;
+    // wave totals -> exclusive wave offsets (in place) and chunk totals
+    if (tid < kL) {
+      int32_t acc = 0;
       for (int m = 0; m < 16; ++m) {
-        if (m < wid) woff += wsum[k][m];
-        t += wsum[k][m];
+        const int32_t t = wsum[tid][m];
+        wsum[tid][m] = acc;
+        acc += t;
       }
-      ex[k] = carry[k] + woff + sc[k] - v[k];
-      tot[k] = t;
+      tot[tid] = acc;
     }
-    info[tid] = make_int4(t0, v[0], ex[2], v[1]);
-    off[tid] = make_int2(ex[0], ex[1]);
     __syncthreads();
-    // each wavefront writes the entries of every 16th replica of the chunk
+    int32_t ex[kL];
+#pragma unroll
+    for (int k = 0; k < kL; ++k) ex[k] = carry[k] + wsum[k][wid] + sc[k] - v[k];
+    if (reb) W.reps[ex[3]] = r;
+    run[tid][0] = make_int4(t0, v[0], ex[0], 0);
+    run[tid][1] = make_int4(ex[4], v[1], ex[1], 0);
+    run[tid][2] = make_int4(ex[5], v[2], ex[2], 0);
+    __syncthreads();
+    // each wavefront writes the runs of every 16th replica of the chunk
     const int nr = min(1024, S.R - b0);
     for (int k = wid; k < nr; k += 16) {
-      const int4 f = info[k];
-      const int2 o = off[k];
-      for (int x = lane; x < f.y; x += 64) tiles[o.x + x] = f.x + x;
-      for (int x = lane; x < f.w; x += 64) blocks[o.y + x] = f.z + x;
+      const int4 a = run[k][0], bl = run[k][1], cl = run[k][2];
+      for (int x = lane; x < a.y; x += 64) W.tiles[a.z + x] = a.x + x;
+      for (int x = lane; x < bl.y; x += 64) W.blocks[bl.z + x] = bl.x + x;
+      for (int x = lane; x < cl.y; x += 64) W.cblocks[cl.z + x] = cl.x + x;
     }
     __syncthreads();
-    if (tid < 3) carry[tid] += tot[tid];
+    if (tid < kL) carry[tid] += tot[tid];
     __syncthreads();
   }
+  // counts: tiles, list-build blocks, replicas, cell-sort blocks
   if (tid == 0) {
-    S.wl[0] = carry[0];
-    S.wl[1] = carry[1];
+    W.count[0] = carry[0];
+    W.count[1] = carry[1];
+    W.count[2] = carry[3];
+    W.count[3] = carry[2];
   }
 }
 
@@ -660,8 +704,9 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
   const int tid = threadIdx.x;
   const int q = tid / kTile;  // share of the candidate scan
   const int lane = tid & (kTile - 1);
-  const int ntl = S.wl[0];
-  const int32_t *tiles = S.wl + 2;
+  const WorkLists W = work_lists(S);
+  const int ntl = W.count[0];
+  const int32_t *tiles = W.tiles;
   const int64_t N = S.N;
   const int nch = S.k_cap >> 3;
   for (int it = blockIdx.x; it < ntl; it += gridDim.x) {  // uniform
@@ -948,8 +993,9 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
   __shared__ int32_t ring_lds[16 * kBlock];
   __shared__ int4 lq[kStage + 1];
   __shared__ int32_t key[kBlock];
-  const int nbl = S.wl[1];
-  const int32_t *blocks = S.wl + 2 + S.N / kTile;
+  const WorkLists W = work_lists(S);
+  const int nbl = W.count[1];
+  const int32_t *blocks = W.blocks;
   for (int it = blockIdx.x; it < nbl; it += gridDim.x) {  // uniform
     const int2 bm = S.bmap[blocks[it]];
     PairBlock B;
@@ -2022,28 +2068,35 @@ void launch_quantise(const Dev &S, hipStream_t s) {
   k_quantise<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
 }
 
-void launch_cells(const Dev &S, hipStream_t s) {
-  k_cell_count<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
-  k_cell_scan<<<S.R, 1024, 0, s>>>(S);
-  k_cell_fill<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S);
-  if (S.ncbmap > 0) k_cell_sort<<<S.ncbmap, kBlock, 0, s>>>(S);
+// Grid of the kernels that loop over a work list.
+constexpr int64_t kWorkGrid = 2048;
+
+static inline unsigned work_grid(int64_t items) {
+  return (unsigned)std::max<int64_t>(1, std::min(items, kWorkGrid));
 }
 
-// Grid of the kernels that loop over a work list (list build, pruning).
-constexpr int64_t kWorkGrid = 2048;
+void launch_worklist(const Dev &S, hipStream_t s) {
+  if (S.R > 0) k_worklist<<<1, 1024, 0, s>>>(S);
+}
+
+void launch_cells(const Dev &S, hipStream_t s) {
+  if (S.R == 0) return;
+  const int64_t nt = S.N / kTile;
+  k_cell_count<<<work_grid((nt + 3) / 4), kBlock, 0, s>>>(S);
+  k_cell_scan<<<work_grid(std::min<int64_t>(S.R, 256)), 1024, 0, s>>>(S);
+  k_cell_fill<<<work_grid((nt + 3) / 4), kBlock, 0, s>>>(S);
+  if (S.ncbmap > 0) k_cell_sort<<<work_grid(S.ncbmap), kBlock, 0, s>>>(S);
+}
 
 void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
   const double rq = rl * S.qscale;
   if (S.nbmap == 0) return;
   if (mixed) {
-    // work lists, the rows of the rebuilt replicas, then the lane-ordered
-    // rows of the rebuilt and the pruned ones
-    k_worklist<<<1, 1024, 0, s>>>(S);
-    const int64_t nt = S.N / kTile;
-    k_nlist_mixed<<<(unsigned)std::min(nt, kWorkGrid), kBlock, 0, s>>>(
-        S, rl * rl, (float)(rq * rq));
-    const int64_t nb = S.nbmap;
-    k_prune<<<(unsigned)std::min(nb, kWorkGrid), kBlock, 0, s>>>(S);
+    // the rows of the rebuilt replicas, then the lane-ordered rows of the
+    // rebuilt and the pruned ones (work lists of the step)
+    k_nlist_mixed<<<work_grid(S.N / kTile), kBlock, 0, s>>>(S, rl * rl,
+                                                          (float)(rq * rq));
+    k_prune<<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
   } else {
     k_nlist_fp64<<<S.nbmap, kBlock, 0, s>>>(S, rl * rl);
   }

@@ -10,6 +10,9 @@ void launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_set_step(int64_t *p, int64_t v, hipStream_t s);
 void launch_quantise(const Dev &S, hipStream_t s);
+// Work lists of the step from the rebuild and pruning flags (all replicas
+// rebuild when S.all); read by the cell, list-build and pruning kernels.
+void launch_worklist(const Dev &S, hipStream_t s);
 void launch_cells(const Dev &S, hipStream_t s);
 // List build of the replicas that rebuild (all when S.all); in mixed
 // precision also the lane-ordered rows of those and of the replicas whose
