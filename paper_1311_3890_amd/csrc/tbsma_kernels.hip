@@ -287,9 +287,6 @@ __constant__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
 constexpr int kStage = 1280;  // staged positions per block (20 KB)
 constexpr int32_t kPadStaged = kStage * 16;
 constexpr int32_t kPadWide = (int32_t)0xFFFFFFF0u;
-__constant__ __attribute__((aligned(16))) int32_t kPadChunkStaged[8] = {
-    kPadStaged, kPadStaged, kPadStaged, kPadStaged,
-    kPadStaged, kPadStaged, kPadStaged, kPadStaged};
 
 __device__ __forceinline__ int32_t pad_of_window(int size) {
   return size > 0 && size <= kStage ? kPadStaged : kPadWide;
@@ -381,11 +378,23 @@ __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
   }
 }
 
+// A chunk of pad entries addressing the LDS sentinel of the pair passes, in
+// global memory (with a constant-memory pointer among the candidates of a
+// load, the compiler emits flat loads, which the wavefront must also wait
+// for before each LDS read).
+__device__ __attribute__((aligned(16))) int32_t kPadChunkStaged[8] = {
+    kPadStaged, kPadStaged, kPadStaged, kPadStaged,
+    kPadStaged, kPadStaged, kPadStaged, kPadStaged};
+
 // Loop over the chunks of one lane's list in which every entry may be read:
 // the wavefront runs as many chunks as its longest list, a lane past its own
 // chunks reads the pad chunk padc, and the unused entries of a lane's last
 // chunk hold the same pad value, so body(j[8]) gets 8 entries with no
-// per-entry test.
+// per-entry test.  The next chunk is loaded while body works on the current
+// one, into the other of two register sets: the loop is unrolled by two, and
+// every load is issued by every lane (the prefetch past the last chunk
+// reloads the last), so that the compiler's wait counts stay exact and a
+// wavefront waits only for the chunk it is about to use.
 template <class F>
 __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
                                                   int64_t N, int64_t i, int n,
@@ -393,21 +402,31 @@ __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
                                                   F &&body) {
   const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
   const int nch = (nmax + 7) >> 3;
+  if (nch == 0) return;  // uniform
   const int own = (n + 7) >> 3;
-  const int32_t *row = list + (i << 3);
-  const int64_t stride = N << 3;
+  const int4 *row = reinterpret_cast<const int4 *>(list + (i << 3));
   const int4 *pad = reinterpret_cast<const int4 *>(padc);
-  const int4 *p = own > 0 ? reinterpret_cast<const int4 *>(row) : pad;
-  int4 a = p[0], b = p[1];
-  for (int c = 0; c < nch; ++c) {
-    const int4 *q =
-        c + 1 < own ? reinterpret_cast<const int4 *>(row + (c + 1) * stride)
-                    : pad;
-    const int4 na = q[0], nb = q[1];
-    const int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  const int64_t stride = N << 1;  // one chunk, in int4
+  auto load = [&](int c, int4 &u, int4 &v) {
+    const int4 *q = c < own ? row + c * stride : pad;
+    u = q[0];
+    v = q[1];
+    // keeps the loads here: the compiler would otherwise sink them to their
+    // use in the next half, and the wavefront would wait for each chunk
+    asm volatile("" ::: "memory");
+  };
+  auto run = [&](const int4 &u, const int4 &v) {
+    const int j[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
     body(j);
-    a = na;
-    b = nb;
+  };
+  int4 a, b, c2, d2;
+  load(0, a, b);
+  for (int c = 0; c < nch; c += 2) {
+    load(min(c + 1, nch - 1), c2, d2);
+    run(a, b);
+    if (c + 1 >= nch) break;  // uniform
+    load(min(c + 2, nch - 1), a, b);
+    run(c2, d2);
   }
 }
 
