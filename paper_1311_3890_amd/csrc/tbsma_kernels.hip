@@ -270,9 +270,10 @@ __device__ __forceinline__ int64_t cl8(int64_t N, int64_t i, int64_t chunk) {
 
 // Value of the unused entries of a lane's last chunk of the Verlet lists
 // (nl), and a chunk made of them (read by lanes whose list has ended while
-// their wavefront goes on).
+// their wavefront goes on), in global memory so that loads that may read it
+// are global loads.
 constexpr int32_t kPadEntry = 0x7fffffff;
-__constant__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
+__device__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
     kPadEntry, kPadEntry, kPadEntry, kPadEntry,
     kPadEntry, kPadEntry, kPadEntry, kPadEntry};
 
