@@ -434,26 +434,21 @@ __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
 // ---------------------------------------------------------------------------
 // Verlet lists
 // ---------------------------------------------------------------------------
-// One lane per atom; each lane writes its list in whole chunks through a ring
-// while its wavefront advances through candidates in a uniform loop (one
-// candidate per lane per step), so that list entries come out in ascending
-// cell order (z, y, x), slots ascending within a cell.  Rows longer than
-// k_cap are truncated and reported.  A block takes up to four tiles of one
-// replica (the block map, built once per workspace), so that a replica's
-// lists do not depend on its neighbours in the batch.
-//
-// Two ways of producing the candidates:
-//  * window scan (mixed precision): cells are slabs in z, so the cells of
-//    the z-slabs around a block's atoms are one contiguous range of the
-//    cell-sorted atom array.  The block copies the positions of that range
-//    into LDS once, as FP32 offsets from the block's first atom; every
-//    wavefront then tests its 64 atoms against the candidates of the slabs
-//    around its own atoms (LDS broadcast reads).  Taken when the range fits
-//    in LDS.
+// One lane per atom.  A replica's lists do not depend on its neighbours in
+// the batch, and rows longer than k_cap are truncated and reported.  Two
+// ways of producing the candidates:
+//  * window scan (mixed precision, k_nlist_mixed): cells are slabs in z, so
+//    the cells of the z-slabs around a tile's atoms are one contiguous range
+//    of the cell-sorted atom array.  The block copies the positions of that
+//    range into LDS once, as FP32 offsets from the tile's first atom, and its
+//    wavefronts test the tile's 64 atoms against them (LDS broadcast reads).
+//    Taken when the range fits in LDS.
 //  * cell scan (otherwise, and in FP64 mode): each lane walks the 27 cells
-//    around its own cell, reading candidates from global memory.  Distances
-//    are FP64 in FP64 mode and exact integer differences of the quantised
-//    positions in mixed precision.
+//    around its own cell, reading candidates from global memory and writing
+//    its list in whole chunks through a ring, so that entries come out in
+//    ascending cell order (z, y, x), slots ascending within a cell.
+//    Distances are FP64 in FP64 mode and exact integer differences of the
+//    quantised positions in mixed precision.
 // Both give every pair with distance below r_cut + skin (rl); since cells
 // are at least rl wide, the extra candidates of the window scan (cells of
 // the same slabs outside the 3x3 columns around an atom) are farther away
