@@ -75,7 +75,9 @@ extern "C" {
 
 /* per-replica status bits (tbsma_md.status) */
 #define TBSMA_ST_OVERFLOW 1u   /* a neighbour-list row exceeded k_cap */
-#define TBSMA_ST_NONFINITE 2u  /* NaN/Inf in energy or kinetic energy */
+#define TBSMA_ST_NONFINITE 2u  /* NaN/Inf in energy or kinetic energy (logged
+                                  steps; every step with Nose-Hoover or the
+                                  barostat) */
 #define TBSMA_ST_OUTSIDE 4u    /* an atom left its cell grid (still exact) */
 #define TBSMA_ST_RUPTURED 8u   /* axial gap >= r_cut found at a logged step */
 #define TBSMA_ST_REBUILT 16u   /* neighbour list rebuilt at some step */

@@ -1333,6 +1333,10 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   }
   double k2 = 0.0, kz = 0.0, gq = 0.0;
   const bool baro = KICK && M.baro_mass > 0.0;
+  // the kinetic tile sums are read every step by the Nose-Hoover thermostat
+  // and the barostat, otherwise only on logged steps (uniform)
+  const bool ksums =
+      KICK && (M.nh_tau > 0.0 || baro || ((*M.step + 1) % M.n_log) == 0);
   if (KICK && valid) {
     const int r = S.tile_rep[B.t0];
     const int64_t step = *M.step;
@@ -1368,7 +1372,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
     e = ev - (gi > 0.0f ? 1.0f / gi : 0.0f);
     eat[i] = e;
   }
-  if (ENERGY || KICK) {
+  if (ENERGY || ksums) {
     // per-tile sums in slot order: each atom's values go to LDS at its slot
     // in the block, then wavefront w sums tile t0 + w.  lsum shares its LDS
     // with the staged positions, which every wavefront must have finished
@@ -1379,7 +1383,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
         lsum[i - B.b0] = (double)e;
         lsum[kBlock + (i - B.b0)] = (double)wz * (double)P.wscale;
       }
-      if (KICK) {
+      if (ksums) {
         lsum[2 * kBlock + (i - B.b0)] = k2;
         lsum[3 * kBlock + (i - B.b0)] = kz;
       }
@@ -1397,7 +1401,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
           pt[kPartW] = w_i;
         }
       }
-      if (KICK) {
+      if (ksums) {
         const double k_i = wave_sum(lsum[2 * kBlock + tid]);
         const double kz_i = wave_sum(lsum[3 * kBlock + tid]);
         if ((tid & 63) == 0) {
@@ -1705,17 +1709,19 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   const bool frozen = (M.status[r] & 32u) != 0;  // retired: record unchanged
   // (each sum is the same whichever other entries are summed with it)
   const bool baro = M.baro_mass > 0.0;
+  // the kinetic sums are current every step only when the thermostat or the
+  // barostat reads them (they then also serve the finiteness check);
+  // otherwise they are summed on logged steps, which also check finiteness
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (logstep) {
     if (baro)
       block_sum_tiles<5>(S.part, t0, t1, kPartE, s, lds);
     else
       block_sum_tiles<4>(S.part, t0, t1, kPartE, s, lds);
-  } else {
-    if (baro)
-      block_sum_tiles<3>(S.part, t0, t1, kPartK, s + 2, lds);
-    else
-      block_sum_tiles<2>(S.part, t0, t1, kPartK, s + 2, lds);
+  } else if (baro) {
+    block_sum_tiles<3>(S.part, t0, t1, kPartK, s + 2, lds);
+  } else if (M.nh_tau > 0.0) {
+    block_sum_tiles<2>(S.part, t0, t1, kPartK, s + 2, lds);
   }
   int nb = 2 * S.grid_dim[3 * r + 2];
   unsigned long long *bmin = S.zbmin + (int64_t)r * S.max_zbins;
