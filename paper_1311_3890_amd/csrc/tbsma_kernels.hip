@@ -444,11 +444,12 @@ __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
 //    wavefronts test the tile's 64 atoms against them (LDS broadcast reads).
 //    Taken when the range fits in LDS.
 //  * cell scan (otherwise, and in FP64 mode): each lane walks the 27 cells
-//    around its own cell, reading candidates from global memory and writing
-//    its list in whole chunks through a ring, so that entries come out in
-//    ascending cell order (z, y, x), slots ascending within a cell.
-//    Distances are FP64 in FP64 mode and exact integer differences of the
-//    quantised positions in mixed precision.
+//    around its own cell, reading candidates from global memory, so that
+//    entries come out in ascending cell order (z, y, x), slots ascending
+//    within a cell (in mixed precision, within each of the four shares of
+//    cells).  Distances are FP64 in FP64 mode, where each lane writes its
+//    list through a ring, and exact integer differences of the quantised
+//    positions in mixed precision.
 // Both give every pair with distance below r_cut + skin (rl); since cells
 // are at least rl wide, the extra candidates of the window scan (cells of
 // the same slabs outside the 3x3 columns around an atom) are farther away
@@ -468,11 +469,12 @@ struct ListRowT {
   }
 };
 
-template <bool MIXED, class Row>
+// FP64 cell scan: this lane's atom against the atoms of the 27 cells around
+// its cell, in cell order (FP64 distances); entries go to the lane's ring.
+template <class Row>
 __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
                                             bool real, int cx, int cy, int cz,
-                                            int4 qi, double rl2, float rl2q,
-                                            int nch, Row &row) {
+                                            double rl2, int nch, Row &row) {
   const int64_t N = S.N;
   const int32_t *gd = S.grid_dim + 3 * r;
   const int32_t *start = S.cell_start + S.cell_off[r] + r;
@@ -501,21 +503,59 @@ __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
     if (live) {
       const int32_t j = S.cell_atoms[s++];
       if (j != (int32_t)i) {
-        bool near;
-        if (MIXED) {
-          const int4 qj = S.qpos[j];
-          const float dx = (float)(qj.x - qi.x);
-          const float dy = (float)(qj.y - qi.y);
-          const float dz = (float)(qj.z - qi.z);
-          near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q;
-        } else {
-          const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
-          near = dx * dx + dy * dy + dz * dz < rl2;
-        }
-        if (near) row.add(j);
+        const double dx = S.x[j] - xi, dy = S.y[j] - yi, dz = S.z[j] - zi;
+        if (dx * dx + dy * dy + dz * dz < rl2) row.add(j);
       }
     }
     if ((it & 7) == 7) row.ring.flush(S.nl, N, i, nch);
+  }
+}
+
+// Mixed-precision cell scan, for tiles whose slabs exceed LDS: this lane's
+// atom against the atoms of cells q, q + nq, q + 2 nq, ... of the 27 around
+// its cell (nq wavefronts share the scan), reading candidate positions from
+// global memory; near(j) is called for each candidate j within the list
+// radius (exact integer differences of the quantised positions), in cell
+// order.
+template <class F>
+__device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
+                                           bool real, int cx, int cy, int cz,
+                                           int4 qi, float rl2q, int q, int nq,
+                                           F &&near) {
+  const int32_t *gd = S.grid_dim + 3 * r;
+  const int32_t *start = S.cell_start + S.cell_off[r] + r;
+  int cc = q - nq;
+  int32_t s = 0, e = 0;
+  bool live = real;
+  for (;;) {
+    if (live) {
+      while (s >= e) {
+        cc += nq;
+        if (cc >= 27) {
+          live = false;
+          break;
+        }
+        const int kz = cz + cc / 9 - 1, ky = cy + (cc / 3) % 3 - 1,
+                  kx = cx + cc % 3 - 1;
+        if (kx >= 0 && kx < gd[0] && ky >= 0 && ky < gd[1] && kz >= 0 &&
+            kz < gd[2]) {
+          const int c = (kz * gd[1] + ky) * gd[0] + kx;
+          s = start[c];
+          e = start[c + 1];
+        }
+      }
+    }
+    if (!wave_any(live)) break;
+    if (live) {
+      const int32_t j = S.cell_atoms[s++];
+      if (j != (int32_t)i) {
+        const int4 qj = S.qpos[j];
+        const float dx = (float)(qj.x - qi.x);
+        const float dy = (float)(qj.y - qi.y);
+        const float dz = (float)(qj.z - qi.z);
+        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q) near(j);
+      }
+    }
   }
 }
 
@@ -587,8 +627,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist_fp64(Dev S, double rl2) {
     const int64_t N = S.N;
     const int nch = S.k_cap >> 3;
     ListRowT<kBlock> row{Ring{ring_lds + tid, 0, 0}, (int32_t)i, (int32_t)i};
-    nlist_cells<false>(S, i, r, real, cx, cy, cz, make_int4(0, 0, 0, 0), rl2,
-                       0.0f, nch, row);
+    nlist_cells(S, i, r, real, cx, cy, cz, rl2, nch, row);
     row.ring.finish(S.nl, N, i, nch);
     const int32_t wlo = -wave_max_i(-row.wlo);
     const int32_t whi = wave_max_i(row.whi);
@@ -706,13 +745,12 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
 // share's pairs, the second writes them at their final entries, share q
 // after shares 0..q-1.  A row is thus the pairs in candidate order within
 // each share, shares in order, whatever the timing.  When the slabs exceed
-// LDS, wavefront 0 walks the 27 cells around each atom alone.  The
-// lane-ordered, pruned rows are made by the pruning kernel.
+// LDS, the four wavefronts share the walk over the 27 cells around each atom
+// the same way (wavefront q takes cells q, q + 4, ...).  The lane-ordered,
+// pruned rows are made by the pruning kernel.
 constexpr int kNlWaves = kBlock / kTile;
 
-__global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
-                                                        float rl2q) {
-  __shared__ int32_t ring_lds[16 * kTile];
+__global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
   __shared__ float4 cand[kCand + 8];
   __shared__ int32_t qcnt[kNlWaves][kTile];
   __shared__ int2 qwin[kNlWaves];
@@ -723,7 +761,6 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
   const int ntl = W.count[0];
   const int32_t *tiles = W.tiles;
   const int64_t N = S.N;
-  const int nch = S.k_cap >> 3;
   for (int it = blockIdx.x; it < ntl; it += gridDim.x) {  // uniform
     const int tile = tiles[it];
     const int r = S.tile_rep[tile];
@@ -769,21 +806,15 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
     __syncthreads();
     int cnt = 0;
     int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
-    if (window) {
-      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, [&](int32_t j) {
-        ++cnt;
-        wlo = min(wlo, j);
-        whi = max(whi, j);
-      });
-    } else if (q == 0) {
-      ListRowT<kTile> row{RingT<kTile>{ring_lds + lane, 0, 0}, (int32_t)i,
-                          (int32_t)i};
-      nlist_cells<true>(S, i, r, real, cx, cy, cz, qi, rl2, rl2q, nch, row);
-      row.ring.finish(S.nl, N, i, nch);
-      cnt = row.ring.cnt;
-      wlo = row.wlo;
-      whi = row.whi;
-    }
+    auto count = [&](int32_t j) {
+      ++cnt;
+      wlo = min(wlo, j);
+      whi = max(whi, j);
+    };
+    if (window)
+      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, count);
+    else
+      cells_scan(S, i, r, real, cx, cy, cz, qi, rl2q, q, kNlWaves, count);
     qcnt[q][lane] = cnt;
     const int32_t wl = -wave_max_i(-wlo);
     const int32_t wh = wave_max_i(whi);
@@ -796,17 +827,19 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, double rl2,
       before += k < q ? c : 0;
       total += c;
     }
-    if (window) {
-      int e = before;
-      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, [&](int32_t j) {
-        if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
-        ++e;
-      });
-      // the unused entries of the row's last chunk
-      if (q == kNlWaves - 1 && total < S.k_cap)
-        for (int f = total; f < ((total + 7) & ~7); ++f)
-          S.nl[cl8(N, i, f >> 3) + (f & 7)] = kPadEntry;
-    }
+    int e = before;
+    auto write = [&](int32_t j) {
+      if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
+      ++e;
+    };
+    if (window)
+      window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, write);
+    else
+      cells_scan(S, i, r, real, cx, cy, cz, qi, rl2q, q, kNlWaves, write);
+    // the unused entries of the row's last chunk
+    if (q == kNlWaves - 1 && total < S.k_cap)
+      for (int f = total; f < ((total + 7) & ~7); ++f)
+        S.nl[cl8(N, i, f >> 3) + (f & 7)] = kPadEntry;
     if (q == 0) {
       if (total > S.k_cap) {
         atomicMax(S.nnmax, total);
@@ -2115,7 +2148,7 @@ void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
   if (mixed) {
     // the rows of the rebuilt replicas, then the lane-ordered rows of the
     // rebuilt and the pruned ones (work lists of the step)
-    k_nlist_mixed<<<work_grid(S.N / kTile), kBlock, 0, s>>>(S, rl * rl,
+    k_nlist_mixed<<<work_grid(S.N / kTile), kBlock, 0, s>>>(S,
                                                           (float)(rq * rq));
     k_prune<<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
   } else {
