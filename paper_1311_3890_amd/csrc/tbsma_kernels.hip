@@ -516,7 +516,8 @@ __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
 // its cell (nq wavefronts share the scan), reading candidate positions from
 // global memory; near(j) is called for each candidate j within the list
 // radius (exact integer differences of the quantised positions), in cell
-// order.
+// order.  A lane takes up to 4 candidates of its current cell at a time,
+// so that their slot and position loads are in flight together.
 template <class F>
 __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
                                            bool real, int cx, int cy, int cz,
@@ -547,14 +548,23 @@ __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
     }
     if (!wave_any(live)) break;
     if (live) {
-      const int32_t j = S.cell_atoms[s++];
-      if (j != (int32_t)i) {
-        const int4 qj = S.qpos[j];
-        const float dx = (float)(qj.x - qi.x);
-        const float dy = (float)(qj.y - qi.y);
-        const float dz = (float)(qj.z - qi.z);
-        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q) near(j);
+      const int nb = min(4, e - s);
+      int32_t jj[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) jj[k] = k < nb ? S.cell_atoms[s + k] : -1;
+      int4 qq[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        qq[k] = jj[k] >= 0 ? S.qpos[jj[k]] : make_int4(0, 0, 0, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (jj[k] < 0 || jj[k] == (int32_t)i) continue;
+        const float dx = (float)(qq[k].x - qi.x);
+        const float dy = (float)(qq[k].y - qi.y);
+        const float dz = (float)(qq[k].z - qi.z);
+        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q) near(jj[k]);
       }
+      s += nb;
     }
   }
 }

@@ -115,8 +115,10 @@ def brute_sets(x, y, z, rl):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_neighbor_lists_are_exact_sets(precision):
+    # the 4.4 nm wire's z-slabs hold more candidates than LDS stages, so its
+    # mixed-precision lists come from the cell walk
     reps = [R(15.0, 30.0, r=0, jitter=0.1), R(20.0, 20.0, T=298.0, r=1, jitter=0.1),
-            R(30.0, 40.0, r=2, jitter=0.1)]
+            R(30.0, 40.0, r=2, jitter=0.1), R(44.0, 30.0, r=3, jitter=0.1)]
     note(f"nlist sets {precision} R={len(reps)}")
     b = WireBatch(reps, precision)
     b.prepare()
