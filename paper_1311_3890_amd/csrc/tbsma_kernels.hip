@@ -346,36 +346,45 @@ __device__ __forceinline__ bool wave_any(bool p) {
 }
 
 // Loop over the entries k < n of one lane's chunked list starting at chunk
-// c0 and moving by dir per chunk.  The indices of chunk c+1 are loaded while
-// chunk c is processed; body(j[8], k0) gets the 8 indices of chunk c (the
-// atom itself for k >= n, which every pair term excludes).
+// c0 and moving by dir per chunk; body(j[8], k0) gets the 8 indices of chunk
+// c (the atom itself for k >= n, which every pair term excludes).  As in
+// chunk_loop_padded below, the next chunk is loaded while body works on the
+// current one, into the other of two register sets, and every lane issues
+// every load (a lane past its own chunks reads the pad chunk).
 template <class F>
 __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
                                            int64_t i, int self, int n,
                                            int64_t c0, int dir, F &&body) {
   const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
   const int nch = (nmax + 7) >> 3;
-  int4 a = make_int4(self, self, self, self), b = a;
-  if (n > 0) {
-    const int4 *p = reinterpret_cast<const int4 *>(list + cl8(N, i, c0));
-    a = p[0];
-    b = p[1];
-  }
-  for (int c = 0; c < nch; ++c) {
-    int4 na = a, nb = b;
-    if ((c + 1) * 8 < n) {
-      const int4 *p = reinterpret_cast<const int4 *>(
-          list + cl8(N, i, c0 + (int64_t)dir * (c + 1)));
-      na = p[0];
-      nb = p[1];
-    }
+  if (nch == 0) return;  // uniform
+  const int own = (n + 7) >> 3;
+  const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
+  auto load = [&](int c, int4 &u, int4 &v) {
+    const int4 *q =
+        c < own ? reinterpret_cast<const int4 *>(
+                      list + cl8(N, i, c0 + (int64_t)dir * c))
+                : pad;
+    u = q[0];
+    v = q[1];
+    // keeps the loads here (the compiler would sink them to their use)
+    asm volatile("" ::: "memory");
+  };
+  auto run = [&](int c, const int4 &u, const int4 &v) {
     const int k0 = c * 8;
-    int j[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int j[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e) j[e] = k0 + e < n ? j[e] : self;
     body(j, k0);
-    a = na;
-    b = nb;
+  };
+  int4 a, b, c2, d2;
+  load(0, a, b);
+  for (int c = 0; c < nch; c += 2) {
+    load(min(c + 1, nch - 1), c2, d2);
+    run(c, a, b);
+    if (c + 1 >= nch) break;  // uniform
+    load(min(c + 2, nch - 1), a, b);
+    run(c + 1, c2, d2);
   }
 }
 
