@@ -116,7 +116,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
       bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
-      wl, total;
+      wl, callb, total;
 };
 
 // Blocks of the cell sort: ceil(cells/kSortCells) per replica.
@@ -184,6 +184,8 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * 2 * (size_t)R);
   L.wl = o;
   o += up(4 * (size_t)work_lists_size(s->N, R, s->C));
+  L.callb = o;
+  o += 256;
 
   L.total = o;
   return L;
@@ -234,6 +236,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.nhw = reinterpret_cast<double *>(w + L.nhw);
   d.baw = reinterpret_cast<double *>(w + L.baw);
   d.wl = reinterpret_cast<int32_t *>(w + L.wl);
+  d.callb = reinterpret_cast<int64_t *>(w + L.callb);
 
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
@@ -422,6 +425,10 @@ DevMD make_devmd(const tbsma_params *p, const tbsma_md *m) {
   M.baro_mass = m->baro_s ? m->baro_mass : 0.0;
   M.baro_load = m->baro_load;
   M.baro_damp = m->baro_damp;
+  M.defer = (p->precision == TBSMA_MIXED && M.nh_tau <= 0.0 &&
+             M.baro_mass <= 0.0)
+                ? 1
+                : 0;
   M.baro_s = m->baro_s;
   return M;
 }
@@ -733,6 +740,7 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   PotF PF = make_potf(prm);
   PotD PD = make_potd(prm);
   const bool mixed = prm->precision == TBSMA_MIXED;
+  if (M.defer) launch_call_bounds(d, M, n_steps, s);
   if (M.nh_tau > 0 || M.baro_mass > 0)
     launch_step_begin(d, M, mixed, out->fz, s);
   for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
@@ -762,6 +770,7 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   PotD PD = make_potd(prm);
   int64_t chunks = n_steps / steps_per_graph;
   int64_t rest = n_steps % steps_per_graph;
+  if (M.defer) launch_call_bounds(d, M, n_steps, s);
   if (M.nh_tau > 0 || M.baro_mass > 0)
     launch_step_begin(d, M, prm->precision == TBSMA_MIXED, out->fz, s);
   if (chunks > 0) {

@@ -83,6 +83,8 @@ struct Dev {
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
   int32_t *wl;                  // work lists of a step (see work_lists)
+  int64_t *callb;               // [2] first step and end step of the current
+                                // step-loop call
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
   // n_log == 0, the step loops)
@@ -113,7 +115,12 @@ struct Dev {
 
 struct DevMD {
   double dt, gamma, c1, r_cut;
-  int32_t lab_frame, n_log, n_slots, pad;
+  int32_t lab_frame, n_log, n_slots;
+  // 1: the second half kick of a step is left to the next step's first
+  // kernel unless the step is logged or ends the call (mixed precision
+  // without Nose-Hoover and barostat, whose sums need the velocities of
+  // every step)
+  int32_t defer;
   const double *T, *v_pull, *z_lo, *z_hi, *vol, *L0;
   const uint64_t *seed;
   const int32_t *dof;

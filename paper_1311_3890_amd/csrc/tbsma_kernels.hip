@@ -1389,7 +1389,12 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   // and the barostat, otherwise only on logged steps (uniform)
   const bool ksums =
       KICK && (M.nh_tau > 0.0 || baro || ((*M.step + 1) % M.n_log) == 0);
-  if (KICK && valid) {
+  // the second half kick, unless the next step's first kernel does it
+  // (DevMD::defer; uniform)
+  const bool kick =
+      KICK && (!M.defer || ((*M.step + 1) % M.n_log) == 0 ||
+               *M.step + 1 == S.callb[1]);
+  if (kick && valid) {
     const int r = S.tile_rep[B.t0];
     const int64_t step = *M.step;
     const uint8_t f = S.flag[i];
@@ -1564,10 +1569,20 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
   uint8_t f = valid ? S.flag[i] : 3;
   double disp2 = 0.0;
   float pd2 = 0.0f;  // |q - qprune|^2 (quanta^2) when pruning
+  // the previous step left its second half kick to this one (DevMD::defer):
+  // it was neither logged nor the last of a call (uniform)
+  const bool pend = MIXED && M.defer && step != S.callb[0] &&
+                    (step % M.n_log) != 0;
   if (f != 3) {
     double x = S.x[i], y = S.y[i], z = S.z[i];
     double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
     if (f == 0) {
+      if (pend) {  // the same two additions, in the same order, as before
+        const double ak = 0.5 * M.dt * kAccel / S.mass;
+        vx = vx + ak * (double)fx[i];
+        vy = vy + ak * (double)fy[i];
+        vz = vz + ak * (double)fz[i];
+      }
       if (M.nh_tau > 0.0) {
         // the thermostat half steps that end the last step and begin this
         // one, as one scale of the peculiar velocity
@@ -2293,6 +2308,17 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
   else
     k_integrate_b<double><<<nb, kBlock, 0, s>>>(
         S, M, (const double *)fx, (const double *)fy, (const double *)fz);
+}
+
+__global__ void k_call_bounds(int64_t *callb, const int64_t *step,
+                              int64_t n) {
+  callb[0] = *step;
+  callb[1] = *step + n;
+}
+
+void launch_call_bounds(const Dev &S, const DevMD &M, int64_t n,
+                        hipStream_t s) {
+  k_call_bounds<<<1, 1, 0, s>>>(S.callb, M.step, n);
 }
 
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {

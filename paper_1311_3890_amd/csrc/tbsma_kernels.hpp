@@ -40,6 +40,10 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
                         const void *fx, const void *fy, const void *fz,
                         hipStream_t s);
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s);
+// Start of a step-loop call of n steps: records its first and end step
+// (read by the deferred second half kick).
+void launch_call_bounds(const Dev &S, const DevMD &M, int64_t n,
+                        hipStream_t s);
 // Start of a step-loop call: Nose-Hoover and barostat state from the
 // current velocities and forces.
 void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
