@@ -1403,9 +1403,9 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
       const double z = S.z[i];
       if (f == 0) {
         const double ac = 0.5 * M.dt * kAccel / S.mass;
-        const double vx = S.vx[i] + ac * (double)ax;
-        const double vy = S.vy[i] + ac * (double)ay;
-        const double vz = S.vz[i] + ac * (double)az;
+        const double vx = fma(ac, (double)ax, S.vx[i]);
+        const double vy = fma(ac, (double)ay, S.vy[i]);
+        const double vz = fma(ac, (double)az, S.vz[i]);
         S.vx[i] = vx;
         S.vy[i] = vy;
         S.vz[i] = vz;
@@ -1577,11 +1577,14 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
     double x = S.x[i], y = S.y[i], z = S.z[i];
     double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
     if (f == 0) {
-      if (pend) {  // the same two additions, in the same order, as before
-        const double ak = 0.5 * M.dt * kAccel / S.mass;
-        vx = vx + ak * (double)fx[i];
-        vy = vy + ak * (double)fy[i];
-        vz = vz + ak * (double)fz[i];
+      const double ac = hdt * kAccel / S.mass;
+      const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
+      // the kicks are explicit fused multiply-adds, the same as the force
+      // pass's, so that a deferred kick rounds exactly as an immediate one
+      if (pend) {
+        vx = fma(ac, gx, vx);
+        vy = fma(ac, gy, vy);
+        vz = fma(ac, gz, vz);
       }
       if (M.nh_tau > 0.0) {
         // the thermostat half steps that end the last step and begin this
@@ -1592,10 +1595,9 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
         vy *= sc;
         vz = u0 + sc * (vz - u0);
       }
-      double ac = hdt * kAccel / S.mass;
-      vx += ac * (double)fx[i];
-      vy += ac * (double)fy[i];
-      vz += ac * (double)fz[i];
+      vx = fma(ac, gx, vx);
+      vy = fma(ac, gy, vy);
+      vz = fma(ac, gz, vz);
       x += hdt * vx;
       y += hdt * vy;
       z += hdt * vz;
