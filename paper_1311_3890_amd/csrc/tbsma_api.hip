@@ -740,7 +740,7 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   PotF PF = make_potf(prm);
   PotD PD = make_potd(prm);
   const bool mixed = prm->precision == TBSMA_MIXED;
-  if (M.defer) launch_call_bounds(d, M, n_steps, s);
+  launch_call_bounds(d, M, n_steps, s);
   if (M.nh_tau > 0 || M.baro_mass > 0)
     launch_step_begin(d, M, mixed, out->fz, s);
   for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
@@ -770,7 +770,7 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
   PotD PD = make_potd(prm);
   int64_t chunks = n_steps / steps_per_graph;
   int64_t rest = n_steps % steps_per_graph;
-  if (M.defer) launch_call_bounds(d, M, n_steps, s);
+  launch_call_bounds(d, M, n_steps, s);
   if (M.nh_tau > 0 || M.baro_mass > 0)
     launch_step_begin(d, M, prm->precision == TBSMA_MIXED, out->fz, s);
   if (chunks > 0) {

@@ -83,8 +83,10 @@ struct Dev {
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
   int32_t *wl;                  // work lists of a step (see work_lists)
-  int64_t *callb;               // [2] first step and end step of the current
-                                // step-loop call
+  int64_t *callb;               // [3] first step and end step of the current
+                                // step-loop call, and the step flags of the
+                                // current step (kStepLog, kStepKick,
+                                // kStepPend)
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
   // n_log == 0, the step loops)
@@ -337,6 +339,23 @@ __device__ __forceinline__ unsigned long long dkey(double v) {
 __device__ __forceinline__ double dkey_inv(unsigned long long k) {
   unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
   return __longlong_as_double((long long)b);
+}
+
+// Flags of the current step of a step-loop call (callb[2]), set once per
+// step so that kernels need no 64-bit division by n_log: the step is logged;
+// the force pass does its second half kick; the position update first
+// applies the previous step's deferred kick (DevMD::defer).
+constexpr int64_t kStepLog = 1, kStepKick = 2, kStepPend = 4;
+
+// The flags of step m of the call recorded in callb (see kStepLog).
+__device__ __forceinline__ int64_t step_flags(const DevMD &M,
+                                              const int64_t *callb,
+                                              int64_t m) {
+  const bool log = (m + 1) % M.n_log == 0;
+  const bool kick = !M.defer || log || m + 1 == callb[1];
+  const bool pend = M.defer && m != callb[0] && m % M.n_log != 0;
+  return (log ? kStepLog : 0) | (kick ? kStepKick : 0) |
+         (pend ? kStepPend : 0);
 }
 
 // Work lists of a step, written by k_worklist from the rebuild and pruning

@@ -1387,13 +1387,12 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   const bool baro = KICK && M.baro_mass > 0.0;
   // the kinetic tile sums are read every step by the Nose-Hoover thermostat
   // and the barostat, otherwise only on logged steps (uniform)
+  const int64_t sf = KICK ? S.callb[2] : 0;  // flags of this step
   const bool ksums =
-      KICK && (M.nh_tau > 0.0 || baro || ((*M.step + 1) % M.n_log) == 0);
+      KICK && (M.nh_tau > 0.0 || baro || (sf & kStepLog) != 0);
   // the second half kick, unless the next step's first kernel does it
   // (DevMD::defer; uniform)
-  const bool kick =
-      KICK && (!M.defer || ((*M.step + 1) % M.n_log) == 0 ||
-               *M.step + 1 == S.callb[1]);
+  const bool kick = KICK && (sf & kStepKick) != 0;
   if (kick && valid) {
     const int r = S.tile_rep[B.t0];
     const int64_t step = *M.step;
@@ -1413,7 +1412,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
         k2 = S.mass * (vx * vx + vy * vy + wv * wv);
         kz = S.mass * wv * wv;
       }
-      if (((step + 1) % M.n_log) == 0) {
+      if (sf & kStepLog) {
         // axial bins of width cell/2 for the rupture gap
         const int nb = 2 * S.grid_dim[3 * r + 2];
         const double t = floor((z - S.grid_lo[3 * r + 2]) * 2.0 * S.inv_cell);
@@ -1486,7 +1485,7 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
   const PairBlock B = pair_block(S);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   const bool energy =
-      S.energies > 0 || (S.energies < 0 && (*S.step + 1) % S.n_log == 0);
+      S.energies > 0 || (S.energies < 0 && (S.callb[2] & kStepLog) != 0);
   int lo, size;
   block_window(S, B, lo, size);
   if (size > 0 && size <= kStage && stage(S, lq, B, lo, size)) {
@@ -1571,8 +1570,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
   float pd2 = 0.0f;  // |q - qprune|^2 (quanta^2) when pruning
   // the previous step left its second half kick to this one (DevMD::defer):
   // it was neither logged nor the last of a call (uniform)
-  const bool pend = MIXED && M.defer && step != S.callb[0] &&
-                    (step % M.n_log) != 0;
+  const bool pend = MIXED && (S.callb[2] & kStepPend) != 0;
   if (f != 3) {
     double x = S.x[i], y = S.y[i], z = S.z[i];
     double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
@@ -1683,7 +1681,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_b(Dev S, DevMD M,
   const double hdt = 0.5 * M.dt;
   uint8_t f = valid ? S.flag[i] : 3;
   double k2 = 0.0, kz = 0.0;
-  bool logstep = ((step + 1) % M.n_log) == 0;
+  const bool logstep = (S.callb[2] & kStepLog) != 0;
   const bool baro = M.baro_mass > 0.0;
   const double gq = !baro ? 0.0
                     : f == 2 ? (double)fz[i]
@@ -1774,7 +1772,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   int64_t n1 = step + 1;
   int64_t t0 = S.rep_off[r] / kTile, t1 = S.rep_off[r + 1] / kTile;
   // energy and virial tile sums are current on logged steps only
-  const bool logstep = (n1 % M.n_log) == 0;
+  const bool logstep = (S.callb[2] & kStepLog) != 0;  // n1 % n_log == 0
   const bool frozen = (M.status[r] & 32u) != 0;  // retired: record unchanged
   // (each sum is the same whichever other entries are summed with it)
   const bool baro = M.baro_mass > 0.0;
@@ -1892,6 +1890,7 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
     uint32_t prev = atomicAdd(S.ticket, 1u);
     if (prev == (uint32_t)S.R - 1) {
       *M.step = n1;
+      S.callb[2] = step_flags(M, S.callb, n1);
       *S.ticket = 0u;
       __threadfence();
     }
@@ -2312,15 +2311,16 @@ void launch_integrate_b(const Dev &S, const DevMD &M, bool mixed,
         S, M, (const double *)fx, (const double *)fy, (const double *)fz);
 }
 
-__global__ void k_call_bounds(int64_t *callb, const int64_t *step,
-                              int64_t n) {
-  callb[0] = *step;
-  callb[1] = *step + n;
+__global__ void k_call_bounds(DevMD M, int64_t *callb, int64_t n) {
+  const int64_t m = *M.step;
+  callb[0] = m;
+  callb[1] = m + n;
+  callb[2] = step_flags(M, callb, m);
 }
 
 void launch_call_bounds(const Dev &S, const DevMD &M, int64_t n,
                         hipStream_t s) {
-  k_call_bounds<<<1, 1, 0, s>>>(S.callb, M.step, n);
+  k_call_bounds<<<1, 1, 0, s>>>(M, S.callb, n);
 }
 
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {
