@@ -114,7 +114,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 }
 
 struct Layout {
-  size_t rflag, cnt, part, zbmin, zbmax, wstatus, ticket, nnmax, rsum, win,
+  size_t rflag, cnt, part, zbmin, zbmax, wstatus, nnmax, rsum, win,
       bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
       wl, callb, total;
 };
@@ -156,8 +156,6 @@ Layout layout(const tbsma_system *s) {
   o += up(8 * (size_t)R * s->max_zbins);
   L.wstatus = o;
   o += up(4 * (size_t)R);
-  L.ticket = o;
-  o += 256;
   L.nnmax = o;
   o += 256;
   L.rsum = o;
@@ -221,7 +219,6 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.zbmin = reinterpret_cast<unsigned long long *>(w + L.zbmin);
   d.zbmax = reinterpret_cast<unsigned long long *>(w + L.zbmax);
   d.wstatus = reinterpret_cast<uint32_t *>(w + L.wstatus);
-  d.ticket = reinterpret_cast<uint32_t *>(w + L.ticket);
   d.nnmax = reinterpret_cast<int32_t *>(w + L.nnmax);
   d.rsum = reinterpret_cast<double *>(w + L.rsum);
   d.win = reinterpret_cast<int2 *>(w + L.win);

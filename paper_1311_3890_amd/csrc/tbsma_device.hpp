@@ -105,7 +105,6 @@ struct Dev {
   double *part;                 // [N/64 * kNPart]
   unsigned long long *zbmin, *zbmax;  // [R * max_zbins] ordered keys of z
   uint32_t *wstatus;            // [R]
-  uint32_t *ticket;             // [1]
   int32_t *nnmax;               // [1]
   double *rsum;                 // [R * 8] per-replica scratch sums
   double *nhw;                  // [R * 5] Nose-Hoover step state (kNh*)

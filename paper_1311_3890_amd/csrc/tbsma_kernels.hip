@@ -1763,8 +1763,10 @@ __global__ void __launch_bounds__(256) k_reduce_forces(Dev S, double *rep_e,
   }
 }
 
-// End of a step, one workgroup per replica: sums, observables, status, and
-// (last workgroup to finish) the step index.
+// End of a step, one workgroup per replica: sums, observables, status.  The
+// step index and the next step's flags are advanced by k_step_advance, the
+// next kernel on the stream.  (A last-workgroup ticket would save that launch
+// but costs a device-wide fence in every workgroup, which is dearer.)
 __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
   __shared__ double lds[5 * 256];
   int r = blockIdx.x;
@@ -1884,17 +1886,13 @@ __global__ void __launch_bounds__(256) k_reduce_step(Dev S, DevMD M) {
       bmax[b] = 0ull;
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    uint32_t prev = atomicAdd(S.ticket, 1u);
-    if (prev == (uint32_t)S.R - 1) {
-      *M.step = n1;
-      S.callb[2] = step_flags(M, S.callb, n1);
-      *S.ticket = 0u;
-      __threadfence();
-    }
-  }
+}
+
+// The step index and the flags of the step it now names.
+__global__ void k_step_advance(DevMD M, int64_t *callb) {
+  const int64_t n1 = *M.step + 1;
+  *M.step = n1;
+  callb[2] = step_flags(M, callb, n1);
 }
 
 // ---------------------------------------------------------------------------
@@ -2325,6 +2323,7 @@ void launch_call_bounds(const Dev &S, const DevMD &M, int64_t n,
 
 void launch_reduce_step(const Dev &S, const DevMD &M, hipStream_t s) {
   k_reduce_step<<<S.R, 256, 0, s>>>(S, M);
+  k_step_advance<<<1, 1, 0, s>>>(M, S.callb);
 }
 
 void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
