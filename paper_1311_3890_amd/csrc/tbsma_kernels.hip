@@ -671,6 +671,23 @@ __global__ void __launch_bounds__(kBlock) k_nlist_fp64(Dev S, double rl2) {
   }
 }
 
+// The runs first, first + 1, ..., first + cnt - 1 at dst[off], ... of every
+// lane of the wavefront, one run at a time over the whole wavefront.  Only
+// the replicas that rebuild or prune add entries, so most wavefronts have
+// few runs or none.
+__device__ __forceinline__ void write_runs(int32_t *dst, int32_t first,
+                                           int32_t cnt, int32_t off,
+                                           int lane) {
+  uint64_t m = __ballot(cnt > 0);
+  while (m) {  // uniform
+    const int l = __builtin_ctzll(m);
+    m &= m - 1;
+    const int32_t f = __shfl(first, l, 64), c = __shfl(cnt, l, 64),
+                  o = __shfl(off, l, 64);
+    for (int x = lane; x < c; x += 64) dst[o + x] = f + x;
+  }
+}
+
 // The work lists of the step (WorkLists) from the rebuild and pruning flags
 // of every replica.  One block of 1024 threads; a scan over the replicas of
 // the entries each adds to each list, and of its blocks in the list-build
@@ -681,7 +698,6 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
   constexpr int kL = 6;
   __shared__ int32_t wsum[kL][16];
   __shared__ int32_t carry[kL], tot[kL];
-  __shared__ int4 run[1024][3];  // per replica: (first, count, offset) x 3
   const WorkLists W = work_lists(S);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid < kL) carry[tid] = 0;
@@ -729,18 +745,10 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
 #pragma unroll
     for (int k = 0; k < kL; ++k) ex[k] = carry[k] + wsum[k][wid] + sc[k] - v[k];
     if (reb) W.reps[ex[3]] = r;
-    run[tid][0] = make_int4(t0, v[0], ex[0], 0);
-    run[tid][1] = make_int4(ex[4], v[1], ex[1], 0);
-    run[tid][2] = make_int4(ex[5], v[2], ex[2], 0);
-    __syncthreads();
-    // each wavefront writes the runs of every 16th replica of the chunk
-    const int nr = min(1024, S.R - b0);
-    for (int k = wid; k < nr; k += 16) {
-      const int4 a = run[k][0], bl = run[k][1], cl = run[k][2];
-      for (int x = lane; x < a.y; x += 64) W.tiles[a.z + x] = a.x + x;
-      for (int x = lane; x < bl.y; x += 64) W.blocks[bl.z + x] = bl.x + x;
-      for (int x = lane; x < cl.y; x += 64) W.cblocks[cl.z + x] = cl.x + x;
-    }
+    // each wavefront writes the runs of its own replicas
+    write_runs(W.tiles, t0, v[0], ex[0], lane);
+    write_runs(W.blocks, ex[4], v[1], ex[1], lane);
+    write_runs(W.cblocks, ex[5], v[2], ex[2], lane);
     __syncthreads();
     if (tid < kL) carry[tid] += tot[tid];
     __syncthreads();
