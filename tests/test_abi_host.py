@@ -173,3 +173,17 @@ def test_dynamics_setting_checks(R, kw, msg):
                             C.byref(out), C.byref(md), None, 1, None)
     assert rc == A.EINVAL
     assert msg in A.lib().tbsma_last_error()
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    # one GPU only: the refusal comes before any device or library is touched
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv],
+                       capture_output=True, text=True, timeout=120,
+                       env={**os.environ, **env})
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
