@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="batch512-d3", choices=["d3-l20", "batch512-d3", "batch2048-mixed", "d10-l100"])
     ap.add_argument("--steps-per-graph", type=int, default=50)
     ap.add_argument("--per-replica", type=int, default=32,
                     help="replicas timed one per launch for the plain-path rate")
@@ -75,7 +75,7 @@ def main():
                     help="Verlet skin (A); default: the workload's")
     ap.add_argument("--prune", type=float, default=None,
                     help="pruning half-width (A); default: the workload's")
-    ap.add_argument("--oracle-configs", action="store_true",
+    ap.add_argument("--oracle-workloads", action="store_true",
                     help="also time the oracle on the D1.5xL3nm, D3xL20nm and D10xL100nm wires")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -95,8 +95,8 @@ def main():
     from paper_1311_3890_amd.engine import WireBatch
 
     torch.cuda.set_device(0)
-    wl = W.CONFIGS[args.workload]()
-    strain_max = 0.1 if args.workload == "cfg5" else 0.5
+    wl = W.WORKLOADS[args.workload]()
+    strain_max = 0.1 if args.workload == "d10-l100" else 0.5
     log(f"[bench] workload {wl.name}: building {len(wl.replicas)} replicas")
     skin = wl.skin if args.skin is None else args.skin
     prune = wl.prune if args.prune is None else args.prune
@@ -278,10 +278,10 @@ def main():
     drift = None
     if args.drift_steps > 0:
         drift = {}
-        for name, rp, prec in (("fp64 D1.5xL3nm", W.cfg1_plain_fp64().replicas[0], "fp64"),
-                               ("mixed D1.5xL3nm", W.cfg1_plain_fp64().replicas[0], "mixed"),
-                               ("fp64 D3xL20nm", W.cfg2_single_mixed().replicas[0], "fp64"),
-                               ("mixed D3xL20nm", W.cfg2_single_mixed().replicas[0], "mixed")):
+        for name, rp, prec in (("fp64 D1.5xL3nm", W.wire_d1p5_l3_fp64().replicas[0], "fp64"),
+                               ("mixed D1.5xL3nm", W.wire_d1p5_l3_fp64().replicas[0], "mixed"),
+                               ("fp64 D3xL20nm", W.wire_d3_l20_mixed().replicas[0], "fp64"),
+                               ("mixed D3xL20nm", W.wire_d3_l20_mixed().replicas[0], "mixed")):
             rp = W.Replica(rp.D, rp.L, rp.T, 0.0, rp.seed, rp.rep_id, jitter=rp.jitter)
             n_log = max(1, args.drift_steps // 100)
             nb = WireBatch([rp], prec, n_log=n_log, n_slots=100, gamma=0.0)
@@ -301,11 +301,11 @@ def main():
             log(f"[bench] NVE {name}: {drift[name]}")
 
     oracle_other = None
-    if args.oracle_configs and not args.no_cpu_baseline:
+    if args.oracle_workloads and not args.no_cpu_baseline:
         import oracle
         oracle_other = {}
-        for name, w in (("D1.5xL3nm", W.cfg1_plain_fp64()), ("D3xL20nm", W.cfg2_single_mixed()),
-                        ("D10xL100nm", W.cfg5_large())):
+        for name, w in (("D1.5xL3nm", W.wire_d1p5_l3_fp64()), ("D3xL20nm", W.wire_d3_l20_mixed()),
+                        ("D10xL100nm", W.wire_d10_l100())):
             rp = w.replicas[0]
             x, y, z, f = oracle.build_wire(W.A_LAT, rp.D, rp.L, rp.n_grip)
             stt = oracle.State(x, y, z, f)
@@ -376,7 +376,7 @@ def main():
     if drift is not None:
         line["nve_drift"] = drift
     if oracle_other is not None:
-        line["oracle_other_configs"] = oracle_other
+        line["oracle_other_workloads"] = oracle_other
     print(json.dumps(line), flush=True)
 
 

@@ -147,7 +147,7 @@ def main(argv=None):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
     ap = argparse.ArgumentParser(description=main.__doc__)
-    ap.add_argument("--workload", default="cfg4", choices=sorted(W.CONFIGS))
+    ap.add_argument("--workload", default="batch2048-mixed", choices=sorted(W.WORKLOADS))
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sample", type=int, default=32)
@@ -155,7 +155,7 @@ def main(argv=None):
     ap.add_argument("--cache", default=None, help="JSON file of earlier choices")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
-    wl = W.CONFIGS[a.workload]()
+    wl = W.WORKLOADS[a.workload]()
     choices = tune(wl.replicas, wl.precision, sample=a.sample, trial_steps=a.trial_steps,
                    warmup=a.warmup, cache=a.cache, log=log)
     run = BucketRun(wl.replicas, choices, wl.precision)

@@ -114,7 +114,7 @@ def test_layout_checks():
 def test_autotune_buckets_group_by_diameter_and_temperature():
     import workloads as W
     from paper_1311_3890_amd import autotune
-    wl = W.cfg4_mixed_shapes(64)
+    wl = W.batch2048_mixed_shapes(64)
     b = autotune.buckets(wl.replicas)
     # diameters go round-robin by r mod 4 and temperatures by r mod 2, so each
     # diameter comes with one temperature class
@@ -129,8 +129,8 @@ def test_autotune_buckets_group_by_diameter_and_temperature():
 
 def test_workloads_are_seeded_and_snapped():
     import workloads as W
-    a = W.cfg3_batched()
-    b = W.cfg3_batched()
+    a = W.batch512_d3()
+    b = W.batch512_d3()
     assert [r.L for r in a.replicas] == [r.L for r in b.replicas]
     assert len(a.replicas) == 512
     for r in a.replicas:

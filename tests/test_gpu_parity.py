@@ -199,11 +199,11 @@ def test_lists_stay_exact_through_in_step_rebuilds_and_pruning():
             assert abs(cnt[i].sum() - np.count_nonzero(d <= rc)) <= edge_c, (r, i)
 
 
-def test_forces_fp64_config1():
-    wl = W.cfg1_plain_fp64()
+def test_forces_fp64_d1p5_wire():
+    wl = W.wire_d1p5_l3_fp64()
     rp = wl.replicas[0]
     rp.jitter = 0.02
-    note("forces fp64 cfg1")
+    note("forces fp64 D1.5 x L3 nm")
     b = WireBatch([rp], "fp64")
     b.prepare()
     torch.cuda.synchronize()
@@ -218,8 +218,8 @@ def test_forces_fp64_config1():
 
 
 def test_forces_mixed_single_wire():
-    rp = W.cfg2_single_mixed().replicas[0]
-    note(f"forces mixed cfg2 D={rp.D} L={rp.L}")
+    rp = W.wire_d3_l20_mixed().replicas[0]
+    note(f"forces mixed D={rp.D} L={rp.L}")
     b = WireBatch([rp], "mixed")
     b.prepare()
     torch.cuda.synchronize()
@@ -277,7 +277,7 @@ def test_init_state_matches_oracle():
 
 
 def test_step_fp64_lockstep_with_oracle():
-    wl = W.cfg1_plain_fp64()
+    wl = W.wire_d1p5_l3_fp64()
     rp = wl.replicas[0]
     note("fp64 lockstep 20 steps")
     b = WireBatch([rp], "fp64", n_log=10)
@@ -445,11 +445,11 @@ def test_nose_hoover_extended_energy_is_conserved_in_mixed_precision():
     assert abs(np.mean(Ts[10:]) - 300.0) < 40.0
 
 
-def test_config1_end_to_end_forces_every_step():
-    """Config 1: 1000 FP64 steps at 10 K with the top grip pulled at 0.5 A/ps;
+def test_d1p5_wire_end_to_end_forces_every_step():
+    """The D 1.5 x L 3 nm wire: 1000 FP64 steps at 10 K with the top grip pulled at 0.5 A/ps;
     forces and energies checked against the oracle at every step."""
-    wl = W.cfg1_plain_fp64()
-    note("cfg1 end-to-end 1000 steps fp64")
+    wl = W.wire_d1p5_l3_fp64()
+    note("D1.5 x L3 nm end-to-end 1000 steps fp64")
     b = WireBatch(wl.replicas, "fp64", n_log=100)
     b.prepare()
     worst = 0.0
@@ -803,11 +803,11 @@ def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1, etol=1e-6):
     return worst
 
 
-def test_full_size_config3_sampled():
-    """Config 3 at full size (512 replicas) in the benchmark's launch shape:
+def test_full_size_batch512_sampled():
+    """The 512-wire D 3 nm batch at full size in the benchmark's launch shape:
     graph-replayed steps, then sampled replicas against the oracle."""
-    wl = W.cfg3_batched()
-    note(f"cfg3 full size R={len(wl.replicas)}")
+    wl = W.batch512_d3()
+    note(f"512-wire batch full size R={len(wl.replicas)}")
     b = WireBatch(wl.replicas, "mixed", n_log=50, skin=wl.skin, prune=wl.prune)
     b.prepare()
     b.run_batch(100, 50)
@@ -824,9 +824,9 @@ def test_full_size_config3_sampled():
     assert T.min() > 150.0 and T.max() < 320.0, (T.min(), T.max())
 
 
-def test_full_size_config5_sampled():
-    wl = W.cfg5_large()
-    note("cfg5 full size D10 x L100 nm")
+def test_full_size_d10_wire_sampled():
+    wl = W.wire_d10_l100()
+    note("D10 x L100 nm full size")
     b = WireBatch(wl.replicas, "mixed", n_log=50, strain_max=0.1)
     b.prepare()
     b.run_batch(50, 25)
@@ -836,9 +836,9 @@ def test_full_size_config5_sampled():
     note(f"  eps_F {worst:.2e}")
 
 
-def test_config4_mixed_shapes_sampled():
-    wl = W.cfg4_mixed_shapes()
-    note(f"cfg4 R={len(wl.replicas)}")
+def test_batch2048_mixed_shapes_sampled():
+    wl = W.batch2048_mixed_shapes()
+    note(f"2048 mixed shapes R={len(wl.replicas)}")
     b = WireBatch(wl.replicas, "mixed", n_log=20, skin=wl.skin, prune=wl.prune)
     b.prepare()
     b.run_batch(40, 20)

@@ -58,21 +58,21 @@ def seed_of(r: int) -> int:
     return S0 * 1000 + r
 
 
-def cfg1_plain_fp64() -> Workload:
+def wire_d1p5_l3_fp64() -> Workload:
     """One D 1.5 nm x L 3 nm wire, FP64, 10 K, 1000 steps at 0.5 A/ps."""
     return Workload("plain-fp64 D1.5xL3nm", [
         Replica(15.0, snap_length(30.0), 10.0, 0.5, seed_of(0), 0)],
         "fp64", 1000)
 
 
-def cfg2_single_mixed() -> Workload:
+def wire_d3_l20_mixed() -> Workload:
     """One D 3 nm x L 20 nm wire with +-0.02 A jitter, mixed precision, 10 K."""
     return Workload("single-mixed D3xL20nm", [
         Replica(30.0, snap_length(200.0), 10.0, 0.5, seed_of(0), 0, jitter=0.02)],
         "mixed", 50000)
 
 
-def cfg3_batched(n_rep: int = 512) -> Workload:
+def batch512_d3(n_rep: int = 512) -> Workload:
     """512 D 3 nm wires, lengths uniform in 5-40 nm, 298 K, 0.5 A/ps."""
     rng = np.random.default_rng(S0)
     Ls = rng.uniform(50.0, 400.0, size=n_rep)
@@ -83,7 +83,7 @@ def cfg3_batched(n_rep: int = 512) -> Workload:
     return Workload(f"batched {n_rep}x D3nm L5-40nm 298K", reps, "mixed", 20000, skin=1.6)
 
 
-def cfg4_mixed_shapes(n_rep: int = 2048) -> Workload:
+def batch2048_mixed_shapes(n_rep: int = 2048) -> Workload:
     """2048 wires: D in {1.5, 2, 2.5, 3} nm (r mod 4), L uniform in 3-30 nm,
     10 K for even r and 298 K for odd r, 0.1/0.5/1.0 A/ps (r mod 3)."""
     rng = np.random.default_rng(S0 + 4)
@@ -95,17 +95,17 @@ def cfg4_mixed_shapes(n_rep: int = 2048) -> Workload:
     return Workload(f"mixed-shapes {n_rep}x D1.5-3nm L3-30nm", reps, "mixed", 20000, skin=1.6)
 
 
-def cfg5_large() -> Workload:
+def wire_d10_l100() -> Workload:
     """One D 10 nm x L 100 nm wire, mixed precision, 298 K, 20k steps."""
     return Workload("large D10xL100nm", [
         Replica(100.0, snap_length(1000.0), 298.0, 0.5, seed_of(0), 0)],
         "mixed", 20000)
 
 
-CONFIGS = {
-    "cfg1": cfg1_plain_fp64,
-    "cfg2": cfg2_single_mixed,
-    "cfg3": cfg3_batched,
-    "cfg4": cfg4_mixed_shapes,
-    "cfg5": cfg5_large,
+WORKLOADS = {
+    "d1.5-l3-fp64": wire_d1p5_l3_fp64,
+    "d3-l20": wire_d3_l20_mixed,
+    "batch512-d3": batch512_d3,
+    "batch2048-mixed": batch2048_mixed_shapes,
+    "d10-l100": wire_d10_l100,
 }
