@@ -159,6 +159,32 @@ def test_neighbor_lists_are_exact_sets(precision):
     assert torch.equal(b.t["nl"], b2.t["nl"]) and torch.equal(b.t["nn"], b2.t["nn"])
 
 
+def _check_lists(b, r):
+    rl = b.pot.r_cut + b.skin
+    rt, rc = b.pot.r_tail, b.pot.r_cut
+    # the Verlet lists are exact at the positions of their last build
+    xr, yr, zr = (b._slice(k, r).astype(np.float64) for k in ("x_ref", "y_ref", "z_ref"))
+    sure = brute_sets(xr, yr, zr, rl - 1e-5)
+    loose = brute_sets(xr, yr, zr, rl + 1e-5)
+    got = b.neighbor_rows(r)
+    for i in range(len(sure)):
+        g = set(got[i].tolist())
+        assert len(g) == got[i].size
+        assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
+    # the pruned lists the pair passes read hold every pair within r_tail
+    # and within (r_tail, r_cut) at the current positions
+    x, y, z = b.positions(r)
+    P = np.stack([x, y, z], 1)
+    cnt = b.active_counts(r)
+    for i in range(P.shape[0]):
+        d = np.sqrt(((P - P[i]) ** 2).sum(1))
+        d[i] = np.inf
+        edge_t = int(np.count_nonzero(np.abs(d - rt) < 1e-4))
+        edge_c = int(np.count_nonzero(np.abs(d - rc) < 1e-4))
+        assert abs(cnt[i, 0] - np.count_nonzero(d <= rt)) <= edge_t, (r, i)
+        assert abs(cnt[i].sum() - np.count_nonzero(d <= rc)) <= edge_c, (r, i)
+
+
 def test_lists_stay_exact_through_in_step_rebuilds_and_pruning():
     # a short skin makes the wires rebuild and prune several times in the
     # step loops, at different steps (a few replicas at a time, through the
@@ -173,30 +199,25 @@ def test_lists_stay_exact_through_in_step_rebuilds_and_pruning():
     st = b.status()
     assert not np.any(st & (A.ST_OVERFLOW | A.ST_NONFINITE | A.ST_OUTSIDE))
     assert st[0] & A.ST_REBUILT and st[2] & A.ST_REBUILT and st[3] & A.ST_REBUILT
-    rl = b.pot.r_cut + b.skin
-    rt, rc = b.pot.r_tail, b.pot.r_cut
     for r in range(b.R):
-        # the Verlet lists are exact at the positions of their last build
-        xr, yr, zr = (b._slice(k, r).astype(np.float64) for k in ("x_ref", "y_ref", "z_ref"))
-        sure = brute_sets(xr, yr, zr, rl - 1e-5)
-        loose = brute_sets(xr, yr, zr, rl + 1e-5)
-        got = b.neighbor_rows(r)
-        for i in range(len(sure)):
-            g = set(got[i].tolist())
-            assert len(g) == got[i].size
-            assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
-        # the pruned lists the pair passes read hold every pair within r_tail
-        # and within (r_tail, r_cut) at the current positions
-        x, y, z = b.positions(r)
-        P = np.stack([x, y, z], 1)
-        cnt = b.active_counts(r)
-        for i in range(P.shape[0]):
-            d = np.sqrt(((P - P[i]) ** 2).sum(1))
-            d[i] = np.inf
-            edge_t = int(np.count_nonzero(np.abs(d - rt) < 1e-4))
-            edge_c = int(np.count_nonzero(np.abs(d - rc) < 1e-4))
-            assert abs(cnt[i, 0] - np.count_nonzero(d <= rt)) <= edge_t, (r, i)
-            assert abs(cnt[i].sum() - np.count_nonzero(d <= rc)) <= edge_c, (r, i)
+        _check_lists(b, r)
+
+
+def test_lists_stay_exact_past_the_first_1024_replicas():
+    # the work lists are made 1024 replicas at a time: replicas after the
+    # first 1024 rebuild and prune through them as the first ones do
+    reps = [R(15.0, 20.0, T=298.0, r=k) for k in range(1100)]
+    note(f"lists through in-step rebuilds R={len(reps)}")
+    b = WireBatch(reps, "mixed", skin=0.6, prune=0.1)
+    b.prepare()
+    b.run_batch(120, 40)
+    torch.cuda.synchronize()
+    st = b.status()
+    assert not np.any(st & (A.ST_OVERFLOW | A.ST_NONFINITE | A.ST_OUTSIDE))
+    second = [r for r in range(1024, b.R) if st[r] & A.ST_REBUILT]
+    assert len(second) >= 10, len(second)
+    for r in [0, 1023] + second[:3] + [b.R - 1]:
+        _check_lists(b, r)
 
 
 def test_forces_fp64_d1p5_wire():
