@@ -32,7 +32,7 @@
 #define ORC_AMU_KG 1.66053906660e-27          /* kg per amu */
 /* 1 eV/(Angstrom amu) expressed in Angstrom/ps^2 */
 #define ORC_ACC (ORC_EV_J / ORC_AMU_KG * 1.0e-4)
-#define ORC_EVA3_GPA 160.21766208             /* 1 eV/A^3 in GPa */
+#define ORC_EVA3_GPA (ORC_EV_J * 1.0e21)       /* 1 eV/A^3 in GPa */
 
 double orc_const_kb(void) { return ORC_KB; }
 double orc_const_acc(void) { return ORC_ACC; }

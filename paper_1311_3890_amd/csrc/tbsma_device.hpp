@@ -24,7 +24,7 @@ constexpr int kPartQ = 4;   // steps: barostat force sum_top F_z - sum_bottom F_
 // values of the electronvolt and the atomic mass unit.
 constexpr double kBoltz = 8.617333262e-5;
 constexpr double kAccel = 1.602176634e-19 / 1.66053906660e-27 * 1.0e-4;
-constexpr double kEvA3ToGPa = 160.21766208;
+constexpr double kEvA3ToGPa = 1.602176634e-19 * 1.0e21;
 
 // Float constants of the mixed-precision pair kernels.  Distances are in
 // position quanta (2^-qbits A); every scale is folded into the constants.

@@ -411,6 +411,110 @@ def test_observe_gap_and_stress_sign():
     assert oracle.observe(AU, md, st3, 1000.0, 40.8)[4] < obs2[4]
 
 
+# --- the streaming profile, eq 5's kinetic term and the pair counter ---------
+# SI values (CODATA 2018, exact since the 2019 SI) written here independently
+# of the oracle: one amu A^2/ps^2 in eV, one eV/A^3 in GPa, k_B in eV/K.
+AMU_A2_PS2_EV = 1.66053906660e-27 * 1e-20 / 1e-24 / 1.602176634e-19
+EVA3_GPA = 1.602176634e-19 / 1e-30 / 1e9
+KB_EV = 1.380649e-23 / 1.602176634e-19
+
+
+def _free_atoms():
+    """Atoms that never interact: two columns of dynamic atoms along z (10 A
+    apart within a column, the columns 12 A apart in x and staggered by 5 A),
+    a bottom grip atom under each column at z = 0 and a top grip atom over
+    each at z = 100; no two atoms are within r_cut, and a stretch along z only
+    separates them further."""
+    za = np.arange(10.0, 91.0, 10.0)
+    zb = np.arange(15.0, 86.0, 10.0)
+    x = np.concatenate([[0.0, 12.0], np.zeros(za.size), np.full(zb.size, 12.0), [0.0, 12.0]])
+    z = np.concatenate([[0.0, 0.0], za, zb, [100.0, 100.0]])
+    f = np.concatenate([[1, 1], np.zeros(za.size + zb.size), [2, 2]]).astype(np.uint8)
+    return oracle.State(x, np.zeros(x.size), z, f)
+
+
+def test_free_atoms_stay_on_the_affine_stretch_profile():
+    """Reading 8: the Langevin O step acts on the velocity relative to the
+    affine stretch u(z) = v_pull (z - z_lo) / (z_hi - z_lo + D), D the pulled
+    grip's travel.  Free atoms started on that profile at T = 0 move
+    ballistically while the grip is pulled and stay exactly on it, since
+    z - z_lo grows in proportion to z_hi - z_lo + D.  So the O step must leave
+    their velocities unchanged (a profile that missed the + D, or took D at
+    another time than the positions, would pull them off it), and their
+    peculiar kinetic energy and temperature are zero at every step."""
+    st = _free_atoms()
+    md = oracle.MD(T=0.0, gamma=5.0, v_pull=0.5, z_lo=0.0, z_hi=100.0, seed=7, rep_id=2)
+    oracle.init_state(md, st, 0.0)
+    dyn = st.flag == 0
+    # at t = 0 the dynamic atoms move with the profile, the pulled grip at v_pull
+    assert np.array_equal(st.vz[dyn], 0.5 * st.z[dyn] / 100.0)
+    assert np.all(st.vz[st.flag == 2] == 0.5) and np.all(st.vz[st.flag == 1] == 0.0)
+    assert np.all(st.vx == 0.0) and np.all(st.vy == 0.0)
+    oracle.compute_forces(AU, st, 0)
+    assert np.abs(np.stack([st.fx, st.fy, st.fz])).max() == 0.0
+    v0, z_init = st.vz.copy(), st.z.copy()
+    for _ in range(5):
+        oracle.run(AU, md, st, 400, 0)
+        t = st.step * md.dt
+        assert np.abs(st.vz[dyn] - v0[dyn]).max() <= 1e-11 * v0.max()
+        assert np.abs(st.z[dyn] - (z_init[dyn] + v0[dyn] * t)).max() < 1e-10
+        assert np.all(st.vx == 0.0) and np.all(st.vy == 0.0)
+        ob = oracle.observe(AU, md, st, 1.0, 100.0)
+        assert ob[1] < 1e-26 and ob[2] < 1e-20, ob   # peculiar KE (eV) and T (K)
+        assert abs(ob[7] - 0.5 * t) < 1e-12 and abs(ob[5] - 0.5 * t / 100.0) < 1e-14
+    # the top grip moved rigidly at v_pull, the bottom one rested
+    assert abs(st.z[-1] - (100.0 + 0.5 * st.step * md.dt)) < 1e-12 and st.z[0] == 0.0
+
+
+def test_stress_of_an_ideal_gas_is_its_kinetic_term():
+    """Eq 5 for atoms that do not interact: the virial term vanishes and
+    sigma_zz is the kinetic term alone, -sum_i m v_z,i^2 / V over the dynamic
+    atoms (reading 12: the printed m v_x,i v_x,j is m v_z,i^2; reading 13: V
+    is the volume passed in).  Transverse velocities enter the kinetic energy
+    and the temperature (3 N_dyn - 3 degrees of freedom), not sigma_zz; grip
+    velocities enter none of them."""
+    st = _free_atoms()
+    rng = np.random.default_rng(5)
+    st.vx, st.vy, st.vz = (rng.normal(size=st.x.size) * 3.0 for _ in range(3))
+    md = oracle.MD(v_pull=0.0, z_lo=0.0, z_hi=100.0)   # at rest: u = 0
+    vol = 1234.5
+    ob = oracle.observe(AU, md, st, vol, 100.0)
+    dyn = st.flag == 0
+    m = oracle.MASS_AU
+    kz = m * (st.vz[dyn] ** 2).sum() * AMU_A2_PS2_EV
+    ke = 0.5 * m * (st.vx[dyn] ** 2 + st.vy[dyn] ** 2 + st.vz[dyn] ** 2).sum() * AMU_A2_PS2_EV
+    assert ob[3] == 0.0                                            # -W_zz
+    assert abs(ob[4] - (-kz / vol * EVA3_GPA)) <= 1e-12 * abs(ob[4])
+    assert abs(ob[1] - ke) <= 1e-12 * ke
+    assert abs(ob[2] - 2.0 * ke / ((3 * dyn.sum() - 3) * KB_EV)) <= 1e-9 * ob[2]
+    # the lab frame and a pulled grip change nothing when u is the lab velocity
+    md2 = oracle.MD(v_pull=0.5, z_lo=0.0, z_hi=100.0, lab_frame=1)
+    assert np.array_equal(oracle.observe(AU, md2, st, vol, 100.0)[[1, 2, 3, 4]], ob[[1, 2, 3, 4]])
+
+
+def test_pair_counter_equals_brute_force_at_the_radius():
+    """The pair counter that checks the neighbour lists (count_pairs) equals
+    an independent numpy brute force on a jittered wire, and counts strictly
+    inside the radius: of two isolated pairs placed 1e-9 A inside and 1e-9 A
+    outside it, only the first counts, for both of its atoms."""
+    x, y, z, _ = oracle.build_wire(4.08, 20.0, 30.6, 2)
+    rng = np.random.default_rng(11)
+    P = np.stack([x, y, z], 1) + rng.uniform(-0.3, 0.3, (x.size, 3))
+    rc = 8.0
+    for k, d in enumerate((rc - 1e-9, rc + 1e-9)):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        c = np.array([200.0 + 50.0 * k, 0.0, 0.0])
+        P = np.vstack([P, c, c + d * u])
+    cnt = oracle.count_pairs(P[:, 0], P[:, 1], P[:, 2], rc)
+    d2 = ((P[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    ref = (d2 < rc * rc).sum(1)
+    assert np.array_equal(cnt, ref)
+    assert list(cnt[-4:]) == [1, 1, 0, 0]
+    assert ref[:-4].min() > 20
+
+
 # --- the paper's protocol: Nose-Hoover thermostat, stepwise grips, notch ----
 def _nh_extended_energy(st, md, kb, acc):
     dyn = st.flag == 0
