@@ -55,7 +55,13 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="batch512-d3", choices=["d3-l20", "batch512-d3", "batch2048-mixed", "d10-l100"])
-    ap.add_argument("--steps-per-graph", type=int, default=50)
+    ap.add_argument("--steps-per-graph", type=int, default=50,
+                    help="steps per captured graph (clamped to --steps, so that every "
+                         "timed step runs from a graph whenever it divides --steps)")
+    ap.add_argument("--thermalize", type=int, default=1000,
+                    help="untimed steps run in setup before the warmup, so that the "
+                         "timed window starts from thermal positions with lists "
+                         "rebuilt there (not from the perfect lattice)")
     ap.add_argument("--per-replica", type=int, default=32,
                     help="replicas timed one per launch for the plain-path rate")
     ap.add_argument("--per-replica-steps", type=int, default=20)
@@ -104,11 +110,22 @@ def main():
                   skin=skin, prune=prune, gamma=wl.gamma)
     b.prepare()
     n_real = int(b.n_atoms.sum())
-    S = args.steps_per_graph
+    S = max(1, min(args.steps_per_graph, args.steps))
     log(f"[bench] {b.R} replicas, {n_real} atoms ({b.N} slots), qbits {b.qbits}; "
-        f"warmup {args.warmup}")
+        f"thermalize {args.thermalize}, warmup {args.warmup}, {S} steps per graph")
+    lib = A.lib()
+
+    def events():
+        out = (C.c_int64 * 2)()
+        A.check(lib.tbsma_event_counts(C.byref(b.params), C.byref(b.sys), b.work, out,
+                                       b.stream()))
+        return out[0], out[1]
+
+    if args.thermalize > 0:
+        b.run_batch(args.thermalize, S)
     b.run_batch(args.warmup, S)
     torch.cuda.synchronize()
+    ev_before = events()
 
     # ---- timed region: K steps of the batched graph path -----------------------------
     stream = torch.cuda.current_stream()
@@ -121,13 +138,18 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     value = n_real * args.steps / (ms * 1e-3)
-    log(f"[bench] batched: {args.steps} steps in {ms:.1f} ms -> {value:.4e} atom-steps/s")
+    ev_after = events()
+    window = {"graph_replays": args.steps // S, "eager_steps": args.steps % S,
+              "replica_rebuilds": ev_after[0] - ev_before[0],
+              "replica_prunings": ev_after[1] - ev_before[1],
+              "first_step": b.step_index() - args.steps}
+    log(f"[bench] batched: {args.steps} steps in {ms:.1f} ms -> {value:.4e} atom-steps/s; "
+        f"window {window}")
     st = b.status()
     bad = int(np.count_nonzero(st & (A.ST_NONFINITE | A.ST_OVERFLOW)))
 
     # ---- per-kernel timing of the two force passes (HIP events, same stream) ----------
     kbar = b.mean_neighbors()
-    lib = A.lib()
 
     def time_pass(p):
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -344,7 +366,9 @@ def main():
                    "precision": "f32 pair math, f64 integration and sums",
                    "steps_per_graph": S, "skin_A": cfg["skin_A"], "r_cut_A": cfg["r_cut_A"],
                    "prune_A": cfg["prune_A"],
+                   "thermalized_steps": args.thermalize,
                    "parallelism": "replica batch, 1 GPU"},
+        "window": window,
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
                      "traffic": counter_traffic("k_force_mixed", wl.name),

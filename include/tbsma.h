@@ -481,6 +481,27 @@ int tbsma_rng_fill(uint64_t seed, uint32_t rep_id, uint64_t step,
                    uint32_t stream_id, int64_t n, uint32_t *out_u32,
                    double *out_gauss, void *stream);
 
+/*
+ * The three FP32 normals that the MIXED Langevin O step draws for counter
+ * (tag, lo32(step), rep_id, stream_id) and key (lo32(seed), hi32(seed)),
+ * tag = 0 .. n-1, written to out_gauss[3 tag ..] (device buffer): the same
+ * Philox words and Box-Muller form as tbsma_rng_fill, in FP32, each within
+ * a few FP32 ulp of the FP64 normal (the noise of Simulation details'
+ * thermostat, replayable from its counter).
+ */
+int tbsma_rng_normals_f32(uint64_t seed, uint32_t rep_id, uint64_t step,
+                          uint32_t stream_id, int64_t n, float *out_gauss,
+                          void *stream);
+
+/*
+ * Counters of the step loops (tbsma_step, tbsma_run_batch) since the
+ * workspace was initialised: out_host[0] = replica neighbour-list rebuilds,
+ * out_host[1] = replica prunings of the pair-pass lists without a rebuild.
+ * Diagnostics; synchronises.
+ */
+int tbsma_event_counts(const tbsma_params *prm, const tbsma_system *sys,
+                   void *work, int64_t *out_host, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *tbsma_last_error(void);
 

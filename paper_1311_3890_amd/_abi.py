@@ -86,6 +86,9 @@ SIGNATURES = {
     "tbsma_list_stats": (C.c_int, [P(Params), P(System), P(NList), vp, P(C.c_int64), vp]),
     "tbsma_rng_fill": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int64,
                                  vp, vp, vp]),
+    "tbsma_rng_normals_f32": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32,
+                                        C.c_int64, vp, vp]),
+    "tbsma_event_counts": (C.c_int, [P(Params), P(System), vp, P(C.c_int64), vp]),
     "tbsma_last_error": (C.c_char_p, []),
 }
 

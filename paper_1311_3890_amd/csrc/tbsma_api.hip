@@ -851,8 +851,41 @@ int tbsma_rng_fill(uint64_t seed, uint32_t rep_id, uint64_t step,
   if (n == 0) return TBSMA_OK;
   TRY(check_device());
   launch_rng_fill(seed, rep_id, step, stream_id, n, out_u32, out_gauss,
-                  static_cast<hipStream_t>(stream));
+                  nullptr, static_cast<hipStream_t>(stream));
   HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_rng_normals_f32(uint64_t seed, uint32_t rep_id, uint64_t step,
+                          uint32_t stream_id, int64_t n, float *out_gauss,
+                          void *stream) {
+  if (n < 0) return fail(TBSMA_EINVAL, "n < 0");
+  if (n > 0 && !out_gauss) return fail(TBSMA_EINVAL, "out_gauss is NULL");
+  if (n == 0) return TBSMA_OK;
+  TRY(check_device());
+  launch_rng_fill(seed, rep_id, step, stream_id, n, nullptr, nullptr,
+                  out_gauss, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_event_counts(const tbsma_params *prm, const tbsma_system *sys,
+                   void *work, int64_t *out_host, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!out_host) return fail(TBSMA_EINVAL, "out_host is NULL");
+  out_host[0] = out_host[1] = 0;
+  if (sys->R == 0) return TBSMA_OK;
+  if (!work) return fail(TBSMA_EINVAL, "work is NULL");
+  TRY(check_device());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(prm, sys, work);
+  int64_t h[2];
+  HIPCHK(hipMemcpyAsync(h, d.callb + kCallRebuilds, sizeof(h),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out_host[0] = h[0];
+  out_host[1] = h[1];
   return TBSMA_OK;
 }
 

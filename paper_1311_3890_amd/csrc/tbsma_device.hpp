@@ -83,10 +83,11 @@ struct Dev {
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
   int32_t *wl;                  // work lists of a step (see work_lists)
-  int64_t *callb;               // [3] first step and end step of the current
-                                // step-loop call, and the step flags of the
+  int64_t *callb;               // first step and end step of the current
+                                // step-loop call, the step flags of the
                                 // current step (kStepLog, kStepKick,
-                                // kStepPend)
+                                // kStepPend), and the step-loop counters
+                                // (kCallRebuilds, kCallPrunes)
   // when the mixed force pass computes energies and the virial: 1 always,
   // 0 never, -1 when the step being completed is logged ((*step + 1) %
   // n_log == 0, the step loops)
@@ -308,26 +309,49 @@ __device__ __forceinline__ void gauss3(uint64_t seed, uint32_t rep,
   n2 = b * cos(twopi * u01(o.w));
 }
 
-// The same three normals in FP32 (mixed precision): u = (w/2^8 + 1/2) 2^-24
-// from the top 24 bits of each word; sqrt(-2 ln u) from the hardware log2,
-// cos/sin(2 pi u) from the hardware sine and cosine, whose argument is in
-// revolutions.
+// -2 ln u for the uniform u = (w + 1/2) 2^-32 of a Philox word, in FP32 with
+// a relative error of a few ulp over the whole of (0, 1).  Below 1/2, u is
+// formed from 2w + 1 with one rounding.  From 1/2 on, v = 1 - u = (~w + 1/2)
+// 2^-32 is formed the same way (exactly, before that rounding) and
+// ln u = ln(1 - v) is taken as ln(y) (-v) / (y - 1) with y = 1 - v rounded,
+// Goldberg's correction for log(1 + x) (y - 1 is exact for y in [1/2, 1]),
+// so that draws next to 1 keep their relative precision instead of being
+// cancelled to the ulp of 1.
+__device__ __forceinline__ float m2ln_u01f(uint32_t w) {
+  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  const bool low = w < 0x80000000u;
+  const uint32_t h = low ? w : ~w;  // below 2^31 either way
+  const float t = (float)(2u * h + 1u) * 0x1p-33f;  // u (low) or v = 1 - u
+  if (low) return m2ln2 * __builtin_amdgcn_logf(t);
+  const float y = 1.0f - t;
+  const float d = y - 1.0f;
+  return d == 0.0f ? 2.0f * t : m2ln2 * __builtin_amdgcn_logf(y) * (-t / d);
+}
+
+// The angle 2 pi u of a Philox word as the revolution count u - [u >= 1/2] in
+// [-1/2, 1/2): the same sine and cosine, with the argument's rounding error
+// bounded by 2^-25 of a revolution.
+__device__ __forceinline__ float rev_u01f(uint32_t w) {
+  return fmaf((float)(int32_t)w, 0x1p-32f, 0x1p-33f);
+}
+
+// The same three normals as gauss3 in FP32 (mixed precision), from the same
+// Philox words: sqrt(-2 ln u) with u of full relative precision (m2ln_u01f),
+// and the sine and cosine of pi (2 t) for the revolution count t of rev_u01f
+// (sincospif, cospif), so that each normal is within a few FP32 ulp of the
+// FP64 value.
 __device__ __forceinline__ void gauss3f(uint64_t seed, uint32_t rep,
                                         uint32_t tag, uint64_t step,
                                         uint32_t stream, float &n0, float &n1,
                                         float &n2) {
   uint4 o = rng_words(seed, rep, tag, step, stream);
-  const float s24 = 0x1p-24f;
-  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
-  float u0 = ((float)(o.x >> 8) + 0.5f) * s24;
-  float u1 = ((float)(o.y >> 8) + 0.5f) * s24;
-  float u2 = ((float)(o.z >> 8) + 0.5f) * s24;
-  float u3 = ((float)(o.w >> 8) + 0.5f) * s24;
-  float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
-  float b = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
-  n0 = a * __builtin_amdgcn_cosf(u1);
-  n1 = a * __builtin_amdgcn_sinf(u1);
-  n2 = b * __builtin_amdgcn_cosf(u3);
+  const float a = __builtin_amdgcn_sqrtf(m2ln_u01f(o.x));
+  const float b = __builtin_amdgcn_sqrtf(m2ln_u01f(o.z));
+  float s1, c1;
+  sincospif(2.0f * rev_u01f(o.y), &s1, &c1);
+  n0 = a * c1;
+  n1 = a * s1;
+  n2 = b * cospif(2.0f * rev_u01f(o.w));
 }
 
 // Order-preserving map of a double to an unsigned key (for atomic min/max).
@@ -345,6 +369,11 @@ __device__ __forceinline__ double dkey_inv(unsigned long long k) {
 // the force pass does its second half kick; the position update first
 // applies the previous step's deferred kick (DevMD::defer).
 constexpr int64_t kStepLog = 1, kStepKick = 2, kStepPend = 4;
+
+// Counters in callb, advanced by the step loops' work-list kernel since the
+// workspace was initialised: replica list rebuilds, and replica prunings
+// without a rebuild.
+constexpr int kCallRebuilds = 3, kCallPrunes = 4;
 
 // The flags of step m of the call recorded in callb (see kStepLog).
 __device__ __forceinline__ int64_t step_flags(const DevMD &M,

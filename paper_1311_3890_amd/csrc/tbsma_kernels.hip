@@ -713,6 +713,16 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
       reb = rebuilds(S, r);
       upd = reb || prunes(S, r);
     }
+    if (S.rstatus != nullptr) {
+      // step loops: replicas rebuilt, and pruned without a rebuild
+      const unsigned long long br = __ballot(reb), bp = __ballot(upd && !reb);
+      if (lane == 0 && (br | bp)) {
+        unsigned long long *ctr = reinterpret_cast<unsigned long long *>(
+            S.callb + kCallRebuilds);
+        atomicAdd(ctr, (unsigned long long)__popcll(br));
+        atomicAdd(ctr + 1, (unsigned long long)__popcll(bp));
+      }
+    }
     const int32_t nb = (nt + 3) >> 2;
     const int32_t ncb = (nc + kSortCells - 1) / kSortCells;
     const int32_t v[kL] = {reb ? nt : 0, upd ? nb : 0, reb ? ncb : 0,
@@ -1359,9 +1369,10 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
       const float Vt = u * (u * fmaf(vb, u, va));
       const float V = tail ? Vt : __builtin_amdgcn_exp2f(fmaf(aV, rr, bV));
       ev += on ? V : 0.0f;
-      const float sz = s * dz;
-      az += sz;
-      wz = fmaf(sz, dz, wz);
+      // f_z as the same fused multiply-add as without energies, so that the
+      // forces, and the trajectory, do not depend on which steps are logged
+      az = fmaf(s, dz, az);
+      wz = fmaf(s * dz, dz, wz);
     } else {
       az = fmaf(s, dz, az);
     }
@@ -2025,8 +2036,8 @@ __global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
       sy = vy;
       sz = vz;
       cn = 1.0;
-    } else if (f == 2 && M.grip_hold == 0) {
-      vz = M.v_pull[r];
+    } else if (f == 2 && M.grip_hold == 0 && M.baro_mass <= 0.0) {
+      vz = M.v_pull[r];  // pulled grip (it rests under the barostat)
     }
     S.vx[i] = vx;
     S.vy[i] = vy;
@@ -2123,7 +2134,7 @@ __global__ void __launch_bounds__(kBlock) k_init_c(Dev S, DevMD M) {
 
 __global__ void k_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
                            uint32_t stream, int64_t n, uint32_t *w,
-                           double *g) {
+                           double *g, float *gf) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   if (w) {
@@ -2139,6 +2150,13 @@ __global__ void k_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
     g[3 * t + 0] = a;
     g[3 * t + 1] = b;
     g[3 * t + 2] = c;
+  }
+  if (gf) {
+    float a, b, c;
+    gauss3f(seed, rep, (uint32_t)t, step, stream, a, b, c);
+    gf[3 * t + 0] = a;
+    gf[3 * t + 1] = b;
+    gf[3 * t + 2] = c;
   }
 }
 
@@ -2361,9 +2379,10 @@ void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
 
 void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
                      uint32_t stream, int64_t n, uint32_t *w, double *g,
-                     hipStream_t s) {
+                     float *gf, hipStream_t s) {
   if (n > 0)
-    k_rng_fill<<<nblk(n, 256), 256, 0, s>>>(seed, rep, step, stream, n, w, g);
+    k_rng_fill<<<nblk(n, 256), 256, 0, s>>>(seed, rep, step, stream, n, w, g,
+                                            gf);
 }
 
 }  // namespace tbsma

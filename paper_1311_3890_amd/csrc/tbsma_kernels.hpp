@@ -51,8 +51,9 @@ void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
 void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s);
 void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
                  hipStream_t s);
+// Philox words, FP64 normals and FP32 normals (each output may be NULL).
 void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
                      uint32_t stream, int64_t n, uint32_t *w, double *g,
-                     hipStream_t s);
+                     float *gf, hipStream_t s);
 
 }  // namespace tbsma

@@ -201,16 +201,6 @@ int main() {
   int64_t st2[2];
   check(tbsma_list_stats(&p, &s1, &nl, nullptr, st2, nullptr) == TBSMA_EINVAL,
         "list_stats: NULL work");
-  // the allocation-free entry point refuses systems beyond its fixed scratch
-  std::vector<int64_t> rep_big = {0, int64_t(1) << 21}, cel_big = {0, 4096};
-  tbsma_system sb = system(1, rep_big, cel_big);
-  check(tbsma_forces_noalloc(&p, &sb, &cells, &nl, &out, nullptr, nullptr) ==
-                TBSMA_ECAPACITY &&
-            msg_has("scratch"),
-        "noalloc: scratch size");
-  check(tbsma_forces_noalloc(&p, &s1, nullptr, &nl, &out, nullptr, nullptr) ==
-            TBSMA_EINVAL,
-        "noalloc: NULL cells");
   std::vector<int64_t> rep0 = {0}, cel0 = {0};
   tbsma_system s0 = system(0, rep0, cel0);
   check(tbsma_step(&p, &s0, &cells, &nl, &out, &md, nullptr, 0, nullptr) ==

@@ -103,6 +103,48 @@ def test_rng_words_and_normals():
             assert np.abs(gh[t] - oracle.gauss3(seed, rep, t, step, strm)).max() < 1e-14
 
 
+def test_fp32_normals_match_the_fp64_normals():
+    """The normals of the mixed-precision Langevin O step are the FP64
+    Box-Muller normals of the same Philox words within a few FP32 ulp:
+    |n32 - n64| <= 2^-20 (1 + a), a = sqrt(-2 ln u) the Box-Muller radius of
+    the normal.  (FP32 uniforms of relative precision 2^-24, the log-near-1
+    correction and sin/cos of pi x give a relative error of about 3e-7 on a
+    and an absolute one of about 3e-7 on the sine and cosine.)  Checked on
+    all 2^24 counters of one step against the GPU's FP64 normals, and on
+    every counter whose words sit within 2^-20 of 0, 1/2 or 1 against the
+    oracle."""
+    n = 1 << 24
+    seed, rep, step, strm = W.seed_of(3), 3, 987654321, 0
+    note(f"fp32 normals, {n} counters")
+    w = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    g64 = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    g32 = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    lib = A.lib()
+    A.check(lib.tbsma_rng_fill(seed, rep, step, strm, n, C.c_void_p(w.data_ptr()),
+                               C.c_void_p(g64.data_ptr()), None))
+    A.check(lib.tbsma_rng_normals_f32(seed, rep, step, strm, n, C.c_void_p(g32.data_ptr()),
+                                      None))
+    torch.cuda.synchronize()
+    wu = w.view(n, 4).to(torch.int64) & 0xFFFFFFFF
+    u = (wu.double() + 0.5) * 2.0 ** -32
+    rad = torch.sqrt(-2.0 * torch.log(u))  # radius of (u0) and of (u2)
+    tol = 2.0 ** -20 * (1.0 + torch.stack([rad[:, 0], rad[:, 0], rad[:, 2]], 1))
+    err = (g32.view(n, 3).double() - g64.view(n, 3)).abs()
+    note(f"  max |n32 - n64| = {err.max().item():.2e}, max err/tol = "
+         f"{(err / tol).max().item():.3f}")
+    assert bool((err <= tol).all())
+    # words at the ends of (0, 1) and at 1/2, where the uniforms round most
+    edge = 1 << 12
+    near = ((wu < edge) | (wu >= (1 << 32) - edge) | ((wu - (1 << 31)).abs() < edge)).any(1)
+    tags = torch.nonzero(near).flatten().cpu().numpy()
+    assert tags.size >= 50, tags.size
+    g32h = g32.view(n, 3).double().cpu().numpy()
+    tolh = tol.cpu().numpy()
+    for t in tags:
+        ref = oracle.gauss3(seed, rep, int(t), step, strm)
+        assert np.all(np.abs(g32h[t] - ref) <= tolh[t]), (t, g32h[t], ref)
+
+
 def brute_sets(x, y, z, rl):
     P = np.stack([x, y, z], 1)
     out = []
@@ -113,16 +155,22 @@ def brute_sets(x, y, z, rl):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_neighbor_lists_are_exact_sets(precision):
+@pytest.mark.parametrize("precision,cell", [("fp64", None), ("mixed", None), ("fp64", 12.0),
+                                            ("mixed", 12.0)])
+def test_neighbor_lists_are_exact_sets(precision, cell):
     # the 4.4 nm wire's z-slabs hold more candidates than LDS stages, so its
-    # mixed-precision lists come from the cell walk
+    # mixed-precision lists come from the cell walk; 12 A cells hold about
+    # 100 atoms inside the wires, more than the 64 the cell sort ranks in
+    # registers (larger cells take its insertion sort)
     reps = [R(15.0, 30.0, r=0, jitter=0.1), R(20.0, 20.0, T=298.0, r=1, jitter=0.1),
             R(30.0, 40.0, r=2, jitter=0.1), R(44.0, 30.0, r=3, jitter=0.1)]
-    note(f"nlist sets {precision} R={len(reps)}")
-    b = WireBatch(reps, precision)
+    note(f"nlist sets {precision} cell={cell} R={len(reps)}")
+    b = WireBatch(reps, precision, cell=cell)
     b.prepare()
     torch.cuda.synchronize()
+    cs = b.t["cell_start"].cpu().numpy()
+    if cell is not None:
+        assert np.diff(cs).max() > 64
     rl = b.pot.r_cut + b.skin
     # FP64 lists are exact; mixed ones compare quantised positions, so pairs
     # within 1e-5 A of r_cut + skin may fall on either side
@@ -152,8 +200,22 @@ def test_neighbor_lists_are_exact_sets(precision):
                 edge_c = int(np.count_nonzero(np.abs(d - rc) < 1e-4))
                 assert abs(cnt[i, 0] - np.count_nonzero(d <= rt)) <= edge_t, (r, i)
                 assert abs(cnt[i].sum() - np.count_nonzero(d <= rc)) <= edge_c, (r, i)
+    if cell is not None:
+        # every cell's slots in ascending order, and every real atom binned once
+        ca = b.t["cell_atoms"].cpu().numpy()
+        for r in range(b.R):
+            st = cs[int(b.cell_off[r]) + r:int(b.cell_off[r + 1]) + r + 1]
+            for c in range(st.size - 1):
+                assert np.all(np.diff(ca[st[c]:st[c + 1]]) > 0), (r, c)
+            o = int(b.rep_off[r])
+            assert np.array_equal(np.sort(ca[st[0]:st[-1]]), o + np.arange(int(b.n_atoms[r])))
+        forces = stackF(b.forces(2))
+        x, y, z = b.positions(2)
+        ref = oracle.forces(AU, x, y, z, 0)
+        assert eps_F(forces, stackF((ref["fx"], ref["fy"], ref["fz"]))) <= (
+            1e-12 if precision == "fp64" else 1e-5)
     # rows are stored in ascending cell-scan order: check determinism
-    b2 = WireBatch(reps, precision)
+    b2 = WireBatch(reps, precision, cell=cell)
     b2.prepare()
     torch.cuda.synchronize()
     assert torch.equal(b.t["nl"], b2.t["nl"]) and torch.equal(b.t["nn"], b2.t["nn"])
@@ -278,10 +340,14 @@ def test_forces_mixed_ragged_batch():
         assert torch.all(b.t["fx"][o + n:e] == 0) and torch.all(b.t["e_atom"][o + n:e] == 0)
 
 
-def test_init_state_matches_oracle():
+@pytest.mark.parametrize("kw", [{}, dict(baro_mass=300.0, baro_damp=2.0)],
+                         ids=["pulled", "barostat"])
+def test_init_state_matches_oracle(kw):
+    """Jitter and Maxwell-Boltzmann velocities equal the oracle's; the pulled
+    grip starts at v_pull, or at rest when the barostat moves the grips."""
     rp = R(20.0, 30.0, T=298.0, v=0.5, r=5, jitter=0.02)
-    note("init state fp64")
-    b = WireBatch([rp], "fp64")
+    note(f"init state fp64 {kw}")
+    b = WireBatch([rp], "fp64", gamma=0.0 if kw else 1.0, **kw)
     b.init_state()
     torch.cuda.synchronize()
     x0, y0, z0, f = oracle.build_wire(4.08, rp.D, rp.L, 2)
@@ -295,6 +361,8 @@ def test_init_state_matches_oracle():
     assert np.abs(v - vr).max() < 1e-12 * np.abs(vr).max()
     o = oracle.observe(AU, md, st, 1.0, rp.L)
     assert abs(o[2] - 298.0) < 1e-8
+    vz_grip = v[b.flags(0) == A.GRIP_PULL, 2]
+    assert np.all(vz_grip == (0.0 if kw else 0.5))
 
 
 def test_step_fp64_lockstep_with_oracle():
@@ -439,6 +507,69 @@ def test_langevin_with_temperature_ramp_lockstep_with_oracle():
         assert dx < 1e-11 and dv < 1e-9
 
 
+@pytest.mark.parametrize("precision,lab", [("mixed", 0), ("mixed", 1), ("fp64", 1)])
+def test_langevin_pulled_lockstep_with_oracle(precision, lab):
+    """The benchmark's dynamics: BAOAB Langevin at 298 K with the top grip
+    pulled at 0.5 A/ps, in the thermostat frame of the stretch profile or in
+    the lab frame.  The GPU draws its noise from the same Philox counters as
+    the oracle (FP32 normals in mixed precision), and in mixed precision
+    leaves the second half kick of the 9 unlogged steps of each 10-step call
+    to the next step's position update.  Positions and velocities follow the
+    oracle step for step (FP64 to rounding, mixed within its force error),
+    and so do the observables of the logged steps."""
+    rp = R(20.0, 40.0, T=298.0, v=0.5, r=11, jitter=0.01)
+    note(f"langevin pulled lockstep {precision} lab_frame={lab}, 60 steps")
+    b = WireBatch([rp], precision, n_log=10, lab_frame=lab)
+    b.prepare()
+    torch.cuda.synchronize()
+    st = orc_state(b, 0)
+    oracle.compute_forces(AU, st, 0)
+    md = orc_md(b, 0)
+    assert md.lab_frame == lab and md.gamma == 1.0 and md.v_pull == 0.5
+    tol_x, tol_v, tol_o = ((1e-11, 1e-9, 1e-9) if precision == "fp64" else (1e-5, 1e-4, 1e-4))
+    for k in range(6):
+        b.step(10)
+        oracle.run(AU, md, st, 10, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+        note(f"  after {10 * (k + 1)} steps: |dx| {dx:.2e} |dv| {dv:.2e}")
+        assert dx < tol_x and dv < tol_v
+        ob = b.obs_at(10 * (k + 1))[0]
+        orf = oracle.observe(AU, md, st, b.vol[0], b.L0[0])
+        for k_gpu, k_or in ((A.OBS_EPOT, 0), (A.OBS_KE, 1), (A.OBS_T, 2), (A.OBS_WZZ, 3),
+                            (A.OBS_SZZ, 4), (A.OBS_STRAIN, 5), (A.OBS_D, 7)):
+            assert abs(ob[k_gpu] - orf[k_or]) <= tol_o * max(1.0, abs(orf[k_or])), (k_gpu, ob, orf)
+    f = b.flags(0)
+    assert np.all(b.velocities(0)[2][f == A.GRIP_PULL] == 0.5)
+
+
+def test_deferred_kick_leaves_trajectories_unchanged_bitwise():
+    """In mixed precision the second half kick of an unlogged step is done by
+    the next step's position update instead of the force pass, and the force
+    pass takes its energy branch on logged steps only.  Logging every step
+    (no deferred kicks, energies every step) or every 25th step (deferred
+    kicks, energies rarely) gives the same positions, velocities and forces
+    bit for bit, in the graph loop and in the plain loop."""
+    reps = _three_replicas()
+    note("deferred kick: n_log 1 vs 25 vs 7, 100 steps mixed")
+    a = WireBatch(reps, "mixed", n_log=1)
+    a.prepare()
+    a.run_batch(100, 50)
+    b = WireBatch(reps, "mixed", n_log=25, qbits=a.qbits)
+    b.prepare()
+    b.run_batch(100, 50)
+    c = WireBatch(reps, "mixed", n_log=7, qbits=a.qbits)
+    c.prepare()
+    c.step(100)  # the call ends on an unlogged step, which then kicks itself
+    for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz"):
+        assert torch.equal(a.t[k], b.t[k]), k
+        assert torch.equal(a.t[k], c.t[k]), k
+    assert a.step_index() == b.step_index() == c.step_index() == 100
+    assert np.array_equal(a.obs_at(100), b.obs_at(100))
+
+
 def test_nose_hoover_extended_energy_is_conserved_in_mixed_precision():
     """Resting grips, Nose-Hoover from 600 K towards 300 K in the batched
     graph loop: E_pot + K + Q zeta^2/2 + g kB T eta stays within the mixed
@@ -468,7 +599,7 @@ def test_nose_hoover_extended_energy_is_conserved_in_mixed_precision():
 
 def test_d1p5_wire_end_to_end_forces_every_step():
     """The D 1.5 x L 3 nm wire: 1000 FP64 steps at 10 K with the top grip pulled at 0.5 A/ps;
-    forces and energies checked against the oracle at every step."""
+    forces and per-atom energies checked against the oracle at every step."""
     wl = W.wire_d1p5_l3_fp64()
     note("D1.5 x L3 nm end-to-end 1000 steps fp64")
     b = WireBatch(wl.replicas, "fp64", n_log=100)
@@ -481,14 +612,57 @@ def test_d1p5_wire_end_to_end_forces_every_step():
         e = eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"])))
         worst = max(worst, e)
         assert e <= 1e-12, s
+        assert np.abs(b.energies(0) - ref["e_atom"]).max() <= 1e-12, s
         if (s + 1) % 100 == 0:
-            assert np.abs(b.energies(0) - ref["e_atom"]).max() <= 1e-12
             note(f"  step {s + 1}: worst eps_F {worst:.2e}")
     assert b.step_index() == 1000
     ob = b.obs_at(1000)[0]
     assert abs(ob[A.OBS_D] - 0.5 * 1000 * 0.002) < 1e-12
     assert abs(ob[A.OBS_STRAIN] - 1.0 / b.L0[0]) < 1e-12
     assert b.status()[0] & (A.ST_NONFINITE | A.ST_OVERFLOW) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paper_hard_cut(precision):
+    """The paper's potential: a hard cut at 5.8 A (r_tail = r_cut, no tail).
+    Forces and energies at a jittered wire equal the oracle's with the same
+    cut; the jitter (0.005 A) keeps every pair at least 0.01 A from the cut,
+    where FP32 distances could otherwise put a pair on either side.  Then 40
+    FP64 steps (10 K, pulled) follow the oracle step for step."""
+    from paper_1311_3890_amd.engine import Potential
+    pot_g = Potential(r_tail=5.8, r_cut=5.8)
+    pot_o = oracle.Pot(r_tail=5.8, r_cut=5.8)
+    rp = R(25.0, 30.0, T=10.0, v=0.5, r=12, jitter=0.005)
+    note(f"hard cut 5.8 A, {precision}")
+    b = WireBatch([rp], precision, pot=pot_g, n_log=10)
+    b.prepare()
+    torch.cuda.synchronize()
+    x, y, z = b.positions(0)
+    P = np.stack([x, y, z], 1)
+    d = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(2))
+    assert np.abs(d - 5.8).min() > 0.01
+    ref = oracle.forces(pot_o, x, y, z, 0)
+    e = eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"])))
+    note(f"  eps_F {e:.2e}")
+    assert e <= (1e-12 if precision == "fp64" else 1e-5)
+    assert abs(b.t["rep_energy"][0].item() - ref["E"]) <= (
+        1e-12 if precision == "fp64" else 1e-6) * abs(ref["E"])
+    # not the 7 A tail: the fifth shell (6.45 A) is cut off
+    ref7 = oracle.forces(AU, x, y, z, 0)
+    assert abs(ref7["E"] - ref["E"]) > 1e-5 * x.size
+    if precision == "fp64":
+        st = orc_state(b, 0)
+        oracle.compute_forces(pot_o, st, 0)
+        md = orc_md(b, 0)
+        for k in range(4):
+            b.step(10)
+            oracle.run(pot_o, md, st, 10, 0)
+            torch.cuda.synchronize()
+            x, y, z = b.positions(0)
+            dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+            dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+            note(f"  after {10 * (k + 1)} steps: |dx| {dx:.2e} |dv| {dv:.2e}")
+            assert dx < 1e-11 and dv < 1e-9
 
 
 def _three_replicas():

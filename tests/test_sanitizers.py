@@ -4,8 +4,7 @@ Two drivers are built in a temporary directory and run:
   * the FP64 oracle (plain C, OpenMP), compiled by gcc with both sanitizers,
     through every one of its entry points on small systems;
   * libtbsma's host code (wire builder, argument and layout checks, workspace
-    sizes, the size check of the allocation-free entry point, error
-    messages), compiled by hipcc with the sanitizers on the host side only;
+    sizes, error messages), compiled by hipcc with the sanitizers on the host side only;
     every call there returns before a device is touched.
 A sanitizer report or a failed check makes the driver exit non-zero.
 """
