@@ -463,6 +463,33 @@ int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,
                     int64_t n_steps, int32_t steps_per_graph, void *stream);
 
 /*
+ * For callers that cannot allocate device memory or hold a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): tbsma_step with the library's own device scratch of
+ * TBSMA_NOALLOC_SCRATCH_BYTES in place of `work`.  The scratch is a static
+ * array of the library, one per device, held until the process ends; the
+ * call allocates nothing.
+ * Because the scratch keeps whatever the previous call on the device left
+ * there, each call first puts it into its initial state (as
+ * tbsma_workspace_init), bins and lists every replica afresh at the current
+ * positions (tbsma_build_cells, tbsma_neighbors), evaluates the forces there
+ * (tbsma_forces: out, including rep_energy and rep_wzz, is written), then
+ * runs the n_steps steps of tbsma_step.  The result equals that sequence on a
+ * freshly initialised workspace.  n_steps = 0 does nothing.
+ * Errors: TBSMA_ECAPACITY when the system's workspace
+ * (tbsma_workspace_query) exceeds TBSMA_NOALLOC_SCRATCH_BYTES, before any
+ * work is enqueued; TBSMA_ECAPACITY after the steps if a list row exceeded
+ * k_cap (as tbsma_step).  Synchronises at the end.
+ * Every call on one device shares the same scratch: calls that overlap on a
+ * device (different streams or host threads) race and must be serialised.
+ */
+#define TBSMA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int tbsma_step_noalloc(const tbsma_params *prm, tbsma_system *sys,
+                       tbsma_cells *cells, tbsma_nlist *nl,
+                       tbsma_forces_out *out, const tbsma_md *md,
+                       int64_t n_steps, void *stream);
+
+/*
  * Diagnostics of the lists: out_host[0] = sum over atoms of nn (the Verlet
  * lists), out_host[1] = sum of the lengths of the lists the mixed pair passes
  * read (pruned; equal to out_host[0] in FP64).  Synchronises.

@@ -83,6 +83,8 @@ SIGNATURES = {
                              vp, C.c_int64, vp]),
     "tbsma_run_batch": (C.c_int, [P(Params), P(System), P(Cells), P(NList), P(ForcesOut),
                                   P(MD), vp, C.c_int64, C.c_int32, vp]),
+    "tbsma_step_noalloc": (C.c_int, [P(Params), P(System), P(Cells), P(NList), P(ForcesOut),
+                                     P(MD), C.c_int64, vp]),
     "tbsma_list_stats": (C.c_int, [P(Params), P(System), P(NList), vp, P(C.c_int64), vp]),
     "tbsma_rng_fill": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int64,
                                  vp, vp, vp]),

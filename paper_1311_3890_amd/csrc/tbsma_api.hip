@@ -18,6 +18,14 @@
 
 using namespace tbsma;
 
+// Device scratch of tbsma_step_noalloc, in place of a caller's workspace.
+// In host code `scratch` names a host-side stand-in, not device memory:
+// kernels and copies get the address that hipGetSymbolAddress returns for
+// the current device (each device holds its own copy of the array).
+static_assert(TBSMA_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+constexpr size_t kScratchBytes = TBSMA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -489,15 +497,124 @@ int finish_run(const Dev &d, const tbsma_md *m, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   int32_t nnmax = 0;
   HIPCHK(hipMemcpy(&nnmax, d.nnmax, 4, hipMemcpyDeviceToHost));
-  std::vector<uint32_t> st(d.R);
-  if (d.R > 0)
-    HIPCHK(hipMemcpy(st.data(), m->status, 4 * (size_t)d.R,
+  // status words read in chunks into a stack buffer (no host allocation)
+  uint32_t st[256];
+  for (int r0 = 0; r0 < d.R; r0 += 256) {
+    const int n = std::min(256, d.R - r0);
+    HIPCHK(hipMemcpy(st, m->status + r0, 4 * (size_t)n,
                      hipMemcpyDeviceToHost));
-  for (int r = 0; r < d.R; ++r)
-    if (st[r] & TBSMA_ST_OVERFLOW)
-      return fail(TBSMA_ECAPACITY,
-                  "neighbour list overflow in replica %d (longest row %d, "
-                  "k_cap %d)", r, nnmax, d.k_cap);
+    for (int k = 0; k < n; ++k)
+      if (st[k] & TBSMA_ST_OVERFLOW)
+        return fail(TBSMA_ECAPACITY,
+                    "neighbour list overflow in replica %d (longest row %d, "
+                    "k_cap %d)", r0 + k, nnmax, d.k_cap);
+  }
+  return TBSMA_OK;
+}
+
+// Bodies of the entry points below, after their argument checks, on an
+// explicit workspace (the caller's, or the library's static scratch).
+int workspace_init_on(const tbsma_params *prm, const tbsma_system *sys,
+                      void *work, hipStream_t s) {
+  Layout L = layout(sys);
+  char *w = static_cast<char *>(work);
+  // zero everything (as 32-bit words), then the min-bins to the empty key
+  launch_fill_u32(reinterpret_cast<uint32_t *>(w), (int64_t)(L.total / 4), 0u,
+                  s);
+  launch_fill_u64(reinterpret_cast<unsigned long long *>(w + L.zbmin),
+                  (int64_t)sys->R * sys->max_zbins, ~0ull, s);
+  launch_block_map(make_dev(prm, sys, work), s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int build_cells_on(const tbsma_params *prm, const tbsma_system *sys,
+                   const tbsma_cells *cells, void *work, hipStream_t s) {
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nullptr);
+  d.all = 1;
+  launch_fill_u32(reinterpret_cast<uint32_t *>(d.cnt), sys->C, 0u, s);
+  launch_worklist(d, s);
+  launch_cells(d, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int neighbors_on(const tbsma_params *prm, const tbsma_system *sys,
+                 const tbsma_cells *cells, const tbsma_nlist *nl, void *work,
+                 int32_t *need_cap, hipStream_t s) {
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nl);
+  d.all = 1;
+  double rl = prm->r_cut + prm->skin;
+  launch_fill_u32(reinterpret_cast<uint32_t *>(d.nnmax), 1, 0u, s);
+  const bool mixed = prm->precision == TBSMA_MIXED;
+  if (mixed) launch_quantise(d, s);
+  launch_worklist(d, s);
+  launch_nlist(d, mixed, rl, s);
+  HIPCHK(hipGetLastError());
+  if (need_cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t mx = 0;
+    HIPCHK(hipMemcpy(&mx, d.nnmax, 4, hipMemcpyDeviceToHost));
+    *need_cap = mx > nl->k_cap ? mx : nl->k_cap;
+    if (mx > nl->k_cap)
+      return fail(TBSMA_ECAPACITY, "longest row %d exceeds k_cap %d", mx,
+                  nl->k_cap);
+  }
+  return TBSMA_OK;
+}
+
+int forces_on(const tbsma_params *prm, const tbsma_system *sys,
+              const tbsma_nlist *nl, const tbsma_forces_out *out, void *work,
+              hipStream_t s) {
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, nullptr, nl);
+  bool mixed = prm->precision == TBSMA_MIXED;
+  if (mixed) launch_quantise(d, s);
+  launch_forces(d, mixed, make_potf(prm), make_potd(prm), out->fx, out->fy,
+                out->fz, out->e_atom, out->g, s);
+  launch_reduce_forces(d, out->rep_energy, out->rep_wzz, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int step_on(const tbsma_params *prm, const tbsma_system *sys,
+            const tbsma_cells *cells, const tbsma_nlist *nl,
+            const tbsma_forces_out *out, const tbsma_md *md, void *work,
+            int64_t n_steps, hipStream_t s) {
+  Dev d = make_dev(prm, sys, work);
+  attach_lists(d, cells, nl);
+  DevMD M = make_devmd(prm, md);
+  PotF PF = make_potf(prm);
+  PotD PD = make_potd(prm);
+  const bool mixed = prm->precision == TBSMA_MIXED;
+  launch_call_bounds(d, M, n_steps, s);
+  if (M.nh_tau > 0 || M.baro_mass > 0)
+    launch_step_begin(d, M, mixed, out->fz, s);
+  for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
+  if (M.nh_tau > 0) launch_nh_finish(d, M, s);
+  return finish_run(d, md, s);
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_ptr(void **out) {
+  static std::mutex mu;
+  static void *ptrs[64] = {nullptr};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(TBSMA_EDEVICE, "device %d", dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TBSMA_EHIP, "hipGetSymbolAddress(scratch): %s",
+                  hipGetErrorString(e));
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
   return TBSMA_OK;
 }
 
@@ -544,18 +661,7 @@ int tbsma_workspace_init(const tbsma_params *prm, const tbsma_system *sys,
   if (sys->R == 0) return TBSMA_OK;
   if (!work) return fail(TBSMA_EINVAL, "work is NULL");
   TRY(check_device());
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Layout L = layout(sys);
-  char *w = static_cast<char *>(work);
-  // zero everything (as 32-bit words), then the min-bins to the empty key
-  launch_fill_u32(reinterpret_cast<uint32_t *>(w), (int64_t)(L.total / 4), 0u,
-                  s);
-  launch_fill_u64(reinterpret_cast<unsigned long long *>(w + L.zbmin),
-                  (int64_t)sys->R * sys->max_zbins, ~0ull, s);
-
-  launch_block_map(make_dev(prm, sys, work), s);
-  HIPCHK(hipGetLastError());
-  return TBSMA_OK;
+  return workspace_init_on(prm, sys, work, static_cast<hipStream_t>(stream));
 }
 
 int tbsma_build_wire(double a, double D, double L, int32_t n_grip,
@@ -629,15 +735,8 @@ int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
   if (!cells) return fail(TBSMA_EINVAL, "cells is NULL");
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Dev d = make_dev(prm, sys, work);
-  attach_lists(d, cells, nullptr);
-  d.all = 1;
-  launch_fill_u32(reinterpret_cast<uint32_t *>(d.cnt), sys->C, 0u, s);
-  launch_worklist(d, s);
-  launch_cells(d, s);
-  HIPCHK(hipGetLastError());
-  return TBSMA_OK;
+  return build_cells_on(prm, sys, cells, work,
+                        static_cast<hipStream_t>(stream));
 }
 
 int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
@@ -649,27 +748,8 @@ int tbsma_neighbors(const tbsma_params *prm, const tbsma_system *sys,
   TRY(check_lists(prm, cells, nl));
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Dev d = make_dev(prm, sys, work);
-  attach_lists(d, cells, nl);
-  d.all = 1;
-  double rl = prm->r_cut + prm->skin;
-  launch_fill_u32(reinterpret_cast<uint32_t *>(d.nnmax), 1, 0u, s);
-  const bool mixed = prm->precision == TBSMA_MIXED;
-  if (mixed) launch_quantise(d, s);
-  launch_worklist(d, s);
-  launch_nlist(d, mixed, rl, s);
-  HIPCHK(hipGetLastError());
-  if (need_cap) {
-    HIPCHK(hipStreamSynchronize(s));
-    int32_t mx = 0;
-    HIPCHK(hipMemcpy(&mx, d.nnmax, 4, hipMemcpyDeviceToHost));
-    *need_cap = mx > nl->k_cap ? mx : nl->k_cap;
-    if (mx > nl->k_cap)
-      return fail(TBSMA_ECAPACITY, "longest row %d exceeds k_cap %d", mx,
-                  nl->k_cap);
-  }
-  return TBSMA_OK;
+  return neighbors_on(prm, sys, cells, nl, work, need_cap,
+                      static_cast<hipStream_t>(stream));
 }
 
 int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
@@ -684,16 +764,7 @@ int tbsma_forces(const tbsma_params *prm, const tbsma_system *sys,
   if (!out->rep_energy || !out->rep_wzz)
     return fail(TBSMA_EINVAL, "rep_energy / rep_wzz missing");
   TRY(check_device());
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Dev d = make_dev(prm, sys, work);
-  attach_lists(d, nullptr, nl);
-  bool mixed = prm->precision == TBSMA_MIXED;
-  if (mixed) launch_quantise(d, s);
-  launch_forces(d, mixed, make_potf(prm), make_potd(prm), out->fx, out->fy,
-                out->fz, out->e_atom, out->g, s);
-  launch_reduce_forces(d, out->rep_energy, out->rep_wzz, s);
-  HIPCHK(hipGetLastError());
-  return TBSMA_OK;
+  return forces_on(prm, sys, nl, out, work, static_cast<hipStream_t>(stream));
 }
 
 int tbsma_forces_pass(const tbsma_params *prm, const tbsma_system *sys,
@@ -730,19 +801,41 @@ int tbsma_step(const tbsma_params *prm, tbsma_system *sys, tbsma_cells *cells,
   if (n_steps < 0) return fail(TBSMA_EINVAL, "n_steps < 0");
   if (sys->R == 0 || n_steps == 0) return TBSMA_OK;
   TRY(check_device());
+  return step_on(prm, sys, cells, nl, out, md, work, n_steps,
+                 static_cast<hipStream_t>(stream));
+}
+
+int tbsma_step_noalloc(const tbsma_params *prm, tbsma_system *sys,
+                       tbsma_cells *cells, tbsma_nlist *nl,
+                       tbsma_forces_out *out, const tbsma_md *md,
+                       int64_t n_steps, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (!cells || !nl) return fail(TBSMA_EINVAL, "cells or nlist is NULL");
+  TRY(check_lists(prm, cells, nl));
+  TRY(check_out(prm, out));
+  if (!out->rep_energy || !out->rep_wzz)
+    return fail(TBSMA_EINVAL, "rep_energy / rep_wzz missing");
+  TRY(check_md(md, sys->R));
+  if (n_steps < 0) return fail(TBSMA_EINVAL, "n_steps < 0");
+  if (sys->R == 0 || n_steps == 0) return TBSMA_OK;
+  const size_t need = layout(sys).total;
+  if (need > kScratchBytes)
+    return fail(TBSMA_ECAPACITY,
+                "system needs %zu bytes of workspace; the static scratch of "
+                "tbsma_step_noalloc holds %zu (use tbsma_step with a "
+                "workspace)", need, kScratchBytes);
+  TRY(check_device());
+  void *work = nullptr;
+  TRY(scratch_ptr(&work));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Dev d = make_dev(prm, sys, work);
-  attach_lists(d, cells, nl);
-  DevMD M = make_devmd(prm, md);
-  PotF PF = make_potf(prm);
-  PotD PD = make_potd(prm);
-  const bool mixed = prm->precision == TBSMA_MIXED;
-  launch_call_bounds(d, M, n_steps, s);
-  if (M.nh_tau > 0 || M.baro_mass > 0)
-    launch_step_begin(d, M, mixed, out->fz, s);
-  for (int64_t k = 0; k < n_steps; ++k) enqueue_step(prm, d, M, out, PF, PD, s);
-  if (M.nh_tau > 0) launch_nh_finish(d, M, s);
-  return finish_run(d, md, s);
+  // the scratch keeps the previous call's contents: put it into the initial
+  // state, then lists and forces of the current positions, then the steps
+  TRY(workspace_init_on(prm, sys, work, s));
+  TRY(build_cells_on(prm, sys, cells, work, s));
+  TRY(neighbors_on(prm, sys, cells, nl, work, nullptr, s));
+  TRY(forces_on(prm, sys, nl, out, work, s));
+  return step_on(prm, sys, cells, nl, out, md, work, n_steps, s);
 }
 
 int tbsma_run_batch(const tbsma_params *prm, tbsma_system *sys,

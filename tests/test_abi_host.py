@@ -187,3 +187,26 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_noalloc_step_refuses_a_system_beyond_its_scratch_on_the_host():
+    """tbsma_step_noalloc checks the system's workspace against its static
+    scratch before any device work (placeholders only, nothing runs)."""
+    R = 1
+    N = 64 * 40000  # 2.56 M slots: about 60 MB of workspace
+    ph = C.c_void_p(0x1000)
+    rep = (C.c_int64 * 2)(0, N)
+    cel = (C.c_int64 * 2)(0, 8)
+    s = A.System(R, 4, N, 8, C.cast(rep, C.c_void_p), C.cast(cel, C.c_void_p),
+                 *([ph] * 14), ph)
+    nb = C.c_size_t()
+    A.check(A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s), C.byref(nb)))
+    assert nb.value > (32 << 20)
+    cells = A.Cells(ph, ph)
+    nl = A.NList(ph, ph, 8, 0, ph, ph, ph, None, ph)
+    out = A.ForcesOut(ph, ph, ph, ph, None, ph, ph)
+    md = A.MD(0.002, 1.0, 0, 10, 4, 0, *([ph] * 11), 0.0, None)
+    rc = A.lib().tbsma_step_noalloc(C.byref(_params()), C.byref(s), C.byref(cells),
+                                    C.byref(nl), C.byref(out), C.byref(md), 1, None)
+    assert rc == A.ECAPACITY
+    assert b"static scratch" in A.lib().tbsma_last_error()
