@@ -33,8 +33,12 @@
  *   slots.  Replica r owns slots [rep_off[r], rep_off[r+1]); every offset is a
  *   multiple of TBSMA_TILE, and the slots after a replica's real atoms are
  *   padding (flag TBSMA_PAD).  Per-atom arrays are structure-of-arrays.
- *   Atoms keep their slot for the whole run: the slot minus rep_off[r] is the
- *   atom's tag (the counter word of its random numbers).
+ *   Atoms keep their slot for the whole run.  An atom's tag (the counter
+ *   word of its random numbers) is tag[slot] when the system has a tag array
+ *   (tbsma_system.tag), else the slot minus rep_off[r]; so a replica may
+ *   hold its atoms in any fixed order, for instance blocked by space so
+ *   that the pair passes can stage the neighbours of each block of slots in
+ *   LDS.
  * Errors: calls return TBSMA_OK (0) or a negative code; the message of the
  *   last failure on the calling thread is returned by tbsma_last_error().
  *   Conditions found on the device while running (neighbour-list overflow,
@@ -115,6 +119,13 @@ extern "C" {
  *                   from the full list whenever some atom of the replica has
  *                   moved more than d since the last pruning, so no pair
  *                   within r_cut is ever left out.
+ *  gather           MIXED only, 0 or 1: 1 lets a block of the pair passes
+ *                   whose slot window is too wide for LDS (thick wires)
+ *                   stage the exact set of its neighbours instead, through
+ *                   a list of up to 1536 neighbour offsets kept in the
+ *                   workspace (about 12 bytes per slot more workspace).
+ *                   Results do not depend on it: the pair arithmetic is the
+ *                   same whichever way positions reach it.
  */
 typedef struct {
   double A, xi, p, q, r0;
@@ -125,6 +136,8 @@ typedef struct {
   int32_t precision;
   int32_t qbits;
   double prune;
+  int32_t gather;
+  int32_t reserved;
 } tbsma_params;
 
 /*
@@ -148,6 +161,9 @@ typedef struct {
  *  flag          device [N] TBSMA_DYN / GRIP_FIXED / GRIP_PULL / PAD.
  *  qpos          device [4N] int32 (MIXED; NULL for FP64): quantised x, y, z
  *                and, after the density pass, the bits of FP32 g_i.
+ *  tag           device [N] int32 or NULL: tag of the atom in each slot,
+ *                0 <= tag < atoms of its replica, distinct within a replica
+ *                (NULL: slot minus rep_off[r]).
  */
 typedef struct {
   int32_t R;
@@ -167,6 +183,7 @@ typedef struct {
   double *z0;
   uint8_t *flag;
   int32_t *qpos;
+  const int32_t *tag;
 } tbsma_system;
 
 /*
@@ -490,9 +507,13 @@ int tbsma_step_noalloc(const tbsma_params *prm, tbsma_system *sys,
                        int64_t n_steps, void *stream);
 
 /*
- * Diagnostics of the lists: out_host[0] = sum over atoms of nn (the Verlet
- * lists), out_host[1] = sum of the lengths of the lists the mixed pair passes
- * read (pruned; equal to out_host[0] in FP64).  Synchronises.
+ * Diagnostics of the lists, out_host[6]: [0] sum over atoms of nn (the
+ * Verlet lists), [1] sum of the lengths of the lists the mixed pair passes
+ * read (pruned; equal to [0] in FP64); MIXED only (0 in FP64): how the pair
+ * passes reach each block's neighbours: [2] blocks whose slot window fits in
+ * LDS, [3] blocks staged through a gather list (tbsma_params.gather), [4]
+ * blocks that gather from global memory, [5] neighbours listed by the
+ * gather-staged blocks.  Synchronises.
  */
 int tbsma_list_stats(const tbsma_params *prm, const tbsma_system *sys,
                      const tbsma_nlist *nl, void *work, int64_t *out_host,

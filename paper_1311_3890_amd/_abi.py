@@ -29,7 +29,8 @@ class Params(C.Structure):
     _fields_ = [("A", C.c_double), ("xi", C.c_double), ("p", C.c_double), ("q", C.c_double),
                 ("r0", C.c_double), ("r_tail", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("cell", C.c_double), ("mass", C.c_double),
-                ("precision", C.c_int32), ("qbits", C.c_int32), ("prune", C.c_double)]
+                ("precision", C.c_int32), ("qbits", C.c_int32), ("prune", C.c_double),
+                ("gather", C.c_int32), ("reserved", C.c_int32)]
 
 
 class System(C.Structure):
@@ -37,7 +38,7 @@ class System(C.Structure):
                 ("rep_off_h", vp), ("cell_off_h", vp), ("rep_off", vp), ("cell_off", vp),
                 ("tile_rep", vp), ("grid_dim", vp), ("grid_lo", vp), ("rep_id", vp),
                 ("x", vp), ("y", vp), ("z", vp), ("vx", vp), ("vy", vp), ("vz", vp),
-                ("z0", vp), ("flag", vp), ("qpos", vp)]
+                ("z0", vp), ("flag", vp), ("qpos", vp), ("tag", vp)]
 
 
 class Cells(C.Structure):

@@ -83,6 +83,8 @@ int check_params(const tbsma_params *p) {
     return fail(TBSMA_EINVAL, "qbits %d outside 16..24", p->qbits);
   if (!(p->prune >= 0 && p->prune <= 0.5 * p->skin))
     return fail(TBSMA_EINVAL, "prune must be in [0, skin/2]");
+  if (p->gather != 0 && p->gather != 1)
+    return fail(TBSMA_EINVAL, "gather must be 0 or 1");
   return TBSMA_OK;
 }
 
@@ -124,7 +126,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, nnmax, rsum, win,
       bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
-      wl, callb, total;
+      wl, callb, gcnt, glist, total;
 };
 
 // Blocks of the cell sort: ceil(cells/kSortCells) per replica.
@@ -148,7 +150,7 @@ int32_t block_map_size(const tbsma_system *s) {
 
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout layout(const tbsma_system *s) {
+Layout layout(const tbsma_params *p, const tbsma_system *s) {
   Layout L;
   size_t o = 0;
   int64_t R = s->R, nt = s->N / TBSMA_TILE;
@@ -192,6 +194,13 @@ Layout layout(const tbsma_system *s) {
   o += up(4 * (size_t)work_lists_size(s->N, R, s->C));
   L.callb = o;
   o += 256;
+  // gather staging of the pair passes (mixed precision)
+  const bool gather = p->precision == TBSMA_MIXED && p->gather;
+  const size_t nbm = s->R > 0 ? (size_t)block_map_size(s) : 0;
+  L.gcnt = o;
+  o += gather ? up(4 * nbm) : 0;
+  L.glist = o;
+  o += gather ? up(2 * (size_t)kStage * nbm) : 0;
 
   L.total = o;
   return L;
@@ -219,7 +228,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.z0 = s->z0;
   d.flag = s->flag;
   d.qpos = reinterpret_cast<int4 *>(s->qpos);
-  Layout L = layout(s);
+  Layout L = layout(p, s);
   char *w = static_cast<char *>(work);
   d.rflag = reinterpret_cast<uint32_t *>(w + L.rflag);
   d.cnt = reinterpret_cast<int32_t *>(w + L.cnt);
@@ -242,6 +251,10 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.baw = reinterpret_cast<double *>(w + L.baw);
   d.wl = reinterpret_cast<int32_t *>(w + L.wl);
   d.callb = reinterpret_cast<int64_t *>(w + L.callb);
+  d.tag = s->tag;
+  d.gather = p->precision == TBSMA_MIXED && p->gather ? 1 : 0;
+  d.gcnt = d.gather ? reinterpret_cast<int32_t *>(w + L.gcnt) : nullptr;
+  d.glist = d.gather ? reinterpret_cast<uint16_t *>(w + L.glist) : nullptr;
 
   if (p->precision == TBSMA_MIXED) {
     // a pair is kept when its quantised distance is below r_cut + 2d, with
@@ -516,7 +529,7 @@ int finish_run(const Dev &d, const tbsma_md *m, hipStream_t s) {
 // explicit workspace (the caller's, or the library's static scratch).
 int workspace_init_on(const tbsma_params *prm, const tbsma_system *sys,
                       void *work, hipStream_t s) {
-  Layout L = layout(sys);
+  Layout L = layout(prm, sys);
   char *w = static_cast<char *>(work);
   // zero everything (as 32-bit words), then the min-bins to the empty key
   launch_fill_u32(reinterpret_cast<uint32_t *>(w), (int64_t)(L.total / 4), 0u,
@@ -650,7 +663,7 @@ int tbsma_workspace_query(const tbsma_params *prm, const tbsma_system *sys,
   TRY(check_params(prm));
   TRY(check_system(prm, sys));
   if (!bytes) return fail(TBSMA_EINVAL, "bytes is NULL");
-  *bytes = sys->R > 0 ? layout(sys).total : 256;
+  *bytes = sys->R > 0 ? layout(prm, sys).total : 256;
   return TBSMA_OK;
 }
 
@@ -819,7 +832,7 @@ int tbsma_step_noalloc(const tbsma_params *prm, tbsma_system *sys,
   TRY(check_md(md, sys->R));
   if (n_steps < 0) return fail(TBSMA_EINVAL, "n_steps < 0");
   if (sys->R == 0 || n_steps == 0) return TBSMA_OK;
-  const size_t need = layout(sys).total;
+  const size_t need = layout(prm, sys).total;
   if (need > kScratchBytes)
     return fail(TBSMA_ECAPACITY,
                 "system needs %zu bytes of workspace; the static scratch of "
@@ -921,7 +934,7 @@ int tbsma_list_stats(const tbsma_params *prm, const tbsma_system *sys,
   if (!nl || !out_host || !work)
     return fail(TBSMA_EINVAL, "nlist, work or out_host is NULL");
   TRY(check_lists(prm, nullptr, nl));
-  out_host[0] = out_host[1] = 0;
+  for (int k = 0; k < 6; ++k) out_host[k] = 0;
   if (sys->R == 0) return TBSMA_OK;
   TRY(check_device());
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -929,11 +942,11 @@ int tbsma_list_stats(const tbsma_params *prm, const tbsma_system *sys,
   attach_lists(d, nullptr, nl);
   launch_list_stats(d, prm->precision == TBSMA_MIXED, s);
   HIPCHK(hipGetLastError());
-  unsigned long long h[2];
+  unsigned long long h[6];
   HIPCHK(hipMemcpyAsync(h, d.stats, sizeof(h), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  out_host[0] = (int64_t)h[0];
-  out_host[1] = (int64_t)h[1];
+  for (int k = 0; k < 6; ++k)
+    out_host[k] = prm->precision == TBSMA_MIXED || k < 2 ? (int64_t)h[k] : 0;
   return TBSMA_OK;
 }
 

@@ -11,6 +11,9 @@ constexpr int kTile = 64;   // slots per tile = one wavefront
 constexpr int kBlock = 256; // threads of every per-atom kernel
 constexpr int kSortCells = 16;  // cells per block of the cell sort
 constexpr int kNPart = 8;   // FP64 partial sums per tile
+constexpr int kStage = 1536;  // neighbour positions a pair-pass block stages
+                              // in LDS (24 KB)
+constexpr int kGatherSpan = 65536;  // widest slot window of gather staging
 
 // per-tile partial sums
 constexpr int kPartE = 0;   // sum of E_i
@@ -59,6 +62,7 @@ struct Dev {
   int64_t N, C;
   const int64_t *rep_off, *cell_off;
   const int32_t *tile_rep, *grid_dim, *rep_id;
+  const int32_t *tag;           // [N] tag of each slot, or NULL: slot - rep_off
   const double *grid_lo;
   double *x, *y, *z, *vx, *vy, *vz, *z0;
   uint8_t *flag;
@@ -82,6 +86,12 @@ struct Dev {
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
+  // gather staging of the pair passes (mixed precision): blocks whose slot
+  // window exceeds LDS stage the exact set of their neighbours
+  int32_t gather;               // 1 when enabled
+  int32_t *gcnt;                // [nbmap] staged neighbours, 0: not staged
+  uint16_t *glist;              // [nbmap * kStage] their offsets from the
+                                // block's window start, ascending
   int32_t *wl;                  // work lists of a step (see work_lists)
   int64_t *callb;               // first step and end step of the current
                                 // step-loop call, the step flags of the
@@ -231,6 +241,12 @@ __device__ __forceinline__ double nh_half(const DevMD &M, int r, double Tt,
   K *= s * s;
   zeta += 0.25 * M.dt * (2.0 * K / gkT - 1.0) / tau2;
   return s;
+}
+
+// Tag of the atom in slot i of replica r (the counter word of its random
+// numbers): the system's tag array when it has one, else the slot offset.
+__device__ __forceinline__ uint32_t atom_tag(const Dev &S, int r, int64_t i) {
+  return S.tag != nullptr ? (uint32_t)S.tag[i] : (uint32_t)(i - S.rep_off[r]);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so

@@ -285,7 +285,11 @@ __device__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
 // window fits in LDS, which addresses the sentinel after the staged
 // positions, and kPadWide in the others; both are at least 16 times the
 // window size.
-constexpr int kStage = 1280;  // staged positions per block (20 KB)
+// A block whose window exceeds LDS (a thick wire) may instead stage the
+// exact set of its neighbours (gather staging, Dev::gather): the pruning
+// kernel lists their offsets from lo in ascending order (Dev::glist, at
+// most kStage of them) and writes each entry as 16 times the neighbour's
+// rank in that list, with kPadStaged for the unused ones.
 constexpr int32_t kPadStaged = kStage * 16;
 constexpr int32_t kPadWide = (int32_t)0xFFFFFFF0u;
 
@@ -967,6 +971,7 @@ __device__ __forceinline__ int4 gather_q(const int4 *qp, int j) {
 // its longest list).  Each atom's own sums run in list order whichever lane
 // takes it, so results do not depend on the assignment.
 struct PairBlock {
+  int64_t blk; // index in the block map
   int64_t b0;  // first slot
   int t0, nt;  // first tile, tiles
   int p;       // this thread's position
@@ -976,8 +981,9 @@ struct PairBlock {
 };
 
 __device__ __forceinline__ PairBlock pair_block(const Dev &S) {
-  const int2 bm = S.bmap[xcd_block()];
   PairBlock B;
+  B.blk = xcd_block();
+  const int2 bm = S.bmap[B.blk];
   B.t0 = bm.x;
   B.nt = bm.y;
   B.b0 = (int64_t)bm.x * kTile;
@@ -1020,9 +1026,10 @@ __device__ __forceinline__ void block_window(const Dev &S, const PairBlock &B,
 // the block lies within 2^29 quanta of that atom along x, so it is at least
 // 2^29 quanta (32 A at 24 bits) from each of them and no difference
 // overflows.  Returns that condition (uniform over the block).
-__device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
-                                      const PairBlock &B, int lo, int size) {
-  for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
+// The sentinel and the condition for it, after the block has copied its
+// staged positions (all threads of the block take part).
+__device__ __forceinline__ bool stage_sentinel(const Dev &S, int4 *lq,
+                                               const PairBlock &B) {
   const int4 q0 = S.qpos[B.b0];
   const int xi = B.valid ? S.qpos[B.b0 + B.p].x : q0.x;
   const int64_t d = (int64_t)xi - (int64_t)q0.x;
@@ -1031,6 +1038,22 @@ __device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
     lq[kStage] = make_int4(q0.x >= 0 ? q0.x - (1 << 30) : q0.x + (1 << 30),
                            q0.y, q0.z, 0);
   return __syncthreads_and(near) != 0;
+}
+
+__device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
+                                      const PairBlock &B, int lo, int size) {
+  for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
+  return stage_sentinel(S, lq, B);
+}
+
+// Gather staging: lq[k] = qpos[lo + glist[k]] for the gc listed neighbours
+// of the block, then the sentinel as above.
+__device__ __forceinline__ bool stage_gather(const Dev &S, int4 *lq,
+                                             const PairBlock &B, int lo,
+                                             int gc) {
+  const uint16_t *g = S.glist + B.blk * kStage;
+  for (int t = threadIdx.x; t < gc; t += kBlock) lq[t] = S.qpos[lo + g[t]];
+  return stage_sentinel(S, lq, B);
 }
 
 // LDS entry of list entry j: lq[min(j, lo + kStage) - lo] (kPadEntry -> the
@@ -1066,6 +1089,47 @@ struct ListDecode {
   }
 };
 
+// The same for a block whose entries are ranks in its gather list (gather
+// staging taken at pruning, but the sentinel condition failed at this pass).
+struct GatherDecode {
+  int lo;
+  const uint16_t *g;
+  uint32_t lim;  // 16 * listed neighbours
+  int self;
+  __device__ __forceinline__ GatherDecode(const Dev &S, const PairBlock &B,
+                                          int lo_, int gc, int self_)
+      : lo(lo_), g(S.glist + B.blk * kStage), lim((uint32_t)gc << 4),
+        self(self_) {}
+  __device__ __forceinline__ int operator()(int32_t e) const {
+    return (uint32_t)e < lim ? lo + (int)g[(uint32_t)e >> 4] : self;
+  }
+};
+
+// Exclusive block-wide prefix of v over the kBlock threads (every thread
+// takes part); *total gets the sum.  wsum: kBlock / 64 ints of LDS.
+__device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
+                                               int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const int t = wsum[k];
+    before += k < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();  // wsum may be reused
+  *total = tot;
+  return before + x - v;
+}
+
 // Lane-ordered, pruned rows (nl_lane) of the list-build blocks of the work
 // list: blocks of replicas whose lists were just rebuilt, which first take
 // their lane order from the new list lengths, and of replicas in which some
@@ -1074,16 +1138,31 @@ struct ListDecode {
 // rows are read coalesced; each lane writes its kept entries to its atom's
 // lane-ordered row.  Positions come from LDS as in the pair passes when the
 // block's window fits.
+// With gather staging, a block whose window exceeds LDS (up to kGatherSpan
+// slots) first marks the neighbours it keeps in a bitmap over its window,
+// then lists the marked slots in ascending order (glist, gcnt) when there
+// are at most kStage of them, and writes each kept entry as 16 times its
+// neighbour's rank in that list (the rank is the number of marked slots
+// before it).  Otherwise gcnt is 0 and entries are slot offsets.
+template <bool GATHER>
 __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
   __shared__ int32_t ring_lds[16 * kBlock];
   __shared__ int4 lq[kStage + 1];
   __shared__ int32_t key[kBlock];
+  // gather staging: the bitmap of kept neighbours over the window and the
+  // marked slots before each of its words, in lq (not staged then)
+  constexpr int kWords = kGatherSpan / 32;
+  static_assert(2 * kWords * sizeof(uint32_t) <= sizeof(lq), "bitmap fits");
+  uint32_t *bits = reinterpret_cast<uint32_t *>(lq);
+  int32_t *wbase = reinterpret_cast<int32_t *>(bits + kWords);
   const WorkLists W = work_lists(S);
   const int nbl = W.count[1];
   const int32_t *blocks = W.blocks;
   for (int it = blockIdx.x; it < nbl; it += gridDim.x) {  // uniform
-    const int2 bm = S.bmap[blocks[it]];
+    const int blk = blocks[it];
+    const int2 bm = S.bmap[blk];
     PairBlock B;
+    B.blk = blk;
     B.t0 = bm.x;
     B.nt = bm.y;
     B.b0 = (int64_t)bm.x * kTile;
@@ -1096,6 +1175,9 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
     block_window(S, B, lo, size);
     const bool staged =
         size > 0 && size <= kStage && stage(S, lq, B, lo, size);
+    // gather staging of this block (uniform)
+    const bool gmark = GATHER && size > kStage && size <= kGatherSpan;
+    const int nwords = gmark ? (size + 31) >> 5 : 0;
     const int64_t i = B.b0 + B.p;
     const int n = B.valid ? S.nn[i] : 0;
     int64_t row = B.b0 + (B.valid ? (int)S.atom_lane[i] : 0);
@@ -1115,14 +1197,70 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
     const float rp2 = S.prune_r2q;
     const int nch = S.k_cap >> 3;
     const int base = size > 0 ? lo : 0;  // entries are offsets from base
-    Ring ring{ring_lds + threadIdx.x, 0, 0};
-    auto keep = [&](const int4 &q, int j, bool in) {
+    auto kept = [&](const int4 &q, bool in) {
       const float dx = (float)(q.x - qi.x);
       const float dy = (float)(q.y - qi.y);
       const float dz = (float)(q.z - qi.z);
-      if (in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2)
-        ring.push(list_entry(j, base));
+      return in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2;
     };
+    int gc = 0;  // listed neighbours when the block is gather-staged
+    if (gmark) {
+      for (int w = threadIdx.x; w < nwords; w += kBlock) bits[w] = 0u;
+      __syncthreads();
+      chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
+        int4 q[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (kept(q[e], k0 + e < n)) {
+            const uint32_t off = (uint32_t)(j[e] - lo);
+            atomicOr(&bits[off >> 5], 1u << (off & 31));
+          }
+      });
+      __syncthreads();
+      // each thread takes kWpt consecutive words
+      constexpr int kWpt = kWords / kBlock;
+      const int w0 = threadIdx.x * kWpt;
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < kWpt; ++k)
+        cnt += w0 + k < nwords ? __popc(bits[w0 + k]) : 0;
+      int total = 0;
+      int at = block_excl_scan(cnt, key, &total);
+      if (total <= kStage) {
+        uint16_t *g = S.glist + (int64_t)blk * kStage;
+#pragma unroll
+        for (int k = 0; k < kWpt; ++k) {
+          if (w0 + k < nwords) {
+            wbase[w0 + k] = at;
+            uint32_t m = bits[w0 + k];
+            while (m) {
+              const int b = __ffs(m) - 1;
+              m &= m - 1u;
+              g[at++] = (uint16_t)((w0 + k) * 32 + b);
+            }
+          }
+        }
+        gc = total;
+      }
+      __syncthreads();  // wbase complete
+      if (threadIdx.x == 0) S.gcnt[blk] = gc;
+    } else if (GATHER && threadIdx.x == 0) {
+      S.gcnt[blk] = 0;
+    }
+    // entry of kept neighbour j: its rank in the gather list, or its offset
+    auto entry = [&](int j) {
+      if (gc > 0) {
+        const uint32_t off = (uint32_t)(j - lo);
+        const uint32_t w = off >> 5;
+        return (int32_t)((uint32_t)(wbase[w] +
+                                    __popc(bits[w] & ((1u << (off & 31)) - 1u)))
+                         << 4);
+      }
+      return list_entry(j, base);
+    };
+    Ring ring{ring_lds + threadIdx.x, 0, 0};
     if (staged) {
       // the row in batches of kPruneBatch chunks, all loaded before any is
       // used: the stores of the ring's flushes then overlap the positions'
@@ -1153,7 +1291,8 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 #pragma unroll
           for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) keep(q[e], j[e], j[e] != kPadEntry);
+          for (int e = 0; e < 8; ++e)
+            if (kept(q[e], j[e] != kPadEntry)) ring.push(list_entry(j[e], base));
           ring.flush(S.nl_lane, S.N, row, nch);
         }
       }
@@ -1163,16 +1302,18 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) keep(q[e], j[e], k0 + e < n);
+        for (int e = 0; e < 8; ++e)
+          if (kept(q[e], k0 + e < n)) ring.push(entry(j[e]));
         ring.flush(S.nl_lane, S.N, row, nch);
       });
     }
     if (B.valid) {
-      ring.finish(S.nl_lane, S.N, row, nch, pad_of_window(size));
+      ring.finish(S.nl_lane, S.N, row, nch,
+                  gc > 0 ? kPadStaged : pad_of_window(size));
       S.nn_lane[row] = ring.cnt;
       S.qprune[i] = qi;
     }
-    __syncthreads();  // lq and key serve the next block
+    __syncthreads();  // lq, bits, wbase and key serve the next block
   }
 }
 
@@ -1180,8 +1321,9 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 // qpos[i].w.  With COUNT, nact[2i] and nact[2i+1] count the pairs with
 // 0 < r <= r_tail and r_tail < r < r_cut.  Staged: positions from LDS, the
 // unused entries hit the sentinel.  Not staged: global gathers, the unused
-// entries are replaced by the atom itself and masked (r = 0).
-template <bool STAGED, bool COUNT>
+// entries are replaced by the atom itself and masked (r = 0); with GATHER
+// the entries are ranks in the block's gather list (size = its length).
+template <bool STAGED, bool COUNT, bool GATHER = false>
 __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
                                             const PairBlock &B,
                                             const int4 *lq, int lo, int size) {
@@ -1228,15 +1370,20 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
                         for (int k = 0; k < 8; ++k) pair(q[k]);
                       });
   } else {
-    const ListDecode dec(lo, size, self);
-    chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
-               [&](const int (&e)[8], int) {
-                 int4 q[8];
+    auto unstaged = [&](const auto &dec) {
+      chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
+                 [&](const int (&e)[8], int) {
+                   int4 q[8];
 #pragma unroll
-                 for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
+                   for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
 #pragma unroll
-                 for (int k = 0; k < 8; ++k) pair(q[k]);
-               });
+                   for (int k = 0; k < 8; ++k) pair(q[k]);
+                 });
+    };
+    if (GATHER)
+      unstaged(GatherDecode(S, B, lo, size, self));
+    else
+      unstaged(ListDecode(lo, size, self));
   }
   if (valid) {
     const float g = rho > 0.0f ? __builtin_amdgcn_rsqf(rho) : 0.0f;
@@ -1245,15 +1392,20 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
   }
 }
 
-template <bool COUNT>
+template <bool COUNT, bool GATHER>
 __global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
   __shared__ int4 lq[kStage + 1];
   const PairBlock B = pair_block(S);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   int lo, size;
   block_window(S, B, lo, size);
+  const int gc = GATHER && size > kStage ? S.gcnt[B.blk] : 0;  // uniform
   if (size > 0 && size <= kStage && stage(S, lq, B, lo, size))
     density_run<true, COUNT>(S, P, B, lq, lo, size);
+  else if (gc > 0 && stage_gather(S, lq, B, lo, gc))
+    density_run<true, COUNT>(S, P, B, lq, lo, gc);
+  else if (gc > 0)
+    density_run<false, COUNT, true>(S, P, B, lq, lo, gc);
   else
     density_run<false, COUNT>(S, P, B, lq, lo, size);
 }
@@ -1320,7 +1472,7 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // partial sums and, on logged steps, the axial bins of the rupture gap.
 // These are the same operations, in the same order and precision, as
 // k_integrate_b, so the results do not depend on which of the two ran.
-template <bool STAGED, bool ENERGY, bool KICK>
+template <bool STAGED, bool ENERGY, bool KICK, bool GATHER = false>
 __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
                                           const DevMD &M, const PairBlock &B,
                                           const int4 *lq, int lo, int size,
@@ -1387,15 +1539,20 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
                         for (int k = 0; k < 8; ++k) pair(q[k]);
                       });
   } else {
-    const ListDecode dec(lo, size, self);
-    chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
-               [&](const int (&e)[8], int) {
-                 int4 q[8];
+    auto unstaged = [&](const auto &dec) {
+      chunk_loop(S.nl_lane, N, row, kPadWide, n, 0, 1,
+                 [&](const int (&e)[8], int) {
+                   int4 q[8];
 #pragma unroll
-                 for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
+                   for (int k = 0; k < 8; ++k) q[k] = gather_q(qp, dec(e[k]));
 #pragma unroll
-                 for (int k = 0; k < 8; ++k) pair(q[k]);
-               });
+                   for (int k = 0; k < 8; ++k) pair(q[k]);
+                 });
+    };
+    if (GATHER)
+      unstaged(GatherDecode(S, B, lo, size, self));
+    else
+      unstaged(ListDecode(lo, size, self));
   }
   if (valid) {
     fx[i] = ax;
@@ -1492,7 +1649,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   }
 }
 
-template <bool KICK>
+template <bool KICK, bool GATHER>
 __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         DevMD M, float *fx,
                                                         float *fy, float *fz,
@@ -1507,11 +1664,26 @@ __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
       S.energies > 0 || (S.energies < 0 && (S.callb[2] & kStepLog) != 0);
   int lo, size;
   block_window(S, B, lo, size);
-  if (size > 0 && size <= kStage && stage(S, lq, B, lo, size)) {
+  const int gc = GATHER && size > kStage ? S.gcnt[B.blk] : 0;  // uniform
+  bool staged = false;
+  if (size > 0 && size <= kStage) {
+    staged = stage(S, lq, B, lo, size);
+  } else if (gc > 0) {
+    staged = stage_gather(S, lq, B, lo, gc);
+    size = gc;  // the staged (or decoded) list length from here on
+  }
+  if (staged) {
     if (energy)
       force_run<true, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
     else
       force_run<true, false, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
+  } else if (gc > 0) {
+    if (energy)
+      force_run<false, true, KICK, true>(S, P, M, B, lq, lo, size, lsum, fx, fy,
+                                         fz, eat);
+    else
+      force_run<false, false, KICK, true>(S, P, M, B, lq, lo, size, lsum, fx,
+                                          fy, fz, eat);
   } else {
     if (energy)
       force_run<false, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
@@ -1620,7 +1792,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
       z += hdt * vz;
       if (M.gamma > 0.0) {
         double n0, n1, n2;
-        uint32_t tag = (uint32_t)(i - S.rep_off[r]);
+        uint32_t tag = atom_tag(S, r, i);
         if (MIXED) {  // FP32 Box-Muller on the same Philox words
           float m0, m1, m2;
           gauss3f(M.seed[r], (uint32_t)S.rep_id[r], tag, (uint64_t)step, 0u,
@@ -2016,7 +2188,7 @@ __global__ void __launch_bounds__(kBlock) k_init_a(Dev S, DevMD M,
   uint8_t f = valid ? S.flag[i] : 3;
   double sx = 0, sy = 0, sz = 0, cn = 0;
   if (f != 3) {
-    uint32_t tag = (uint32_t)(i - S.rep_off[r]);
+    uint32_t tag = atom_tag(S, r, i);
     uint32_t rid = (uint32_t)S.rep_id[r];
     if (jitter != 0.0) {
       uint4 o = rng_words(M.seed[r], rid, tag, 0, 2u);
@@ -2209,7 +2381,10 @@ void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
     // rebuilt and the pruned ones (work lists of the step)
     k_nlist_mixed<<<work_grid(S.N / kTile), kBlock, 0, s>>>(S,
                                                           (float)(rq * rq));
-    k_prune<<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
+    if (S.gather)
+      k_prune<true><<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
+    else
+      k_prune<false><<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
   } else {
     k_nlist_fp64<<<S.nbmap, kBlock, 0, s>>>(S, rl * rl);
   }
@@ -2242,14 +2417,69 @@ __global__ void __launch_bounds__(kBlock) k_list_stats(Dev S, int mixed) {
   }
 }
 
+// How the pair passes reach the neighbours of each block (mixed precision):
+// stats[2] blocks whose slot window fits LDS, stats[3] blocks staged through
+// their gather lists, stats[4] the others (global gathers), stats[5] the
+// neighbours listed by the gather-staged blocks.
+__global__ void __launch_bounds__(kBlock) k_stage_stats(Dev S) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= S.nbmap) return;
+  const int2 bm = S.bmap[b];
+  int l = 0x7fffffff, h = 0;
+  bool ok = true;
+  for (int t = 0; t < bm.y; ++t) {
+    const int2 w = S.win[bm.x + t];
+    ok = ok && w.y > w.x;
+    l = min(l, w.x);
+    h = max(h, w.y);
+  }
+  const int size = ok ? h - l : 0;
+  const int gc = size > kStage && S.gather ? S.gcnt[b] : 0;
+  if (size > 0 && size <= kStage)
+    atomicAdd(&S.stats[2], 1ull);
+  else if (gc > 0) {
+    atomicAdd(&S.stats[3], 1ull);
+    atomicAdd(&S.stats[5], (unsigned long long)gc);
+  } else
+    atomicAdd(&S.stats[4], 1ull);
+}
+
 void launch_list_stats(const Dev &S, bool mixed, hipStream_t s) {
-  k_fill_u64<<<1, 64, 0, s>>>(S.stats, 2, 0ull);
+  k_fill_u64<<<1, 64, 0, s>>>(S.stats, 6, 0ull);
   k_list_stats<<<nblk(S.N, kBlock), kBlock, 0, s>>>(S, mixed ? 1 : 0);
+  if (mixed && S.nbmap > 0)
+    k_stage_stats<<<nblk(S.nbmap, kBlock), kBlock, 0, s>>>(S);
 }
 
 void launch_block_map(const Dev &S, hipStream_t s) {
   k_block_map<<<1, 1024, 0, s>>>(S);
   k_cell_map<<<1, 1024, 0, s>>>(S);
+}
+
+// The mixed pair passes, in their gather-staging variant when the system
+// enables it (the other variant has none of its code).
+template <bool GATHER>
+void density_pass(const Dev &S, const PotF &PF, hipStream_t s) {
+  if (S.nact)
+    k_density_mixed<true, GATHER><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+  else
+    k_density_mixed<false, GATHER><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+}
+void density_pass(const Dev &S, const PotF &PF, hipStream_t s) {
+  if (S.gather)
+    density_pass<true>(S, PF, s);
+  else
+    density_pass<false>(S, PF, s);
+}
+template <bool KICK>
+void force_pass(const Dev &S, const PotF &PF, const DevMD &M, void *fx,
+                void *fy, void *fz, void *eat, hipStream_t s) {
+  if (S.gather)
+    k_force_mixed<KICK, true><<<S.nbmap, kBlock, 0, s>>>(
+        S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
+  else
+    k_force_mixed<KICK, false><<<S.nbmap, kBlock, 0, s>>>(
+        S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
 }
 
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
@@ -2258,12 +2488,8 @@ void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
     if (S.nbmap == 0) return;
-    if (S.nact)
-      k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-    else
-      k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-    k_force_mixed<false><<<S.nbmap, kBlock, 0, s>>>(
-        S, PF, DevMD{}, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
+    density_pass(S, PF, s);
+    force_pass<false>(S, PF, DevMD{}, fx, fy, fz, eat, s);
   } else {
     k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);
     k_force_fp64<<<nb, kBlock, 0, s>>>(S, PD, g, (double *)fx, (double *)fy,
@@ -2275,12 +2501,8 @@ void launch_forces_kick(const Dev &S, const DevMD &M, const PotF &PF,
                         void *fx, void *fy, void *fz, void *eat,
                         hipStream_t s) {
   if (S.nbmap == 0) return;
-  if (S.nact)
-    k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-  else
-    k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-  k_force_mixed<true><<<S.nbmap, kBlock, 0, s>>>(
-      S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
+  density_pass(S, PF, s);
+  force_pass<true>(S, PF, M, fx, fy, fz, eat, s);
 }
 
 void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
@@ -2289,14 +2511,10 @@ void launch_force_pass(const Dev &S, bool mixed, int pass, const PotF &PF,
   unsigned nb = nblk(S.N, kBlock);
   if (mixed) {
     if (S.nbmap == 0) return;
-    if (pass == 1 && S.nact)
-      k_density_mixed<true><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-    else if (pass == 1)
-      k_density_mixed<false><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+    if (pass == 1)
+      density_pass(S, PF, s);
     else
-      k_force_mixed<false><<<S.nbmap, kBlock, 0, s>>>(
-          S, PF, DevMD{}, (float *)fx, (float *)fy, (float *)fz,
-          (float *)eat);
+      force_pass<false>(S, PF, DevMD{}, fx, fy, fz, eat, s);
   } else {
     if (pass == 1)
       k_density_fp64<<<nb, kBlock, 0, s>>>(S, PD, g);

@@ -56,6 +56,30 @@ def build_wire_host(a: float, D: float, L: float, n_grip: int = 2, notch_layers:
     return x, y, z, f
 
 
+def blocked_order(x, y, z, a: float):
+    """Slot order of a thick wire in which every 256 consecutive atoms are a
+    compact piece of it: atoms grouped by supercells of 4a x 4a x 4a (256
+    lattice sites), supercells visited slab by slab along the axis and
+    row by row in each slab, rows in alternating directions (so that
+    consecutive supercells touch), sites within a supercell by plane, row and
+    column.  Returns the tags (generation indices) in slot order.  The pair
+    passes can then stage each block's neighbours in LDS (gather staging)."""
+    h = 0.5 * a
+    i = np.rint(np.asarray(x) / h).astype(np.int64)
+    j = np.rint(np.asarray(y) / h).astype(np.int64)
+    k = np.rint(np.asarray(z) / h).astype(np.int64)
+    sx, sy, sz = np.floor_divide(i + 4, 8), np.floor_divide(j + 4, 8), np.floor_divide(k, 8)
+    row = np.where(sz % 2 == 0, sy, -sy)
+    col = np.where(sy % 2 == 0, sx, -sx)
+    return np.lexsort((i, j, k, col, row, sz)).astype(np.int32)
+
+
+# wires at least this thick (A) get the blocked slot order under order="auto":
+# their axial (generation) order puts about 1700 or more atoms in the slot
+# window of a block of 256, more than the pair passes stage in LDS
+BLOCKED_MIN_D = 36.0
+
+
 class WireBatch:
     """R independent [100] Au nanowires advanced together on one GPU.
 
@@ -79,6 +103,12 @@ class WireBatch:
     retire        grip travel (A) after the first rupture before a replica is
                   retired (0: never).
     qbits         position quantum 2^-qbits A (mixed; default from the grid).
+    order         slot order of each replica's atoms: "axial" (generation
+                  order, along the wire), "blocked" (blocked_order), or
+                  "auto" (blocked for D >= BLOCKED_MIN_D).  Accessors return
+                  per-atom arrays by tag whatever the order.
+    gather        gather staging of the pair passes (mixed; tbsma_params);
+                  default: on when some replica is in the blocked order.
     The settings mean what include/tbsma.h says of tbsma_md and tbsma_params.
     """
 
@@ -90,7 +120,8 @@ class WireBatch:
                  retire: float = 0.0, nh_tau: float = 0.0, grip_step: float = 0.0,
                  grip_hold: int = 0, notch: tuple | None = None, T_start=None,
                  ramp_begin: int = 0, ramp_steps: int = 0, baro_mass: float = 0.0,
-                 baro_load: float = 0.0, baro_damp: float = 0.0):
+                 baro_load: float = 0.0, baro_damp: float = 0.0, order: str = "auto",
+                 gather: int | None = None):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
@@ -103,7 +134,8 @@ class WireBatch:
                         device=device, prune=prune, retire=retire, nh_tau=nh_tau,
                         grip_step=grip_step, grip_hold=grip_hold, notch=notch,
                         T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps,
-                        baro_mass=baro_mass, baro_load=baro_load, baro_damp=baro_damp)
+                        baro_mass=baro_mass, baro_load=baro_load, baro_damp=baro_damp,
+                        order=order, gather=gather)
         self.baro_mass, self.baro_load = float(baro_mass), float(baro_load)
         self.baro_damp = float(baro_damp)
         self.nh_tau, self.grip_step, self.grip_hold = float(nh_tau), float(grip_step), int(grip_hold)
@@ -125,6 +157,14 @@ class WireBatch:
         self.wires = wires if wires is not None else [
             build_wire_host(a, rp.D, rp.L, rp.n_grip, nl_, nd_) for rp in self.replicas]
         self.n_atoms = np.array([w[0].size for w in self.wires], dtype=np.int64)
+        if order not in ("auto", "axial", "blocked"):
+            raise ValueError(f"unknown slot order {order!r}")
+        self.order = order
+        # tags of each replica's slots (None: slot order = tag order)
+        self.slot_tag = [
+            blocked_order(w[0], w[1], w[2], a)
+            if order == "blocked" or (order == "auto" and rp.D >= BLOCKED_MIN_D) else None
+            for w, rp in zip(self.wires, self.replicas)]
         pad = (self.n_atoms + A.TILE - 1) // A.TILE * A.TILE
         self.rep_off = np.zeros(R + 1, dtype=np.int64)
         self.rep_off[1:] = np.cumsum(pad)
@@ -154,13 +194,20 @@ class WireBatch:
         yh = np.zeros(N)
         zh = np.zeros(N)
         fh = np.full(N, A.PAD, dtype=np.uint8)
+        tagh = np.zeros(N, dtype=np.int32)
         z_lo = np.zeros(R)
         z_hi = np.zeros(R)
         dof = np.zeros(R, dtype=np.int32)
         for r, (x, y, z, f) in enumerate(self.wires):
             o = self.rep_off[r]
             n = x.size
-            xh[o:o + n], yh[o:o + n], zh[o:o + n], fh[o:o + n] = x, y, z, f
+            perm = self.slot_tag[r]
+            sl = slice(None) if perm is None else perm
+            xh[o:o + n], yh[o:o + n], zh[o:o + n], fh[o:o + n] = x[sl], y[sl], z[sl], f[sl]
+            npad = int(self.rep_off[r + 1] - o)
+            tagh[o:o + npad] = np.arange(npad, dtype=np.int32)
+            if perm is not None:
+                tagh[o:o + n] = perm
             z_lo[r] = z[f == A.GRIP_FIXED].max() if np.any(f == A.GRIP_FIXED) else z.min()
             z_hi[r] = z[f == A.GRIP_PULL].min() if np.any(f == A.GRIP_PULL) else z.max()
             dof[r] = max(0, 3 * int((f == A.DYN).sum()) - 3)
@@ -189,6 +236,10 @@ class WireBatch:
         for k in ("vx", "vy", "vz", "z0", "x_ref", "y_ref", "z_ref"):
             T[k] = torch.zeros(N, **f64)
         T["flag"] = torch.tensor(fh, device=dev)
+        self.permuted = any(t is not None for t in self.slot_tag)
+        if gather is None:  # gather staging where a replica is in the blocked order
+            gather = 1 if self.permuted else 0
+        T["tag"] = torch.tensor(tagh if self.permuted else np.zeros(1, np.int32), device=dev)
         T["qpos"] = torch.zeros(4 * N, dtype=torch.int32, device=dev)
         T["cell_start"] = torch.zeros(self.C + R, dtype=torch.int32, device=dev)
         T["cell_atoms"] = torch.zeros(max(N, 1), dtype=torch.int32, device=dev)
@@ -229,7 +280,7 @@ class WireBatch:
         self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
                                self.pot.r_tail, self.pot.r_cut, skin, cell, MASS_AU,
                                A.MIXED if precision == "mixed" else A.FP64, self.qbits,
-                               self.prune)
+                               self.prune, int(gather) if precision == "mixed" else 0, 0)
         self._rep_off_h = (C.c_int64 * (R + 1))(*self.rep_off.tolist())
         self._cell_off_h = (C.c_int64 * (R + 1))(*self.cell_off.tolist())
         self.sys = A.System(R, self.max_zbins, N, self.C,
@@ -238,7 +289,8 @@ class WireBatch:
                             *[_ptr(T[k]) for k in ("rep_off", "cell_off", "tile_rep", "grid_dim",
                                                    "grid_lo", "rep_id", "x", "y", "z", "vx",
                                                    "vy", "vz", "z0", "flag")],
-                            _ptr(T["qpos"]) if precision == "mixed" else None)
+                            _ptr(T["qpos"]) if precision == "mixed" else None,
+                            _ptr(T["tag"]) if self.permuted else None)
         self.cells = A.Cells(_ptr(T["cell_start"]), _ptr(T["cell_atoms"]))
         # the per-atom pair counts are a diagnostic: the step loop runs
         # without them, count_pairs() asks for them
@@ -341,9 +393,18 @@ class WireBatch:
                 cur.wait_stream(side)
 
     # ------------------------------------------------------------------------------------
+    def _by_tag(self, a, r):
+        """Per-slot values of replica r (first axis) in tag order."""
+        perm = self.slot_tag[r]
+        if perm is None:
+            return a
+        out = np.empty_like(a)
+        out[perm] = a
+        return out
+
     def _slice(self, key, r):
         o = int(self.rep_off[r])
-        return self.t[key][o:o + int(self.n_atoms[r])].detach().cpu().numpy()
+        return self._by_tag(self.t[key][o:o + int(self.n_atoms[r])].detach().cpu().numpy(), r)
 
     def positions(self, r: int):
         return tuple(self._slice(k, r).astype(np.float64) for k in ("x", "y", "z"))
@@ -361,13 +422,17 @@ class WireBatch:
         return self._slice("flag", r)
 
     def neighbor_rows(self, r: int):
-        """List of neighbour slot arrays (replica-local indices) of replica r."""
+        """Neighbour tag arrays of replica r, sorted, by tag."""
         nn = self.t["nn"].cpu().numpy()
         # chunks of 8: entry k of slot i at ((k // 8) * N + i) * 8 + k % 8
         nl = self.t["nl"].view(self.k_cap // 8, self.N, 8).cpu().numpy()
         o = int(self.rep_off[r])
-        return [np.sort(nl[:, o + i, :].reshape(-1)[:nn[o + i]]) - o
-                for i in range(int(self.n_atoms[r]))]
+        perm = self.slot_tag[r]
+        rows = []
+        for i in range(int(self.n_atoms[r])):
+            j = nl[:, o + i, :].reshape(-1)[:nn[o + i]] - o
+            rows.append(np.sort(j if perm is None else perm[j]))
+        return rows if perm is None else [rows[s] for s in np.argsort(perm)]
 
     def count_pairs(self):
         """Runs a density pass at the current positions that also counts,
@@ -389,7 +454,7 @@ class WireBatch:
         self.count_pairs()
         na = self.t["nact"].view(self.N, 2).cpu().numpy()
         o = int(self.rep_off[r])
-        return na[o:o + int(self.n_atoms[r])].copy()
+        return self._by_tag(na[o:o + int(self.n_atoms[r])].copy(), r)
 
     # ------------------------------------------------------------------------------------
     # checkpoint / resume: the device state that the next step reads.  With the
@@ -515,11 +580,28 @@ class WireBatch:
     def list_lengths(self):
         """(mean Verlet-list length, mean length of the lists the pair passes
         read) per real atom; they differ in mixed precision with pruning."""
-        out = (C.c_int64 * 2)()
-        A.check(A.lib().tbsma_list_stats(C.byref(self.params), C.byref(self.sys),
-                                         C.byref(self.nlist), self.work, out, self.stream()))
+        out = self._list_stats()
         n = max(1, int(self.n_atoms.sum()))
         return out[0] / n, out[1] / n
+
+    def _list_stats(self):
+        out = (C.c_int64 * 6)()
+        A.check(A.lib().tbsma_list_stats(C.byref(self.params), C.byref(self.sys),
+                                         C.byref(self.nlist), self.work, out, self.stream()))
+        return list(out)
+
+    def nbmap_blocks(self) -> int:
+        """Blocks of the pair passes (up to four tiles of one replica)."""
+        tiles = (self.rep_off[1:] - self.rep_off[:-1]) // A.TILE
+        return int(((tiles + 3) // 4).sum())
+
+    def staging(self):
+        """How the pair passes reach each block's neighbours (mixed):
+        blocks whose window fits LDS, blocks staged by gather list, blocks
+        gathering from global memory, and the mean gather-list length."""
+        out = self._list_stats()
+        return dict(window=out[2], gather=out[3], unstaged=out[4],
+                    mean_gathered=out[5] / out[3] if out[3] else 0.0)
 
     def mean_active_pairs(self) -> float:
         """Mean number of pairs within r_cut per real atom at the current

@@ -45,7 +45,7 @@ def orc_state(b: WireBatch, r: int):
     st.vx, st.vy, st.vz = b.velocities(r)
     o = int(b.rep_off[r])
     n = int(b.n_atoms[r])
-    st.z0 = b.t["z0"][o:o + n].cpu().numpy().copy()
+    st.z0 = b._slice("z0", r).copy()
     st.step = b.step_index()
     st.zeta[0] = float(b.t["nh_xi"][r])
     st.eta[0] = float(b.t["nh_eta"][r])
@@ -998,6 +998,82 @@ def _sampled_parity(b: WireBatch, reps_to_check, tol=1e-5, mode=1, etol=1e-6):
     return worst
 
 
+def test_blocked_order_fp64_lockstep_with_oracle():
+    """A 4 nm wire whose atoms sit in the blocked slot order: the initial
+    state and 20 FP64 Langevin steps follow the oracle, whose atoms are in
+    generation order (noise keyed by the tag, not the slot)."""
+    rp = R(40.0, 20.0, T=298.0, v=0.5, r=6, jitter=0.02)
+    note("blocked order fp64 lockstep 20 steps")
+    b = WireBatch([rp], "fp64", n_log=10, order="blocked")
+    assert b.slot_tag[0] is not None
+    assert not np.array_equal(b.slot_tag[0], np.arange(int(b.n_atoms[0])))
+    b.init_state()
+    torch.cuda.synchronize()
+    x0, y0, z0, f = oracle.build_wire(4.08, rp.D, rp.L, 2)
+    st = oracle.State(x0, y0, z0, f)
+    md = orc_md(b, 0)
+    oracle.init_state(md, st, rp.jitter)
+    x, y, z = b.positions(0)
+    assert max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max()) < 1e-14
+    assert np.array_equal(b.flags(0), f)
+    b.build_lists()
+    b.compute_forces()
+    oracle.compute_forces(AU, st, 0)
+    for k in range(4):
+        b.step(5)
+        oracle.run(AU, md, st, 5, 0)
+        torch.cuda.synchronize()
+        x, y, z = b.positions(0)
+        dx = max(np.abs(x - st.x).max(), np.abs(y - st.y).max(), np.abs(z - st.z).max())
+        dv = np.abs(stackF(b.velocities(0)) - stackF((st.vx, st.vy, st.vz))).max()
+        note(f"  after {5 * (k + 1)} steps: |dx| {dx:.2e}  |dv| {dv:.2e}")
+        assert dx < 1e-11 and dv < 1e-9
+
+
+def test_thick_wire_blocks_stage_their_neighbours_by_gather_list():
+    """A 5 nm wire (blocked slot order by default): after in-step rebuilds
+    and prunings every block of the pair passes stages the exact set of its
+    neighbours through a gather list, the Verlet lists are exact at their
+    build positions, the pruned lists complete at the current ones, and
+    forces and energies match the oracle."""
+    rp = R(50.0, 60.0, T=298.0, v=0.5, r=3, jitter=0.02)
+    note("D5 nm blocked order, gather staging, 150 steps mixed")
+    # a short skin makes the wire rebuild and prune within the run
+    b = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1)
+    assert b.slot_tag[0] is not None
+    b.prepare()
+    b.run_batch(150, 50)
+    torch.cuda.synchronize()
+    assert b.status()[0] & A.ST_REBUILT
+    stg = b.staging()
+    note(f"  staging {stg}")
+    assert stg["gather"] > 0 and stg["unstaged"] == 0
+    assert 0 < stg["mean_gathered"] <= 1536
+    _check_lists(b, 0)
+    worst = _sampled_parity(b, [0])
+    note(f"  eps_F {worst:.2e}")
+
+
+def test_gather_staging_leaves_trajectories_unchanged_bitwise():
+    """Gather staging changes only where the pair passes read neighbour
+    positions from (LDS instead of global memory), not the arithmetic or its
+    order: 200 steps at 298 K with rebuilds and prunings, on and off, agree
+    bit for bit."""
+    rp = R(50.0, 40.0, T=298.0, v=0.5, r=4, jitter=0.02)
+    note("gather staging on vs off, 200 steps mixed")
+    a = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1, gather=1)
+    a.prepare()
+    a.run_batch(200, 50)
+    g = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1, gather=0, qbits=a.qbits)
+    g.prepare()
+    g.run_batch(200, 50)
+    torch.cuda.synchronize()
+    assert a.status()[0] & A.ST_REBUILT
+    assert a.staging()["gather"] > 0 and g.staging()["gather"] == 0
+    for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "obs", "status"):
+        assert torch.equal(a.t[k], g.t[k]), k
+
+
 def test_full_size_batch512_sampled():
     """The 512-wire D 3 nm batch at full size in the benchmark's launch shape:
     graph-replayed steps, then sampled replicas against the oracle."""
@@ -1028,7 +1104,9 @@ def test_full_size_d10_wire_sampled():
     torch.cuda.synchronize()
     assert not b.status()[0] & (A.ST_NONFINITE | A.ST_OVERFLOW)
     worst = _sampled_parity(b, [0])
-    note(f"  eps_F {worst:.2e}")
+    stg = b.staging()
+    note(f"  eps_F {worst:.2e}, staging {stg}")
+    assert stg["gather"] > 0.9 * b.nbmap_blocks()
 
 
 def test_batch2048_mixed_shapes_sampled():
