@@ -38,15 +38,17 @@ def counter_traffic(kernel: str, workload: str):
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
-            rec = json.load(f)[kernel]
+            recs = json.load(f)[kernel]
         with open(os.path.join(ROOT, "paper_1311_3890_amd", "csrc", "tbsma_kernels.hip"),
                   "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("source_sha256") != sha or rec.get("workload") != workload:
-        return None
-    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    for rec in recs:
+        if rec.get("source_sha256") == sha and rec.get("workload") == workload:
+            return (rec["fetch_kib"] * rec["fetch_scale"]
+                    + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return None
 
 
 def main():
