@@ -83,6 +83,12 @@ def main():
                     help="Verlet skin (A); default: the workload's")
     ap.add_argument("--prune", type=float, default=None,
                     help="pruning half-width (A); default: the workload's")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the pair passes' launch shapes per bucket of replicas in "
+                         "untimed trials on the whole batch before the timed window "
+                         "(paper_1311_3890_amd.autotune); the line also reports the rate "
+                         "with the default shapes")
+    ap.add_argument("--autotune-cache", default=None, help="JSON cache of earlier choices")
     ap.add_argument("--oracle-workloads", action="store_true",
                     help="also time the oracle on the D1.5xL3nm, D3xL20nm and D10xL100nm wires")
     args = ap.parse_args()
@@ -125,6 +131,12 @@ def main():
 
     if args.thermalize > 0:
         b.run_batch(args.thermalize, S)
+    tuned = untuned_value = None
+    if args.autotune:
+        from paper_1311_3890_amd import autotune
+        untuned_value = autotune.measure(b, args.steps, args.warmup, 1, S)
+        log(f"[bench] default launch shapes: {untuned_value:.4e} atom-steps/s")
+        tuned = autotune.tune(b, steps_per_graph=S, cache=args.autotune_cache, log=log)
     b.run_batch(args.warmup, S)
     torch.cuda.synchronize()
     ev_before = events()
@@ -369,6 +381,8 @@ def main():
                    "steps_per_graph": S, "skin_A": cfg["skin_A"], "r_cut_A": cfg["r_cut_A"],
                    "prune_A": cfg["prune_A"],
                    "thermalized_steps": args.thermalize,
+                   "launch_shapes": tuned["names"] if tuned else "default (4 tiles/block, "
+                                                                  "stage 1536)",
                    "parallelism": "replica batch, 1 GPU"},
         "window": window,
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
@@ -397,6 +411,8 @@ def main():
         "bad_replicas": bad,
         "cpu_baseline": cpu,
     }
+    if untuned_value is not None:
+        line["untuned_value"] = untuned_value
     if protocols is not None:
         line["protocols"] = protocols
     if drift is not None:

@@ -164,7 +164,18 @@ typedef struct {
  *  tag           device [N] int32 or NULL: tag of the atom in each slot,
  *                0 <= tag < atoms of its replica, distinct within a replica
  *                (NULL: slot minus rep_off[r]).
+ *  shape_h, shape  host and device copies of [R] int32, or both NULL: the
+ *                launch shape of each replica's pair-pass blocks,
+ *                TBSMA_SHAPE(tiles_per_block, stage_class) with
+ *                tiles_per_block 1, 2 or 4 and stage_class 0 (1152 staged
+ *                neighbour positions per block) or 1 (1536).  NULL means
+ *                TBSMA_SHAPE(4, 1) for every replica.  Shapes change how
+ *                work is laid out on the GPU, never a result bit: per-bucket
+ *                choices of an autotuner coexist in one batch.  A workspace
+ *                belongs to the shapes it was sized and initialised for.
  */
+#define TBSMA_SHAPE(tiles_per_block, stage_class) \
+  ((tiles_per_block) | ((stage_class) << 4))
 typedef struct {
   int32_t R;
   int32_t max_zbins;
@@ -184,6 +195,8 @@ typedef struct {
   uint8_t *flag;
   int32_t *qpos;
   const int32_t *tag;
+  const int32_t *shape_h;
+  const int32_t *shape;
 } tbsma_system;
 
 /*

@@ -14,6 +14,14 @@ LIB_PATH = os.path.join(HERE, "libtbsma.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tbsma.h")
 
 TILE = 64
+
+
+def shape(tiles_per_block: int, stage_class: int) -> int:
+    """TBSMA_SHAPE of include/tbsma.h."""
+    return int(tiles_per_block) | (int(stage_class) << 4)
+
+
+SHAPE_DEFAULT = shape(4, 1)
 NOBS = 10
 OK, EINVAL, ECAPACITY, EHIP, EDEVICE = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
@@ -38,7 +46,8 @@ class System(C.Structure):
                 ("rep_off_h", vp), ("cell_off_h", vp), ("rep_off", vp), ("cell_off", vp),
                 ("tile_rep", vp), ("grid_dim", vp), ("grid_lo", vp), ("rep_id", vp),
                 ("x", vp), ("y", vp), ("z", vp), ("vx", vp), ("vy", vp), ("vz", vp),
-                ("z0", vp), ("flag", vp), ("qpos", vp), ("tag", vp)]
+                ("z0", vp), ("flag", vp), ("qpos", vp), ("tag", vp),
+                ("shape_h", vp), ("shape", vp)]
 
 
 class Cells(C.Structure):

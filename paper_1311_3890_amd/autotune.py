@@ -1,37 +1,39 @@
-"""Per-bucket launch settings chosen by short timed trials.
+"""Per-bucket launch shapes of the pair passes, chosen by timed trials on the
+whole batch.
 
-Replicas are grouped into buckets of equal diameter and temperature class.
-For each bucket a sample of its replicas is run through the batched graph
-path for every candidate Verlet skin (with the cell edge r_cut + skin),
-pruning half-width and graph chunk length; the fastest setting in
-atom-timesteps/s is kept.  The skin trades the length of the full lists
-(the work of each rebuild and pruning) against rebuild frequency, which
-depends on temperature and diameter; the pruning half-width trades the length
-of the lists the pair passes read against pruning frequency; the chunk length
-trades graph launch overhead against the step granularity of the host loop.
-Choices are cached as JSON so later runs reuse them.
+Replicas fall into buckets of equal diameter and temperature class.  For each
+bucket the tuner tries every candidate launch shape, made of the tiles per
+pair-pass block (1, 2 or 4) and the stage class (1152 or 1536 neighbour
+positions staged in LDS per block).  Smaller blocks give more, shorter
+workgroups.  The smaller stage lets the density pass keep more workgroups
+resident per CU, but blocks whose slot window exceeds it read their
+neighbours from global memory.  Every trial times the whole batch, with the
+other buckets at their current choice, so per-bucket shapes are chosen for
+the way they run together: one batch, one HIP graph, one launch per stage
+class per pass.  Shapes change where work runs, not what is computed: the
+tuned batch's trajectories equal the untuned ones bit for bit.
+
+The trial rate is the median of a few timed windows (HIP events on the
+launch stream) after a short warm-up.  A candidate replaces the current
+choice only when it is faster by more than the tolerance.  Choices are
+cached as JSON, keyed by the workload's bucket signature, the precision, the
+Verlet skin and pruning width, and the candidate grid.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
-from dataclasses import asdict, dataclass
 from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 import torch
 
+from . import _abi as A
 from .engine import WireBatch
 
-
-@dataclass
-class Choice:
-    skin: float
-    prune: float
-    steps_per_graph: int
-    rate: float          # atom-timesteps/s of the trial
-    trials: list
+CANDIDATES = tuple(A.shape(t, c) for t in (4, 2, 1) for c in (1, 0))
 
 
 def bucket_of(rp) -> Tuple[float, str]:
@@ -45,144 +47,154 @@ def buckets(replicas: Sequence) -> Dict[Tuple[float, str], List[int]]:
     return dict(sorted(out.items()))
 
 
-def _key(b) -> str:
+def bucket_key(b) -> str:
     return f"D{b[0]:g}-{b[1]}"
 
 
-def _time_batch(reps, skin, prune, spg, trial_steps, warmup, precision):
-    wb = WireBatch(reps, precision, skin=skin, prune=prune, n_log=spg)
-    wb.prepare()
+def shape_name(s: int) -> str:
+    return f"{s & 15} tiles/block, stage {1152 if (s >> 4) == 0 else 1536}"
+
+
+def cache_key(wb: WireBatch, candidates: Sequence[int]) -> str:
+    sig = {"buckets": {bucket_key(b): [len(idx), int(sum(int(wb.n_atoms[r]) for r in idx))]
+                       for b, idx in buckets(wb.replicas).items()},
+           "precision": wb.precision, "skin": wb.skin, "prune": wb.prune,
+           "candidates": list(candidates)}
+    return hashlib.sha1(json.dumps(sig, sort_keys=True).encode()).hexdigest()[:16]
+
+
+def measure(wb: WireBatch, steps: int, warmup: int, windows: int, spg: int) -> float:
+    """Median atom-timesteps/s of `windows` timed windows of `steps` steps."""
+    n = float(wb.n_atoms.sum())
     wb.run_batch(warmup, spg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    wb.run_batch(trial_steps, spg)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    rate = float(wb.n_atoms.sum()) * trial_steps / dt
-    del wb
-    return rate
+    rates = []
+    stream = torch.cuda.current_stream()
+    for _ in range(windows):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        wb.run_batch(steps, spg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rates.append(n * steps / (e0.elapsed_time(e1) * 1e-3))
+    return float(np.median(rates))
 
 
-def tune(replicas: Sequence, precision: str = "mixed", *,
-         skins=(1.0, 1.3, 1.6, 2.0), prunes=(0.1, 0.15, 0.2), chunks=(50,),
-         sample: int = 32, trial_steps: int = 100, warmup: int = 100,
-         cache: str | None = None, log=print) -> Dict[str, Choice]:
-    """Best (skin, prune, steps_per_graph) per bucket of `replicas`."""
+def tune(wb: WireBatch, *, candidates: Sequence[int] = CANDIDATES, steps: int = 100,
+         warmup: int = 50, windows: int = 3, steps_per_graph: int = 50, tol: float = 0.005,
+         cache: str | None = None, log=print) -> dict:
+    """Chooses one launch shape per bucket of wb's replicas by coordinate
+    descent over the buckets on the whole batch, applies the choices to wb
+    (set_shapes) and returns them with the trial rates."""
+    key = cache_key(wb, candidates)
+    blist = buckets(wb.replicas)
     cached = {}
     if cache and os.path.exists(cache):
         with open(cache) as fh:
             cached = json.load(fh)
-    result: Dict[str, Choice] = {}
-    for b, idx in buckets(replicas).items():
-        k = _key(b)
-        if k in cached:
-            result[k] = Choice(**cached[k])
-            continue
-        pick = np.linspace(0, len(idx) - 1, min(sample, len(idx))).round().astype(int)
-        reps = [replicas[idx[p]] for p in pick]
-        trials = []
-        for skin in skins:
-            for prune in (prunes if precision == "mixed" else (0.0,)):
-                for spg in chunks:
-                    rate = _time_batch(reps, skin, prune, spg, trial_steps, warmup, precision)
-                    trials.append((skin, prune, spg, rate))
-                    log(f"[autotune] {k}: skin {skin} prune {prune} chunk {spg}: "
-                        f"{rate:.3e} atom-steps/s")
-        skin, prune, spg, rate = max(trials, key=lambda t: t[3])
-        result[k] = Choice(skin, prune, spg, rate, trials)
+    if key in cached:
+        res = cached[key]
+        shapes = [A.SHAPE_DEFAULT] * wb.R
+        for b, idx in blist.items():
+            for r in idx:
+                shapes[r] = res["choice"][bucket_key(b)]
+        wb.set_shapes(shapes)
+        log(f"[autotune] cached choices {res['choice']}")
+        return res
+    t0 = time.perf_counter()
+    shapes = list(wb.shapes) if wb.shapes is not None else [A.SHAPE_DEFAULT] * wb.R
+    wb.set_shapes(shapes)
+    best_rate = measure(wb, steps, warmup, windows, steps_per_graph)
+    untuned = best_rate
+    log(f"[autotune] start: {best_rate:.4e} atom-steps/s")
+    choice, trials = {}, []
+    for b, idx in blist.items():
+        k = bucket_key(b)
+        cur = shapes[idx[0]]
+        for cand in candidates:
+            if cand == cur:
+                continue
+            trial = list(shapes)
+            for r in idx:
+                trial[r] = cand
+            wb.set_shapes(trial)
+            rate = measure(wb, steps, warmup, windows, steps_per_graph)
+            trials.append({"bucket": k, "shape": cand, "rate": rate})
+            log(f"[autotune] {k}: {shape_name(cand)}: {rate:.4e} atom-steps/s "
+                f"(best {best_rate:.4e})")
+            if rate > best_rate * (1.0 + tol):
+                best_rate, cur = rate, cand
+        for r in idx:
+            shapes[r] = cur
+        choice[k] = cur
+    wb.set_shapes(shapes)
+    res = {"choice": choice, "names": {k: shape_name(v) for k, v in choice.items()},
+           "untuned_trial_rate": untuned, "tuned_trial_rate": best_rate, "trials": trials,
+           "seconds": time.perf_counter() - t0}
     if cache:
         merged = dict(cached)
-        merged.update({k: asdict(v) for k, v in result.items()})
+        merged[key] = res
         with open(cache, "w") as fh:
             json.dump(merged, fh, indent=1)
-    return result
+    return res
 
 
-class BucketRun:
-    """The replicas of a workload as one WireBatch per bucket, each with its
-    tuned settings, advanced in turn."""
-
-    def __init__(self, replicas: Sequence, choices: Dict[str, Choice],
-                 precision: str = "mixed", n_log: int = 100):
-        self.parts = []
-        for b, idx in buckets(replicas).items():
-            c = choices[_key(b)]
-            wb = WireBatch([replicas[r] for r in idx], precision, skin=c.skin, prune=c.prune,
-                           n_log=n_log)
-            self.parts.append((_key(b), idx, c, wb))
-        self.n_atoms = sum(int(wb.n_atoms.sum()) for _, _, _, wb in self.parts)
-
-    def prepare(self):
-        for _, _, _, wb in self.parts:
-            wb.prepare()
-
-    def run(self, n: int):
-        for _, _, c, wb in self.parts:
-            wb.run_batch(n, c.steps_per_graph)
-
-
-def _pass_us(wb, p: int, n: int = 10) -> float:
-    """Average launch time (us) of force pass p on wb's current state, HIP
-    events on the launch stream."""
-    import ctypes as C
-    from . import _abi as A
-    lib = A.lib()
-    args = (C.byref(wb.params), C.byref(wb.sys), C.byref(wb.nlist), C.byref(wb.out), wb.work)
-    A.check(lib.tbsma_forces_pass(*args, p, wb.stream()))
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(n):
-        A.check(lib.tbsma_forces_pass(*args, p, wb.stream()))
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / n * 1e3
+def per_bucket_rates(replicas: Sequence, choice: dict, precision: str, *, skin: float,
+                     prune: float, steps: int = 200, warmup: int = 200,
+                     steps_per_graph: int = 50, log=print) -> dict:
+    """Rate of each bucket alone (one batch of its replicas, with its tuned
+    shape): the per-replica-size throughput.  Context for the one-batch
+    rate, which is the one a workload runs at."""
+    out = {}
+    for b, idx in buckets(replicas).items():
+        k = bucket_key(b)
+        wb = WireBatch([replicas[r] for r in idx], precision, skin=skin, prune=prune,
+                       n_log=steps_per_graph, shapes=[choice[k]] * len(idx))
+        wb.prepare()
+        rate = measure(wb, steps, warmup, 1, steps_per_graph)
+        out[k] = {"replicas": len(idx), "atoms": int(wb.n_atoms.sum()),
+                  "shape": shape_name(choice[k]), "atom_timesteps_per_s": rate}
+        log(f"[autotune] bucket {k} alone: {out[k]}")
+        del wb
+        torch.cuda.empty_cache()
+    return out
 
 
 def main(argv=None):
-    """Tunes the buckets of a workload, then times each bucket's batch with its
-    chosen settings; prints one JSON object."""
+    """Tunes the launch shapes of a workload's buckets in one batch and
+    prints one JSON object: the choices, the one-batch rate before and after
+    (timed windows of --steps after the tuning), and each bucket's rate
+    alone."""
     import argparse
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--workload", default="batch2048-mixed", choices=sorted(W.WORKLOADS))
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--sample", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--thermalize", type=int, default=1000)
     ap.add_argument("--trial-steps", type=int, default=100)
     ap.add_argument("--cache", default=None, help="JSON file of earlier choices")
+    ap.add_argument("--no-per-bucket", action="store_true")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     wl = W.WORKLOADS[a.workload]()
-    choices = tune(wl.replicas, wl.precision, sample=a.sample, trial_steps=a.trial_steps,
-                   warmup=a.warmup, cache=a.cache, log=log)
-    run = BucketRun(wl.replicas, choices, wl.precision)
-    run.prepare()
-    out = {"workload": wl.name, "atoms": run.n_atoms, "steps": a.steps, "buckets": {}}
-    total_s = 0.0
-    for k, idx, c, wb in run.parts:
-        wb.run_batch(a.warmup, c.steps_per_graph)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        wb.run_batch(a.steps, c.steps_per_graph)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        total_s += dt
-        n = int(wb.n_atoms.sum())
-        kbar, kp = wb.list_lengths()
-        t3 = _pass_us(wb, 3)
-        out["buckets"][k] = {
-            "replicas": len(idx), "atoms": n, "skin_A": c.skin, "prune_A": c.prune,
-            "steps_per_graph": c.steps_per_graph,
-            "atom_timesteps_per_s": n * a.steps / dt,
-            "mean_listed_neighbours": kbar,
-            "mean_pruned_list": kp,
-            "force_pass_us": t3,
-            "force_pass_GB_per_s": n * (4.0 * kp + 32.0) / (t3 * 1e-6) / 1e9}
-        log(f"[autotune] {k}: {out['buckets'][k]}")
-    out["atom_timesteps_per_s"] = run.n_atoms * a.steps / total_s
+    torch.cuda.set_device(0)
+    wb = WireBatch(wl.replicas, wl.precision, skin=wl.skin, prune=wl.prune, n_log=50,
+                   gamma=wl.gamma)
+    wb.prepare()
+    wb.run_batch(a.thermalize, 50)
+    untuned = measure(wb, a.steps, 50, 1, 50)
+    res = tune(wb, steps=a.trial_steps, cache=a.cache, log=log)
+    tuned = measure(wb, a.steps, 50, 1, 50)
+    out = {"workload": wl.name, "atoms": int(wb.n_atoms.sum()), "steps": a.steps,
+           "untuned_atom_timesteps_per_s": untuned, "tuned_atom_timesteps_per_s": tuned,
+           "choice": res["names"], "tuning_seconds": res.get("seconds")}
+    del wb
+    torch.cuda.empty_cache()
+    if not a.no_per_bucket:
+        out["per_bucket"] = per_bucket_rates(wl.replicas, res["choice"], wl.precision,
+                                             skin=wl.skin, prune=wl.prune, log=log)
     print(json.dumps(out), flush=True)
 
 

@@ -111,6 +111,17 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
   }
   if (s->C + s->R >= (int64_t)1 << 31)
     return fail(TBSMA_EINVAL, "too many cells");
+  if ((s->shape_h == nullptr) != (s->shape == nullptr))
+    return fail(TBSMA_EINVAL, "shape_h and shape must both be given or both NULL");
+  if (s->shape_h)
+    for (int r = 0; r < s->R; ++r) {
+      const int32_t sh = s->shape_h[r];
+      const int tpb = shape_tpb(sh), cls = shape_cls(sh);
+      if ((tpb != 1 && tpb != 2 && tpb != 4) || cls >= kStageClasses ||
+          (sh & ~0xff) != 0)
+        return fail(TBSMA_EINVAL, "shape of replica %d (%d) is not a valid "
+                    "launch shape", r, sh);
+    }
   if (s->max_zbins < 2) return fail(TBSMA_EINVAL, "max_zbins < 2");
   if (!s->rep_off || !s->cell_off || !s->tile_rep || !s->grid_dim ||
       !s->grid_lo || !s->rep_id || !s->x || !s->y || !s->z || !s->vx ||
@@ -125,8 +136,8 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, nnmax, rsum, win,
-      bmap, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw, baw,
-      wl, callb, gcnt, glist, total;
+      bmap, boff, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw,
+      baw, wl, callb, gcnt, glist, total;
 };
 
 // Blocks of the cell sort: ceil(cells/kSortCells) per replica.
@@ -138,12 +149,22 @@ int32_t cell_map_size(const tbsma_system *s) {
   return (int32_t)nb;
 }
 
-// Blocks of the list build: ceil(tiles/4) per replica.
-int32_t block_map_size(const tbsma_system *s) {
+int32_t host_shape(const tbsma_system *s, int r) {
+  return s->shape_h ? s->shape_h[r] : kShapeDefault;
+}
+
+// Blocks of the list build and pair passes: ceil(tiles / tpb) per replica;
+// per stage class when cls is given (cls[c] = blocks of class c).
+int32_t block_map_size(const tbsma_system *s, int64_t *cls = nullptr) {
   int64_t nb = 0;
+  if (cls)
+    for (int c = 0; c < kStageClasses; ++c) cls[c] = 0;
   for (int r = 0; r < s->R; ++r) {
     const int64_t nt = (s->rep_off_h[r + 1] - s->rep_off_h[r]) / TBSMA_TILE;
-    nb += (nt + 3) / 4;
+    const int32_t sh = host_shape(s, r);
+    const int64_t v = (nt + shape_tpb(sh) - 1) / shape_tpb(sh);
+    nb += v;
+    if (cls) cls[shape_cls(sh)] += v;
   }
   return (int32_t)nb;
 }
@@ -173,7 +194,9 @@ Layout layout(const tbsma_params *p, const tbsma_system *s) {
   L.win = o;
   o += up(8 * (size_t)nt);
   L.bmap = o;
-  o += up(8 * (size_t)(nt / 4 + R + 1));
+  o += up(8 * ((size_t)block_map_size(s) + 1));
+  L.boff = o;
+  o += up(4 * (size_t)R);
   L.cbmap = o;
   o += up(16 * (size_t)(s->C / kSortCells + R + 1));
   L.lane_atom = o;
@@ -252,6 +275,15 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.wl = reinterpret_cast<int32_t *>(w + L.wl);
   d.callb = reinterpret_cast<int64_t *>(w + L.callb);
   d.tag = s->tag;
+  d.shape = s->shape;
+  d.boff = reinterpret_cast<int32_t *>(w + L.boff);
+  {
+    int64_t cls[kStageClasses];
+    block_map_size(s, cls);
+    d.cls_off[0] = 0;
+    for (int c = 0; c < kStageClasses; ++c)
+      d.cls_off[c + 1] = d.cls_off[c] + (int32_t)cls[c];
+  }
   d.gather = p->precision == TBSMA_MIXED && p->gather ? 1 : 0;
   d.gcnt = d.gather ? reinterpret_cast<int32_t *>(w + L.gcnt) : nullptr;
   d.glist = d.gather ? reinterpret_cast<uint16_t *>(w + L.glist) : nullptr;

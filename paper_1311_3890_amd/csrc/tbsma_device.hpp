@@ -12,8 +12,22 @@ constexpr int kBlock = 256; // threads of every per-atom kernel
 constexpr int kSortCells = 16;  // cells per block of the cell sort
 constexpr int kNPart = 8;   // FP64 partial sums per tile
 constexpr int kStage = 1536;  // neighbour positions a pair-pass block stages
-                              // in LDS (24 KB)
+                              // in LDS (24 KB), at most
 constexpr int kGatherSpan = 65536;  // widest slot window of gather staging
+
+// Launch shapes of the mixed pair passes, chosen per replica (tbsma_system
+// shape): tiles per block (1, 2 or 4) and the stage class, the LDS the block
+// reserves for staged positions (class 0: 1152 entries, 18 KB, which leaves
+// room for the density pass's full occupancy; class 1: kStage).  The block
+// map holds the blocks of class 0 first, then those of class 1, and each
+// class is one launch of its own kernel variant.
+constexpr int kStageClasses = 2;
+__host__ __device__ constexpr int stage_of_class(int c) {
+  return c == 0 ? 1152 : kStage;
+}
+constexpr int32_t kShapeDefault = 4 | (1 << 4);  // 4 tiles, class 1
+__host__ __device__ inline int shape_tpb(int32_t s) { return s & 15; }
+__host__ __device__ inline int shape_cls(int32_t s) { return (s >> 4) & 15; }
 
 // per-tile partial sums
 constexpr int kPartE = 0;   // sum of E_i
@@ -86,6 +100,10 @@ struct Dev {
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
+  const int32_t *shape;         // [R] launch shape of each replica, or NULL
+                                // (kShapeDefault)
+  int32_t *boff;                // [R] first block of each replica in bmap
+  int32_t cls_off[kStageClasses + 1];  // first block of each stage class
   // gather staging of the pair passes (mixed precision): blocks whose slot
   // window exceeds LDS stage the exact set of their neighbours
   int32_t gather;               // 1 when enabled
@@ -414,20 +432,29 @@ struct WorkLists {
   int32_t *reps;     // the replicas that rebuild
   int32_t *cblocks;  // cell-sort blocks (cbmap entries) of those replicas
 };
-// Capacities: N/64 tiles, N/256 + R + 1 list-build blocks, R replicas,
-// C/kSortCells + R + 1 cell-sort blocks.
+// Capacities: N/64 tiles, N/64 + R + 1 list-build blocks (one tile per block
+// at the least), R replicas, C/kSortCells + R + 1 cell-sort blocks.
 __host__ __device__ inline int64_t work_lists_size(int64_t N, int64_t R,
                                                    int64_t C) {
-  return 4 + N / kTile + (N / kTile / 4 + R + 1) + R + (C / kSortCells + R + 1);
+  return 4 + N / kTile + (N / kTile + R + 1) + R + (C / kSortCells + R + 1);
 }
 __device__ __forceinline__ WorkLists work_lists(const Dev &S) {
   WorkLists W;
   W.count = S.wl;
   W.tiles = S.wl + 4;
   W.blocks = W.tiles + S.N / kTile;
-  W.reps = W.blocks + (S.N / kTile / 4 + S.R + 1);
+  W.reps = W.blocks + (S.N / kTile + S.R + 1);
   W.cblocks = W.reps + S.R;
   return W;
+}
+
+__device__ __forceinline__ int32_t rep_shape(const Dev &S, int r) {
+  return S.shape != nullptr ? S.shape[r] : kShapeDefault;
+}
+
+// Stage (LDS entries) of the pair-pass block at index blk of the block map.
+__device__ __forceinline__ int block_stage(const Dev &S, int64_t blk) {
+  return blk < S.cls_off[1] ? stage_of_class(0) : stage_of_class(1);
 }
 
 __device__ __forceinline__ bool rebuilds(const Dev &S, int r) {

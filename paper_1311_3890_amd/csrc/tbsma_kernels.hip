@@ -290,11 +290,14 @@ __device__ __attribute__((aligned(16))) int32_t kPadChunk[8] = {
 // kernel lists their offsets from lo in ascending order (Dev::glist, at
 // most kStage of them) and writes each entry as 16 times the neighbour's
 // rank in that list, with kPadStaged for the unused ones.
-constexpr int32_t kPadStaged = kStage * 16;
+// The stage (cap entries, per block: block_stage) and so kPadStaged = 16 cap
+// depend on the block's stage class.
 constexpr int32_t kPadWide = (int32_t)0xFFFFFFF0u;
 
-__device__ __forceinline__ int32_t pad_of_window(int size) {
-  return size > 0 && size <= kStage ? kPadStaged : kPadWide;
+__device__ __forceinline__ int32_t pad_staged(int cap) { return cap * 16; }
+
+__device__ __forceinline__ int32_t pad_of_window(int size, int cap) {
+  return size > 0 && size <= cap ? pad_staged(cap) : kPadWide;
 }
 
 // Entry of neighbour j in a block whose window starts at lo (j >= lo; slot
@@ -396,9 +399,18 @@ __device__ __forceinline__ void chunk_loop(const int32_t *list, int64_t N,
 // global memory (with a constant-memory pointer among the candidates of a
 // load, the compiler emits flat loads, which the wavefront must also wait
 // for before each LDS read).
-__device__ __attribute__((aligned(16))) int32_t kPadChunkStaged[8] = {
-    kPadStaged, kPadStaged, kPadStaged, kPadStaged,
-    kPadStaged, kPadStaged, kPadStaged, kPadStaged};
+// (one per stage class)
+constexpr int32_t kPad0 = stage_of_class(0) * 16, kPad1 = stage_of_class(1) * 16;
+__device__ __attribute__((aligned(16))) int32_t kPadChunkStaged0[8] = {
+    kPad0, kPad0, kPad0, kPad0, kPad0, kPad0, kPad0, kPad0};
+__device__ __attribute__((aligned(16))) int32_t kPadChunkStaged1[8] = {
+    kPad1, kPad1, kPad1, kPad1, kPad1, kPad1, kPad1, kPad1};
+template <int STAGE>
+__device__ __forceinline__ const int32_t *pad_chunk_staged() {
+  static_assert(STAGE == stage_of_class(0) || STAGE == stage_of_class(1),
+                "a stage class");
+  return STAGE == stage_of_class(0) ? kPadChunkStaged0 : kPadChunkStaged1;
+}
 
 // Loop over the chunks of one lane's list in which every entry may be read:
 // the wavefront runs as many chunks as its longest list, a lane past its own
@@ -727,7 +739,8 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
         atomicAdd(ctr + 1, (unsigned long long)__popcll(bp));
       }
     }
-    const int32_t nb = (nt + 3) >> 2;
+    const int tpb = r < S.R ? shape_tpb(rep_shape(S, r)) : 4;
+    const int32_t nb = (nt + tpb - 1) / tpb;
     const int32_t ncb = (nc + kSortCells - 1) / kSortCells;
     const int32_t v[kL] = {reb ? nt : 0, upd ? nb : 0, reb ? ncb : 0,
                            reb ? 1 : 0,  nb,          ncb};
@@ -761,7 +774,7 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
     if (reb) W.reps[ex[3]] = r;
     // each wavefront writes the runs of its own replicas
     write_runs(W.tiles, t0, v[0], ex[0], lane);
-    write_runs(W.blocks, ex[4], v[1], ex[1], lane);
+    write_runs(W.blocks, r < S.R ? S.boff[r] : 0, v[1], ex[1], lane);
     write_runs(W.cblocks, ex[5], v[2], ex[2], lane);
     __syncthreads();
     if (tid < kL) carry[tid] += tot[tid];
@@ -906,41 +919,60 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
   }
 }
 
-// Block map of the list build: for each replica, blocks of up to four of
-// its tiles, replicas in order (one block of 1024 threads; a scan over the
-// replicas of their block counts).
+// Block map of the list build and the pair passes: for each replica, blocks
+// of up to tpb of its tiles (its launch shape), replicas in order within each
+// stage class, the classes one after another from cls_off[c]; boff[r] is the
+// replica's first block.  One block of 1024 threads; a scan over the
+// replicas of their block counts per class.
 __global__ void __launch_bounds__(1024) k_block_map(Dev S) {
-  __shared__ int32_t wsum[16];
-  __shared__ int32_t carry_s;
+  __shared__ int32_t wsum[kStageClasses][16];
+  __shared__ int32_t carry_s[kStageClasses];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry_s = 0;
+  if (threadIdx.x < kStageClasses) carry_s[threadIdx.x] = 0;
   __syncthreads();
   for (int b0 = 0; b0 < S.R; b0 += 1024) {
     const int r = b0 + threadIdx.x;
-    int32_t t0 = 0, nt = 0;
+    int32_t t0 = 0, nt = 0, tpb = 4, cls = 0;
     if (r < S.R) {
       t0 = (int32_t)(S.rep_off[r] / kTile);
       nt = (int32_t)(S.rep_off[r + 1] / kTile) - t0;
+      const int32_t sh = rep_shape(S, r);
+      tpb = shape_tpb(sh);
+      cls = shape_cls(sh);
     }
-    const int32_t v = (nt + 3) >> 2;
-    int32_t s = v;
+    const int32_t v = (nt + tpb - 1) / tpb;
+    int32_t ex[kStageClasses], tot[kStageClasses];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t t = __shfl_up(s, o, 64);
-      if (lane >= o) s += t;
+    for (int c = 0; c < kStageClasses; ++c) {
+      const int32_t vc = cls == c ? v : 0;
+      int32_t sc = vc;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(sc, o, 64);
+        if (lane >= o) sc += t;
+      }
+      if (lane == 63) wsum[c][wid] = sc;
+      ex[c] = sc - vc;
     }
-    if (lane == 63) wsum[wid] = s;
     __syncthreads();
-    int32_t woff = 0, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      if (k < wid) woff += wsum[k];
-      tot += wsum[k];
+#pragma unroll
+    for (int c = 0; c < kStageClasses; ++c) {
+      int32_t woff = 0, t = 0;
+      for (int k = 0; k < 16; ++k) {
+        if (k < wid) woff += wsum[c][k];
+        t += wsum[c][k];
+      }
+      ex[c] += carry_s[c] + woff + S.cls_off[c];
+      tot[c] = t;
     }
-    const int32_t ex = carry_s + woff + s - v;
-    for (int k = 0; k < v; ++k)
-      S.bmap[ex + k] = make_int2(t0 + 4 * k, min(4, nt - 4 * k));
+    if (r < S.R) {
+      const int32_t first = ex[cls];
+      S.boff[r] = first;
+      for (int k = 0; k < v; ++k)
+        S.bmap[first + k] = make_int2(t0 + tpb * k, min(tpb, nt - tpb * k));
+    }
     __syncthreads();
-    if (threadIdx.x == 0) carry_s += tot;
+    if (threadIdx.x < kStageClasses) carry_s[threadIdx.x] += tot[threadIdx.x];
     __syncthreads();
   }
 }
@@ -980,9 +1012,10 @@ struct PairBlock {
   int n;       // its list length; its list is row b0 + p of nl_lane
 };
 
-__device__ __forceinline__ PairBlock pair_block(const Dev &S) {
+// base: first block-map index of this launch (its stage class).
+__device__ __forceinline__ PairBlock pair_block(const Dev &S, int base) {
   PairBlock B;
-  B.blk = xcd_block();
+  B.blk = base + xcd_block();
   const int2 bm = S.bmap[B.blk];
   B.t0 = bm.x;
   B.nt = bm.y;
@@ -1029,40 +1062,41 @@ __device__ __forceinline__ void block_window(const Dev &S, const PairBlock &B,
 // The sentinel and the condition for it, after the block has copied its
 // staged positions (all threads of the block take part).
 __device__ __forceinline__ bool stage_sentinel(const Dev &S, int4 *lq,
-                                               const PairBlock &B) {
+                                               const PairBlock &B, int cap) {
   const int4 q0 = S.qpos[B.b0];
   const int xi = B.valid ? S.qpos[B.b0 + B.p].x : q0.x;
   const int64_t d = (int64_t)xi - (int64_t)q0.x;
   const bool near = d > -(1ll << 29) && d < (1ll << 29);
   if (threadIdx.x == 0)
-    lq[kStage] = make_int4(q0.x >= 0 ? q0.x - (1 << 30) : q0.x + (1 << 30),
+    lq[cap] = make_int4(q0.x >= 0 ? q0.x - (1 << 30) : q0.x + (1 << 30),
                            q0.y, q0.z, 0);
   return __syncthreads_and(near) != 0;
 }
 
 __device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
-                                      const PairBlock &B, int lo, int size) {
+                                      const PairBlock &B, int lo, int size,
+                                      int cap) {
   for (int t = threadIdx.x; t < size; t += kBlock) lq[t] = S.qpos[lo + t];
-  return stage_sentinel(S, lq, B);
+  return stage_sentinel(S, lq, B, cap);
 }
 
 // Gather staging: lq[k] = qpos[lo + glist[k]] for the gc listed neighbours
 // of the block, then the sentinel as above.
 __device__ __forceinline__ bool stage_gather(const Dev &S, int4 *lq,
                                              const PairBlock &B, int lo,
-                                             int gc) {
+                                             int gc, int cap) {
   const uint16_t *g = S.glist + B.blk * kStage;
   for (int t = threadIdx.x; t < gc; t += kBlock) lq[t] = S.qpos[lo + g[t]];
-  return stage_sentinel(S, lq, B);
+  return stage_sentinel(S, lq, B, cap);
 }
 
-// LDS entry of list entry j: lq[min(j, lo + kStage) - lo] (kPadEntry -> the
+// LDS entry of list entry j: lq[min(j, lo + cap) - lo] (kPadEntry -> the
 // sentinel), with the byte offset formed as min(j, jmax) * 16 - lo * 16.
 struct StagedIndex {
-  int jmax;       // lo + kStage
+  int jmax;       // lo + cap
   uint32_t nlo;   // -lo * 16 (mod 2^32)
-  __device__ __forceinline__ StagedIndex(int lo)
-      : jmax(lo + kStage), nlo(0u - ((uint32_t)lo << 4)) {}
+  __device__ __forceinline__ StagedIndex(int lo, int cap)
+      : jmax(lo + cap), nlo(0u - ((uint32_t)lo << 4)) {}
   __device__ __forceinline__ int4 get(const int4 *lq, int j) const {
     const uint32_t off = ((uint32_t)min(j, jmax) << 4) + nlo;
     return *reinterpret_cast<const int4 *>(
@@ -1141,7 +1175,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
 // With gather staging, a block whose window exceeds LDS (up to kGatherSpan
 // slots) first marks the neighbours it keeps in a bitmap over its window,
 // then lists the marked slots in ascending order (glist, gcnt) when there
-// are at most kStage of them, and writes each kept entry as 16 times its
+// are at most as many as its stage holds, and writes each kept entry as 16 times its
 // neighbour's rank in that list (the rank is the number of marked slots
 // before it).  Otherwise gcnt is 0 and entries are slot offsets.
 template <bool GATHER>
@@ -1171,12 +1205,13 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
     B.i = B.b0 + B.p;
     B.n = 0;
     const bool rebuilt = rebuilds(S, S.tile_rep[B.t0]);  // uniform
+    const int cap = block_stage(S, blk);  // stage of the block's class
     int lo, size;
     block_window(S, B, lo, size);
     const bool staged =
-        size > 0 && size <= kStage && stage(S, lq, B, lo, size);
+        size > 0 && size <= cap && stage(S, lq, B, lo, size, cap);
     // gather staging of this block (uniform)
-    const bool gmark = GATHER && size > kStage && size <= kGatherSpan;
+    const bool gmark = GATHER && size > cap && size <= kGatherSpan;
     const int nwords = gmark ? (size + 31) >> 5 : 0;
     const int64_t i = B.b0 + B.p;
     const int n = B.valid ? S.nn[i] : 0;
@@ -1228,7 +1263,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
         cnt += w0 + k < nwords ? __popc(bits[w0 + k]) : 0;
       int total = 0;
       int at = block_excl_scan(cnt, key, &total);
-      if (total <= kStage) {
+      if (total <= cap) {
         uint16_t *g = S.glist + (int64_t)blk * kStage;
 #pragma unroll
         for (int k = 0; k < kWpt; ++k) {
@@ -1267,7 +1302,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       // LDS reads instead of delaying the next list loads (loads and stores
       // retire in order)
       constexpr int kPruneBatch = 7;
-      const StagedIndex sx(lo);
+      const StagedIndex sx(lo, cap);
       const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
       const int own = (n + 7) >> 3;
       const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
@@ -1309,7 +1344,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
     }
     if (B.valid) {
       ring.finish(S.nl_lane, S.N, row, nch,
-                  gc > 0 ? kPadStaged : pad_of_window(size));
+                  gc > 0 ? pad_staged(cap) : pad_of_window(size, cap));
       S.nn_lane[row] = ring.cnt;
       S.qprune[i] = qi;
     }
@@ -1323,7 +1358,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 // unused entries hit the sentinel.  Not staged: global gathers, the unused
 // entries are replaced by the atom itself and masked (r = 0); with GATHER
 // the entries are ranks in the block's gather list (size = its length).
-template <bool STAGED, bool COUNT, bool GATHER = false>
+template <bool STAGED, bool COUNT, int STAGE, bool GATHER = false>
 __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
                                             const PairBlock &B,
                                             const int4 *lq, int lo, int size) {
@@ -1361,7 +1396,7 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
     }
   };
   if (STAGED) {
-    chunk_loop_padded(S.nl_lane, N, row, n, kPadChunkStaged,
+    chunk_loop_padded(S.nl_lane, N, row, n, pad_chunk_staged<STAGE>(),
                       [&](const int (&e)[8]) {
                         int4 q[8];
 #pragma unroll
@@ -1392,22 +1427,25 @@ __device__ __forceinline__ void density_run(const Dev &S, const PotF &P,
   }
 }
 
-template <bool COUNT, bool GATHER>
-__global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P) {
-  __shared__ int4 lq[kStage + 1];
-  const PairBlock B = pair_block(S);
+// One launch per stage class: blocks base .. base + gridDim.x - 1 of the
+// block map, all of stage STAGE.
+template <bool COUNT, bool GATHER, int STAGE>
+__global__ void __launch_bounds__(kBlock) k_density_mixed(Dev S, PotF P,
+                                                          int base) {
+  __shared__ int4 lq[STAGE + 1];
+  const PairBlock B = pair_block(S, base);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   int lo, size;
   block_window(S, B, lo, size);
-  const int gc = GATHER && size > kStage ? S.gcnt[B.blk] : 0;  // uniform
-  if (size > 0 && size <= kStage && stage(S, lq, B, lo, size))
-    density_run<true, COUNT>(S, P, B, lq, lo, size);
-  else if (gc > 0 && stage_gather(S, lq, B, lo, gc))
-    density_run<true, COUNT>(S, P, B, lq, lo, gc);
+  const int gc = GATHER && size > STAGE ? S.gcnt[B.blk] : 0;  // uniform
+  if (size > 0 && size <= STAGE && stage(S, lq, B, lo, size, STAGE))
+    density_run<true, COUNT, STAGE>(S, P, B, lq, lo, size);
+  else if (gc > 0 && stage_gather(S, lq, B, lo, gc, STAGE))
+    density_run<true, COUNT, STAGE>(S, P, B, lq, lo, gc);
   else if (gc > 0)
-    density_run<false, COUNT, true>(S, P, B, lq, lo, gc);
+    density_run<false, COUNT, STAGE, true>(S, P, B, lq, lo, gc);
   else
-    density_run<false, COUNT>(S, P, B, lq, lo, size);
+    density_run<false, COUNT, STAGE>(S, P, B, lq, lo, size);
 }
 
 __device__ __forceinline__ double radial_d(const PotD &P, bool dens,
@@ -1472,7 +1510,7 @@ __global__ void __launch_bounds__(kBlock) k_density_fp64(Dev S, PotD P,
 // partial sums and, on logged steps, the axial bins of the rupture gap.
 // These are the same operations, in the same order and precision, as
 // k_integrate_b, so the results do not depend on which of the two ran.
-template <bool STAGED, bool ENERGY, bool KICK, bool GATHER = false>
+template <bool STAGED, bool ENERGY, bool KICK, int STAGE, bool GATHER = false>
 __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
                                           const DevMD &M, const PairBlock &B,
                                           const int4 *lq, int lo, int size,
@@ -1530,7 +1568,7 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
     }
   };
   if (STAGED) {
-    chunk_loop_padded(S.nl_lane, N, row, n, kPadChunkStaged,
+    chunk_loop_padded(S.nl_lane, N, row, n, pad_chunk_staged<STAGE>(),
                       [&](const int (&e)[8]) {
                         int4 q[8];
 #pragma unroll
@@ -1649,47 +1687,51 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   }
 }
 
-template <bool KICK, bool GATHER>
+// One launch per stage class, as the density pass.
+template <bool KICK, bool GATHER, int STAGE>
 __global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         DevMD M, float *fx,
                                                         float *fy, float *fz,
-                                                        float *eat) {
-  __shared__ int4 lq[kStage + 1];
+                                                        float *eat, int base) {
+  __shared__ int4 lq[STAGE + 1];
   // per-tile sums after the pair loop, in the staged positions' LDS
   static_assert(5 * kBlock * sizeof(double) <= sizeof(lq), "lsum fits");
   double *lsum = reinterpret_cast<double *>(lq);
-  const PairBlock B = pair_block(S);
+  const PairBlock B = pair_block(S, base);
   if (retired(S, S.tile_rep[B.t0])) return;  // uniform over the block
   const bool energy =
       S.energies > 0 || (S.energies < 0 && (S.callb[2] & kStepLog) != 0);
   int lo, size;
   block_window(S, B, lo, size);
-  const int gc = GATHER && size > kStage ? S.gcnt[B.blk] : 0;  // uniform
+  const int gc = GATHER && size > STAGE ? S.gcnt[B.blk] : 0;  // uniform
   bool staged = false;
-  if (size > 0 && size <= kStage) {
-    staged = stage(S, lq, B, lo, size);
+  if (size > 0 && size <= STAGE) {
+    staged = stage(S, lq, B, lo, size, STAGE);
   } else if (gc > 0) {
-    staged = stage_gather(S, lq, B, lo, gc);
+    staged = stage_gather(S, lq, B, lo, gc, STAGE);
     size = gc;  // the staged (or decoded) list length from here on
   }
   if (staged) {
     if (energy)
-      force_run<true, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
-    else
-      force_run<true, false, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
-  } else if (gc > 0) {
-    if (energy)
-      force_run<false, true, KICK, true>(S, P, M, B, lq, lo, size, lsum, fx, fy,
+      force_run<true, true, KICK, STAGE>(S, P, M, B, lq, lo, size, lsum, fx, fy,
                                          fz, eat);
     else
-      force_run<false, false, KICK, true>(S, P, M, B, lq, lo, size, lsum, fx,
+      force_run<true, false, KICK, STAGE>(S, P, M, B, lq, lo, size, lsum, fx,
                                           fy, fz, eat);
+  } else if (gc > 0) {
+    if (energy)
+      force_run<false, true, KICK, STAGE, true>(S, P, M, B, lq, lo, size, lsum,
+                                                fx, fy, fz, eat);
+    else
+      force_run<false, false, KICK, STAGE, true>(S, P, M, B, lq, lo, size,
+                                                 lsum, fx, fy, fz, eat);
   } else {
     if (energy)
-      force_run<false, true, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz, eat);
+      force_run<false, true, KICK, STAGE>(S, P, M, B, lq, lo, size, lsum, fx,
+                                          fy, fz, eat);
     else
-      force_run<false, false, KICK>(S, P, M, B, lq, lo, size, lsum, fx, fy, fz,
-                                    eat);
+      force_run<false, false, KICK, STAGE>(S, P, M, B, lq, lo, size, lsum, fx,
+                                           fy, fz, eat);
   }
 }
 
@@ -2434,8 +2476,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_stats(Dev S) {
     h = max(h, w.y);
   }
   const int size = ok ? h - l : 0;
-  const int gc = size > kStage && S.gather ? S.gcnt[b] : 0;
-  if (size > 0 && size <= kStage)
+  const int cap = block_stage(S, b);
+  const int gc = size > cap && S.gather ? S.gcnt[b] : 0;
+  if (size > 0 && size <= cap)
     atomicAdd(&S.stats[2], 1ull);
   else if (gc > 0) {
     atomicAdd(&S.stats[3], 1ull);
@@ -2456,14 +2499,23 @@ void launch_block_map(const Dev &S, hipStream_t s) {
   k_cell_map<<<1, 1024, 0, s>>>(S);
 }
 
-// The mixed pair passes, in their gather-staging variant when the system
-// enables it (the other variant has none of its code).
+// The mixed pair passes: one launch per stage class that has blocks, each in
+// its gather-staging variant when the system enables it (the other variant
+// has none of its code).
+template <bool GATHER, int C>
+void density_class(const Dev &S, const PotF &PF, hipStream_t s) {
+  constexpr int ST = stage_of_class(C);
+  const int base = S.cls_off[C], nb = S.cls_off[C + 1] - base;
+  if (nb <= 0) return;
+  if (S.nact)
+    k_density_mixed<true, GATHER, ST><<<nb, kBlock, 0, s>>>(S, PF, base);
+  else
+    k_density_mixed<false, GATHER, ST><<<nb, kBlock, 0, s>>>(S, PF, base);
+}
 template <bool GATHER>
 void density_pass(const Dev &S, const PotF &PF, hipStream_t s) {
-  if (S.nact)
-    k_density_mixed<true, GATHER><<<S.nbmap, kBlock, 0, s>>>(S, PF);
-  else
-    k_density_mixed<false, GATHER><<<S.nbmap, kBlock, 0, s>>>(S, PF);
+  density_class<GATHER, 0>(S, PF, s);
+  density_class<GATHER, 1>(S, PF, s);
 }
 void density_pass(const Dev &S, const PotF &PF, hipStream_t s) {
   if (S.gather)
@@ -2471,15 +2523,25 @@ void density_pass(const Dev &S, const PotF &PF, hipStream_t s) {
   else
     density_pass<false>(S, PF, s);
 }
+template <bool KICK, bool GATHER, int C>
+void force_class(const Dev &S, const PotF &PF, const DevMD &M, void *fx,
+                 void *fy, void *fz, void *eat, hipStream_t s) {
+  constexpr int ST = stage_of_class(C);
+  const int base = S.cls_off[C], nb = S.cls_off[C + 1] - base;
+  if (nb <= 0) return;
+  k_force_mixed<KICK, GATHER, ST><<<nb, kBlock, 0, s>>>(
+      S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat, base);
+}
 template <bool KICK>
 void force_pass(const Dev &S, const PotF &PF, const DevMD &M, void *fx,
                 void *fy, void *fz, void *eat, hipStream_t s) {
-  if (S.gather)
-    k_force_mixed<KICK, true><<<S.nbmap, kBlock, 0, s>>>(
-        S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
-  else
-    k_force_mixed<KICK, false><<<S.nbmap, kBlock, 0, s>>>(
-        S, PF, M, (float *)fx, (float *)fy, (float *)fz, (float *)eat);
+  if (S.gather) {
+    force_class<KICK, true, 0>(S, PF, M, fx, fy, fz, eat, s);
+    force_class<KICK, true, 1>(S, PF, M, fx, fy, fz, eat, s);
+  } else {
+    force_class<KICK, false, 0>(S, PF, M, fx, fy, fz, eat, s);
+    force_class<KICK, false, 1>(S, PF, M, fx, fy, fz, eat, s);
+  }
 }
 
 void launch_forces(const Dev &S, bool mixed, const PotF &PF, const PotD &PD,

@@ -109,6 +109,9 @@ class WireBatch:
                   per-atom arrays by tag whatever the order.
     gather        gather staging of the pair passes (mixed; tbsma_params);
                   default: on when some replica is in the blocked order.
+    shapes        launch shape of each replica's pair-pass blocks
+                  (_abi.shape(tiles_per_block, stage_class)), or None for
+                  the default; see set_shapes.
     The settings mean what include/tbsma.h says of tbsma_md and tbsma_params.
     """
 
@@ -121,7 +124,7 @@ class WireBatch:
                  grip_hold: int = 0, notch: tuple | None = None, T_start=None,
                  ramp_begin: int = 0, ramp_steps: int = 0, baro_mass: float = 0.0,
                  baro_load: float = 0.0, baro_damp: float = 0.0, order: str = "auto",
-                 gather: int | None = None):
+                 gather: int | None = None, shapes: Sequence[int] | None = None):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
@@ -136,6 +139,9 @@ class WireBatch:
                         T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps,
                         baro_mass=baro_mass, baro_load=baro_load, baro_damp=baro_damp,
                         order=order, gather=gather)
+        self.shapes = None if shapes is None else [int(v) for v in shapes]
+        if self.shapes is not None and len(self.shapes) != len(self.replicas):
+            raise ValueError("shapes needs one launch shape per replica")
         self.baro_mass, self.baro_load = float(baro_mass), float(baro_load)
         self.baro_damp = float(baro_damp)
         self.nh_tau, self.grip_step, self.grip_hold = float(nh_tau), float(grip_step), int(grip_hold)
@@ -282,6 +288,7 @@ class WireBatch:
                                A.MIXED if precision == "mixed" else A.FP64, self.qbits,
                                self.prune, int(gather) if precision == "mixed" else 0, 0)
         self._rep_off_h = (C.c_int64 * (R + 1))(*self.rep_off.tolist())
+        self._shape_h = None
         self._cell_off_h = (C.c_int64 * (R + 1))(*self.cell_off.tolist())
         self.sys = A.System(R, self.max_zbins, N, self.C,
                             C.cast(self._rep_off_h, C.c_void_p),
@@ -307,13 +314,43 @@ class WireBatch:
                        self.grip_step, self.grip_hold, _ptr(T["T_start"]), self.ramp_begin,
                        self.ramp_steps, self.baro_mass, self.baro_load, self.baro_damp,
                        _ptr(T["baro_s"]))
+        self._attach_shapes()
+        self._new_workspace()
+
+    def _attach_shapes(self):
+        if self.shapes is None:
+            self._shape_h = None
+            self.sys.shape_h = self.sys.shape = None
+            return
+        self._shape_h = (C.c_int32 * self.R)(*self.shapes)
+        self.t["shape"] = torch.tensor(self.shapes, dtype=torch.int32, device=self.device)
+        self.sys.shape_h = C.cast(self._shape_h, C.c_void_p)
+        self.sys.shape = _ptr(self.t["shape"])
+
+    def _new_workspace(self):
         nb = C.c_size_t()
         A.check(A.lib().tbsma_workspace_query(C.byref(self.params), C.byref(self.sys),
                                               C.byref(nb)))
-        T["work"] = torch.zeros(int(nb.value), dtype=torch.uint8, device=dev)
-        self.work = _ptr(T["work"])
+        self.t["work"] = torch.zeros(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.work = _ptr(self.t["work"])
         A.check(A.lib().tbsma_workspace_init(C.byref(self.params), C.byref(self.sys), self.work,
                                              self.stream()))
+
+    def set_shapes(self, shapes: Sequence[int] | None):
+        """New launch shapes for the pair passes (one per replica, or None for
+        the default) between calls: a fresh workspace for them, then lists and
+        forces rebuilt at the current positions (the step index, positions and
+        velocities carry on).  Shapes never change a result bit, but the
+        rebuild at this step reorders list entries as any rebuild does."""
+        if shapes is not None:
+            shapes = [int(v) for v in shapes]
+            if len(shapes) != self.R:
+                raise ValueError("shapes needs one launch shape per replica")
+        self.shapes = shapes
+        self._attach_shapes()
+        self._new_workspace()
+        self.build_lists()
+        self.compute_forces()
 
     # ------------------------------------------------------------------------------------
     def stream(self):
@@ -541,6 +578,7 @@ class WireBatch:
         nb = WireBatch([self.replicas[r] for r in keep], self.precision,
                        wires=[self.wires[r] for r in keep], qbits=self.qbits,
                        k_cap=self.k_cap,
+                       shapes=None if self.shapes is None else [self.shapes[r] for r in keep],
                        **dict(self._kw, device=self.device,
                               T_start=self.t["T_start"].cpu().numpy()[keep]))
         for j, r in enumerate(keep):
@@ -591,9 +629,11 @@ class WireBatch:
         return list(out)
 
     def nbmap_blocks(self) -> int:
-        """Blocks of the pair passes (up to four tiles of one replica)."""
+        """Blocks of the pair passes (up to tiles_per_block tiles of one
+        replica, four by default)."""
         tiles = (self.rep_off[1:] - self.rep_off[:-1]) // A.TILE
-        return int(((tiles + 3) // 4).sum())
+        tpb = np.array([4] * self.R if self.shapes is None else [s & 15 for s in self.shapes])
+        return int(((tiles + tpb - 1) // tpb).sum())
 
     def staging(self):
         """How the pair passes reach each block's neighbours (mixed):

@@ -210,3 +210,32 @@ def test_noalloc_step_refuses_a_system_beyond_its_scratch_on_the_host():
                                     C.byref(nl), C.byref(out), C.byref(md), 1, None)
     assert rc == A.ECAPACITY
     assert b"static scratch" in A.lib().tbsma_last_error()
+
+
+@pytest.mark.parametrize("shape,ok", [(A.shape(4, 1), True), (A.shape(1, 0), True),
+                                      (A.shape(2, 1), True), (A.shape(3, 0), False),
+                                      (A.shape(4, 2), False), (A.shape(8, 0), False)])
+def test_launch_shape_checks(shape, ok):
+    """Per-replica launch shapes: 1, 2 or 4 tiles per block and stage class
+    0 or 1; the workspace holds a block map of ceil(tiles / tiles_per_block)
+    blocks per replica."""
+    R, N = 2, 64 * 10
+    ph = C.c_void_p(0x1000)
+    rep = (C.c_int64 * 3)(0, 64 * 6, N)
+    cel = (C.c_int64 * 3)(0, 8, 16)
+    s = A.System(R, 4, N, 16, C.cast(rep, C.c_void_p), C.cast(cel, C.c_void_p),
+                 *([ph] * 14), ph)
+    nb0 = C.c_size_t()
+    A.check(A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s), C.byref(nb0)))
+    sh = (C.c_int32 * R)(A.SHAPE_DEFAULT, shape)
+    s.shape_h = C.cast(sh, C.c_void_p)
+    nb = C.c_size_t()
+    rc = A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s), C.byref(nb))
+    assert rc == A.EINVAL and b"both" in A.lib().tbsma_last_error()  # device copy missing
+    s.shape = ph
+    rc = A.lib().tbsma_workspace_query(C.byref(_params()), C.byref(s), C.byref(nb))
+    if ok:
+        assert rc == A.OK
+        assert (nb.value >= nb0.value) == ((shape & 15) <= 4)
+    else:
+        assert rc == A.EINVAL and b"launch shape" in A.lib().tbsma_last_error()

@@ -1102,6 +1102,57 @@ def test_config2_pulled_to_rupture_forces_stay_within_parity():
     note(f"  max eps_F over {len(rows)} samples: {max(r[4] for r in rows):.2e}")
 
 
+def test_launch_shapes_leave_trajectories_unchanged_bitwise():
+    """Per-replica launch shapes (tiles per pair-pass block, stage class)
+    change only where work runs: a batch with a mix of shapes follows the
+    default batch bit for bit through rebuilds and prunings (150 steps at
+    298 K, energies logged)."""
+    reps = [R(15.0, 30.0, T=298.0, r=0), R(20.0, 40.0, T=10.0, r=1),
+            R(25.0, 25.0, T=298.0, r=2), R(30.0, 35.0, T=298.0, r=3),
+            R(15.0, 12.0, T=298.0, r=4)]
+    shapes = [A.shape(1, 0), A.shape(2, 1), A.shape(4, 0), A.shape(2, 0), A.shape(1, 1)]
+    note("launch shapes vs default, 150 steps mixed")
+    a = WireBatch(reps, "mixed", n_log=25, skin=0.6, prune=0.1)
+    a.prepare()
+    a.run_batch(150, 50)
+    b = WireBatch(reps, "mixed", n_log=25, skin=0.6, prune=0.1, qbits=a.qbits, shapes=shapes)
+    b.prepare()
+    b.run_batch(150, 50)
+    torch.cuda.synchronize()
+    assert np.all(a.status() & A.ST_REBUILT)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "e_atom", "obs", "status"):
+        assert torch.equal(a.t[k], b.t[k]), k
+    assert b.nbmap_blocks() == sum(-(-(int(n) // 64) // (s & 15))
+                                   for n, s in zip(b.rep_off[1:] - b.rep_off[:-1], shapes))
+    assert b.nbmap_blocks() > a.nbmap_blocks()
+
+
+def test_autotune_chooses_a_shape_per_bucket_in_one_batch(tmp_path):
+    """The tuner's trials run on the whole batch, one bucket at a time; the
+    chosen shapes are applied to the batch, which stays within parity, and a
+    cached choice is reused without trials."""
+    from paper_1311_3890_amd import autotune
+    reps = [R(15.0 if k % 2 else 30.0, 20.0 + 3 * k, T=298.0, r=k) for k in range(8)]
+    note("autotune smoke, 8 replicas in 2 buckets")
+    b = WireBatch(reps, "mixed", n_log=20)
+    b.prepare()
+    cache = str(tmp_path / "tune.json")
+    cands = (A.shape(4, 1), A.shape(2, 0))
+    res = autotune.tune(b, candidates=cands, steps=20, warmup=10, windows=1,
+                        steps_per_graph=20, cache=cache, log=note)
+    assert set(res["choice"]) == {"D15-warm", "D30-warm"}
+    assert len(res["trials"]) == 2
+    for r, rp in enumerate(reps):
+        assert b.shapes[r] == res["choice"][autotune.bucket_key(autotune.bucket_of(rp))]
+    b.run_batch(40 + (-b.step_index()) % 20, 20)  # to a logged step
+    torch.cuda.synchronize()
+    _sampled_parity(b, [0, 1])
+    c = WireBatch(reps, "mixed", n_log=20)
+    c.prepare()
+    again = autotune.tune(c, candidates=cands, cache=cache, log=note)
+    assert again["choice"] == res["choice"] and c.shapes == b.shapes
+
+
 def test_full_size_batch512_sampled():
     """The 512-wire D 3 nm batch at full size in the benchmark's launch shape:
     graph-replayed steps, then sampled replicas against the oracle."""
