@@ -410,6 +410,38 @@ int tbsma_init_state(const tbsma_params *prm, tbsma_system *sys,
                      void *stream);
 
 /*
+ * Per-replica constants of the dynamics and observables, from the atoms in
+ * their current slots (flags and z; call it before tbsma_init_state's jitter
+ * to take them from the lattice sites), written to device arrays [R]:
+ *  dof   3 N_dyn - 3, the kinetic degrees of freedom of the temperature
+ *        (N_dyn dynamic atoms; 0 when N_dyn <= 1; Simulation details'
+ *        thermostat, the temperature in the observables);
+ *  vol   eq 5's constant volume N (4/3) pi (r0/2)^3 over the replica's N
+ *        atoms (hard spheres of radius r0/2: the paper leaves the radius
+ *        unstated);
+ *  z_lo, z_hi  the inner faces of the fixed and pulled grips at this state
+ *        (largest z of the TBSMA_GRIP_FIXED atoms, smallest z of the
+ *        TBSMA_GRIP_PULL atoms; the replica's lowest / highest z when it has
+ *        no such grip), which anchor the stretching profile of tbsma_md.
+ * They are tbsma_md's dof, vol, z_lo and z_hi.  Counts, minima and maxima
+ * are exact, so results do not depend on the device's reduction order.
+ */
+int tbsma_replica_constants(const tbsma_params *prm, const tbsma_system *sys,
+                            int32_t *dof, double *vol, double *z_lo,
+                            double *z_hi, void *stream);
+
+/*
+ * The current state as the start of a new stretch (after equilibration,
+ * Simulation details): every atom's grip reference z0 = z, and for each
+ * replica the initial length of eq 4 grows by the barostat's elongation,
+ * L0[r] += 2 s[r], with s[r] and ds/dt then zeroed (baro_s: device [2R] as in
+ * tbsma_md, or NULL to leave L0 as it is).  L0: device [R].  The step index,
+ * status and records are the caller's to reset.
+ */
+int tbsma_rebase(const tbsma_params *prm, tbsma_system *sys, double *L0,
+                 double *baro_s, void *stream);
+
+/*
  * Cell binning (the cell list behind the Verlet list): bins every real atom
  * of every replica into its grid (atoms outside are clamped to the border
  * cells, which keeps the list exact, and raise TBSMA_ST_OUTSIDE in the

@@ -83,6 +83,8 @@ SIGNATURES = {
     "tbsma_build_wire": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                    C.c_double, vp, vp, vp, vp, C.c_int64, P(C.c_int64)]),
     "tbsma_init_state": (C.c_int, [P(Params), P(System), P(MD), vp, C.c_double, vp]),
+    "tbsma_replica_constants": (C.c_int, [P(Params), P(System), vp, vp, vp, vp, vp]),
+    "tbsma_rebase": (C.c_int, [P(Params), P(System), vp, vp, vp]),
     "tbsma_build_cells": (C.c_int, [P(Params), P(System), P(Cells), vp, vp]),
     "tbsma_neighbors": (C.c_int, [P(Params), P(System), P(Cells), P(NList), vp,
                                   P(C.c_int32), vp]),

@@ -772,6 +772,48 @@ int tbsma_init_state(const tbsma_params *prm, tbsma_system *sys,
   return TBSMA_OK;
 }
 
+int tbsma_replica_constants(const tbsma_params *prm, const tbsma_system *sys,
+                            int32_t *dof, double *vol, double *z_lo,
+                            double *z_hi, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (sys->R == 0) return TBSMA_OK;
+  if (!dof || !vol || !z_lo || !z_hi)
+    return fail(TBSMA_EINVAL, "dof, vol, z_lo and z_hi are required");
+  TRY(check_device());
+  // the kernel reads only the system's arrays, no workspace
+  Dev d;
+  memset(&d, 0, sizeof(d));
+  d.R = sys->R;
+  d.N = sys->N;
+  d.rep_off = sys->rep_off;
+  d.flag = sys->flag;
+  d.z = sys->z;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_replica_constants(d, prm->r0, dof, vol, z_lo, z_hi, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
+int tbsma_rebase(const tbsma_params *prm, tbsma_system *sys, double *L0,
+                 double *baro_s, void *stream) {
+  TRY(check_params(prm));
+  TRY(check_system(prm, sys));
+  if (sys->R == 0) return TBSMA_OK;
+  if (!L0) return fail(TBSMA_EINVAL, "L0 is required");
+  TRY(check_device());
+  Dev d;
+  memset(&d, 0, sizeof(d));
+  d.R = sys->R;
+  d.N = sys->N;
+  d.z = sys->z;
+  d.z0 = sys->z0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_rebase(d, L0, baro_s, s);
+  HIPCHK(hipGetLastError());
+  return TBSMA_OK;
+}
+
 int tbsma_build_cells(const tbsma_params *prm, const tbsma_system *sys,
                       tbsma_cells *cells, void *work, void *stream) {
   TRY(check_params(prm));

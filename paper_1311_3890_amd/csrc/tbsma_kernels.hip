@@ -2358,6 +2358,86 @@ __global__ void __launch_bounds__(kBlock) k_init_c(Dev S, DevMD M) {
   }
 }
 
+// Per-replica constants from the atoms as they are (one workgroup per
+// replica): dof = 3 N_dyn - 3 (0 when N_dyn <= 1); vol = N (4/3) pi r_hs^3
+// with r_hs = r0/2 and N the replica's atoms (eq 5's constant volume);
+// z_lo / z_hi the inner faces of the fixed and pulled grips (largest z of
+// the fixed grip, smallest z of the pulled one; the replica's lowest and
+// highest z when it has no such grip).  Counts, minima and maxima are
+// exact, so the result does not depend on the reduction order.
+__global__ void __launch_bounds__(256) k_replica_constants(Dev S, double r0,
+                                                           int32_t *dof,
+                                                           double *vol,
+                                                           double *z_lo,
+                                                           double *z_hi) {
+  __shared__ double red[4][4];
+  __shared__ int cnt[4][2];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int ndyn = 0, nreal = 0;
+  double gmax = -INFINITY, pmin = INFINITY, zmin = INFINITY, zmax = -INFINITY;
+  for (int64_t i = S.rep_off[r] + threadIdx.x; i < S.rep_off[r + 1]; i += 256) {
+    const uint8_t f = S.flag[i];
+    if (f == 3) continue;
+    const double z = S.z[i];
+    ++nreal;
+    ndyn += f == 0 ? 1 : 0;
+    if (f == 1) gmax = gmax > z ? gmax : z;
+    if (f == 2) pmin = pmin < z ? pmin : z;
+    zmin = zmin < z ? zmin : z;
+    zmax = zmax > z ? zmax : z;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ndyn += __shfl_xor(ndyn, o, 64);
+    nreal += __shfl_xor(nreal, o, 64);
+    gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
+    zmin = fmin(zmin, __shfl_xor(zmin, o, 64));
+    zmax = fmax(zmax, __shfl_xor(zmax, o, 64));
+  }
+  if (lane == 0) {
+    cnt[w][0] = ndyn;
+    cnt[w][1] = nreal;
+    red[w][0] = gmax;
+    red[w][1] = pmin;
+    red[w][2] = zmin;
+    red[w][3] = zmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      ndyn += cnt[k][0];
+      nreal += cnt[k][1];
+      gmax = fmax(gmax, red[k][0]);
+      pmin = fmin(pmin, red[k][1]);
+      zmin = fmin(zmin, red[k][2]);
+      zmax = fmax(zmax, red[k][3]);
+    }
+    dof[r] = ndyn > 1 ? 3 * ndyn - 3 : 0;
+    const double rhs = 0.5 * r0;
+    vol[r] = (double)nreal * (4.0 / 3.0) * 3.14159265358979323846 * (rhs * rhs * rhs);
+    z_lo[r] = gmax > -INFINITY ? gmax : zmin;
+    z_hi[r] = pmin < INFINITY ? pmin : zmax;
+  }
+}
+
+// The current state as the start of a new stretch (step loops' observables):
+// grip references z0 = z for every atom; each replica's initial length L0
+// grows by the barostat's elongation 2 s, whose s and ds/dt are zeroed.
+__global__ void __launch_bounds__(kBlock) k_rebase(Dev S, double *L0,
+                                                   double *baro_s) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < S.N) S.z0[i] = S.z[i];
+  if (i < S.R) {
+    if (baro_s != nullptr) {
+      L0[i] += 2.0 * baro_s[2 * i];
+      baro_s[2 * i] = 0.0;
+      baro_s[2 * i + 1] = 0.0;
+    }
+  }
+}
+
 __global__ void k_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
                            uint32_t stream, int64_t n, uint32_t *w,
                            double *g, float *gf) {
@@ -2675,6 +2755,18 @@ void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
   if (n > 0)
     k_rng_fill<<<nblk(n, 256), 256, 0, s>>>(seed, rep, step, stream, n, w, g,
                                             gf);
+}
+
+void launch_replica_constants(const Dev &S, double r0, int32_t *dof,
+                              double *vol, double *z_lo, double *z_hi,
+                              hipStream_t s) {
+  if (S.R > 0)
+    k_replica_constants<<<S.R, 256, 0, s>>>(S, r0, dof, vol, z_lo, z_hi);
+}
+
+void launch_rebase(const Dev &S, double *L0, double *baro_s, hipStream_t s) {
+  const int64_t n = std::max<int64_t>(S.N, S.R);
+  if (n > 0) k_rebase<<<nblk(n, kBlock), kBlock, 0, s>>>(S, L0, baro_s);
 }
 
 }  // namespace tbsma

@@ -51,6 +51,12 @@ void launch_step_begin(const Dev &S, const DevMD &M, bool mixed,
 void launch_nh_finish(const Dev &S, const DevMD &M, hipStream_t s);
 void launch_init(const Dev &S, const DevMD &M, bool mixed, double jitter,
                  hipStream_t s);
+// Per-replica dof, constant volume and grip faces from the atoms as they are.
+void launch_replica_constants(const Dev &S, double r0, int32_t *dof,
+                              double *vol, double *z_lo, double *z_hi,
+                              hipStream_t s);
+// z0 = z; L0 += 2 s and s, ds/dt = 0 for each replica (baro_s may be NULL).
+void launch_rebase(const Dev &S, double *L0, double *baro_s, hipStream_t s);
 // Philox words, FP64 normals and FP32 normals (each output may be NULL).
 void launch_rng_fill(uint64_t seed, uint32_t rep, uint64_t step,
                      uint32_t stream, int64_t n, uint32_t *w, double *g,

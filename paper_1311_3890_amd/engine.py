@@ -201,9 +201,6 @@ class WireBatch:
         zh = np.zeros(N)
         fh = np.full(N, A.PAD, dtype=np.uint8)
         tagh = np.zeros(N, dtype=np.int32)
-        z_lo = np.zeros(R)
-        z_hi = np.zeros(R)
-        dof = np.zeros(R, dtype=np.int32)
         for r, (x, y, z, f) in enumerate(self.wires):
             o = self.rep_off[r]
             n = x.size
@@ -214,13 +211,7 @@ class WireBatch:
             tagh[o:o + npad] = np.arange(npad, dtype=np.int32)
             if perm is not None:
                 tagh[o:o + n] = perm
-            z_lo[r] = z[f == A.GRIP_FIXED].max() if np.any(f == A.GRIP_FIXED) else z.min()
-            z_hi[r] = z[f == A.GRIP_PULL].min() if np.any(f == A.GRIP_PULL) else z.max()
-            dof[r] = max(0, 3 * int((f == A.DYN).sum()) - 3)
         # pads sit at the replica's grid corner (never used)
-        self.z_lo, self.z_hi, self.dof = z_lo, z_hi, dof
-        r_hs = 0.5 * self.pot.r0
-        self.vol = self.n_atoms * (4.0 / 3.0) * math.pi * r_hs ** 3
         self.L0 = np.array([rp.L for rp in self.replicas], dtype=np.float64)
         tile_rep = np.repeat(np.arange(R, dtype=np.int32), pad // A.TILE)
         # --- device buffers ------------------------------------------------------------
@@ -262,13 +253,14 @@ class WireBatch:
         T["rep_wzz"] = torch.zeros(R, **f64)
         T["T"] = torch.tensor([rp.T for rp in self.replicas], **f64)
         T["v_pull"] = torch.tensor([rp.v_pull for rp in self.replicas], **f64)
-        T["z_lo"] = torch.tensor(z_lo, **f64)
-        T["z_hi"] = torch.tensor(z_hi, **f64)
-        T["vol"] = torch.tensor(self.vol, **f64)
+        # dof, hard-sphere volume and grip faces: tbsma_replica_constants
+        T["z_lo"] = torch.zeros(R, **f64)
+        T["z_hi"] = torch.zeros(R, **f64)
+        T["vol"] = torch.zeros(R, **f64)
         T["L0"] = torch.tensor(self.L0, **f64)
         seeds = np.array([rp.seed for rp in self.replicas], dtype=np.uint64).view(np.int64)
         T["seed"] = torch.tensor(seeds, device=dev)
-        T["dof"] = torch.tensor(dof, device=dev)
+        T["dof"] = torch.zeros(R, dtype=torch.int32, device=dev)
         T["step"] = torch.zeros(1, dtype=torch.int64, device=dev)
         T["obs"] = torch.zeros(n_slots * R * A.NOBS, **f64)
         T["status"] = torch.zeros(R, dtype=torch.int32, device=dev)
@@ -315,6 +307,15 @@ class WireBatch:
                        self.ramp_steps, self.baro_mass, self.baro_load, self.baro_damp,
                        _ptr(T["baro_s"]))
         self._attach_shapes()
+        # the per-replica constants from the lattice sites (before any jitter)
+        A.check(A.lib().tbsma_replica_constants(C.byref(self.params), C.byref(self.sys),
+                                                _ptr(T["dof"]), _ptr(T["vol"]), _ptr(T["z_lo"]),
+                                                _ptr(T["z_hi"]), self.stream()))
+        torch.cuda.synchronize(dev)
+        self.z_lo = T["z_lo"].cpu().numpy().copy()
+        self.z_hi = T["z_hi"].cpu().numpy().copy()
+        self.dof = T["dof"].cpu().numpy().copy()
+        self.vol = T["vol"].cpu().numpy().copy()
         self._new_workspace()
 
     def _attach_shapes(self):
@@ -546,10 +547,8 @@ class WireBatch:
         barostat's elongation 2 s (which is then zeroed), status, rupture
         marks and records cleared.  Grips then rest where they are unless
         the settings move them (v_pull is zeroed)."""
-        self.t["z0"].copy_(self.t["z"])
-        s = self.t["baro_s"].view(self.R, 2)
-        self.t["L0"].add_(2.0 * s[:, 0])
-        s.zero_()
+        A.check(A.lib().tbsma_rebase(C.byref(self.params), C.byref(self.sys),
+                                     _ptr(self.t["L0"]), _ptr(self.t["baro_s"]), self.stream()))
         self.t["v_pull"].zero_()
         self.t["step"].zero_()
         self.t["status"].zero_()

@@ -239,3 +239,17 @@ def test_launch_shape_checks(shape, ok):
         assert (nb.value >= nb0.value) == ((shape & 15) <= 4)
     else:
         assert rc == A.EINVAL and b"launch shape" in A.lib().tbsma_last_error()
+
+
+def test_replica_constants_and_rebase_check_their_outputs():
+    ph = C.c_void_p(0x1000)
+    rep = (C.c_int64 * 2)(0, 64)
+    cel = (C.c_int64 * 2)(0, 8)
+    s = A.System(1, 4, 64, 8, C.cast(rep, C.c_void_p), C.cast(cel, C.c_void_p),
+                 *([ph] * 14), ph)
+    lib = A.lib()
+    assert lib.tbsma_replica_constants(C.byref(_params()), C.byref(s), ph, None, ph, ph,
+                                       None) == A.EINVAL
+    assert b"required" in lib.tbsma_last_error()
+    assert lib.tbsma_rebase(C.byref(_params()), C.byref(s), None, None, None) == A.EINVAL
+    assert b"L0" in lib.tbsma_last_error()

@@ -1153,6 +1153,40 @@ def test_autotune_chooses_a_shape_per_bucket_in_one_batch(tmp_path):
     assert again["choice"] == res["choice"] and c.shapes == b.shapes
 
 
+def test_replica_constants_and_rebase():
+    """tbsma_replica_constants gives each replica's degrees of freedom, the
+    hard-sphere volume of eq 5 and the inner grip faces exactly as their
+    definitions over the wire's sites (notched, blocked order, and a wire
+    without grips included); tbsma_rebase moves the grip references to the
+    current positions and grows L0 by the barostat's elongation 2 s."""
+    reps = [R(15.0, 30.0, T=10.0, r=0), R(40.0, 20.0, T=298.0, r=1),
+            W.Replica(20.0, W.snap_length(25.0), 298.0, 0.5, W.seed_of(2), 2, n_grip=0)]
+    note("replica constants and rebase")
+    b = WireBatch(reps, "mixed", n_log=10, notch=(3, 4.08))
+    torch.cuda.synchronize()
+    for r, (x, y, z, f) in enumerate(b.wires):
+        ndyn = int((f == A.DYN).sum())
+        assert b.dof[r] == max(0, 3 * ndyn - 3)
+        assert b.z_lo[r] == (z[f == A.GRIP_FIXED].max() if np.any(f == A.GRIP_FIXED) else z.min())
+        assert b.z_hi[r] == (z[f == A.GRIP_PULL].min() if np.any(f == A.GRIP_PULL) else z.max())
+        v = x.size * (4.0 / 3.0) * np.pi * (0.5 * AU.r0) ** 3
+        assert abs(b.vol[r] - v) <= 1e-14 * v
+    assert b.slot_tag[1] is not None
+    # rebase after a barostat run: z0 = z and L0 + 2 s
+    e = WireBatch(reps[:2], "mixed", n_log=10, gamma=0.0, nh_tau=0.1, baro_mass=300.0,
+                  baro_damp=2.0)
+    e.prepare()
+    e.run_batch(60, 20)
+    torch.cuda.synchronize()
+    s = e.t["baro_s"].view(e.R, 2)[:, 0].cpu().numpy().copy()
+    L0 = e.L0.copy()
+    assert np.all(s != 0.0)
+    e.rebase()
+    assert torch.equal(e.t["z0"], e.t["z"])
+    assert np.array_equal(e.L0, L0 + 2.0 * s)
+    assert torch.all(e.t["baro_s"] == 0) and e.step_index() == 0
+
+
 def test_full_size_batch512_sampled():
     """The 512-wire D 3 nm batch at full size in the benchmark's launch shape:
     graph-replayed steps, then sampled replicas against the oracle."""
