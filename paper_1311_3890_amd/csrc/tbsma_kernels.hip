@@ -789,6 +789,31 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
   }
 }
 
+// Exclusive block-wide prefix of v over the kBlock threads (every thread
+// takes part); *total gets the sum.  wsum: kBlock / 64 ints of LDS.
+__device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
+                                               int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const int t = wsum[k];
+    before += k < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();  // wsum may be reused
+  *total = tot;
+  return before + x - v;
+}
+
 // Mixed-precision list build, one tile per block and work item (the tiles
 // of the work list).  The block's kNlWaves wavefronts share the scan of
 // the tile's candidates, the cell-sorted atoms of the z-slabs around its
@@ -804,10 +829,14 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
 // pruned rows are made by the pruning kernel.
 constexpr int kNlWaves = kBlock / kTile;
 
+constexpr int kBoxRows = 64;  // rows of cells of the box scan, at most
+
 __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
   __shared__ float4 cand[kCand + 8];
   __shared__ int32_t qcnt[kNlWaves][kTile];
   __shared__ int2 qwin[kNlWaves];
+  __shared__ int32_t rowbeg[kBoxRows], rowlen[kBoxRows], rowpre[kBoxRows + 1];
+  __shared__ int32_t wsum[kBlock / 64];
   const int tid = threadIdx.x;
   const int q = tid / kTile;  // share of the candidate scan
   const int lane = tid & (kTile - 1);
@@ -855,6 +884,76 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
         }
         pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
                          (float)(qi.z - o.z), 0.f);
+      } else {
+        // slabs too wide (thick wires): the cells around the tile's cell box,
+        // one range of cell_atoms per row of cells along x, keeping the
+        // candidates within the list radius of the box of the tile's
+        // quantised positions (a superset of every atom's neighbours), in
+        // row order (z, then y), compacted by a block-wide scan
+        const int xlo = -wave_max_i(real ? -cx : -0x7fffffff);
+        const int xhi = wave_max_i(real ? cx : -1);
+        const int ylo = -wave_max_i(real ? -cy : -0x7fffffff);
+        const int yhi = wave_max_i(real ? cy : -1);
+        const int x0 = max(xlo - 1, 0), x1 = min(xhi + 1, gd[0] - 1);
+        const int y0 = max(ylo - 1, 0), y1 = min(yhi + 1, gd[1] - 1);
+        const int z0 = max(zlo - 1, 0), z1 = min(zhi + 1, gd[2] - 1);
+        const int ny = y1 - y0 + 1, nrow = ny * (z1 - z0 + 1);
+        if (nrow <= kBoxRows) {
+          if (tid < nrow) {
+            const int c = ((z0 + tid / ny) * gd[1] + y0 + tid % ny) * gd[0];
+            rowbeg[tid] = start[c + x0];
+            rowlen[tid] = start[c + x1 + 1] - start[c + x0];
+          }
+          __syncthreads();
+          if (tid == 0) {
+            int acc = 0;
+            for (int k = 0; k < nrow; ++k) {
+              rowpre[k] = acc;
+              acc += rowlen[k];
+            }
+            rowpre[nrow] = acc;
+          }
+          __syncthreads();
+          const int total = rowpre[nrow];
+          // the tile's box in quanta (the same in every wavefront)
+          const int bx0 = -wave_max_i(real ? -qi.x : -0x7fffffff);
+          const int bx1 = wave_max_i(real ? qi.x : -0x7fffffff);
+          const int by0 = -wave_max_i(real ? -qi.y : -0x7fffffff);
+          const int by1 = wave_max_i(real ? qi.y : -0x7fffffff);
+          const int bz0 = -wave_max_i(real ? -qi.z : -0x7fffffff);
+          const int bz1 = wave_max_i(real ? qi.z : -0x7fffffff);
+          const int4 o = S.qpos[(int64_t)tile * kTile];
+          int kept = 0;
+          for (int t0 = 0; t0 < total; t0 += kBlock) {  // uniform
+            const int t = t0 + tid;
+            bool keep = false;
+            float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t < total) {
+              int k = 0;
+              while (k + 1 < nrow && rowpre[k + 1] <= t) ++k;
+              const int32_t j = S.cell_atoms[rowbeg[k] + (t - rowpre[k])];
+              const int4 qj = S.qpos[j];
+              const float ex = (float)max(max(bx0 - qj.x, qj.x - bx1), 0);
+              const float ey = (float)max(max(by0 - qj.y, qj.y - by1), 0);
+              const float ez = (float)max(max(bz0 - qj.z, qj.z - bz1), 0);
+              keep = fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rl2q;
+              c = make_float4((float)(qj.x - o.x), (float)(qj.y - o.y),
+                              (float)(qj.z - o.z), __int_as_float(j));
+            }
+            int n_kept = 0;
+            const int pos = kept + block_excl_scan(keep ? 1 : 0, wsum, &n_kept);
+            if (keep && pos < kCand) cand[pos] = c;
+            kept += n_kept;
+          }
+          if (kept <= kCand) {
+            window = true;
+            m = kept;
+            if (tid < 8)
+              cand[m + tid] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
+                             (float)(qi.z - o.z), 0.f);
+          }
+        }
       }
     }
     __syncthreads();
@@ -1138,31 +1237,6 @@ struct GatherDecode {
     return (uint32_t)e < lim ? lo + (int)g[(uint32_t)e >> 4] : self;
   }
 };
-
-// Exclusive block-wide prefix of v over the kBlock threads (every thread
-// takes part); *total gets the sum.  wsum: kBlock / 64 ints of LDS.
-__device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
-                                               int *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(x, o, 64);
-    if (lane >= o) x += t;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  int before = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    const int t = wsum[k];
-    before += k < w ? t : 0;
-    tot += t;
-  }
-  __syncthreads();  // wsum may be reused
-  *total = tot;
-  return before + x - v;
-}
 
 // Lane-ordered, pruned rows (nl_lane) of the list-build blocks of the work
 // list: blocks of replicas whose lists were just rebuilt, which first take

@@ -221,6 +221,62 @@ def test_neighbor_lists_are_exact_sets(precision, cell):
     assert torch.equal(b.t["nl"], b2.t["nl"]) and torch.equal(b.t["nn"], b2.t["nn"])
 
 
+def _tile_box_counts(b, r, rl):
+    """Atoms of replica r within rl of the box of each tile's positions (the
+    candidates the list build stages for a tile whose slabs exceed LDS)."""
+    from scipy.spatial import cKDTree
+    x, y, z = (b._slice(k, r) for k in ("x", "y", "z"))
+    tag = b.slot_tag[r]
+    P = np.stack([x, y, z], 1)
+    Ps = P if tag is None else P[tag]  # slot order
+    tree = cKDTree(P)
+    out = []
+    for t0 in range(0, Ps.shape[0], 64):
+        T = Ps[t0:t0 + 64]
+        lo, hi = T.min(0), T.max(0)
+        c = 0.5 * (lo + hi)
+        cand = tree.query_ball_point(c, np.linalg.norm(0.5 * (hi - lo)) + rl)
+        d = np.maximum(np.maximum(lo - P[cand], P[cand] - hi), 0.0)
+        out.append(int(np.count_nonzero((d ** 2).sum(1) < rl * rl)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("order", ["blocked", "axial"])
+def test_thick_wire_lists_from_the_box_scan_and_the_cell_walk(order):
+    """Lists of wires whose z-slabs exceed LDS.  A tile whose box (its
+    atoms' extent, widened by the list radius) holds at most 1536 atoms
+    stages them in LDS (box scan); others walk the 27 cells around each atom.
+    In the blocked order tiles are compact and most take the box scan; in
+    the axial order a tile of a 7 nm wire is a strip across the wire and
+    many take the cell walk.  Either way the lists equal brute force."""
+    from scipy.spatial import cKDTree
+    D = 50.0 if order == "blocked" else 70.0
+    rp = R(D, 120.0, T=298.0, r=7, jitter=0.1)
+    note(f"thick-wire lists, {order} order, D {D / 10:.0f} nm")
+    b = WireBatch([rp], "mixed", order=order)
+    b.prepare()
+    torch.cuda.synchronize()
+    rl = b.pot.r_cut + b.skin
+    counts = _tile_box_counts(b, 0, rl)
+    # both paths run in both orders; most blocked tiles take the box scan,
+    # many axial ones the cell walk
+    fit = np.mean(counts <= 1536)
+    note(f"  tiles whose box candidates fit in LDS: {fit:.2f}")
+    assert 0.0 < fit < 1.0
+    assert fit > 0.9 if order == "blocked" else fit < 0.9
+    x, y, z = b.positions(0)
+    P = np.stack([x, y, z], 1)
+    tree = cKDTree(P)
+    got = b.neighbor_rows(0)
+    for i in range(P.shape[0]):
+        sure = set(tree.query_ball_point(P[i], rl - 1e-5)) - {i}
+        loose = set(tree.query_ball_point(P[i], rl + 1e-5)) - {i}
+        g = set(got[i].tolist())
+        assert len(g) == got[i].size and sure <= g <= loose, i
+    ref = oracle.forces(AU, x, y, z, 1)
+    assert eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"]))) <= 1e-5
+
+
 def _check_lists(b, r):
     rl = b.pot.r_cut + b.skin
     rt, rc = b.pot.r_tail, b.pot.r_cut
