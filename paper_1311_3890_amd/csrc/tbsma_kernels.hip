@@ -1644,8 +1644,8 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
   if (STAGED) {
     chunk_loop_padded(S.nl_lane, N, row, n, pad_chunk_staged<STAGE>(),
                       [&](const int (&e)[8]) {
-                        // half a chunk of positions at a time, which keeps
-                        // the loop within the VGPR budget of the kernel
+                        // half a chunk of positions at a time (1 % faster
+                        // steps than all eight at once)
                         int4 q[4];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) q[k] = lds_at(lq, e[k]);
@@ -1769,13 +1769,8 @@ __device__ __forceinline__ void force_run(const Dev &S, const PotF &P,
 }
 
 // One launch per stage class, as the density pass.
-// At most 96 VGPRs (five wavefronts per SIMD instead of four): the staged
-// forces-only loop keeps everything in registers, the rarer variants (energies,
-// global gathers) spill a few values; the step is 1 % faster than at 119
-// VGPRs.
 template <bool KICK, bool GATHER, int STAGE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
-k_force_mixed(Dev S, PotF P,
+__global__ void __launch_bounds__(kBlock) k_force_mixed(Dev S, PotF P,
                                                         DevMD M, float *fx,
                                                         float *fy, float *fz,
                                                         float *eat, int base) {
