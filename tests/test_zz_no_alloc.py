@@ -58,6 +58,8 @@ def _compare(reps, precision, n, **kw):
     a.prepare()
     b = WireBatch(reps, precision, n_log=10, qbits=a.qbits, **kw)
     b.prepare()
+    if precision == "mixed" and any(t is not None for t in a.slot_tag):
+        assert a.staging()["gather"] > 0
     for k in KEYS:
         assert torch.equal(a.t[k], b.t[k]), f"initial state differs in {k}"
     _reference(a, n)
@@ -82,6 +84,15 @@ def test_noalloc_equals_step_on_a_workspace_twice_second_smaller(precision):
     small = [_rep(15.0, 4.0, 298.0, 0.5, 3)]
     _compare(big, precision, 60)
     _compare(small, precision, 30)
+
+
+def test_noalloc_thick_wire_with_gather_staging_and_launch_shapes():
+    """The scratch also holds the gather lists of a thick wire in the
+    blocked slot order, and the block map of non-default launch shapes."""
+    reps = [_rep(50.0, 60.0, 298.0, 0.5, 4), _rep(20.0, 30.0, 10.0, 0.5, 5)]
+    shapes = [A.shape(4, 1), A.shape(2, 0)]
+    _compare(reps, "mixed", 40, shapes=shapes)
+    _compare([_rep(15.0, 4.0, 298.0, 0.5, 6)], "mixed", 20)
 
 
 def test_noalloc_rejects_a_system_beyond_its_scratch_and_zero_steps():
