@@ -24,17 +24,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# unpacked VALU issue: 256 CUs x 1 wave64 instruction per cycle x 2.4 GHz
+VALU_PEAK_IPS = 256 * 2.4e9
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def counter_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    profiler counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it
-    reads for a plain elementwise kernel of known size), or None when there is
-    no record or the kernel source has changed since it was taken."""
+def counter_record(kernel: str, workload: str):
+    """The committed profiler counter record of `kernel` on `workload`
+    (profiles/hbm_traffic.json), or None when there is none or the kernel
+    source has changed since it was taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
@@ -46,9 +47,29 @@ def counter_traffic(kernel: str, workload: str):
         return None
     for rec in recs:
         if rec.get("source_sha256") == sha and rec.get("workload") == workload:
-            return (rec["fetch_kib"] * rec["fetch_scale"]
-                    + rec["write_kib"] * rec["write_scale"]) * 1024.0
+            return rec
     return None
+
+
+def counter_traffic(rec):
+    """HBM bytes per launch from a counter record: FETCH_SIZE and WRITE_SIZE,
+    each scaled by what it reads for a plain elementwise kernel of known
+    size."""
+    if rec is None:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+
+
+def valu_issue(rec, launch_s: float):
+    """VALU issue of a launch: the wavefront VALU instructions the counter run
+    recorded per launch, over the launch time measured here, against one
+    unpacked wave64 instruction per CU per cycle (4 SIMDs of 16 lanes, a
+    wave64 instruction every 4 cycles each) on 256 CUs at 2.4 GHz."""
+    if rec is None or "valu_instr" not in rec:
+        return None
+    achieved = rec["valu_instr"] / launch_s
+    return {"instr_per_launch": rec["valu_instr"], "achieved_instr_per_s": achieved,
+            "peak_instr_per_s": VALU_PEAK_IPS, "frac": achieved / VALU_PEAK_IPS}
 
 
 def main():
@@ -363,6 +384,7 @@ def main():
                                   "cores": oracle.num_threads()}
             log(f"[bench] oracle {name}: {oracle_other[name]}")
 
+    force_rec = counter_record("k_force_mixed", wl.name)
     line = {
         "metric": "atom-timesteps/s, batched vs per-replica TB-SMA NVT; force-kernel % HBM peak",
         "value": value,
@@ -387,7 +409,8 @@ def main():
         "window": window,
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("k_force_mixed", wl.name),
+                     "traffic": counter_traffic(force_rec),
+                     "valu_issue": valu_issue(force_rec, t_force * 1e-3),
                      "kernel": "k_force_mixed",
                      "algorithmic_bytes_per_launch": bytes_force,
                      "avg_launch_us": t_force * 1e3,

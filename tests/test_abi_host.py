@@ -189,6 +189,32 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
     assert r.stdout == ""
 
 
+def test_bench_counter_records_match_the_kernel_source():
+    """The profiler counter records that bench.py reports beside its timing
+    (HBM bytes, VALU instructions) are read only while the kernel source
+    still has the hash they were taken on, and the VALU issue fraction is the
+    recorded instructions over the launch time, against one wave64
+    instruction per CU per cycle on 256 CUs at 2.4 GHz."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(os.path.join(root, "profiles", "hbm_traffic.json")) as f:
+        recs = json.load(f)["k_force_mixed"]
+    rec = bench.counter_record("k_force_mixed", recs[0]["workload"])
+    if rec is None:  # kernels changed since the counters were taken
+        assert bench.counter_traffic(None) is None and bench.valu_issue(None, 1e-3) is None
+        return
+    assert bench.counter_traffic(rec) == pytest.approx(
+        (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024)
+    v = bench.valu_issue(rec, 400e-6)
+    assert v["peak_instr_per_s"] == pytest.approx(256 * 2.4e9)
+    assert v["frac"] == pytest.approx(rec["valu_instr"] / 400e-6 / (256 * 2.4e9))
+    assert bench.counter_record("k_force_mixed", "no such workload") is None
+
+
 def test_noalloc_step_refuses_a_system_beyond_its_scratch_on_the_host():
     """tbsma_step_noalloc checks the system's workspace against its static
     scratch before any device work (placeholders only, nothing runs)."""
