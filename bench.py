@@ -202,15 +202,28 @@ def main():
     t_dens = time_pass(1)
     t_force_e = time_pass(2)  # force pass with energies (logged steps)
     t_force = time_pass(3)    # force pass as run on the other steps
+    # a plain elementwise kernel that reads and writes 512 MiB each: its
+    # measured bandwidth is the practical HBM ceiling the force pass is also
+    # reported against, and (--copy-calibration) the HBM byte counters of a
+    # profiler run are scaled by what they read for one launch of it
+    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    copy_gbs = None
     if args.copy_calibration:
-        # a plain elementwise kernel that reads and writes 512 MiB each: the
-        # HBM byte counters of a profiler run are scaled by what they read here
-        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
         log(f"[bench] calibration kernel: {src.numel() * 8} bytes read and written")
-        del src, dst
+    else:
+        cst = torch.cuda.current_stream()
+        ce = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ce[0].record(cst)
+        for _ in range(10):
+            torch.mul(src, 2.0, out=dst)
+        ce[1].record(cst)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 8 / (ce[0].elapsed_time(ce[1]) / 10 * 1e-3) / 1e9
+        log(f"[bench] plain elementwise kernel: {copy_gbs:.0f} GB/s")
+    del src, dst
     # bytes each kernel must move per launch (per real atom), with kp the mean
     # length of the (pruned) lists the passes read:
     #  density: length 4 + row 4 kp + own position 16 + g 4
@@ -411,6 +424,10 @@ def main():
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
                      "traffic": counter_traffic(force_rec),
                      "valu_issue": valu_issue(force_rec, t_force * 1e-3),
+                     "copy_kernel_GBs": copy_gbs,
+                     "frac_of_copy": gbs_force / copy_gbs if copy_gbs else None,
+                     "traffic_frac_of_copy": (counter_traffic(force_rec) / (t_force * 1e-3) / 1e9
+                                              / copy_gbs if copy_gbs and force_rec else None),
                      "kernel": "k_force_mixed",
                      "algorithmic_bytes_per_launch": bytes_force,
                      "avg_launch_us": t_force * 1e3,
