@@ -72,6 +72,59 @@ def valu_issue(rec, launch_s: float):
             "peak_instr_per_s": VALU_PEAK_IPS, "frac": achieved / VALU_PEAK_IPS}
 
 
+# The paper's Table 2: one unstretched wire per row, timesteps/s at 10 K and
+# at 298 K on one GTX 680 in FP32 (atoms, 10 K, 298 K).
+PAPER_TABLE2 = ((8823, 2536, 2286), (17673, 1723, 1507), (26523, 1311, 1141),
+                (35373, 1045, 897), (44223, 881, 717), (53073, 758, 616),
+                (61923, 655, 550), (70773, 584, 484), (79623, 514, 409),
+                (88473, 470, 354), (97323, 427, 330), (106173, 396, 300))
+
+
+def paper_table(steps: int, warmup: int, spg: int):
+    """Single unstretched wires at the sizes of the paper's Table 2 with the
+    settings of its benchmark (Simulation details, TB-SMA benchmarks):
+    Nose-Hoover NVT at 10 K and 298 K, dt 2 fs, a hard cut at 5.8 A, a 0.29 A
+    list buffer, atoms ordered along [100] (no blocked order at D 3 nm), FP32
+    pair arithmetic, static grips.  Wires of D 3 nm and 100 k (002) layers
+    hold 8850 k atoms, within 0.3 % of the table's rows.  Each wire runs
+    alone: one replica per batch, `steps` timed steps of the graph loop after
+    `warmup` untimed ones."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1311_3890_amd import _abi as A
+    from paper_1311_3890_amd.engine import Potential, WireBatch
+    pot = Potential(r_tail=5.8, r_cut=5.8)
+    rows = []
+    for k, (pa, p10, p298) in enumerate(PAPER_TABLE2, start=1):
+        for T, pts in ((10.0, p10), (298.0, p298)):
+            rp = W.Replica(30.0, W.snap_length(204.0 * k), T, 0.0, W.seed_of(k), k)
+            b = WireBatch([rp], "mixed", skin=0.29, prune=0.0, gamma=0.0, nh_tau=0.1,
+                          pot=pot, n_log=100)
+            b.prepare()
+            b.run_batch(warmup, spg)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            b.run_batch(steps, spg)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            n = int(b.n_atoms[0])
+            bad = int(np.count_nonzero(b.status() & (A.ST_NONFINITE | A.ST_OVERFLOW)))
+            rows.append({"atoms": n, "T_K": T, "timesteps_per_s": steps / sec,
+                         "atom_timesteps_per_s": n * steps / sec, "paper_atoms": pa,
+                         "paper_timesteps_per_s": pts,
+                         "atom_timesteps_over_paper": (n * steps / sec) / (pa * pts),
+                         "bad": bad})
+            log(f"[bench] paper table: {rows[-1]}")
+            del b
+            torch.cuda.empty_cache()
+    return {"steps": steps, "warmup": warmup, "potential": "hard cut 5.8 A",
+            "skin_A": 0.29, "thermostat": "Nose-Hoover, tau 0.1 ps", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +148,10 @@ def main():
     ap.add_argument("--no-protocols", action="store_true",
                     help="skip the timing of the paper's elongation and equilibration "
                          "protocols on the same replicas")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="also time single wires at the sizes and settings of the paper's "
+                         "Table 2 (12 sizes x 10 K, 298 K)")
+    ap.add_argument("--paper-table-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--drift-steps", type=int, default=0,
@@ -451,6 +508,8 @@ def main():
         "bad_replicas": bad,
         "cpu_baseline": cpu,
     }
+    if args.paper_table:
+        line["paper_table"] = paper_table(args.paper_table_steps, 200, 50)
     if untuned_value is not None:
         line["untuned_value"] = untuned_value
     if protocols is not None:
