@@ -211,6 +211,90 @@ int main() {
             TBSMA_OK,
         "step: nothing to do for R = 0");
 
+  // --- the other entry points: refusals and no-ops, all before device work
+  check(tbsma_workspace_init(&p, &s0, nullptr, nullptr) == TBSMA_OK,
+        "workspace_init: nothing to do for R = 0");
+  check(tbsma_workspace_init(&p, &s1, nullptr, nullptr) == TBSMA_EINVAL &&
+            msg_has("work"),
+        "workspace_init: NULL work");
+  check(tbsma_init_state(&p, &s0, &md, nullptr, 0.0, nullptr) == TBSMA_OK,
+        "init_state: nothing to do for R = 0");
+  check(tbsma_init_state(&p, &s1, nullptr, nullptr, 0.0, nullptr) ==
+            TBSMA_EINVAL,
+        "init_state: NULL md");
+  int32_t dof1[1];
+  double v1[1], lo1[1], hi1[1];
+  check(tbsma_replica_constants(&p, &s1, nullptr, v1, lo1, hi1, nullptr) ==
+                TBSMA_EINVAL &&
+            msg_has("dof"),
+        "replica_constants: NULL dof");
+  check(tbsma_replica_constants(&p, &s0, dof1, v1, lo1, hi1, nullptr) ==
+            TBSMA_OK,
+        "replica_constants: nothing to do for R = 0");
+  check(tbsma_rebase(&p, &s1, nullptr, nullptr, nullptr) == TBSMA_EINVAL &&
+            msg_has("L0"),
+        "rebase: NULL L0");
+  check(tbsma_rebase(&p, &s0, v1, nullptr, nullptr) == TBSMA_OK,
+        "rebase: nothing to do for R = 0");
+  check(tbsma_build_cells(&p, &s1, nullptr, nullptr, nullptr) ==
+                TBSMA_EINVAL &&
+            msg_has("cells"),
+        "build_cells: NULL cells");
+  tbsma_cells no_cells = {nullptr, static_cast<int32_t *>(ph)};
+  check(tbsma_build_cells(&p, &s1, &no_cells, nullptr, nullptr) ==
+                TBSMA_EINVAL &&
+            msg_has("cell arrays"),
+        "build_cells: cell arrays missing");
+  check(tbsma_build_cells(&p, &s0, &cells, nullptr, nullptr) == TBSMA_OK,
+        "build_cells: nothing to do for R = 0");
+  check(tbsma_rng_normals_f32(1, 2, 3, 0, -1, nullptr, nullptr) ==
+            TBSMA_EINVAL,
+        "rng_normals_f32: n < 0");
+  check(tbsma_rng_normals_f32(1, 2, 3, 0, 4, nullptr, nullptr) ==
+            TBSMA_EINVAL,
+        "rng_normals_f32: NULL output");
+  check(tbsma_rng_normals_f32(1, 2, 3, 0, 0, nullptr, nullptr) == TBSMA_OK,
+        "rng_normals_f32: n = 0");
+  // launch shapes: both arrays or neither, and only the listed shapes
+  int32_t shape_bad[1] = {3}, shape_ok[1] = {TBSMA_SHAPE(2, 0)};
+  tbsma_system sh = s1;
+  sh.shape_h = shape_ok;
+  check(tbsma_workspace_query(&p, &sh, &bytes) == TBSMA_EINVAL &&
+            msg_has("both"),
+        "shape_h without shape");
+  sh.shape = static_cast<const int32_t *>(ph);
+  check(tbsma_workspace_query(&p, &sh, &bytes) == TBSMA_OK,
+        "a valid launch shape");
+  sh.shape_h = shape_bad;
+  check(tbsma_workspace_query(&p, &sh, &bytes) == TBSMA_EINVAL &&
+            msg_has("launch shape"),
+        "3 tiles per block");
+  shape_bad[0] = TBSMA_SHAPE(4, 2);
+  check(tbsma_workspace_query(&p, &sh, &bytes) == TBSMA_EINVAL,
+        "stage class 2");
+  // the allocation-free step: settings, then the size of its static scratch
+  md.nh_tau = 0.0;
+  check(tbsma_step_noalloc(&p, &s1, &cells, &nl, &out, &md, -1, nullptr) ==
+            TBSMA_EINVAL,
+        "step_noalloc: n_steps < 0");
+  check(tbsma_step_noalloc(&p, &s1, &cells, &nl, &out, &md, 0, nullptr) ==
+            TBSMA_OK,
+        "step_noalloc: zero steps");
+  check(tbsma_step_noalloc(&p, &s1, nullptr, &nl, &out, &md, 1, nullptr) ==
+            TBSMA_EINVAL,
+        "step_noalloc: NULL cells");
+  tbsma_forces_out out_nr = out;
+  out_nr.rep_energy = nullptr;
+  check(tbsma_step_noalloc(&p, &s1, &cells, &nl, &out_nr, &md, 1, nullptr) ==
+            TBSMA_EINVAL,
+        "step_noalloc: no per-replica outputs");
+  std::vector<int64_t> rep_big = {0, (int64_t)64 * 40000}, cel_big = {0, 8};
+  tbsma_system sb = system(1, rep_big, cel_big);
+  check(tbsma_step_noalloc(&p, &sb, &cells, &nl, &out, &md, 1, nullptr) ==
+                TBSMA_ECAPACITY &&
+            msg_has("static scratch"),
+        "step_noalloc: system beyond its scratch");
+
   if (failures) return 1;
   std::printf("abi host driver: all checks passed (%lld-atom wire)\n",
               (long long)n);
