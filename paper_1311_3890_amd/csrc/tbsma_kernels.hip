@@ -322,6 +322,13 @@ struct RingT {
     lds[(cnt & 15) * STRIDE] = j;
     ++cnt;
   }
+  // Branch-free append: j is written to the next free slot in any case and
+  // counted only when keep holds (an uncounted write is overwritten by the
+  // next one).  The slot is never a pending one: at most 15 are pending.
+  __device__ __forceinline__ void put(int j, bool keep) {
+    lds[(cnt & 15) * STRIDE] = j;
+    cnt += keep ? 1 : 0;
+  }
   __device__ __forceinline__ void store_chunk(int32_t *list, int64_t N,
                                               int64_t i, int nch) {
     if ((head >> 3) < nch) {
@@ -1310,7 +1317,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       const float dx = (float)(q.x - qi.x);
       const float dy = (float)(q.y - qi.y);
       const float dz = (float)(q.z - qi.z);
-      return in && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2;
+      return in & (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2);
     };
     int gc = 0;  // listed neighbours when the block is gather-staged
     if (gmark) {
@@ -1399,9 +1406,11 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
           int4 q[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
+          // pad entries read the sentinel, which lies beyond the pruning
+          // radius, so they need no test of their own
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            if (kept(q[e], j[e] != kPadEntry)) ring.push(list_entry(j[e], base));
+            ring.put(list_entry(j[e], base), kept(q[e], true));
           ring.flush(S.nl_lane, S.N, row, nch);
         }
       }
@@ -1411,8 +1420,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (kept(q[e], k0 + e < n)) ring.push(entry(j[e]));
+        for (int e = 0; e < 8; ++e) ring.put(entry(j[e]), kept(q[e], k0 + e < n));
         ring.flush(S.nl_lane, S.N, row, nch);
       });
     }
