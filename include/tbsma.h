@@ -215,9 +215,9 @@ typedef struct {
  * entry k of atom i is nl[((k/8)*N + i)*8 + k%8], k < nn[i] <= k_cap, in
  * an order fixed by the positions alone: cell-scan order (cells by z, y, x;
  * slots ascending within a cell) in FP64; in MIXED, that order within each
- * of four interleaved shares of the candidate scan (groups of 8 candidates,
- * or every fourth of the 27 cells when a tile's slabs exceed LDS), shares in
- * turn.  The entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk
+ * of eight interleaved shares of the candidate scan (groups of 8
+ * candidates, or every eighth of the 27 cells when a tile's candidates
+ * exceed LDS), shares in turn.  The entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk
  * hold 0x7fffffff.
  * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.

@@ -796,8 +796,9 @@ __global__ void __launch_bounds__(1024) k_worklist(Dev S) {
   }
 }
 
-// Exclusive block-wide prefix of v over the kBlock threads (every thread
-// takes part); *total gets the sum.  wsum: kBlock / 64 ints of LDS.
+// Exclusive block-wide prefix of v over the NT threads (every thread takes
+// part); *total gets the sum.  wsum: NT / 64 ints of LDS.
+template <int NT = kBlock>
 __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
                                                int *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -811,7 +812,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
   __syncthreads();
   int before = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     const int t = wsum[k];
     before += k < w ? t : 0;
     tot += t;
@@ -831,19 +832,24 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
 // share's pairs, the second writes them at their final entries, share q
 // after shares 0..q-1.  A row is thus the pairs in candidate order within
 // each share, shares in order, whatever the timing.  When the slabs exceed
-// LDS, the four wavefronts share the walk over the 27 cells around each atom
-// the same way (wavefront q takes cells q, q + 4, ...).  The lane-ordered,
-// pruned rows are made by the pruning kernel.
-constexpr int kNlWaves = kBlock / kTile;
+// LDS, the wavefronts share the walk over the 27 cells around each atom the
+// same way (wavefront q takes cells q, q + kNlWaves, ...).  The
+// lane-ordered, pruned rows are made by the pruning kernel.
+// Threads of a list-build block: eight wavefronts share the scan of one
+// tile (a single replica's rebuild runs about one such block per CU, and
+// eight shares halve each wavefront's serial walk against four; sixteen
+// were slower).
+constexpr int kNlBlock = 512;
+constexpr int kNlWaves = kNlBlock / kTile;
 
 constexpr int kBoxRows = 64;  // rows of cells of the box scan, at most
 
-__global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
+__global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
   __shared__ float4 cand[kCand + 8];
   __shared__ int32_t qcnt[kNlWaves][kTile];
   __shared__ int2 qwin[kNlWaves];
   __shared__ int32_t rowbeg[kBoxRows], rowlen[kBoxRows], rowpre[kBoxRows + 1];
-  __shared__ int32_t wsum[kBlock / 64];
+  __shared__ int32_t wsum[kNlBlock / 64];
   const int tid = threadIdx.x;
   const int q = tid / kTile;  // share of the candidate scan
   const int lane = tid & (kTile - 1);
@@ -879,7 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
       window = m <= kCand;
       if (window) {
         const int4 o = S.qpos[(int64_t)tile * kTile];
-        for (int t = tid; t < m + 8; t += kBlock) {
+        for (int t = tid; t < m + 8; t += kNlBlock) {
           float4 c = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
           if (t < m) {
             const int32_t j = S.cell_atoms[s0 + t];
@@ -931,7 +937,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
           const int bz1 = wave_max_i(real ? qi.z : -0x7fffffff);
           const int4 o = S.qpos[(int64_t)tile * kTile];
           int kept = 0;
-          for (int t0 = 0; t0 < total; t0 += kBlock) {  // uniform
+          for (int t0 = 0; t0 < total; t0 += kNlBlock) {  // uniform
             const int t = t0 + tid;
             bool keep = false;
             float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -948,7 +954,7 @@ __global__ void __launch_bounds__(kBlock) k_nlist_mixed(Dev S, float rl2q) {
                               (float)(qj.z - o.z), __int_as_float(j));
             }
             int n_kept = 0;
-            const int pos = kept + block_excl_scan(keep ? 1 : 0, wsum, &n_kept);
+            const int pos = kept + block_excl_scan<kNlBlock>(keep ? 1 : 0, wsum, &n_kept);
             if (keep && pos < kCand) cand[pos] = c;
             kept += n_kept;
           }
@@ -2590,7 +2596,7 @@ void launch_nlist(const Dev &S, bool mixed, double rl, hipStream_t s) {
   if (mixed) {
     // the rows of the rebuilt replicas, then the lane-ordered rows of the
     // rebuilt and the pruned ones (work lists of the step)
-    k_nlist_mixed<<<work_grid(S.N / kTile), kBlock, 0, s>>>(S,
+    k_nlist_mixed<<<work_grid(S.N / kTile), kNlBlock, 0, s>>>(S,
                                                           (float)(rq * rq));
     if (S.gather)
       k_prune<true><<<work_grid(S.nbmap), kBlock, 0, s>>>(S);
