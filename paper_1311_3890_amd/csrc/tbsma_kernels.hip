@@ -942,8 +942,16 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
             bool keep = false;
             float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
             if (t < total) {
-              int k = 0;
-              while (k + 1 < nrow && rowpre[k + 1] <= t) ++k;
+              // the row of candidate t: the last row that starts at or
+              // before it (rowpre is non-decreasing), by bisection
+              int k = 0, kh = nrow - 1;
+              while (k < kh) {
+                const int mid = (k + kh + 1) >> 1;
+                if (rowpre[mid] <= t)
+                  k = mid;
+                else
+                  kh = mid - 1;
+              }
               const int32_t j = S.cell_atoms[rowbeg[k] + (t - rowpre[k])];
               const int4 qj = S.qpos[j];
               const float ex = (float)max(max(bx0 - qj.x, qj.x - bx1), 0);
