@@ -488,7 +488,11 @@ __device__ __forceinline__ void chunk_loop_padded(const int32_t *list,
 // than that and never pass the test.  Pairs within a few 1e-6 A of rl may
 // fall on either side in the window scan (FP32 offsets); they lie beyond
 // r_cut, where every pair term is exactly zero.
-constexpr int kCand = 1536;  // window candidates staged per block (24 KB)
+// Candidates staged per list-build block (40 KB of LDS).  At 2560 every
+// tile of a 10 nm wire in the blocked order fits the box scan (at 1536, one
+// in six took the per-lane cell walk); the 512-thread blocks are limited to
+// two per CU by registers either way.
+constexpr int kCand = 2560;
 
 template <int STRIDE>
 struct ListRowT {
