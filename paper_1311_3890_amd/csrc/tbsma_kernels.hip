@@ -1288,6 +1288,12 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
   static_assert(2 * kWords * sizeof(uint32_t) <= sizeof(lq), "bitmap fits");
   uint32_t *bits = reinterpret_cast<uint32_t *>(lq);
   int32_t *wbase = reinterpret_cast<int32_t *>(bits + kWords);
+  // and the kept entries of each lane's row chunks (8 bits per chunk, chunk
+  // c of thread t at c * kBlock + t), for rows of at most kMaskChunks chunks
+  constexpr int kMaskChunks = 32;
+  static_assert(2 * kWords * sizeof(uint32_t) + kMaskChunks * kBlock <= sizeof(lq),
+                "kept masks fit");
+  uint8_t *kmask = reinterpret_cast<uint8_t *>(wbase + kWords);
   const WorkLists W = work_lists(S);
   const int nbl = W.count[1];
   const int32_t *blocks = W.blocks;
@@ -1338,6 +1344,9 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       return in & (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rp2);
     };
     int gc = 0;  // listed neighbours when the block is gather-staged
+    // the marking pass also records which entries it keeps, so that the
+    // pass writing the rows needs no positions (uniform)
+    const bool masked = gmark && S.k_cap <= 8 * kMaskChunks;
     if (gmark) {
       for (int w = threadIdx.x; w < nwords; w += kBlock) bits[w] = 0u;
       __syncthreads();
@@ -1345,12 +1354,15 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
         int4 q[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) q[e] = gather_q(S.qpos, j[e]);
+        uint32_t m = 0;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           if (kept(q[e], k0 + e < n)) {
             const uint32_t off = (uint32_t)(j[e] - lo);
             atomicOr(&bits[off >> 5], 1u << (off & 31));
+            m |= 1u << e;
           }
+        if (masked) kmask[(k0 >> 3) * kBlock + threadIdx.x] = (uint8_t)m;
       });
       __syncthreads();
       // each thread takes kWpt consecutive words
@@ -1400,7 +1412,7 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       // used: the stores of the ring's flushes then overlap the positions'
       // LDS reads instead of delaying the next list loads (loads and stores
       // retire in order)
-      constexpr int kPruneBatch = 7;
+      constexpr int kPruneBatch = GATHER ? 4 : 7;
       const StagedIndex sx(lo, cap);
       const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
       const int own = (n + 7) >> 3;
@@ -1432,6 +1444,14 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
           ring.flush(S.nl_lane, S.N, row, nch);
         }
       }
+    } else if (masked) {
+      // each thread reads back only the masks it wrote
+      chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
+        const uint32_t m = kmask[(k0 >> 3) * kBlock + threadIdx.x];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ring.put(entry(j[e]), ((m >> e) & 1u) != 0u);
+        ring.flush(S.nl_lane, S.N, row, nch);
+      });
     } else {
       chunk_loop(S.nl, S.N, i, (int)i, n, 0, 1, [&](const int (&j)[8], int k0) {
         int4 q[8];
