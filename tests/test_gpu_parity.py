@@ -1116,20 +1116,29 @@ def test_gather_staging_leaves_trajectories_unchanged_bitwise():
     """Gather staging changes only where the pair passes read neighbour
     positions from (LDS instead of global memory), not the arithmetic or its
     order: 200 steps at 298 K with rebuilds and prunings, on and off, agree
-    bit for bit."""
+    bit for bit.  So does gather staging with a list capacity above 256,
+    where the pruning kernel's row-writing sweep repeats the distance tests
+    instead of reading back the kept masks of its marking sweep."""
     rp = R(50.0, 40.0, T=298.0, v=0.5, r=4, jitter=0.02)
-    note("gather staging on vs off, 200 steps mixed")
+    note("gather staging on vs off, and with k_cap 264, 200 steps mixed")
     a = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1, gather=1)
+    assert a.k_cap <= 256
     a.prepare()
     a.run_batch(200, 50)
     g = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1, gather=0, qbits=a.qbits)
     g.prepare()
     g.run_batch(200, 50)
+    h = WireBatch([rp], "mixed", n_log=25, skin=0.6, prune=0.1, gather=1, qbits=a.qbits,
+                  k_cap=264)
+    h.prepare()
+    h.run_batch(200, 50)
     torch.cuda.synchronize()
     assert a.status()[0] & A.ST_REBUILT
     assert a.staging()["gather"] > 0 and g.staging()["gather"] == 0
+    assert h.k_cap == 264 and h.staging()["gather"] == a.staging()["gather"]
     for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "obs", "status"):
         assert torch.equal(a.t[k], g.t[k]), k
+        assert torch.equal(a.t[k], h.t[k]), k
 
 
 def test_config2_pulled_to_rupture_forces_stay_within_parity():
