@@ -126,6 +126,17 @@ extern "C" {
  *                   workspace (about 12 bytes per slot more workspace).
  *                   Results do not depend on it: the pair arithmetic is the
  *                   same whichever way positions reach it.
+ *  rebuild_exact    0 or 1.  A replica's lists are rebuilt once some atom
+ *                   may have moved more than skin/2 since the last build.
+ *                   With pruning (MIXED, prune > 0) and 0, the position
+ *                   update bounds each atom's displacement since the build
+ *                   by its displacement since the last pruning plus the one
+ *                   since the build recorded at that pruning, and does not
+ *                   read the build positions; lists then rebuild a little
+ *                   sooner.  With 1, or without pruning, it tests the FP64
+ *                   distance from the build positions (x_ref, y_ref, z_ref),
+ *                   so that runs with and without pruning rebuild on the
+ *                   same steps.
  */
 typedef struct {
   double A, xi, p, q, r0;
@@ -137,7 +148,7 @@ typedef struct {
   int32_t qbits;
   double prune;
   int32_t gather;
-  int32_t reserved;
+  int32_t rebuild_exact;
 } tbsma_params;
 
 /*

@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("r0", C.c_double), ("r_tail", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("cell", C.c_double), ("mass", C.c_double),
                 ("precision", C.c_int32), ("qbits", C.c_int32), ("prune", C.c_double),
-                ("gather", C.c_int32), ("reserved", C.c_int32)]
+                ("gather", C.c_int32), ("rebuild_exact", C.c_int32)]
 
 
 class System(C.Structure):

@@ -85,6 +85,8 @@ int check_params(const tbsma_params *p) {
     return fail(TBSMA_EINVAL, "prune must be in [0, skin/2]");
   if (p->gather != 0 && p->gather != 1)
     return fail(TBSMA_EINVAL, "gather must be 0 or 1");
+  if (p->rebuild_exact != 0 && p->rebuild_exact != 1)
+    return fail(TBSMA_EINVAL, "rebuild_exact must be 0 or 1");
   return TBSMA_OK;
 }
 
@@ -296,8 +298,10 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
     const double rp = p->prune > 0 ? p->r_cut + 2.0 * p->prune + 1e-5
                                    : p->r_cut + p->skin + 1.0;
     d.pruning = p->prune > 0 ? 1 : 0;
+    d.rebuild_bound = d.pruning && !p->rebuild_exact ? 1 : 0;
     d.prune_r2q = (float)(rp * rp * q * q);
     d.prune_d2q = (float)(p->prune * p->prune * q * q);
+    d.skin_half_q = (float)(0.5 * p->skin * q) - 1.0f;
   }
   d.nbmap = s->R > 0 ? block_map_size(s) : 0;
   d.cell = p->cell;

@@ -94,9 +94,13 @@ struct Dev {
   int32_t *nl_lane;             // lists in lane order (CL8 layout), or NULL
   // pruning of the lane-ordered lists (mixed precision)
   int32_t pruning;              // 1 when enabled
+  int32_t rebuild_bound;        // 1: rebuild test by the pruning bound
   float prune_r2q;              // (r_cut + 2d)^2 + margin, quanta^2
   float prune_d2q;              // d^2, quanta^2
-  int4 *qprune;                 // [N] quantised positions at the last pruning
+  float skin_half_q;            // skin/2 less one quantum, in quanta
+  int4 *qprune;                 // [N] quantised positions at the last pruning;
+                                // .w: the displacement since the list build
+                                // then (float, quanta, rounded up)
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks

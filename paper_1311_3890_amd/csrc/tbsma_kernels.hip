@@ -1466,7 +1466,15 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       ring.finish(S.nl_lane, S.N, row, nch,
                   gc > 0 ? pad_staged(cap) : pad_of_window(size, cap));
       S.nn_lane[row] = ring.cnt;
-      S.qprune[i] = qi;
+      // beside the pruning position, the atom's displacement since the list
+      // build (quanta, one added for rounding): the position update bounds
+      // the displacement since the build by its own since the pruning plus
+      // this, without reading the build positions
+      const double bx = S.x[i] - S.xr[i], by = S.y[i] - S.yr[i],
+                   bz = S.z[i] - S.zr[i];
+      const float db =
+          (float)(sqrt(bx * bx + by * by + bz * bz) * S.qscale) + 1.0f;
+      S.qprune[i] = make_int4(qi.x, qi.y, qi.z, __float_as_int(db));
     }
     __syncthreads();  // lq, bits, wbase and key serve the next block
   }
@@ -1928,6 +1936,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
   uint8_t f = valid ? S.flag[i] : 3;
   double disp2 = 0.0;
   float pd2 = 0.0f;  // |q - qprune|^2 (quanta^2) when pruning
+  float dbq = 0.0f;  // displacement since the build at the last pruning
   // the previous step left its second half kick to this one (DevMD::defer):
   // it was neither logged nor the last of a call (uniform)
   const bool pend = MIXED && (S.callb[2] & kStepPend) != 0;
@@ -2014,15 +2023,23 @@ __global__ void __launch_bounds__(kBlock) k_integrate_a(Dev S, DevMD M,
         const float ex = (float)(q.x - p.x), ey = (float)(q.y - p.y),
                     ez = (float)(q.z - p.z);
         pd2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-        if (out) pd2 = 3.0e38f;
+        if (out) pd2 = 3.0e38f;  // also NaN positions
+        dbq = __int_as_float(p.w);
       }
     }
-    double ex = x - S.xr[i], ey = y - S.yr[i], ez = z - S.zr[i];
-    disp2 = ex * ex + ey * ey + ez * ez;
-    if (!(disp2 == disp2)) disp2 = 1.0e300;  // NaN forces a rebuild
+    if (!(MIXED && S.rebuild_bound)) {
+      double ex = x - S.xr[i], ey = y - S.yr[i], ez = z - S.zr[i];
+      disp2 = ex * ex + ey * ey + ez * ez;
+      if (!(disp2 == disp2)) disp2 = 1.0e300;  // NaN forces a rebuild
+    }
   }
-  // per-replica flags (a NaN displacement counts as far)
-  const bool far = !(disp2 <= S.skin_half2);
+  // per-replica flags (a NaN displacement counts as far).  With the pruning
+  // bound, the displacement since the list build is at most the one since
+  // the last pruning (from the quantised positions, plus two quanta for their
+  // rounding) plus the one since the build at that pruning.
+  const bool far = MIXED && S.rebuild_bound
+                       ? !(sqrtf(pd2) + 2.0f + dbq <= S.skin_half_q)
+                       : !(disp2 <= S.skin_half2);
   const bool pfar = MIXED && S.pruning && !(pd2 <= S.prune_d2q);
   const uint32_t m = (wave_any(far) ? 1u : 0u) | (wave_any(pfar) ? 2u : 0u);
   if ((threadIdx.x & 63) == 0 && valid && m) atomicOr(&S.rflag[r], m);

@@ -112,6 +112,10 @@ class WireBatch:
     shapes        launch shape of each replica's pair-pass blocks
                   (_abi.shape(tiles_per_block, stage_class)), or None for
                   the default; see set_shapes.
+    rebuild_exact with pruning, test the displacement since the list build
+                  on the FP64 build positions instead of bounding it from
+                  the pruning (tbsma_params.rebuild_exact): the lists then
+                  rebuild on the same steps as without pruning.
     The settings mean what include/tbsma.h says of tbsma_md and tbsma_params.
     """
 
@@ -124,7 +128,8 @@ class WireBatch:
                  grip_hold: int = 0, notch: tuple | None = None, T_start=None,
                  ramp_begin: int = 0, ramp_steps: int = 0, baro_mass: float = 0.0,
                  baro_load: float = 0.0, baro_damp: float = 0.0, order: str = "auto",
-                 gather: int | None = None, shapes: Sequence[int] | None = None):
+                 gather: int | None = None, shapes: Sequence[int] | None = None,
+                 rebuild_exact: bool = False):
         self.replicas = list(replicas)
         if not self.replicas:
             raise ValueError("a batch needs at least one replica")
@@ -138,7 +143,7 @@ class WireBatch:
                         grip_step=grip_step, grip_hold=grip_hold, notch=notch,
                         T_start=T_start, ramp_begin=ramp_begin, ramp_steps=ramp_steps,
                         baro_mass=baro_mass, baro_load=baro_load, baro_damp=baro_damp,
-                        order=order, gather=gather)
+                        order=order, gather=gather, rebuild_exact=rebuild_exact)
         self.shapes = None if shapes is None else [int(v) for v in shapes]
         if self.shapes is not None and len(self.shapes) != len(self.replicas):
             raise ValueError("shapes needs one launch shape per replica")
@@ -278,7 +283,8 @@ class WireBatch:
         self.params = A.Params(self.pot.A, self.pot.xi, self.pot.p, self.pot.q, self.pot.r0,
                                self.pot.r_tail, self.pot.r_cut, skin, cell, MASS_AU,
                                A.MIXED if precision == "mixed" else A.FP64, self.qbits,
-                               self.prune, int(gather) if precision == "mixed" else 0, 0)
+                               self.prune, int(gather) if precision == "mixed" else 0,
+                               int(bool(rebuild_exact)))
         self._rep_off_h = (C.c_int64 * (R + 1))(*self.rep_off.tolist())
         self._shape_h = None
         self._cell_off_h = (C.c_int64 * (R + 1))(*self.cell_off.tolist())

@@ -88,6 +88,8 @@ def _params(**kw):
     (dict(cell=20.0), b"cell/2"),
     (dict(prune=0.6), b"prune"),
     (dict(prune=-0.1), b"prune"),
+    (dict(gather=2), b"gather"),
+    (dict(rebuild_exact=2), b"rebuild_exact"),
 ])
 def test_parameter_checks(kw, msg):
     sysm = A.System()

@@ -751,11 +751,14 @@ def test_batched_equals_one_replica_at_a_time_bitwise(kw):
 def test_pruned_lists_leave_trajectories_unchanged_bitwise():
     """The pair passes read lists pruned to r_cut + 2d and re-pruned when an
     atom moves more than d; the pairs they drop contribute exactly zero, so
-    the trajectory equals the one on full lists bit for bit (several
-    prunings and rebuilds happen at 298 K in 300 steps)."""
+    with the rebuild test on the build positions (the one used without
+    pruning, so that both rebuild on the same steps) the trajectory equals
+    the one on full lists bit for bit (several prunings and rebuilds happen
+    at 298 K in 300 steps).  The default rebuild test bounds the
+    displacement from the pruning instead: it rebuilds at least as often."""
     reps = _three_replicas()
     note("pruned vs full lists, 300 steps mixed")
-    a = WireBatch(reps, "mixed", n_log=50, prune=0.1)
+    a = WireBatch(reps, "mixed", n_log=50, prune=0.1, rebuild_exact=True)
     a.prepare()
     a.run_batch(300, steps_per_graph=50)
     b = WireBatch(reps, "mixed", n_log=50, prune=0.0, qbits=a.qbits)
@@ -765,6 +768,21 @@ def test_pruned_lists_leave_trajectories_unchanged_bitwise():
         assert torch.equal(a.t[k], b.t[k]), k
     assert torch.equal(a.t["obs"], b.t["obs"])
     assert np.all(a.status() & A.ST_REBUILT)
+    # the bound: the first rebuild of each replica comes no later
+    c = WireBatch(reps, "mixed", n_log=1, n_slots=300, prune=0.1, qbits=a.qbits)
+    c.prepare()
+    e = WireBatch(reps, "mixed", n_log=1, n_slots=300, prune=0.1, qbits=a.qbits,
+                  rebuild_exact=True)
+    e.prepare()
+    c.run_batch(300, steps_per_graph=50)
+    e.run_batch(300, steps_per_graph=50)
+    def first_rebuild(bb, r):
+        o = bb.obs()[:, r]
+        hit = (o[:, A.OBS_STATUS].astype(np.int64) & A.ST_REBUILT) != 0
+        assert hit.any()
+        return o[hit, A.OBS_STEP].min()
+    for r in range(len(reps)):
+        assert first_rebuild(c, r) <= first_rebuild(e, r), r
 
 
 @VARIANTS
