@@ -1209,8 +1209,24 @@ __device__ __forceinline__ bool stage(const Dev &S, int4 *lq,
 __device__ __forceinline__ bool stage_gather(const Dev &S, int4 *lq,
                                              const PairBlock &B, int lo,
                                              int gc, int cap) {
+  // all of a thread's list reads, then all of its position reads (each
+  // position read depends on a list read; gc <= kStage)
   const uint16_t *g = S.glist + B.blk * kStage;
-  for (int t = threadIdx.x; t < gc; t += kBlock) lq[t] = S.qpos[lo + g[t]];
+  constexpr int kPer = (kStage + kBlock - 1) / kBlock;
+  int off[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int t = threadIdx.x + k * kBlock;
+    off[k] = t < gc ? (int)g[t] : 0;
+  }
+  int4 v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = S.qpos[lo + off[k]];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int t = threadIdx.x + k * kBlock;
+    if (t < gc) lq[t] = v[k];
+  }
   return stage_sentinel(S, lq, B, cap);
 }
 
