@@ -242,8 +242,12 @@ typedef struct {
  * list as row (block start + p) of the same chunked layout, pruned to the
  * pairs within r_cut + 2 prune (see tbsma_params), each entry encoded as
  * the byte offset 16 (j - lo) of neighbour j from the start lo of the
- * block's slot window.  Written by the list build and by the pruning in the
- * step loops; opaque to the caller (save and restore it as a whole).
+ * block's slot window, or, in a block staged through its gather list
+ * (tbsma_params.gather), 16 times the neighbour's rank in that list.
+ * Written by the list build and by the pruning in the step loops; opaque to
+ * the caller (save and restore it as a whole, with the workspace, which
+ * holds the lane order, the gather lists and the positions at the last
+ * pruning).
  */
 typedef struct {
   int32_t *nl;
