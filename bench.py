@@ -480,6 +480,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": gbs_force, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs_force / HBM_PEAK_GBS,
                      "traffic": counter_traffic(force_rec),
+                     # counter-measured HBM bytes per launch over the launch time,
+                     # against the same 8 TB/s
+                     "traffic_frac": (counter_traffic(force_rec) / (t_force * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS if force_rec else None),
                      "valu_issue": valu_issue(force_rec, t_force * 1e-3),
                      "copy_kernel_GBs": copy_gbs,
                      "frac_of_copy": gbs_force / copy_gbs if copy_gbs else None,
