@@ -44,6 +44,27 @@ def test_host_wire_builder_equals_oracle(D, L):
     assert np.array_equal(f, fo)
 
 
+from hypothesis import given, settings, strategies as st
+
+
+@settings(max_examples=60, deadline=None)
+@given(a=st.floats(3.6, 4.4), D=st.floats(0.0, 40.0), L=st.floats(0.0, 90.0),
+       n_grip=st.integers(0, 4), layers=st.integers(0, 6), depth=st.floats(0.0, 25.0))
+def test_host_wire_builder_equals_oracle_on_random_geometries(a, D, L, n_grip, layers, depth):
+    """The library's wire builder and the oracle's, written apart, give the
+    same sites, order and flags for any lattice constant, diameter, length,
+    grip thickness and notch."""
+    x, y, z, f = build_wire_host(a, D, L, n_grip, layers, depth)
+    xo, yo, zo, fo = oracle.build_wire(a, D, L, n_grip, layers, depth)
+    assert x.size == xo.size
+    assert np.array_equal(x, xo) and np.array_equal(y, yo) and np.array_equal(z, zo)
+    assert np.array_equal(f, fo)
+    # the blocked slot order of thick wires is a permutation of the sites
+    from paper_1311_3890_amd.engine import blocked_order
+    perm = blocked_order(x, y, z, a)
+    assert np.array_equal(np.sort(perm), np.arange(x.size))
+
+
 def test_wire_builder_capacity_and_errors():
     lib = A.lib()
     n = C.c_int64()
