@@ -154,6 +154,36 @@ def test_forces_are_minus_energy_gradient(seed):
             assert abs(fd - F[i, c]) < 1e-7 * max(1.0, fmax), (i, c, fd, F[i, c])
 
 
+from hypothesis import given, settings, strategies as st
+
+
+@settings(max_examples=40, deadline=None)
+@given(n=st.integers(2, 36), seed=st.integers(0, 10 ** 6), k=st.integers(0, 10 ** 6))
+def test_force_invariants_on_random_clusters(n, seed, k):
+    """For any cluster: the forces sum to zero (Newton's third law), the
+    energy does not change under a translation, the cell-list mode equals
+    brute force, and one randomly chosen force component equals minus the
+    central difference of the energy (h = 1e-5 A)."""
+    x, y, z = random_cluster(n, seed, box=9.0 * (n / 30.0) ** (1.0 / 3.0) + 2.0)
+    out = oracle.forces(AU, x, y, z, 0)
+    F = np.stack([out["fx"], out["fy"], out["fz"]], 1)
+    assert np.abs(F.sum(0)).max() <= 1e-12 * np.abs(F).sum() + 1e-14
+    t = oracle.forces(AU, x + 31.7, y - 4.2, z + 0.9, 0)
+    assert abs(t["E"] - out["E"]) < 1e-11
+    c = oracle.forces(AU, x, y, z, 1)
+    for key in ("e_atom", "fx", "fy", "fz", "rho"):
+        assert np.abs(c[key] - out[key]).max() < 1e-12
+    i, comp = k % n, (k // n) % 3
+    arr = (x, y, z)[comp]
+    h = 1e-5
+    arr[i] += h
+    ep = oracle.forces(AU, x, y, z, 0)["E"]
+    arr[i] -= 2 * h
+    em = oracle.forces(AU, x, y, z, 0)["E"]
+    arr[i] += h
+    assert abs(-(ep - em) / (2 * h) - F[i, comp]) < 1e-7 * max(1.0, np.abs(F).max())
+
+
 def test_newton_third_law_and_invariance():
     x, y, z = random_cluster(36, 7)
     out = oracle.forces(AU, x, y, z, 0)
