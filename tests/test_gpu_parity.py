@@ -398,6 +398,39 @@ def test_forces_mixed_ragged_batch():
         assert torch.all(b.t["fx"][o + n:e] == 0) and torch.all(b.t["e_atom"][o + n:e] == 0)
 
 
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+
+@settings(max_examples=12, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(D=st.floats(8.0, 45.0), L=st.floats(6.0, 60.0), jitter=st.floats(0.0, 0.15),
+       precision=st.sampled_from(["fp64", "mixed"]), order=st.sampled_from(["axial", "blocked"]),
+       r=st.integers(0, 999))
+def test_lists_and_forces_on_random_wires(D, L, jitter, precision, order, r):
+    """Wires of random diameter, length and jitter, in either slot order and
+    precision: the Verlet lists equal brute force and the forces and energy
+    match the oracle at the GPU's positions (derandomised examples, so that
+    every run checks the same wires)."""
+    rp = R(D, L, T=298.0, r=r, jitter=jitter)
+    note(f"random wire D {D:.2f} L {L:.2f} jitter {jitter:.3f} {precision} {order}")
+    b = WireBatch([rp], precision, order=order)
+    b.prepare()
+    torch.cuda.synchronize()
+    x, y, z = b.positions(0)
+    rl = b.pot.r_cut + b.skin
+    sure = brute_sets(x, y, z, rl - 1e-5)
+    loose = brute_sets(x, y, z, rl + 1e-5)
+    got = b.neighbor_rows(0)
+    for i in range(x.size):
+        g = set(got[i].tolist())
+        assert len(g) == got[i].size and set(sure[i].tolist()) <= g <= set(loose[i].tolist()), i
+    ref = oracle.forces(AU, x, y, z, 1)
+    tol, etol = (1e-12, 1e-12) if precision == "fp64" else (1e-5, 1e-6)
+    if x.size > 1:
+        assert eps_F(stackF(b.forces(0)), stackF((ref["fx"], ref["fy"], ref["fz"]))) <= tol
+    assert abs(b.t["rep_energy"][0].item() - ref["E"]) <= etol * max(1.0, abs(ref["E"]))
+
+
 @pytest.mark.parametrize("kw", [{}, dict(baro_mass=300.0, baro_damp=2.0)],
                          ids=["pulled", "barostat"])
 def test_init_state_matches_oracle(kw):
