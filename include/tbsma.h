@@ -214,7 +214,10 @@ typedef struct {
  * Cell lists.  cell_start: device [C + R] int32.  For replica r and local
  * cell c (c = (cz*gy + cy)*gx + cx), the slots of its atoms are
  * cell_atoms[cell_start[cell_off[r]+r+c] .. cell_start[cell_off[r]+r+c+1]),
- * in ascending slot order.  cell_atoms: device [N] int32.
+ * in ascending slot order.  cell_atoms: device [N] int32, the permutation
+ * of each replica's slots sorted by cell (the atom arrays themselves are not
+ * reordered by a build: their slot order is fixed when the system is laid
+ * out, see Layout above).
  */
 typedef struct {
   int32_t *cell_start;
