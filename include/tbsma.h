@@ -118,7 +118,11 @@ extern "C" {
  *                   is pruned to the pairs within r_cut + 2d, and pruned again
  *                   from the full list whenever some atom of the replica has
  *                   moved more than d since the last pruning, so no pair
- *                   within r_cut is ever left out.
+ *                   within r_cut is ever left out.  The pairs within
+ *                   r_cut - skin/2 at the last build are kept without a test
+ *                   until the next one (such a pair leaves r_cut + 2d only
+ *                   when stretched by more than skin/2 + 2d, and contributes
+ *                   nothing beyond r_cut).
  *  gather           MIXED only, 0 or 1: 1 lets a block of the pair passes
  *                   whose slot window is too wide for LDS (thick wires)
  *                   stage the exact set of its neighbours instead, through
@@ -228,10 +232,11 @@ typedef struct {
  * Verlet lists (full: both i->j and j->i), stored in chunks of 8 entries:
  * entry k of atom i is nl[((k/8)*N + i)*8 + k%8], k < nn[i] <= k_cap, in
  * an order fixed by the positions alone: cell-scan order (cells by z, y, x;
- * slots ascending within a cell) in FP64; in MIXED, that order within each
- * of eight interleaved shares of the candidate scan (groups of 8
- * candidates, or every eighth of the 27 cells when a tile's candidates
- * exceed LDS), shares in turn.  The entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk
+ * slots ascending within a cell) in FP64; in MIXED, the pairs within r_cut - skin/2
+ * first, then the others, each part in that order within each of eight
+ * interleaved shares of the candidate scan (groups of 8 candidates, or
+ * every eighth of the 27 cells when a tile's candidates exceed LDS),
+ * shares in turn.  The entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk
  * hold 0x7fffffff.
  * nl: device [k_cap*N] int32; k_cap must be a multiple of 8.
  * x_ref, y_ref, z_ref: device [N] positions at the last build.
@@ -243,7 +248,8 @@ typedef struct {
  * mixed pair passes read them: within each block of up to four tiles of one
  * replica, atoms by descending list length (ties by slot), the p-th atom's
  * list as row (block start + p) of the same chunked layout, pruned to the
- * pairs within r_cut + 2 prune (see tbsma_params), each entry encoded as
+ * pairs within r_cut + 2 prune and those kept without a test (see
+ * tbsma_params.prune), in the order of nl, each entry encoded as
  * the byte offset 16 (j - lo) of neighbour j from the start lo of the
  * block's slot window, or, in a block staged through its gather list
  * (tbsma_params.gather), 16 times the neighbour's rank in that list.

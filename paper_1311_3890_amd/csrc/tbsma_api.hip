@@ -138,7 +138,7 @@ int check_system(const tbsma_params *p, const tbsma_system *s) {
 
 struct Layout {
   size_t rflag, cnt, part, zbmin, zbmax, wstatus, nnmax, rsum, win,
-      bmap, boff, cbmap, lane_atom, nn_lane, qprune, atom_lane, stats, nhw,
+      bmap, boff, cbmap, lane_atom, nn_lane, qprune, atom_lane, ncore, stats, nhw,
       baw, wl, callb, gcnt, glist, total;
 };
 
@@ -209,6 +209,8 @@ Layout layout(const tbsma_params *p, const tbsma_system *s) {
   o += up(16 * (size_t)s->N);
   L.atom_lane = o;
   o += up((size_t)s->N);
+  L.ncore = o;
+  o += up(4 * (size_t)s->N);
   L.stats = o;
   o += 256;
   L.nhw = o;
@@ -271,6 +273,7 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
   d.nn_lane = reinterpret_cast<int32_t *>(w + L.nn_lane);
   d.qprune = reinterpret_cast<int4 *>(w + L.qprune);
   d.atom_lane = reinterpret_cast<uint8_t *>(w + L.atom_lane);
+  d.ncore = reinterpret_cast<int32_t *>(w + L.ncore);
   d.stats = reinterpret_cast<unsigned long long *>(w + L.stats);
   d.nhw = reinterpret_cast<double *>(w + L.nhw);
   d.baw = reinterpret_cast<double *>(w + L.baw);
@@ -299,6 +302,13 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
                                    : p->r_cut + p->skin + 1.0;
     d.pruning = p->prune > 0 ? 1 : 0;
     d.rebuild_bound = d.pruning && !p->rebuild_exact ? 1 : 0;
+    // the core of the full lists: pairs within r_cut - skin/2 at the build,
+    // listed first and kept by every pruning until the next build.  They
+    // leave the pruning radius only when stretched by more than skin/2 + 2d,
+    // and a pair beyond r_cut contributes nothing.  The radius does not
+    // depend on d, so runs with and without pruning list pairs alike.
+    const double rcore = p->r_cut - 0.5 * p->skin;
+    d.core_r2q = rcore > 0 ? (float)(rcore * rcore * q * q) : 0.0f;
     d.prune_r2q = (float)(rp * rp * q * q);
     d.prune_d2q = (float)(p->prune * p->prune * q * q);
     d.skin_half_q = (float)(0.5 * p->skin * q) - 1.0f;

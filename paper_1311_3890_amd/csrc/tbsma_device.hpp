@@ -102,6 +102,9 @@ struct Dev {
                                 // .w: the displacement since the list build
                                 // then (float, quanta, rounded up)
   uint8_t *atom_lane;           // [N] row of each atom in its block's lane order
+  int32_t *ncore;               // [N] leading entries of each full row (mixed)
+                                // within the core radius at the build
+  float core_r2q;               // core radius^2, quanta^2 (0: no core)
   unsigned long long *stats;    // [2] list-length sums (diagnostics)
   int32_t nbmap;                // number of list-build blocks
   const int32_t *shape;         // [R] launch shape of each replica, or NULL

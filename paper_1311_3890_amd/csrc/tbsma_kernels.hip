@@ -550,9 +550,9 @@ __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
 // Mixed-precision cell scan, for tiles whose slabs exceed LDS: this lane's
 // atom against the atoms of cells q, q + nq, q + 2 nq, ... of the 27 around
 // its cell (nq wavefronts share the scan), reading candidate positions from
-// global memory; near(j) is called for each candidate j within the list
-// radius (exact integer differences of the quantised positions), in cell
-// order.  A lane takes up to 4 candidates of its current cell at a time,
+// global memory; near(j, d2) is called for each candidate j within the
+// list radius, with its squared distance d2 (exact integer differences of
+// the quantised positions, quanta^2), in cell order.  A lane takes up to 4 candidates of its current cell at a time,
 // so that their slot and position loads are in flight together.
 template <class F>
 __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
@@ -598,7 +598,8 @@ __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
         const float dx = (float)(qq[k].x - qi.x);
         const float dy = (float)(qq[k].y - qi.y);
         const float dz = (float)(qq[k].z - qi.z);
-        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q) near(jj[k]);
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (d2 < rl2q) near(jj[k], d2);
       }
       s += nb;
     }
@@ -607,8 +608,9 @@ __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
 
 // Tests this lane's atom (FP32 offset pi from the block origin) against
 // window candidates [a, b) of cand (x, y, z offsets and the slot as bits;
-// a and b uniform over the wavefront) and calls near(j) for each candidate
-// j within the list radius, in candidate order.  Candidates are read in
+// a and b uniform over the wavefront) and calls near(j, d2) for each
+// candidate j within the list radius, with its squared distance d2
+// (quanta^2), in candidate order.  Candidates are read in
 // groups of 8, and this wavefront takes groups q, q + nq, q + 2 nq, ... of
 // the range (nq wavefronts share the scan of one tile).  cand holds 8
 // filler entries past the window so the last group stays in bounds, and
@@ -631,9 +633,8 @@ __device__ __forceinline__ void window_scan(int64_t i, bool real, float4 pi,
       const float dy = c[e].y - pi.y;
       const float dz = c[e].z - pi.z;
       const int32_t j = __float_as_int(c[e].w);
-      if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rl2q && j != self &&
-          t0 + e < b && real)
-        near(j);
+      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      if (d2 < rl2q && j != self && t0 + e < b && real) near(j, d2);
     }
   }
 }
@@ -835,7 +836,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
 // ~1000 candidates.  The scan runs twice: the first pass counts each
 // share's pairs, the second writes them at their final entries, share q
 // after shares 0..q-1.  A row is thus the pairs in candidate order within
-// each share, shares in order, whatever the timing.  When the slabs exceed
+// each share, shares in order, whatever the timing: first the pairs within
+// the core radius (Dev::core_r2q; their number in ncore), then the others,
+// each part so ordered.  When the slabs exceed
 // LDS, the wavefronts share the walk over the 27 cells around each atom the
 // same way (wavefront q takes cells q, q + kNlWaves, ...).  The
 // lane-ordered, pruned rows are made by the pruning kernel.
@@ -851,6 +854,7 @@ constexpr int kBoxRows = 64;  // rows of cells of the box scan, at most
 __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
   __shared__ float4 cand[kCand + 8];
   __shared__ int32_t qcnt[kNlWaves][kTile];
+  __shared__ int32_t qcore[kNlWaves][kTile];
   __shared__ int2 qwin[kNlWaves];
   __shared__ int32_t rowbeg[kBoxRows], rowlen[kBoxRows], rowpre[kBoxRows + 1];
   __shared__ int32_t wsum[kNlBlock / 64];
@@ -982,10 +986,12 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
       }
     }
     __syncthreads();
-    int cnt = 0;
+    int cnt = 0, cnt_c = 0;  // pairs of this share, of them in the core
     int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
-    auto count = [&](int32_t j) {
+    const float core2 = S.core_r2q;
+    auto count = [&](int32_t j, float d2) {
       ++cnt;
+      cnt_c += d2 < core2 ? 1 : 0;
       wlo = min(wlo, j);
       whi = max(whi, j);
     };
@@ -994,21 +1000,26 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
     else
       cells_scan(S, i, r, real, cx, cy, cz, qi, rl2q, q, kNlWaves, count);
     qcnt[q][lane] = cnt;
+    qcore[q][lane] = cnt_c;
     const int32_t wl = -wave_max_i(-wlo);
     const int32_t wh = wave_max_i(whi);
     if (lane == 0) qwin[q] = make_int2(wl, wh);
     __syncthreads();
-    int total = 0, before = 0;  // entries of all shares, of shares 0..q-1
+    // entries of all shares and of shares 0..q-1, in all and in the core:
+    // the row holds the core pairs of every share first, then the others
+    int total = 0, before = 0, total_c = 0, before_c = 0;
 #pragma unroll
     for (int k = 0; k < kNlWaves; ++k) {
-      const int c = qcnt[k][lane];
+      const int c = qcnt[k][lane], cc = qcore[k][lane];
       before += k < q ? c : 0;
       total += c;
+      before_c += k < q ? cc : 0;
+      total_c += cc;
     }
-    int e = before;
-    auto write = [&](int32_t j) {
+    int ec = before_c, es = total_c + before - before_c;
+    auto write = [&](int32_t j, float d2) {
+      const int e = d2 < core2 ? ec++ : es++;
       if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
-      ++e;
     };
     if (window)
       window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, write);
@@ -1024,6 +1035,7 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
         atomicOr(&S.wstatus[r], 1u);
       }
       S.nn[i] = real ? min(total, S.k_cap) : 0;
+      S.ncore[i] = real ? min(total_c, S.k_cap) : 0;
       S.xr[i] = S.x[i];
       S.yr[i] = S.y[i];
       S.zr[i] = S.z[i];
@@ -1430,10 +1442,20 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
       // retire in order)
       constexpr int kPruneBatch = GATHER ? 4 : 7;
       const StagedIndex sx(lo, cap);
-      const int nmax = __builtin_amdgcn_readfirstlane(wave_max_i(n));
       const int own = (n + 7) >> 3;
       const int4 *pad = reinterpret_cast<const int4 *>(kPadChunk);
-      for (int c0 = 0; c0 < (nmax + 7) >> 3; c0 += kPruneBatch) {
+      // the core: a row's leading ncore entries, within the core radius at
+      // the build, stay in its pruned row until the next build.  After the
+      // build's own pruning, a row's chunks that hold core entries only are
+      // left as written (the block's window, and so the entries' encoding,
+      // is fixed between builds): each lane starts at its first chunk past
+      // them, and the other core entries are kept without a test.
+      const int nc = S.core_r2q > 0.0f && B.valid ? S.ncore[i] : 0;
+      const int cs = rebuilt ? 0 : nc >> 3;
+      const int span = __builtin_amdgcn_readfirstlane(wave_max_i(own - cs));
+      ring.cnt = ring.head = 8 * cs;
+      for (int t0 = 0; t0 < span; t0 += kPruneBatch) {
+        const int c0 = cs + t0;
         int4 buf[2 * kPruneBatch];
 #pragma unroll
         for (int k = 0; k < kPruneBatch; ++k) {
@@ -1454,9 +1476,10 @@ __global__ void __launch_bounds__(kBlock) k_prune(Dev S) {
           for (int e = 0; e < 8; ++e) q[e] = sx.get(lq, j[e]);
           // pad entries read the sentinel, which lies beyond the pruning
           // radius, so they need no test of their own
+          const int k0 = 8 * (c0 + k);
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            ring.put(list_entry(j[e], base), kept(q[e], true));
+            ring.put(list_entry(j[e], base), (k0 + e < nc) | kept(q[e], true));
           ring.flush(S.nl_lane, S.N, row, nch);
         }
       }

@@ -465,8 +465,9 @@ class WireBatch:
     def flags(self, r: int):
         return self._slice("flag", r)
 
-    def neighbor_rows(self, r: int):
-        """Neighbour tag arrays of replica r, sorted, by tag."""
+    def neighbor_rows(self, r: int, sort: bool = True):
+        """Neighbour tag arrays of replica r, by tag: sorted, or with
+        sort=False in list order."""
         nn = self.t["nn"].cpu().numpy()
         # chunks of 8: entry k of slot i at ((k // 8) * N + i) * 8 + k % 8
         nl = self.t["nl"].view(self.k_cap // 8, self.N, 8).cpu().numpy()
@@ -475,7 +476,8 @@ class WireBatch:
         rows = []
         for i in range(int(self.n_atoms[r])):
             j = nl[:, o + i, :].reshape(-1)[:nn[o + i]] - o
-            rows.append(np.sort(j if perm is None else perm[j]))
+            j = j if perm is None else perm[j]
+            rows.append(np.sort(j) if sort else j)
         return rows if perm is None else [rows[s] for s in np.argsort(perm)]
 
     def count_pairs(self):

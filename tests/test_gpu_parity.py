@@ -291,6 +291,16 @@ def _check_lists(b, r):
         g = set(got[i].tolist())
         assert len(g) == got[i].size
         assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
+    if b.precision == "mixed":
+        # mixed rows list the pairs within r_cut - skin/2 at the build first
+        P0 = np.stack([xr, yr, zr], 1)
+        rcore = b.pot.r_cut - 0.5 * b.skin
+        for i, row in enumerate(b.neighbor_rows(r, sort=False)):
+            d = np.sqrt(((P0[row] - P0[i]) ** 2).sum(1))
+            inner = np.flatnonzero(d < rcore - 1e-4)
+            outer = np.flatnonzero(d > rcore + 1e-4)
+            if inner.size and outer.size:
+                assert inner[-1] < outer[0], (r, i)
     # the pruned lists the pair passes read hold every pair within r_tail
     # and within (r_tail, r_cut) at the current positions
     x, y, z = b.positions(r)
