@@ -550,10 +550,11 @@ __device__ __forceinline__ void nlist_cells(const Dev &S, int64_t i, int r,
 // Mixed-precision cell scan, for tiles whose slabs exceed LDS: this lane's
 // atom against the atoms of cells q, q + nq, q + 2 nq, ... of the 27 around
 // its cell (nq wavefronts share the scan), reading candidate positions from
-// global memory; near(j, d2) is called for each candidate j within the
+// global memory; near(j, d2, -1) is called for each candidate j within the
 // list radius, with its squared distance d2 (exact integer differences of
-// the quantised positions, quanta^2), in cell order.  A lane takes up to 4 candidates of its current cell at a time,
-// so that their slot and position loads are in flight together.
+// the quantised positions, quanta^2), in cell order.  A lane takes up to 4
+// candidates of its current cell at a time, so that their slot and position
+// loads are in flight together.
 template <class F>
 __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
                                            bool real, int cx, int cy, int cz,
@@ -599,7 +600,7 @@ __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
         const float dy = (float)(qq[k].y - qi.y);
         const float dz = (float)(qq[k].z - qi.z);
         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (d2 < rl2q) near(jj[k], d2);
+        if (d2 < rl2q) near(jj[k], d2, -1);
       }
       s += nb;
     }
@@ -608,9 +609,9 @@ __device__ __forceinline__ void cells_scan(const Dev &S, int64_t i, int r,
 
 // Tests this lane's atom (FP32 offset pi from the block origin) against
 // window candidates [a, b) of cand (x, y, z offsets and the slot as bits;
-// a and b uniform over the wavefront) and calls near(j, d2) for each
-// candidate j within the list radius, with its squared distance d2
-// (quanta^2), in candidate order.  Candidates are read in
+// a and b uniform over the wavefront) and calls near(j, d2, t) for each
+// candidate t, of slot j, within the list radius, with its squared distance
+// d2 (quanta^2), in candidate order.  Candidates are read in
 // groups of 8, and this wavefront takes groups q, q + nq, q + 2 nq, ... of
 // the range (nq wavefronts share the scan of one tile).  cand holds 8
 // filler entries past the window so the last group stays in bounds, and
@@ -634,7 +635,7 @@ __device__ __forceinline__ void window_scan(int64_t i, bool real, float4 pi,
       const float dz = c[e].z - pi.z;
       const int32_t j = __float_as_int(c[e].w);
       const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      if (d2 < rl2q && j != self && t0 + e < b && real) near(j, d2);
+      if (d2 < rl2q && j != self && t0 + e < b && real) near(j, d2, t0 + e);
     }
   }
 }
@@ -848,12 +849,17 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
 // were slower).
 constexpr int kNlBlock = 512;
 constexpr int kNlWaves = kNlBlock / kTile;
+// Pairs per row and share that the list build's counting scan keeps for its
+// writing pass (a share averages about a sixth of this for the 3 nm wires).
+constexpr int kFound = 32;
+static_assert(kCand + 8 <= 0x8000, "candidate indices fit in 15 bits");
 
 constexpr int kBoxRows = 64;  // rows of cells of the box scan, at most
 
 __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
   __shared__ float4 cand[kCand + 8];
   __shared__ int32_t qcnt[kNlWaves][kTile];
+  __shared__ uint16_t found[kNlWaves][kFound][kTile];
   __shared__ int32_t qcore[kNlWaves][kTile];
   __shared__ int2 qwin[kNlWaves];
   __shared__ int32_t rowbeg[kBoxRows], rowlen[kBoxRows], rowpre[kBoxRows + 1];
@@ -893,15 +899,29 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
       window = m <= kCand;
       if (window) {
         const int4 o = S.qpos[(int64_t)tile * kTile];
-        for (int t = tid; t < m + 8; t += kNlBlock) {
-          float4 c = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-          if (t < m) {
-            const int32_t j = S.cell_atoms[s0 + t];
-            const int4 qj = S.qpos[j];
-            c = make_float4((float)(qj.x - o.x), (float)(qj.y - o.y),
-                            (float)(qj.z - o.z), __int_as_float(j));
-          }
-          cand[t] = c;
+        // all of a thread's slot reads, then all of its position reads (m is
+        // uniform, so are the trip counts)
+        constexpr int kPer = (kCand + 8 + kNlBlock - 1) / kNlBlock;
+        int32_t jj[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+          const int t = tid + k * kNlBlock;
+          jj[k] = t < m ? S.cell_atoms[s0 + t] : -1;
+        }
+        int4 qq[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+          qq[k] = jj[k] >= 0 ? S.qpos[jj[k]] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+          const int t = tid + k * kNlBlock;
+          if (t < m + 8)
+            cand[t] = jj[k] >= 0
+                          ? make_float4((float)(qq[k].x - o.x),
+                                        (float)(qq[k].y - o.y),
+                                        (float)(qq[k].z - o.z),
+                                        __int_as_float(jj[k]))
+                          : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
         }
         pi = make_float4((float)(qi.x - o.x), (float)(qi.y - o.y),
                          (float)(qi.z - o.z), 0.f);
@@ -989,9 +1009,14 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
     int cnt = 0, cnt_c = 0;  // pairs of this share, of them in the core
     int32_t wlo = (int32_t)i, whi = (int32_t)i;  // slot window of the row
     const float core2 = S.core_r2q;
-    auto count = [&](int32_t j, float d2) {
+    // from window candidates, the first kFound pairs of the share are also
+    // kept (candidate index, core flag in the top bit) for the writing pass
+    auto count = [&](int32_t j, float d2, int t) {
+      const bool c = d2 < core2;
+      if (cnt < kFound)
+        found[q][cnt][lane] = (uint16_t)(t | (c ? 0x8000 : 0));
       ++cnt;
-      cnt_c += d2 < core2 ? 1 : 0;
+      cnt_c += c ? 1 : 0;
       wlo = min(wlo, j);
       whi = max(whi, j);
     };
@@ -1017,14 +1042,24 @@ __global__ void __launch_bounds__(kNlBlock) k_nlist_mixed(Dev S, float rl2q) {
       total_c += cc;
     }
     int ec = before_c, es = total_c + before - before_c;
-    auto write = [&](int32_t j, float d2) {
+    auto write = [&](int32_t j, float d2, int) {
       const int e = d2 < core2 ? ec++ : es++;
       if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
     };
-    if (window)
+    // the kept pairs when every share of every row fitted (uniform), else a
+    // second scan; either writes the same entries in the same order
+    if (window && !__syncthreads_or(cnt > kFound)) {
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t f = found[q][k][lane];
+        const int32_t j = __float_as_int(cand[f & 0x7fffu].w);
+        const int e = (f & 0x8000u) ? ec++ : es++;
+        if (e < S.k_cap) S.nl[cl8(N, i, e >> 3) + (e & 7)] = j;
+      }
+    } else if (window) {
       window_scan(i, real, pi, cand, 0, m, rl2q, q, kNlWaves, write);
-    else
+    } else {
       cells_scan(S, i, r, real, cx, cy, cz, qi, rl2q, q, kNlWaves, write);
+    }
     // the unused entries of the row's last chunk
     if (q == kNlWaves - 1 && total < S.k_cap)
       for (int f = total; f < ((total + 7) & ~7); ++f)
