@@ -850,7 +850,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *wsum,
 constexpr int kNlBlock = 512;
 constexpr int kNlWaves = kNlBlock / kTile;
 // Pairs per row and share that the list build's counting scan keeps for its
-// writing pass (a share averages about a sixth of this for the 3 nm wires).
+// writing pass (a share of a 3 nm wire's row averages about 15).
 constexpr int kFound = 32;
 static_assert(kCand + 8 <= 0x8000, "candidate indices fit in 15 bits");
 
