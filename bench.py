@@ -134,10 +134,12 @@ def main():
     ap.add_argument("--steps-per-graph", type=int, default=50,
                     help="steps per captured graph (clamped to --steps, so that every "
                          "timed step runs from a graph whenever it divides --steps)")
-    ap.add_argument("--thermalize", type=int, default=1000,
+    ap.add_argument("--thermalize", type=int, default=3000,
                     help="untimed steps run in setup before the warmup, so that the "
                          "timed window starts from thermal positions with lists "
-                         "rebuilt there (not from the perfect lattice)")
+                         "rebuilt there (not from the perfect lattice); with the "
+                         "batched workloads' 2.6 A skin the rebuild rate settles "
+                         "after some 2000 steps")
     ap.add_argument("--per-replica", type=int, default=32,
                     help="replicas timed one per launch for the plain-path rate")
     ap.add_argument("--per-replica-steps", type=int, default=20)
@@ -193,7 +195,7 @@ def main():
     skin = wl.skin if args.skin is None else args.skin
     prune = wl.prune if args.prune is None else args.prune
     b = WireBatch(wl.replicas, wl.precision, n_log=100, strain_max=strain_max,
-                  skin=skin, prune=prune, gamma=wl.gamma)
+                  skin=skin, prune=prune, gamma=wl.gamma, k_cap=wl.k_cap)
     b.prepare()
     n_real = int(b.n_atoms.sum())
     S = max(1, min(args.steps_per_graph, args.steps))
@@ -309,7 +311,7 @@ def main():
         t_graph = 0.0
         for r in idx:
             s1 = WireBatch([wl.replicas[r]], wl.precision, n_log=100, strain_max=strain_max,
-                           qbits=b.qbits, skin=wl.skin, gamma=wl.gamma)
+                           qbits=b.qbits, skin=wl.skin, gamma=wl.gamma, k_cap=wl.k_cap)
             s1.prepare()
             s1.step(2)
             torch.cuda.synchronize()
@@ -349,7 +351,7 @@ def main():
                  dict(gamma=0.0, nh_tau=0.1, T_start=0.01, ramp_begin=0, ramp_steps=200000,
                       baro_mass=1.0e4, baro_damp=1.0))):
             pb = WireBatch(wl.replicas, wl.precision, n_log=100, strain_max=strain_max,
-                           skin=skin, prune=prune, **kw)
+                           skin=skin, prune=prune, k_cap=wl.k_cap, **kw)
             pb.prepare()
             pb.run_batch(args.warmup, S)
             torch.cuda.synchronize()

@@ -119,10 +119,10 @@ extern "C" {
  *                   from the full list whenever some atom of the replica has
  *                   moved more than d since the last pruning, so no pair
  *                   within r_cut is ever left out.  The pairs within
- *                   r_cut - skin/2 at the last build are kept without a test
- *                   until the next one (such a pair leaves r_cut + 2d only
- *                   when stretched by more than skin/2 + 2d, and contributes
- *                   nothing beyond r_cut).
+ *                   r_cut - m at the last build, m = min(skin/2, 0.8 A), are
+ *                   kept without a test until the next one (such a pair
+ *                   leaves r_cut + 2d only when stretched by more than
+ *                   m + 2d, and contributes nothing beyond r_cut).
  *  gather           MIXED only, 0 or 1: 1 lets a block of the pair passes
  *                   whose slot window is too wide for LDS (thick wires)
  *                   stage the exact set of its neighbours instead, through
@@ -232,8 +232,8 @@ typedef struct {
  * Verlet lists (full: both i->j and j->i), stored in chunks of 8 entries:
  * entry k of atom i is nl[((k/8)*N + i)*8 + k%8], k < nn[i] <= k_cap, in
  * an order fixed by the positions alone: cell-scan order (cells by z, y, x;
- * slots ascending within a cell) in FP64; in MIXED, the pairs within r_cut - skin/2
- * first, then the others, each part in that order within each of eight
+ * slots ascending within a cell) in FP64; in MIXED, the pairs within
+ * r_cut - min(skin/2, 0.8 A) first, then the others, each part in that order within each of eight
  * interleaved shares of the candidate scan (groups of 8 candidates, or
  * every eighth of the 27 cells when a tile's candidates exceed LDS),
  * shares in turn.  The entries nn[i] <= k < 8*ceil(nn[i]/8) of an atom's last chunk

@@ -140,7 +140,7 @@ def tune(wb: WireBatch, *, candidates: Sequence[int] = CANDIDATES, steps: int = 
 
 
 def per_bucket_rates(replicas: Sequence, choice: dict, precision: str, *, skin: float,
-                     prune: float, steps: int = 200, warmup: int = 200,
+                     prune: float, k_cap: int = 176, steps: int = 200, warmup: int = 200,
                      steps_per_graph: int = 50, log=print) -> dict:
     """Rate of each bucket alone (one batch of its replicas, with its tuned
     shape): the per-replica-size throughput.  Context for the one-batch
@@ -149,7 +149,7 @@ def per_bucket_rates(replicas: Sequence, choice: dict, precision: str, *, skin: 
     for b, idx in buckets(replicas).items():
         k = bucket_key(b)
         wb = WireBatch([replicas[r] for r in idx], precision, skin=skin, prune=prune,
-                       n_log=steps_per_graph, shapes=[choice[k]] * len(idx))
+                       k_cap=k_cap, n_log=steps_per_graph, shapes=[choice[k]] * len(idx))
         wb.prepare()
         rate = measure(wb, steps, warmup, 1, steps_per_graph)
         out[k] = {"replicas": len(idx), "atoms": int(wb.n_atoms.sum()),
@@ -181,7 +181,7 @@ def main(argv=None):
     wl = W.WORKLOADS[a.workload]()
     torch.cuda.set_device(0)
     wb = WireBatch(wl.replicas, wl.precision, skin=wl.skin, prune=wl.prune, n_log=50,
-                   gamma=wl.gamma)
+                   gamma=wl.gamma, k_cap=wl.k_cap)
     wb.prepare()
     wb.run_batch(a.thermalize, 50)
     untuned = measure(wb, a.steps, 50, 1, 50)
@@ -194,7 +194,8 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if not a.no_per_bucket:
         out["per_bucket"] = per_bucket_rates(wl.replicas, res["choice"], wl.precision,
-                                             skin=wl.skin, prune=wl.prune, log=log)
+                                             skin=wl.skin, prune=wl.prune, k_cap=wl.k_cap,
+                                             log=log)
     print(json.dumps(out), flush=True)
 
 

@@ -302,12 +302,13 @@ Dev make_dev(const tbsma_params *p, const tbsma_system *s, void *work) {
                                    : p->r_cut + p->skin + 1.0;
     d.pruning = p->prune > 0 ? 1 : 0;
     d.rebuild_bound = d.pruning && !p->rebuild_exact ? 1 : 0;
-    // the core of the full lists: pairs within r_cut - skin/2 at the build,
-    // listed first and kept by every pruning until the next build.  They
-    // leave the pruning radius only when stretched by more than skin/2 + 2d,
-    // and a pair beyond r_cut contributes nothing.  The radius does not
-    // depend on d, so runs with and without pruning list pairs alike.
-    const double rcore = p->r_cut - 0.5 * p->skin;
+    // the core of the full lists: pairs within r_cut - min(skin/2, 0.8 A) at
+    // the build, listed first and kept by every pruning until the next build.
+    // They leave the pruning radius only when stretched by more than that
+    // margin plus 2d, and a pair beyond r_cut contributes nothing.  The
+    // radius does not depend on d, so runs with and without pruning list
+    // pairs alike.
+    const double rcore = p->r_cut - std::min(0.5 * p->skin, 0.8);
     d.core_r2q = rcore > 0 ? (float)(rcore * rcore * q * q) : 0.0f;
     d.prune_r2q = (float)(rp * rp * q * q);
     d.prune_d2q = (float)(p->prune * p->prune * q * q);

@@ -292,9 +292,10 @@ def _check_lists(b, r):
         assert len(g) == got[i].size
         assert set(sure[i].tolist()) <= g <= set(loose[i].tolist()), (r, i)
     if b.precision == "mixed":
-        # mixed rows list the pairs within r_cut - skin/2 at the build first
+        # mixed rows list the pairs within r_cut - min(skin/2, 0.8 A) at the
+        # build first
         P0 = np.stack([xr, yr, zr], 1)
-        rcore = b.pot.r_cut - 0.5 * b.skin
+        rcore = b.pot.r_cut - min(0.5 * b.skin, 0.8)
         for i, row in enumerate(b.neighbor_rows(r, sort=False)):
             d = np.sqrt(((P0[row] - P0[i]) ** 2).sum(1))
             inner = np.flatnonzero(d < rcore - 1e-4)
@@ -1211,7 +1212,7 @@ def test_config2_pulled_to_rupture_forces_stay_within_parity():
     wl = W.wire_d3_l20_mixed()
     note("D3 x L20 nm mixed, 10 K, pulled to rupture")
     b = WireBatch(wl.replicas, "mixed", n_log=500, n_slots=128, skin=wl.skin, prune=wl.prune,
-                  retire=2.0, strain_max=1.3)
+                  k_cap=wl.k_cap, retire=2.0, strain_max=1.3)
     b.prepare()
     rows = []
     while b.step_index() < 250000:
@@ -1320,7 +1321,7 @@ def test_full_size_batch512_sampled():
     graph-replayed steps, then sampled replicas against the oracle."""
     wl = W.batch512_d3()
     note(f"512-wire batch full size R={len(wl.replicas)}")
-    b = WireBatch(wl.replicas, "mixed", n_log=50, skin=wl.skin, prune=wl.prune)
+    b = WireBatch(wl.replicas, "mixed", n_log=50, skin=wl.skin, prune=wl.prune, k_cap=wl.k_cap)
     b.prepare()
     b.run_batch(100, 50)
     torch.cuda.synchronize()
@@ -1353,7 +1354,7 @@ def test_full_size_d10_wire_sampled():
 def test_batch2048_mixed_shapes_sampled():
     wl = W.batch2048_mixed_shapes()
     note(f"2048 mixed shapes R={len(wl.replicas)}")
-    b = WireBatch(wl.replicas, "mixed", n_log=20, skin=wl.skin, prune=wl.prune)
+    b = WireBatch(wl.replicas, "mixed", n_log=20, skin=wl.skin, prune=wl.prune, k_cap=wl.k_cap)
     b.prepare()
     b.run_batch(40, 20)
     torch.cuda.synchronize()

@@ -44,6 +44,7 @@ class Workload:
     gamma: float = 1.0  # 1/ps
     skin: float = 1.0   # Angstrom, Verlet skin of the full lists
     prune: float = 0.15  # Angstrom, half-width of the pruned lists (mixed)
+    k_cap: int = 176    # Verlet-list capacity per atom (grown at the first build)
     notes: str = ""
     extra: dict = field(default_factory=dict)
 
@@ -78,9 +79,12 @@ def batch512_d3(n_rep: int = 512) -> Workload:
     Ls = rng.uniform(50.0, 400.0, size=n_rep)
     reps = [Replica(30.0, snap_length(float(Ls[r])), 298.0, 0.5, seed_of(r), r)
             for r in range(n_rep)]
-    # skin 1.6 A: with pruned lists the pair work does not grow with the
-    # skin, and rebuilds become rare (measured fastest of 1.0-2.0 A)
-    return Workload(f"batched {n_rep}x D3nm L5-40nm 298K", reps, "mixed", 20000, skin=1.6)
+    # skin 2.6 A: with pruned lists the pair work does not grow with the
+    # skin, and the pruning reads only the part of each row beyond its core,
+    # so longer rows cost little while rebuilds become rare (measured fastest
+    # of 1.6-3.2 A); the capacity leaves room for rows to grow in the run
+    return Workload(f"batched {n_rep}x D3nm L5-40nm 298K", reps, "mixed", 20000, skin=2.6,
+                    k_cap=264)
 
 
 def batch2048_mixed_shapes(n_rep: int = 2048) -> Workload:
@@ -92,7 +96,8 @@ def batch2048_mixed_shapes(n_rep: int = 2048) -> Workload:
     rates = (0.1, 0.5, 1.0)
     reps = [Replica(Ds[r % 4], snap_length(float(Ls[r])), 10.0 if r % 2 == 0 else 298.0,
                     rates[r % 3], seed_of(r), r) for r in range(n_rep)]
-    return Workload(f"mixed-shapes {n_rep}x D1.5-3nm L3-30nm", reps, "mixed", 20000, skin=1.6)
+    return Workload(f"mixed-shapes {n_rep}x D1.5-3nm L3-30nm", reps, "mixed", 20000, skin=2.6,
+                    k_cap=264)
 
 
 def wire_d10_l100() -> Workload:
